@@ -1,0 +1,201 @@
+"""FP64 CPU oracle for tricubic direct volume ray casting.
+
+TEST INFRASTRUCTURE ONLY: the test suite, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package; the GPU library and
+its Python binding never do.  It shares no code with the GPU path; only the
+seeded inputs of ``synth`` feed both.
+
+The arithmetic lives in ``oracle.c`` (plain scalar C, FP64, OpenMP over
+pixels); ``brute.py`` is an independent pure-Python brute force for tiny
+volumes.  This module only marshals NumPy arrays into the C calls.
+
+Parity notes:
+  * every function here is pinned by the ``-m "not gpu"`` tests in
+    ``tests/test_oracle_*.py`` (closed forms, invariants, brute force).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+
+DTYPES = {np.dtype(np.uint16): 0, np.dtype(np.int16): 1, np.dtype(np.float32): 2, np.dtype(np.float64): 3}
+
+
+def build(force: bool = True) -> str:
+    """Compile ``oracle.c`` into ``liboracle.so`` with gcc (no FMA contraction,
+    no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = [
+            "gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+            "-Wall", "-Wno-unknown-pragmas", "-o", _LIB_PATH + ".tmp", _SRC, "-lm",
+        ]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_long
+        i32 = ctypes.c_int
+        f64 = ctypes.c_double
+        f32 = ctypes.c_float
+        L.oracle_num_threads.restype = i32
+        L.oracle_blocks.argtypes = [P, i32, i64, i64, i64, i32, P]
+        L.oracle_blocks.restype = i32
+        L.oracle_occupancy.argtypes = [P, i64, P, i32, f32, f32, P]
+        L.oracle_occupancy.restype = i32
+        L.oracle_render.argtypes = [P, i32, i64, i64, i64, P, i32, i32, i32, P, i32, f64, f64, f64, f64,
+                                    P, i32, P, i64, P, P, P]
+        L.oracle_render.restype = i32
+        L.oracle_grad.argtypes = [P, i32, i64, i64, i64, P, i32, i32, i32, P, i32, f64, f64, f64, f64,
+                                  P, i32, P, P, P]
+        L.oracle_grad.restype = i32
+        L.oracle_ray.argtypes = [P, i32, i32, i64, i64, i64, i64, i64, f64, P, P]
+        L.oracle_ray.restype = i32
+        L.oracle_sample.argtypes = [P, i32, i64, i64, i64, f64, f64, f64]
+        L.oracle_sample.restype = f64
+        L.oracle_weights.argtypes = [f64, P]
+        L.oracle_weights.restype = None
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _vol(vol):
+    vol = np.ascontiguousarray(vol)
+    if vol.dtype not in DTYPES:
+        raise TypeError(f"unsupported volume dtype {vol.dtype}")
+    nz, ny, nx = vol.shape
+    return vol, DTYPES[vol.dtype], nx, ny, nz
+
+
+def pack_cameras(cameras) -> np.ndarray:
+    """Pack cameras into the oracle's 16-double rows: projection, eye, right,
+    up, forward, fov_y, ortho_w, ortho_h."""
+    rows = []
+    for c in cameras:
+        rows.append(
+            [float(c.projection), *map(float, c.eye), *map(float, c.right), *map(float, c.up),
+             *map(float, c.forward), float(c.fov_y), float(c.ortho_w), float(c.ortho_h)]
+        )
+    return np.ascontiguousarray(np.array(rows, dtype=np.float64))
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())
+
+
+def blocks(vol, edge: int = 16) -> np.ndarray:
+    """Per-block (min, max) over the tricubic footprint; shape (nbz, nby, nbx, 2)."""
+    vol, dt, nx, ny, nz = _vol(vol)
+    nbx, nby, nbz = -(-nx // edge), -(-ny // edge), -(-nz // edge)
+    out = np.zeros((nbz, nby, nbx, 2), dtype=np.float64)
+    rc = lib().oracle_blocks(_ptr(vol), dt, nx, ny, nz, edge, _ptr(out))
+    if rc:
+        raise ValueError("oracle_blocks rejected its arguments")
+    return out
+
+
+def occupancy(minmax, tf) -> np.ndarray:
+    """One byte per block: 1 when the block can hold a visible sample under tf."""
+    mm = np.ascontiguousarray(minmax, dtype=np.float64)
+    nb = mm.size // 2
+    occ = np.zeros(mm.shape[:-1], dtype=np.uint8)
+    table = np.ascontiguousarray(tf.table, dtype=np.float32)
+    rc = lib().oracle_occupancy(_ptr(mm), nb, _ptr(table), table.shape[0], float(tf.v0), float(tf.v1), _ptr(occ))
+    if rc:
+        raise ValueError("oracle_occupancy rejected its arguments")
+    return occ
+
+
+def render(vol, cameras, tf, step, ert=0.0, occ=None, edge=16, pixels=None):
+    """FP64 render.  Returns dict(rgba, flags, counts); rgba is (views, H, W, 4)
+    for a full render or (n, 4) for a pixel list."""
+    vol, dt, nx, ny, nz = _vol(vol)
+    cams = pack_cameras(cameras)
+    W, H = int(cameras[0].width), int(cameras[0].height)
+    table = np.ascontiguousarray(tf.table, dtype=np.float32)
+    occ_a = None if occ is None else np.ascontiguousarray(occ, dtype=np.uint8)
+    if pixels is None:
+        n = len(cameras) * W * H
+        pix = None
+        shape = (len(cameras), H, W)
+    else:
+        pix = np.ascontiguousarray(pixels, dtype=np.int64)
+        n = pix.shape[0]
+        shape = (n,)
+    rgba = np.zeros(shape + (4,), dtype=np.float64)
+    flags = np.zeros(shape, dtype=np.uint8)
+    counts = np.zeros(shape + (2,), dtype=np.int64)
+    rc = lib().oracle_render(
+        _ptr(vol), dt, nx, ny, nz, _ptr(cams), len(cameras), W, H, _ptr(table), table.shape[0],
+        float(tf.v0), float(tf.v1), float(step), float(ert), _ptr(occ_a), int(edge), _ptr(pix), n,
+        _ptr(rgba), _ptr(flags), _ptr(counts),
+    )
+    if rc:
+        raise ValueError("oracle_render rejected its arguments")
+    return dict(rgba=rgba, flags=flags, counts=counts)
+
+
+def grad(vol, cameras, tf, step, grad_rgba, ert=0.0, occ=None, edge=16, want_volume=True, want_tf=True):
+    """Gradient of sum(grad_rgba * RGBA) w.r.t. the voxel values and the TF
+    table, in FP64.  Returns (grad_volume shaped like vol or None, grad_tf (K, 4)
+    or None)."""
+    vol, dt, nx, ny, nz = _vol(vol)
+    cams = pack_cameras(cameras)
+    W, H = int(cameras[0].width), int(cameras[0].height)
+    table = np.ascontiguousarray(tf.table, dtype=np.float32)
+    g = np.ascontiguousarray(grad_rgba, dtype=np.float64).reshape(len(cameras), H, W, 4)
+    gv = np.zeros(vol.shape, dtype=np.float64) if want_volume else None
+    gt = np.zeros(table.shape, dtype=np.float64) if want_tf else None
+    occ_a = None if occ is None else np.ascontiguousarray(occ, dtype=np.uint8)
+    rc = lib().oracle_grad(
+        _ptr(vol), dt, nx, ny, nz, _ptr(cams), len(cameras), W, H, _ptr(table), table.shape[0],
+        float(tf.v0), float(tf.v1), float(step), float(ert), _ptr(occ_a), int(edge), _ptr(g), _ptr(gv), _ptr(gt),
+    )
+    if rc:
+        raise ValueError("oracle_grad rejected its arguments")
+    return gv, gt
+
+
+def ray(camera, row, col, dims_xyz, step):
+    """(origin, direction, t_in, t_out, lattice count, hit) of one pixel's ray."""
+    cam = pack_cameras([camera])
+    out = np.zeros(8, dtype=np.float64)
+    ns = ctypes.c_long(0)
+    hit = lib().oracle_ray(_ptr(cam), int(camera.width), int(camera.height), int(row), int(col),
+                           int(dims_xyz[0]), int(dims_xyz[1]), int(dims_xyz[2]), float(step), _ptr(out),
+                           ctypes.byref(ns))
+    return out[:3].copy(), out[3:6].copy(), float(out[6]), float(out[7]), int(ns.value), bool(hit)
+
+
+def sample(vol, p) -> float:
+    """Tricubic B-spline value of ``vol`` at point p = (x, y, z)."""
+    vol, dt, nx, ny, nz = _vol(vol)
+    return float(lib().oracle_sample(_ptr(vol), dt, nx, ny, nz, float(p[0]), float(p[1]), float(p[2])))
+
+
+def weights(f) -> np.ndarray:
+    w = np.zeros(4, dtype=np.float64)
+    lib().oracle_weights(float(f), _ptr(w))
+    return w

@@ -1,0 +1,539 @@
+/*
+ * oracle.c -- plain, slow FP64 CPU reference for tricubic direct volume ray
+ * casting with post-classification, front-to-back compositing, early ray
+ * termination and block empty-space skipping.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark load this library.  It shares no code, header,
+ * table or helper with the GPU library, and the GPU library never calls it.
+ *
+ * What is computed follows the paper's Section 2 ("Methodology"):
+ *   - one ray per image pixel, from the observer along a direction, moving
+ *     with a fixed step and accumulating the pixel colour (ray casting,
+ *     Fig. 2 and the paragraph before it);
+ *   - voxels are a translucent emitting/absorbing medium ("Voxel graphics");
+ *   - the scalar is reconstructed at every sample with cubic-spline
+ *     (tricubic) interpolation (Section 2, "In this work the cubic
+ *     interpolation is being used"; Fig. 4 discussion);
+ *   - the interpolated value is then classified through the transfer function
+ *     T(V) (post-classification, Fig. 3/Fig. 4 discussion);
+ *   - rays terminate early once opaque and blocks holding nothing visible are
+ *     skipped ("Pros" (b) of the block-decomposition analysis).
+ * The paper gives no formulas for any of these steps.  The readings used here
+ * (voxel-centred geometry, midpoint sample lattice, uniform cubic B-spline,
+ * node-centred piecewise-linear transfer function, extinction optical model,
+ * inclusive termination test, per-sample block skip) are the textbook
+ * emission-absorption discretisation; each is stated at the function that
+ * implements it.
+ *
+ * Everything is FP64 except the block-occupancy decision, which the paper
+ * leaves to the implementation and which is taken in FP32 so that the GPU and
+ * the oracle take the same integer decision.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { OR_U16 = 0, OR_I16 = 1, OR_F32 = 2, OR_F64 = 3 };
+
+typedef struct {
+    const void *data;
+    int dtype;
+    long nx, ny, nz;
+} or_vol;
+
+/* Voxel (x, y, z) with every index clamped to the grid (clamp-to-edge). */
+static double or_voxel(const or_vol *v, long x, long y, long z)
+{
+    if (x < 0) x = 0;
+    if (x > v->nx - 1) x = v->nx - 1;
+    if (y < 0) y = 0;
+    if (y > v->ny - 1) y = v->ny - 1;
+    if (z < 0) z = 0;
+    if (z > v->nz - 1) z = v->nz - 1;
+    long idx = x + v->nx * (y + v->ny * z);
+    switch (v->dtype) {
+    case OR_U16: return (double)((const uint16_t *)v->data)[idx];
+    case OR_I16: return (double)((const int16_t *)v->data)[idx];
+    case OR_F32: return (double)((const float *)v->data)[idx];
+    default: return ((const double *)v->data)[idx];
+    }
+}
+
+static long or_clampl(long a, long lo, long hi) { return a < lo ? lo : (a > hi ? hi : a); }
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Block min/max (the auxiliary structure for empty-space leaping).          */
+/*                                                                           */
+/* The paper splits the volume into fixed-size blocks with smaller remainder */
+/* blocks at the far faces, overlapping their neighbours by the voxels a     */
+/* cubic stencil reads (Section 2, block decomposition and Fig. 3).  Here    */
+/* that becomes, for each block b along an axis, the voxel range a tricubic  */
+/* sample with floor(p) in [bE, bE+E-1] can touch: [bE-1, bE+E+1], clamped   */
+/* to the grid.  Brute force over that footprint.                            */
+/* out: nbz*nby*nbx*2 doubles, (min, max) per block, x-block fastest.        */
+/* ------------------------------------------------------------------------ */
+int oracle_blocks(const void *data, int dtype, long nx, long ny, long nz, int edge, double *out)
+{
+    if (!data || !out || edge <= 0 || nx <= 0 || ny <= 0 || nz <= 0) return 1;
+    or_vol v = {data, dtype, nx, ny, nz};
+    long nbx = (nx + edge - 1) / edge, nby = (ny + edge - 1) / edge, nbz = (nz + edge - 1) / edge;
+    long nb = nbx * nby * nbz;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long b = 0; b < nb; ++b) {
+        long bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+        long x0 = or_clampl(bx * edge - 1, 0, nx - 1), x1 = or_clampl(bx * edge + edge + 1, 0, nx - 1);
+        long y0 = or_clampl(by * edge - 1, 0, ny - 1), y1 = or_clampl(by * edge + edge + 1, 0, ny - 1);
+        long z0 = or_clampl(bz * edge - 1, 0, nz - 1), z1 = or_clampl(bz * edge + edge + 1, 0, nz - 1);
+        double mn = INFINITY, mx = -INFINITY;
+        for (long z = z0; z <= z1; ++z)
+            for (long y = y0; y <= y1; ++y)
+                for (long x = x0; x <= x1; ++x) {
+                    double a = or_voxel(&v, x, y, z);
+                    if (a < mn) mn = a;
+                    if (a > mx) mx = a;
+                }
+        out[2 * b] = mn;
+        out[2 * b + 1] = mx;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Block occupancy under a transfer function.                                */
+/*                                                                           */
+/* A block may be skipped only if nothing inside it can be visible (Section  */
+/* 2, "Pros" (b): empty-space skipping with auxiliary structures).  With a   */
+/* piecewise-linear TF and non-negative extinction, every value v of a       */
+/* sample in the block lies in [min, max]; such a sample reads only TF nodes */
+/* between floor(u(min)) and ceil(u(max)).  One node of margin on each side  */
+/* absorbs rounding of v.  The block is empty iff every node in              */
+/* [floor(u(min)) - 1, ceil(u(max)) + 1] (clamped to [0, K-1]) has zero      */
+/* extinction.  u is evaluated in FP32 as (v - v0) * ((K-1) / (v1 - v0)).    */
+/* occ: one byte per block (1 occupied, 0 empty).                            */
+/* ------------------------------------------------------------------------ */
+int oracle_occupancy(const double *minmax, long nblocks, const float *tf, int K, float v0, float v1,
+                     uint8_t *occ)
+{
+    if (!minmax || !tf || !occ || K < 2 || !(v1 > v0)) return 1;
+    float scale = (float)(K - 1) / (v1 - v0);
+    for (long b = 0; b < nblocks; ++b) {
+        float ulo = ((float)minmax[2 * b] - v0) * scale;
+        float uhi = ((float)minmax[2 * b + 1] - v0) * scale;
+        if (ulo < -2.0f) ulo = -2.0f;
+        if (ulo > (float)K + 1.0f) ulo = (float)K + 1.0f;
+        if (uhi < -2.0f) uhi = -2.0f;
+        if (uhi > (float)K + 1.0f) uhi = (float)K + 1.0f;
+        long jlo = (long)floorf(ulo) - 1, jhi = (long)ceilf(uhi) + 1;
+        jlo = or_clampl(jlo, 0, K - 1);
+        jhi = or_clampl(jhi, 0, K - 1);
+        uint8_t o = 0;
+        for (long j = jlo; j <= jhi; ++j)
+            if (tf[4 * j + 3] != 0.0f) o = 1;
+        occ[b] = o;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Camera -> ray for pixel (i, j) (Section 2: a ray is an origin, e.g. the   */
+/* observer, and a direction, one per image pixel).                          */
+/* cam: 16 doubles = projection, eye[3], right[3], up[3], forward[3], fov_y, */
+/* ortho_w, ortho_h.  Pixel centre (i+1/2, j+1/2); sx = 2(i+1/2)/W - 1,      */
+/* sy = 1 - 2(j+1/2)/H.  Perspective: o = eye, d = normalize(forward +       */
+/* sx tan(fov/2) (W/H) right + sy tan(fov/2) up).  Orthographic: o = eye +   */
+/* sx (ortho_w/2) right + sy (ortho_h/2) up, d = normalize(forward).         */
+/* ------------------------------------------------------------------------ */
+static void or_ray(const double *cam, int W, int H, long i, long j, double o[3], double d[3])
+{
+    double sx = 2.0 * ((double)i + 0.5) / (double)W - 1.0;
+    double sy = 1.0 - 2.0 * ((double)j + 0.5) / (double)H;
+    const double *eye = cam + 1, *r = cam + 4, *u = cam + 7, *f = cam + 10;
+    if (cam[0] != 0.0) {
+        double th = tan(0.5 * cam[13]);
+        double a = sx * th * ((double)W / (double)H);
+        double b = sy * th;
+        for (int k = 0; k < 3; ++k) {
+            o[k] = eye[k];
+            d[k] = f[k] + a * r[k] + b * u[k];
+        }
+    } else {
+        double a = sx * (0.5 * cam[14]);
+        double b = sy * (0.5 * cam[15]);
+        for (int k = 0; k < 3; ++k) {
+            o[k] = eye[k] + a * r[k] + b * u[k];
+            d[k] = f[k];
+        }
+    }
+    double n = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    for (int k = 0; k < 3; ++k) d[k] = d[k] / n;
+}
+
+/* Clip the ray against the volume box [-1/2, n-1/2] per axis (voxel-centred */
+/* grid).  Returns 0 on a miss, else the entry and exit parameters.          */
+static int or_clip(const double o[3], const double d[3], long nx, long ny, long nz, double *tin,
+                   double *tout)
+{
+    double lo[3] = {-0.5, -0.5, -0.5};
+    double hi[3] = {(double)nx - 0.5, (double)ny - 0.5, (double)nz - 0.5};
+    double t0 = -INFINITY, t1 = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0) {
+            if (o[a] < lo[a] || o[a] > hi[a]) return 0;
+            continue;
+        }
+        double ta = (lo[a] - o[a]) / d[a];
+        double tb = (hi[a] - o[a]) / d[a];
+        if (ta > tb) {
+            double s = ta;
+            ta = tb;
+            tb = s;
+        }
+        if (ta > t0) t0 = ta;
+        if (tb < t1) t1 = tb;
+    }
+    double te = t0 > 0.0 ? t0 : 0.0;
+    if (!(t1 > te)) return 0;
+    *tin = te;
+    *tout = t1;
+    return 1;
+}
+
+/* Uniform cubic B-spline weights for the taps floor(p)-1 .. floor(p)+2 at   */
+/* fractional offset f (the reading of "cubic spline interpolation").        */
+static void or_bspline(double f, double w[4])
+{
+    double g = 1.0 - f;
+    w[0] = g * g * g / 6.0;
+    w[1] = (3.0 * f * f * f - 6.0 * f * f + 4.0) / 6.0;
+    w[2] = (-3.0 * f * f * f + 3.0 * f * f + 3.0 * f + 1.0) / 6.0;
+    w[3] = f * f * f / 6.0;
+}
+
+/* One reconstructed sample: the 64 taps, their weights and the value.      */
+typedef struct {
+    long tap[64];
+    double wt[64];
+    double v;
+} or_sample;
+
+/* Tricubic reconstruction at p: the explicit 64-term sum over the 4x4x4     */
+/* stencil, clamp-to-edge addressing.                                        */
+static void or_reconstruct(const or_vol *vol, const double p[3], or_sample *s)
+{
+    long ix = (long)floor(p[0]), iy = (long)floor(p[1]), iz = (long)floor(p[2]);
+    double wx[4], wy[4], wz[4];
+    or_bspline(p[0] - (double)ix, wx);
+    or_bspline(p[1] - (double)iy, wy);
+    or_bspline(p[2] - (double)iz, wz);
+    double v = 0.0;
+    int n = 0;
+    for (int c = 0; c < 4; ++c)
+        for (int b = 0; b < 4; ++b)
+            for (int a = 0; a < 4; ++a) {
+                long x = or_clampl(ix - 1 + a, 0, vol->nx - 1);
+                long y = or_clampl(iy - 1 + b, 0, vol->ny - 1);
+                long z = or_clampl(iz - 1 + c, 0, vol->nz - 1);
+                double w = wx[a] * wy[b] * wz[c];
+                s->tap[n] = x + vol->nx * (y + vol->ny * z);
+                s->wt[n] = w;
+                v += w * or_voxel(vol, x, y, z);
+                ++n;
+            }
+    s->v = v;
+}
+
+/* Post-classification: T(V) on the interpolated value.  Node j sits at      */
+/* v0 + j (v1 - v0)/(K-1); u is clamped to [0, K-1]; linear between nodes.   */
+/* Outputs (r, g, b, sigma), the segment j, its weight w and whether u was   */
+/* clamped.                                                                  */
+static void or_classify(const float *tf, int K, double v0, double v1, double v, double out[4], long *j_out,
+                        double *w_out, int *clamped)
+{
+    double u = (v - v0) * (double)(K - 1) / (v1 - v0);
+    *clamped = 0;
+    if (u < 0.0) {
+        u = 0.0;
+        *clamped = 1;
+    }
+    if (u > (double)(K - 1)) {
+        u = (double)(K - 1);
+        *clamped = 1;
+    }
+    long j = (long)floor(u);
+    if (j > K - 2) j = K - 2;
+    double w = u - (double)j;
+    for (int c = 0; c < 4; ++c) out[c] = (1.0 - w) * (double)tf[4 * j + c] + w * (double)tf[4 * (j + 1) + c];
+    *j_out = j;
+    *w_out = w;
+}
+
+typedef struct {
+    const or_vol *vol;
+    const double *cams;
+    int W, H;
+    const float *tf;
+    int K;
+    double v0, v1, step, ert;
+    const uint8_t *occ; /* NULL: no skipping */
+    int edge;
+} or_ctx;
+
+/* Sample lattice: midpoints t_k = t_in + (k + 1/2) step for every k >= 0    */
+/* with (k + 1/2) step < t_out - t_in.  Every segment has the full length.   */
+static long or_lattice_count(double tin, double tout, double step)
+{
+    double L = tout - tin;
+    long k = 0;
+    while (((double)k + 0.5) * step < L) ++k;
+    return k;
+}
+
+static int or_block_occupied(const or_ctx *cx, const double p[3])
+{
+    long cx_ = or_clampl((long)floor(p[0]), 0, cx->vol->nx - 1);
+    long cy_ = or_clampl((long)floor(p[1]), 0, cx->vol->ny - 1);
+    long cz_ = or_clampl((long)floor(p[2]), 0, cx->vol->nz - 1);
+    long nbx = (cx->vol->nx + cx->edge - 1) / cx->edge, nby = (cx->vol->ny + cx->edge - 1) / cx->edge;
+    long b = cx_ / cx->edge + nbx * (cy_ / cx->edge + nby * (cz_ / cx->edge));
+    return cx->occ[b] != 0;
+}
+
+/* One ray, forward.  rgba gets premultiplied (C, 1 - T) over transparent    */
+/* black.  counts[0] = lattice samples, counts[1] = evaluated samples.       */
+/* flag = 1 when the termination test came within 1e-5 of the threshold.     */
+static void or_trace(const or_ctx *cx, long view, long row, long col, double rgba[4], long counts[2], uint8_t *flag)
+{
+    double o[3], d[3], tin, tout;
+    rgba[0] = rgba[1] = rgba[2] = rgba[3] = 0.0;
+    counts[0] = counts[1] = 0;
+    *flag = 0;
+    const double *cam = cx->cams + 16 * view;
+    or_ray(cam, cx->W, cx->H, col, row, o, d);
+    if (!or_clip(o, d, cx->vol->nx, cx->vol->ny, cx->vol->nz, &tin, &tout)) return;
+    long ns = or_lattice_count(tin, tout, cx->step);
+    counts[0] = ns;
+    int ert_on = cx->ert > 0.0 && cx->ert < 1.0;
+    double C[3] = {0.0, 0.0, 0.0}, T = 1.0;
+    or_sample s;
+    for (long k = 0; k < ns; ++k) {
+        double t = tin + ((double)k + 0.5) * cx->step;
+        double p[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+        if (cx->occ && !or_block_occupied(cx, p)) continue;
+        counts[1]++;
+        or_reconstruct(cx->vol, p, &s);
+        double val[4], w;
+        long j;
+        int cl;
+        or_classify(cx->tf, cx->K, cx->v0, cx->v1, s.v, val, &j, &w, &cl);
+        double alpha = -expm1(-val[3] * cx->step);
+        for (int c = 0; c < 3; ++c) C[c] += T * alpha * val[c];
+        T *= exp(-val[3] * cx->step);
+        if (ert_on) {
+            if (fabs((1.0 - T) - cx->ert) < 1e-5) *flag = 1;
+            if (1.0 - T >= cx->ert) break;
+        }
+    }
+    rgba[0] = C[0];
+    rgba[1] = C[1];
+    rgba[2] = C[2];
+    rgba[3] = 1.0 - T;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Forward render.                                                           */
+/* cams: n_cams x 16 doubles (see or_ray); all views W x H.                  */
+/* pix: optional list of n_pix (view, row, col) triples; NULL renders every  */
+/* pixel of every view in [view][row][col] order.                            */
+/* out_rgba: 4 doubles per output pixel; out_flags (optional): 1 byte;       */
+/* out_counts (optional): 2 longs (lattice, evaluated).                      */
+/* occ (optional): one byte per block from oracle_occupancy; NULL = no skip. */
+/* ------------------------------------------------------------------------ */
+int oracle_render(const void *data, int dtype, long nx, long ny, long nz, const double *cams, int n_cams, int W,
+                  int H, const float *tf, int K, double v0, double v1, double step, double ert,
+                  const uint8_t *occ, int edge, const long *pix, long n_pix, double *out_rgba,
+                  uint8_t *out_flags, long *out_counts)
+{
+    if (!data || !cams || !tf || !out_rgba || n_cams <= 0 || W <= 0 || H <= 0 || K < 2 || !(v1 > v0) ||
+        !(step > 0.0))
+        return 1;
+    or_vol vol = {data, dtype, nx, ny, nz};
+    or_ctx cx = {&vol, cams, W, H, tf, K, v0, v1, step, ert, occ, edge};
+    long total = pix ? n_pix : (long)n_cams * W * H;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long q = 0; q < total; ++q) {
+        long view, row, col;
+        if (pix) {
+            view = pix[3 * q];
+            row = pix[3 * q + 1];
+            col = pix[3 * q + 2];
+        } else {
+            view = q / ((long)W * H);
+            row = (q / W) % H;
+            col = q % W;
+        }
+        double rgba[4];
+        long cnt[2];
+        uint8_t flag;
+        or_trace(&cx, view, row, col, rgba, cnt, &flag);
+        for (int c = 0; c < 4; ++c) out_rgba[4 * q + c] = rgba[c];
+        if (out_flags) out_flags[q] = flag;
+        if (out_counts) {
+            out_counts[2 * q] = cnt[0];
+            out_counts[2 * q + 1] = cnt[1];
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gradient of L = sum_pixels <g, RGBA> with respect to the voxel values and */
+/* the TF table (the adjoint of the forward model above).                    */
+/*                                                                           */
+/* Forward: C = sum_k T_k a_k c_k, T_{k+1} = T_k (1 - a_k), A = 1 - T_end,   */
+/* a_k = 1 - exp(-s_k step).  Hence                                          */
+/*   dC/dc_k     = T_k a_k                                                   */
+/*   dC/ds_k     = step (T_{k+1} c_k - S_k),  S_k = sum_{m>k} T_m a_m c_m    */
+/*   dA/ds_k     = step T_end                                                */
+/* and the chain rule through the TF segment (slope (K-1)/(v1-v0) times the  */
+/* node difference, zero where u was clamped) and the 64 B-spline weights.   */
+/* The stopping index of early termination is held fixed.  The per-ray      */
+/* samples are stored and the suffix sums S_k formed explicitly.             */
+/* grad_rgba: 4 doubles per pixel of the full image set.                     */
+/* grad_vol (nx*ny*nz) and grad_tf (K*4) are accumulated into (+=).          */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    or_sample s;
+    long j;
+    double w;
+    int clamped;
+    double val[4];
+    double alpha, Tk;
+} or_rec;
+
+int oracle_grad(const void *data, int dtype, long nx, long ny, long nz, const double *cams, int n_cams, int W,
+                int H, const float *tf, int K, double v0, double v1, double step, double ert, const uint8_t *occ,
+                int edge, const double *grad_rgba, double *grad_vol, double *grad_tf)
+{
+    if (!data || !cams || !tf || !grad_rgba || n_cams <= 0 || W <= 0 || H <= 0 || K < 2 || !(v1 > v0) ||
+        !(step > 0.0))
+        return 1;
+    or_vol vol = {data, dtype, nx, ny, nz};
+    or_ctx cx = {&vol, cams, W, H, tf, K, v0, v1, step, ert, occ, edge};
+    long total = (long)n_cams * W * H;
+    double slope_scale = (double)(K - 1) / (v1 - v0);
+    int ert_on = ert > 0.0 && ert < 1.0;
+#pragma omp parallel
+    {
+        long cap = 0;
+        or_rec *rec = NULL;
+#pragma omp for schedule(dynamic, 16)
+        for (long q = 0; q < total; ++q) {
+            long view = q / ((long)W * H), row = (q / W) % H, col = q % W;
+            const double *g = grad_rgba + 4 * q;
+            if (g[0] == 0.0 && g[1] == 0.0 && g[2] == 0.0 && g[3] == 0.0) continue;
+            double o[3], d[3], tin, tout;
+            or_ray(cams + 16 * view, W, H, col, row, o, d);
+            if (!or_clip(o, d, nx, ny, nz, &tin, &tout)) continue;
+            long ns = or_lattice_count(tin, tout, step);
+            if (ns > cap) {
+                free(rec);
+                cap = ns;
+                rec = (or_rec *)malloc(sizeof(or_rec) * (size_t)cap);
+            }
+            /* forward, storing every evaluated sample */
+            long n = 0;
+            double T = 1.0;
+            for (long k = 0; k < ns; ++k) {
+                double t = tin + ((double)k + 0.5) * step;
+                double p[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+                if (occ && !or_block_occupied(&cx, p)) continue;
+                or_rec *r = &rec[n++];
+                or_reconstruct(&vol, p, &r->s);
+                or_classify(tf, K, v0, v1, r->s.v, r->val, &r->j, &r->w, &r->clamped);
+                r->alpha = -expm1(-r->val[3] * step);
+                r->Tk = T;
+                T *= exp(-r->val[3] * step);
+                if (ert_on && 1.0 - T >= ert) break;
+            }
+            double Tend = T;
+            /* backward: walk from the last sample, S holds sum_{m>k} */
+            double S[3] = {0.0, 0.0, 0.0};
+            for (long m = n - 1; m >= 0; --m) {
+                or_rec *r = &rec[m];
+                double Tnext = r->Tk * exp(-r->val[3] * step);
+                double dval[4];
+                double ds = 0.0;
+                for (int c = 0; c < 3; ++c) {
+                    dval[c] = g[c] * r->Tk * r->alpha;
+                    ds += g[c] * (Tnext * r->val[c] - S[c]);
+                }
+                ds += g[3] * Tend;
+                dval[3] = step * ds;
+                for (int c = 0; c < 3; ++c) S[c] += r->Tk * r->alpha * r->val[c];
+                if (grad_tf) {
+                    for (int c = 0; c < 4; ++c) {
+#pragma omp atomic
+                        grad_tf[4 * r->j + c] += (1.0 - r->w) * dval[c];
+#pragma omp atomic
+                        grad_tf[4 * (r->j + 1) + c] += r->w * dval[c];
+                    }
+                }
+                if (grad_vol && !r->clamped) {
+                    double dv = 0.0;
+                    for (int c = 0; c < 4; ++c)
+                        dv += dval[c] * ((double)tf[4 * (r->j + 1) + c] - (double)tf[4 * r->j + c]) * slope_scale;
+                    for (int t = 0; t < 64; ++t) {
+#pragma omp atomic
+                        grad_vol[r->s.tap[t]] += dv * r->s.wt[t];
+                    }
+                }
+            }
+        }
+        free(rec);
+    }
+    return 0;
+}
+
+/* Lattice count and ray parameters for one pixel (exposed for tests).       */
+int oracle_ray(const double *cam, int W, int H, long row, long col, long nx, long ny, long nz, double step,
+               double out[8], long *ns)
+{
+    double o[3], d[3], tin = 0.0, tout = 0.0;
+    or_ray(cam, W, H, col, row, o, d);
+    int hit = or_clip(o, d, nx, ny, nz, &tin, &tout);
+    for (int k = 0; k < 3; ++k) {
+        out[k] = o[k];
+        out[3 + k] = d[k];
+    }
+    out[6] = tin;
+    out[7] = tout;
+    *ns = hit ? or_lattice_count(tin, tout, step) : 0;
+    return hit;
+}
+
+/* Tricubic value at an arbitrary point (exposed for the reconstruction pins). */
+double oracle_sample(const void *data, int dtype, long nx, long ny, long nz, double px, double py, double pz)
+{
+    or_vol vol = {data, dtype, nx, ny, nz};
+    double p[3] = {px, py, pz};
+    or_sample s;
+    or_reconstruct(&vol, p, &s);
+    return s.v;
+}
+
+/* B-spline weights at fractional offset f (exposed for the weight pins).   */
+void oracle_weights(double f, double w[4]) { or_bspline(f, w); }
