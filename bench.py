@@ -1,0 +1,318 @@
+#!/usr/bin/env python3
+"""Throughput of the MI355X tricubic ray caster on its headline workload.
+
+Workload (one "step" = one frame of the per-frame hot path): a 512x512x400
+int16 CT-like phantom (resident in HBM with its 16^3 block min/max) rendered
+to a 1024^2 perspective image, 60 deg FOV, seeded orbit pose, step 0.5 voxel,
+tricubic B-spline sampling, TF post-classification, front-to-back
+compositing, early termination at opacity 0.99, block empty-space leaping.
+
+Printed as one JSON line:
+  value          evaluated samples/s of the forward frame (whole job, wall clock
+                 over exactly --steps frames bracketed by device syncs)
+  rays_per_s     pixels/s of the same frames
+  fwd_bwd        the same frame plus its adjoint (grad w.r.t. the voxels and
+                 the TF, loss 0.5 ||image||^2)
+  serve          the serving mix: 8 resident volumes, Poisson arrivals at
+                 200 req/s, random poses, 256^2 / 512^2 / 1024^2 images;
+                 p50/p99 latency (submit -> completion) and rays/s
+  roofline       effective gather bytes (evaluated samples x 64 taps x 2 B)
+                 per forward launch / that launch's average duration (HIP
+                 events on the launch stream) against the 8 TB/s HBM peak
+  cpu_baseline   the FP64 oracle on a bounded seeded sample of the same frame
+                 on this host's cores
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import threading
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "samples/s and rays/s (fwd, fwd+bwd) on 512x512x400 at 1024^2; HBM roofline %; p99"
+HBM_PEAK_GBS = 8000.0
+TAPS_BYTES_I16 = 64 * 2
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--bwd-steps", type=int, default=5)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-bwd", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "render_fwd_c1_traffic.json"))
+    return ap.parse_args()
+
+
+def time_steps(fn, steps, warmup, torch):
+    """W untimed steps, then exactly K steps bracketed by device syncs; per
+    step HIP events on the current (launch) stream."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        starts[i].record()
+        fn()
+        ends[i].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    return wall, ev_ms
+
+
+def cpu_baseline(c, lattice, seconds):
+    """Time the FP64 oracle on seeded hit pixels of the frame."""
+    import numpy as np
+
+    import oracle
+    import synth
+
+    hits = np.argwhere(lattice[0] > 0)
+    rng = np.random.default_rng(80)
+    order = rng.permutation(len(hits))
+    def run(n):
+        pix = np.concatenate([np.zeros((n, 1), np.int64), hits[order[:n]]], axis=1)
+        t = time.perf_counter()
+        r = oracle.render(c["volume"], c["cameras"], c["tf"], c["step"], ert=c["ert"], pixels=pix)
+        return time.perf_counter() - t, int(r["counts"][:, 1].sum())
+    dt, _ = run(256)
+    n = int(min(len(hits), max(256, 256 * seconds / max(dt, 1e-3))))
+    dt, evaluated = run(n)
+    # whole-frame rays/s: hit fraction of the frame scaled in
+    return dict(
+        value=evaluated / dt,
+        unit="samples/s",
+        rays_per_s=n / dt,
+        seconds=dt,
+        cores=oracle.num_threads(),
+        kind="oracle",
+        sample=f"{n} seeded hit pixels of the 1024^2 frame (skip + ERT 0.99), FP64, OpenMP over pixels",
+    )
+
+
+def serve_mix(vr, torch, n_req, n_warm, rate):
+    import numpy as np
+
+    import synth
+
+    dims = synth.config_c4_volumes(seed=10, count=8)
+    vols = []
+    for (nx, ny, nz), seed in dims:
+        vols.append(vr.Volume(torch.from_numpy(synth.ct_phantom_i16(nx, ny, nz, seed)).cuda()))
+    log(f"serve: {len(vols)} volumes resident ({sum(v.tensor.numel() * 2 for v in vols) / 2**30:.2f} GiB)")
+    srv = vr.Server(hbm_budget_bytes=4 << 30, max_inflight=32)
+    ids = [srv.add_volume(v) for v in vols]
+    tf = synth.tf1()
+    total = n_warm + n_req
+    reqs = synth.c4_arrivals(total, seed=11, rate_hz=rate, n_volumes=8, dims_list=[d for d, _ in dims])
+    tickets = [None] * total
+    ready = [threading.Event() for _ in range(total)]
+    finished = [threading.Event() for _ in range(total)]
+    phase_start = {}
+
+    def producer():
+        t_base = time.perf_counter()
+        for i, r in enumerate(reqs):
+            if i == n_warm:
+                # warm-up done: wait for it to drain, then reset statistics
+                finished[n_warm - 1].wait()
+                srv.reset_stats()
+                t_base = time.perf_counter() - r["t"]
+                phase_start["t"] = time.perf_counter()
+            delay = t_base + r["t"] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tickets[i] = srv.submit(ids[r["volume"]], r["camera"], tf.table, tf.v0, tf.v1, 0.5, 0.99, True)
+            ready[i].set()
+
+    done_at = {}
+
+    def consumer():
+        for i in range(total):
+            ready[i].wait()
+            srv.wait(tickets[i])
+            srv.release(tickets[i])
+            finished[i].set()
+        done_at["t"] = time.perf_counter()
+
+    th_p = threading.Thread(target=producer)
+    th_c = threading.Thread(target=consumer)
+    th_p.start()
+    th_c.start()
+    th_p.join()
+    th_c.join()
+    st = srv.stats()
+    wall = done_at["t"] - phase_start["t"]
+    pixels = sum(r["size"] ** 2 for r in reqs[n_warm:])
+    srv.close()
+    return dict(
+        requests=n_req,
+        offered_req_per_s=rate,
+        achieved_req_per_s=n_req / wall,
+        p50_ms=st["p50_ms"],
+        p99_ms=st["p99_ms"],
+        mean_ms=st["mean_ms"],
+        max_ms=st["max_ms"],
+        rays_per_s=pixels / wall,
+        rays_per_busy_s=st["rays_per_s"],
+        launches=st["launches"],
+        hbm_peak_bytes=st["hbm_peak"],
+    )
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(
+            f"bench.py measures one GPU: --gpus {args.gpus} is not supported (this build runs on a single "
+            "MI355X; the multi-GPU sharding is design only)",
+            file=sys.stderr,
+        )
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2005_01442_amd as vr
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log("building the 512x512x400 int16 phantom")
+    c = synth.config_c1()
+    cams = c["cameras"]
+    W, H = cams[0].width, cams[0].height
+    vol = vr.Volume(torch.from_numpy(c["volume"]).cuda())
+    tf = vr.TF(torch.from_numpy(c["tf"].table).cuda(), c["tf"].v0, c["tf"].v1)
+
+    # A1: block min/max, once per volume
+    for _ in range(2):
+        blocks = vr.vr_build_blocks(vol, 16)
+    torch.cuda.synchronize()
+    wall_b, ev_b = time_steps(lambda: vr.vr_build_blocks(vol, 16), 5, 1, torch)
+    blocks = vr.vr_build_blocks(vol, 16)
+    out = torch.empty((1, H, W, 4), dtype=torch.float32, device="cuda")
+
+    # evaluated/lattice sample counts of the frame (instrumented run, untimed)
+    ctr = torch.zeros(4, dtype=torch.int64, device="cuda")
+    vr.vr_render(vol, blocks, cams, tf, c["step"], c["ert"], True, out=out, counters=ctr)
+    torch.cuda.synchronize()
+    evaluated, lattice_total, hit = (int(x) for x in ctr.cpu().numpy()[:3])
+    log(f"frame: evaluated {evaluated:.4g} samples, lattice {lattice_total:.4g}, hit rays {hit}")
+
+    def fwd():
+        vr.vr_render(vol, blocks, cams, tf, c["step"], c["ert"], True, out=out)
+
+    wall, ev_ms = time_steps(fwd, args.steps, args.warmup, torch)
+    ms_per_step = wall / args.steps * 1e3
+    kern_ms = float(np.mean(ev_ms))
+    value = evaluated / (wall / args.steps)
+    rays = W * H / (wall / args.steps)
+    achieved_gbs = evaluated * TAPS_BYTES_I16 / (kern_ms * 1e-3) / 1e9
+    log(f"fwd: {ms_per_step:.3f} ms/frame wall, {kern_ms:.3f} ms/launch events, {value:.4g} samples/s, "
+        f"{achieved_gbs:.1f} GB/s effective")
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "c1_ct512x512x400_i16_to_1024x1024_persp60_step0.5_skip16_ert0.99",
+            "volume": [512, 512, 400],
+            "volume_dtype": "i16",
+            "image": [W, H],
+            "step": c["step"],
+            "ert": c["ert"],
+            "block_edge": 16,
+            "pose_seed": 2,
+            "volume_seed": 1,
+        },
+        "rays_per_s": rays,
+        "evaluated_samples_per_frame": evaluated,
+        "lattice_samples_per_frame": lattice_total,
+        "hit_rays_per_frame": hit,
+        "kernel_ms": kern_ms,
+        "block_build_ms": float(np.mean(ev_b)),
+    }
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        try:
+            tj = json.load(open(args.traffic_json))
+            traffic = tj.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    result["roofline"] = {
+        "bound": "hbm",
+        "achieved": achieved_gbs,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved_gbs / HBM_PEAK_GBS,
+        "traffic": traffic,
+        "kernel": "k_render<kI16>",
+        "bytes_per_launch": evaluated * TAPS_BYTES_I16,
+    }
+
+    if not args.no_bwd:
+        gv_holder = {}
+
+        def fwd_bwd():
+            img = vr.vr_render(vol, blocks, cams, tf, c["step"], c["ert"], True, out=out)
+            gv_holder["g"] = vr.vr_render_backward(vol, blocks, cams, tf, c["step"], c["ert"], True, img, img)
+
+        wall_fb, ev_fb = time_steps(fwd_bwd, args.bwd_steps, 1, torch)
+        ms_fb = wall_fb / args.bwd_steps * 1e3
+        result["fwd_bwd"] = {
+            "ms_per_step": ms_fb,
+            "samples_per_s": lattice_total / (ms_fb * 1e-3),
+            "rays_per_s": W * H / (ms_fb * 1e-3),
+            "note": "forward (skip+ERT) + adjoint to grid (fp32) and TF; samples counted as lattice samples "
+                    "because the TF gradient disables skipping in the adjoint",
+        }
+        log(f"fwd+bwd: {ms_fb:.3f} ms/step")
+        del gv_holder
+
+    if not args.no_serve:
+        log("serving mix")
+        result["serve"] = serve_mix(vr, torch, args.serve_requests, args.serve_warmup, args.serve_rate)
+        result["p99_ms"] = result["serve"]["p99_ms"]
+        log(f"serve: p50 {result['serve']['p50_ms']:.2f} ms, p99 {result['serve']['p99_ms']:.2f} ms")
+
+    if not args.no_cpu:
+        import oracle
+
+        log("cpu baseline (oracle)")
+        lat = oracle.lattice(cams, (512, 512, 400), c["step"])
+        result["cpu_baseline"] = cpu_baseline(c, lat, args.cpu_seconds)
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

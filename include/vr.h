@@ -1,0 +1,275 @@
+/*
+ * vr.h -- C ABI of the MI355X (gfx950) tricubic volume ray caster.
+ *
+ * The calls follow the paper's statement of the problem (Section 2,
+ * "Methodology", the ray-casting paragraph before Fig. 2): a volume, a
+ * camera (the observer's position and a ray direction per pixel), a step
+ * with which the ray moves, and a transfer function T(V) that maps a value
+ * to colour and opacity (Fig. 3 discussion) go in; an RGBA image comes out.
+ * Reconstruction is the cubic spline the paper adopts (Section 2, Fig. 4
+ * discussion), classification happens after interpolation
+ * (post-classification), rays stop early once opaque and blocks holding
+ * nothing visible are skipped ("Pros" (b) of the block-decomposition
+ * analysis).
+ *
+ * Conventions shared by every call:
+ *   - Index space.  Voxel (i, j, k) is centred at (i, j, k); the volume
+ *     occupies the box [-1/2, n-1/2] on each axis.  Memory order is x
+ *     fastest, then y, then z.  Addresses outside the grid read the nearest
+ *     edge voxel.  Voxel spacing is folded into the camera by the caller, so
+ *     distances, the step and the extinction are in voxel units.
+ *   - Memory.  Pointers documented as DEVICE are HIP device pointers on the
+ *     current device, caller-owned unless stated otherwise.  Pointers
+ *     documented as HOST are read before the call returns.
+ *   - Streams.  `stream` is a hipStream_t (NULL = the default stream).  Work
+ *     is enqueued asynchronously; nothing synchronises unless stated.
+ *     Arguments are validated on the host before anything is enqueued.
+ *   - Errors.  Every call returns a vr_status; no exception crosses the ABI.
+ *     vr_last_error() gives a message for the calling thread's last non-OK
+ *     status.  A device fault surfaces as VR_E_DEVICE at a later call.
+ */
+#ifndef VR_H
+#define VR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VR_ABI_VERSION 1
+
+typedef enum {
+    VR_OK = 0,
+    VR_E_INVALID_ARG = 1, /* an argument failed validation; nothing was enqueued */
+    VR_E_UNSUPPORTED = 2, /* valid but not supported (dtype, size limit)          */
+    VR_E_OOM = 3,         /* a library allocation failed                           */
+    VR_E_DEVICE = 4,      /* a HIP runtime call failed                             */
+    VR_E_BUDGET = 5,      /* serving: the request can never fit the HBM budget     */
+    VR_E_NOT_FOUND = 6,   /* serving: unknown volume id or ticket                  */
+    VR_E_BUSY = 7,        /* serving: the volume has requests in flight            */
+    VR_E_TIMEOUT = 8,     /* serving: wait timed out; the ticket stays valid        */
+    VR_E_SHUTDOWN = 9     /* serving: the server was destroyed before completion   */
+} vr_status;
+
+typedef enum { VR_U16 = 0, VR_I16 = 1, VR_F32 = 2 } vr_dtype;
+
+/* A scalar volume.  data: DEVICE, nx*ny*nz elements of `dtype`, dense, x
+ * fastest, 4-byte aligned.  The CT data the paper renders are 12-bit values
+ * stored in 16 bits (Section 2, Fig. 4 discussion); u16/i16 keep that
+ * footprint, f32 serves real-valued (differentiable) grids. */
+typedef struct {
+    const void *data;
+    int32_t dtype; /* vr_dtype */
+    int32_t reserved;
+    int64_t nx, ny, nz;
+} vr_volume;
+
+/* A camera ("the position of the observer and the direction of the ray",
+ * Section 2).  All vectors in index space; right/up/forward orthonormal.
+ * Pixel (i, j), i the column and j the row, has centre (i+1/2, j+1/2) and
+ *   sx = 2 (i + 1/2) / width - 1,   sy = 1 - 2 (j + 1/2) / height.
+ * Perspective (projection 1): origin = eye,
+ *   direction = normalize(forward + sx tan(fov_y/2) (width/height) right
+ *                                 + sy tan(fov_y/2) up).
+ * Orthographic (projection 0): origin = eye + sx (ortho_w/2) right
+ *   + sy (ortho_h/2) up, direction = normalize(forward).
+ * Ray setup is evaluated in FP64. */
+typedef struct {
+    int32_t projection; /* 0 orthographic, 1 perspective */
+    int32_t width, height;
+    int32_t reserved;
+    double eye[3], right[3], up[3], forward[3];
+    double fov_y;            /* radians, perspective only, in (0, pi) */
+    double ortho_w, ortho_h; /* image-plane extent in voxels, orthographic only */
+} vr_camera;
+
+/* A transfer function T(V) (Section 2, Fig. 3 discussion): K nodes of
+ * (r, g, b, sigma) fp32, node j at value v0 + j (v1 - v0) / (K - 1), linear
+ * between nodes, the end nodes beyond [v0, v1].  r, g, b are emission colours;
+ * sigma >= 0 is the extinction per voxel length, so a sample's opacity is
+ * 1 - exp(-sigma step) (0 fully transparent, 1 opaque).
+ * table: DEVICE, K*4 floats.  2 <= K <= VR_MAX_TF_NODES, v1 > v0. */
+#define VR_MAX_TF_NODES 1024
+typedef struct {
+    const float *table;
+    int32_t K;
+    float v0, v1;
+} vr_tf;
+
+/* Marching parameters.
+ *   step           in [1/1024, 1024] voxels.  Samples sit at the midpoints
+ *                  t_in + (k + 1/2) step of every full step inside the box.
+ *   ert_threshold  early ray termination: a ray stops after the sample whose
+ *                  accumulated opacity reaches the threshold; values outside
+ *                  (0, 1) disable it.
+ *   use_skip       nonzero: skip samples in blocks that cannot be visible
+ *                  under the TF (needs a vr_blocks of this volume).  The
+ *                  image is bit-identical to rendering without skipping.
+ *   counters       optional DEVICE uint64_t[4] that the render ADDS to:
+ *                  [0] evaluated samples, [1] lattice samples, [2] rays that
+ *                  hit the box, [3] reserved.  NULL = not counted. */
+typedef struct {
+    float step;
+    float ert_threshold;
+    int32_t use_skip;
+    int32_t reserved;
+    uint64_t *counters;
+} vr_params;
+
+/* ---------------------------------------------------------------------- */
+/* Blocks: the auxiliary structure for empty-space leaping (Section 2,     */
+/* block decomposition into overlapping fixed-size blocks with smaller     */
+/* remainder blocks, Fig. 3; "Pros" (a) and (b)).                           */
+/* ---------------------------------------------------------------------- */
+
+/* Opaque, library-owned.  Holds, for every block b (grid ceil(n/E) per
+ * axis, x-block fastest), the min and max voxel value over the block's
+ * footprint: [bE-1, bE+E+1] per axis clamped to the grid, i.e. every voxel a
+ * cubic-spline sample whose cell floor(p) lies in b can read (the paper's
+ * overlap for cubic sampling).  It refers to the volume's memory, which must
+ * stay alive and unchanged while the blocks are used. */
+typedef struct vr_blocks vr_blocks;
+
+/* Build the block min/max for `vol` with edge `block_edge` (4..64).
+ * Enqueued on `stream`; *out is valid immediately and usable on the same
+ * stream.  Allocates device memory (8 bytes per block).
+ * Errors: VR_E_INVALID_ARG (null/invalid volume, edge out of range),
+ * VR_E_OOM, VR_E_DEVICE. */
+vr_status vr_build_blocks(const vr_volume *vol, int32_t block_edge, void *stream, vr_blocks **out);
+
+/* Block-grid dimensions (nbx, nby, nbz) and edge.  Host only. */
+vr_status vr_blocks_info(const vr_blocks *blocks, int64_t dims_out[3], int32_t *edge_out);
+
+/* Copy the per-block (min, max) as fp32 pairs, x-block fastest, into
+ * dst_device (DEVICE, at least 2 * nblocks floats).  Values of 16-bit
+ * volumes are exact.  Enqueued on `stream`. */
+vr_status vr_blocks_minmax(const vr_blocks *blocks, float *dst_device, int64_t dst_count, void *stream);
+
+/* TF-dependent occupancy of every block: occ_device[b] = 1 unless every TF
+ * node in [floor(u(min_b)) - 1, ceil(u(max_b)) + 1] (clamped to [0, K-1])
+ * has zero extinction, u(v) = (v - v0) * ((K-1) / (v1 - v0)) in fp32.  The
+ * renderer takes the same decision on the fly.  occ_device: DEVICE, at least
+ * nblocks bytes.  Enqueued on `stream`. */
+vr_status vr_block_occupancy(const vr_blocks *blocks, const vr_tf *tf, uint8_t *occ_device, int64_t n,
+                             void *stream);
+
+void vr_blocks_free(vr_blocks *blocks);
+
+/* ---------------------------------------------------------------------- */
+/* Rendering.                                                              */
+/* ---------------------------------------------------------------------- */
+
+/* Render n_cams views (all the same width x height) of `vol`.
+ * cams: HOST array of n_cams cameras.  tf, p: HOST structs.
+ * blocks: required when p->use_skip, built from this volume; else may be NULL.
+ * out_rgba: DEVICE, n_cams * height * width * 4 floats, [view][row][col][rgba],
+ *   written in full: premultiplied (C_r, C_g, C_b, 1 - T) over transparent
+ *   black; rays that miss the box give (0, 0, 0, 0).
+ * Per ray: front-to-back C += T a c, T *= 1 - a with a = 1 - exp(-sigma step),
+ * starting from C = 0, T = 1.
+ * Errors: VR_E_INVALID_ARG (null pointers, non-finite camera, sizes <= 0,
+ * step out of range, K out of range, v1 <= v0, skip without blocks or with blocks of
+ * another volume), VR_E_DEVICE. */
+vr_status vr_render(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,
+                    const vr_tf *tf, const vr_params *p, float *out_rgba, void *stream);
+
+/* Adjoint of vr_render: gradients of L with respect to the voxel values and
+ * the TF table, given g = dL/dRGBA.  Per ray the forward march is recomputed
+ * front to back (no per-sample state is stored); the stopping sample of
+ * early termination is held fixed.
+ * out_rgba: DEVICE, the forward result of vr_render with the same arguments.
+ * grad_rgba: DEVICE, same layout as out_rgba.
+ * grad_volume: DEVICE fp32 nx*ny*nz or NULL; grad_tf: DEVICE fp32 K*4 or NULL.
+ *   Both are OVERWRITTEN (zeroed, then accumulated with atomics, so the
+ *   summation order is not deterministic).
+ * Skipping is used only when grad_tf is NULL (zero-extinction nodes still
+ * receive TF gradients).  Errors as vr_render. */
+vr_status vr_render_backward(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,
+                             const vr_tf *tf, const vr_params *p, const float *out_rgba, const float *grad_rgba,
+                             float *grad_volume, float *grad_tf, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Serving: volumes resident in HBM, many clients, continuous batching     */
+/* (the paper's multi-client cloud service, Section 2 "Cloud architecture" */
+/* and Section 3).                                                          */
+/* ---------------------------------------------------------------------- */
+
+typedef struct vr_server vr_server;
+
+typedef struct {
+    uint64_t hbm_budget_bytes; /* device bytes the server may hold for result images */
+    int32_t max_inflight;      /* admitted requests at once (slots), >= 1             */
+    int32_t max_batch_tiles;   /* 16x16-pixel work items per launch (0 = 2048)        */
+    int32_t device;            /* HIP device ordinal                                  */
+    int32_t reserved;
+} vr_serve_config;
+
+/* One request.  tf_table_host: HOST K*4 floats, copied at submit. */
+typedef struct {
+    int32_t volume_id;
+    int32_t K;
+    const float *tf_table_host;
+    float tf_v0, tf_v1;
+    vr_camera cam;
+    float step, ert_threshold;
+    int32_t use_skip;
+    int32_t reserved;
+} vr_request;
+
+typedef struct {
+    uint64_t submitted, admitted, completed, rejected, queued, inflight;
+    uint64_t hbm_used, hbm_peak;
+    uint64_t launches, tiles;
+    double p50_ms, p99_ms, mean_ms, max_ms; /* arrival (submit) -> completion */
+    double rays_per_s;                      /* completed pixels / busy wall time */
+    double busy_s;                          /* wall time with work in flight     */
+} vr_serve_stats;
+
+/* Create a server with its own scheduler thread and HIP streams. */
+vr_status vr_serve_create(const vr_serve_config *cfg, vr_server **out);
+
+/* Register a resident volume (caller keeps its memory alive until removal)
+ * and build its blocks with edge `block_edge`.  Blocks count against the
+ * budget.  *volume_id receives the id. */
+vr_status vr_serve_add_volume(vr_server *s, const vr_volume *vol, int32_t block_edge, int32_t *volume_id);
+
+/* Unregister; VR_E_BUSY while requests on it are queued or in flight. */
+vr_status vr_serve_remove_volume(vr_server *s, int32_t volume_id);
+
+/* Non-blocking submit; *ticket identifies the request.  VR_E_BUDGET if the
+ * result image alone exceeds the whole budget, VR_E_NOT_FOUND for an unknown
+ * volume, VR_E_INVALID_ARG for invalid fields, VR_E_SHUTDOWN after destroy. */
+vr_status vr_serve_submit(vr_server *s, const vr_request *req, uint64_t *ticket);
+
+/* Wait up to timeout_us (negative = forever) for `ticket`.  On VR_OK,
+ * *rgba_device points to the DEVICE result (height*width*4 floats, layout of
+ * vr_render), valid until vr_serve_release.  The result is complete and
+ * visible to every stream. */
+vr_status vr_serve_wait(vr_server *s, uint64_t ticket, int64_t timeout_us, const float **rgba_device);
+
+/* Return a completed ticket's image to the pool. */
+vr_status vr_serve_release(vr_server *s, uint64_t ticket);
+
+vr_status vr_serve_stats_get(vr_server *s, vr_serve_stats *out);
+
+/* Reset latency/throughput statistics (counters of resident state stay). */
+vr_status vr_serve_stats_reset(vr_server *s);
+
+/* Stop the scheduler, cancel queued requests (their waits return
+ * VR_E_SHUTDOWN), drain in-flight launches and free every server
+ * allocation.  Volumes stay caller-owned. */
+vr_status vr_serve_destroy(vr_server *s);
+
+/* ---------------------------------------------------------------------- */
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char *vr_last_error(void);
+
+int vr_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VR_H */

@@ -5,6 +5,10 @@ CPU-baseline leg of ``bench.py`` may import this package; the GPU library and
 its Python binding never do.  It shares no code with the GPU path; only the
 seeded inputs of ``synth`` feed both.
 
+Scalar parameters that the GPU ABI carries in fp32 (step, early-termination
+threshold, TF value range) are rounded to fp32 here before the FP64
+arithmetic, so both sides march the same lattice.
+
 The arithmetic lives in ``oracle.c`` (plain scalar C, FP64, OpenMP over
 pixels); ``brute.py`` is an independent pure-Python brute force for tiny
 volumes.  This module only marshals NumPy arrays into the C calls.
@@ -73,8 +77,15 @@ def lib():
         L.oracle_sample.restype = f64
         L.oracle_weights.argtypes = [f64, P]
         L.oracle_weights.restype = None
+        L.oracle_lattice.argtypes = [P, i32, i32, i32, i64, i64, i64, f64, P]
+        L.oracle_lattice.restype = i32
         _lib = L
     return _lib
+
+
+def f32(x) -> float:
+    """The value as the fp32 the GPU ABI carries (step, thresholds, TF range)."""
+    return float(np.float32(x))
 
 
 def _ptr(a):
@@ -122,7 +133,7 @@ def occupancy(minmax, tf) -> np.ndarray:
     nb = mm.size // 2
     occ = np.zeros(mm.shape[:-1], dtype=np.uint8)
     table = np.ascontiguousarray(tf.table, dtype=np.float32)
-    rc = lib().oracle_occupancy(_ptr(mm), nb, _ptr(table), table.shape[0], float(tf.v0), float(tf.v1), _ptr(occ))
+    rc = lib().oracle_occupancy(_ptr(mm), nb, _ptr(table), table.shape[0], f32(tf.v0), f32(tf.v1), _ptr(occ))
     if rc:
         raise ValueError("oracle_occupancy rejected its arguments")
     return occ
@@ -149,7 +160,7 @@ def render(vol, cameras, tf, step, ert=0.0, occ=None, edge=16, pixels=None):
     counts = np.zeros(shape + (2,), dtype=np.int64)
     rc = lib().oracle_render(
         _ptr(vol), dt, nx, ny, nz, _ptr(cams), len(cameras), W, H, _ptr(table), table.shape[0],
-        float(tf.v0), float(tf.v1), float(step), float(ert), _ptr(occ_a), int(edge), _ptr(pix), n,
+        f32(tf.v0), f32(tf.v1), f32(step), f32(ert), _ptr(occ_a), int(edge), _ptr(pix), n,
         _ptr(rgba), _ptr(flags), _ptr(counts),
     )
     if rc:
@@ -171,11 +182,23 @@ def grad(vol, cameras, tf, step, grad_rgba, ert=0.0, occ=None, edge=16, want_vol
     occ_a = None if occ is None else np.ascontiguousarray(occ, dtype=np.uint8)
     rc = lib().oracle_grad(
         _ptr(vol), dt, nx, ny, nz, _ptr(cams), len(cameras), W, H, _ptr(table), table.shape[0],
-        float(tf.v0), float(tf.v1), float(step), float(ert), _ptr(occ_a), int(edge), _ptr(g), _ptr(gv), _ptr(gt),
+        f32(tf.v0), f32(tf.v1), f32(step), f32(ert), _ptr(occ_a), int(edge), _ptr(g), _ptr(gv), _ptr(gt),
     )
     if rc:
         raise ValueError("oracle_grad rejected its arguments")
     return gv, gt
+
+
+def lattice(cameras, dims_xyz, step) -> np.ndarray:
+    """Lattice sample count of every pixel, shape (views, H, W)."""
+    cams = pack_cameras(cameras)
+    W, H = int(cameras[0].width), int(cameras[0].height)
+    out = np.zeros((len(cameras), H, W), dtype=np.int64)
+    rc = lib().oracle_lattice(_ptr(cams), len(cameras), W, H, int(dims_xyz[0]), int(dims_xyz[1]),
+                              int(dims_xyz[2]), f32(step), _ptr(out))
+    if rc:
+        raise ValueError("oracle_lattice rejected its arguments")
+    return out
 
 
 def ray(camera, row, col, dims_xyz, step):
@@ -184,7 +207,7 @@ def ray(camera, row, col, dims_xyz, step):
     out = np.zeros(8, dtype=np.float64)
     ns = ctypes.c_long(0)
     hit = lib().oracle_ray(_ptr(cam), int(camera.width), int(camera.height), int(row), int(col),
-                           int(dims_xyz[0]), int(dims_xyz[1]), int(dims_xyz[2]), float(step), _ptr(out),
+                           int(dims_xyz[0]), int(dims_xyz[1]), int(dims_xyz[2]), f32(step), _ptr(out),
                            ctypes.byref(ns))
     return out[:3].copy(), out[3:6].copy(), float(out[6]), float(out[7]), int(ns.value), bool(hit)
 

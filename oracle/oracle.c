@@ -537,3 +537,19 @@ double oracle_sample(const void *data, int dtype, long nx, long ny, long nz, dou
 
 /* B-spline weights at fractional offset f (exposed for the weight pins).   */
 void oracle_weights(double f, double w[4]) { or_bspline(f, w); }
+
+/* Lattice sample count of every pixel of every view (ray setup and clip     */
+/* only; exposed so that integer counts can be compared at full size).       */
+int oracle_lattice(const double *cams, int n_cams, int W, int H, long nx, long ny, long nz, double step, long *out)
+{
+    if (!cams || !out || n_cams <= 0 || W <= 0 || H <= 0 || !(step > 0.0)) return 1;
+    long total = (long)n_cams * W * H;
+#pragma omp parallel for schedule(static)
+    for (long q = 0; q < total; ++q) {
+        long view = q / ((long)W * H), row = (q / W) % H, col = q % W;
+        double o[3], d[3], tin, tout;
+        or_ray(cams + 16 * view, W, H, col, row, o, d);
+        out[q] = or_clip(o, d, nx, ny, nz, &tin, &tout) ? or_lattice_count(tin, tout, step) : 0;
+    }
+    return 0;
+}

@@ -1,0 +1,311 @@
+// api.cpp -- the C ABI of include/vr.h (except serving, in serve.cpp):
+// argument validation, FP64 camera constants, launch configuration and
+// error reporting.  Kernels live in the .hip files.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "vr.h"
+#include "vr_internal.h"
+
+struct vr_blocks {
+  const void *data;
+  int32_t dtype;
+  int64_t nx, ny, nz;
+  int32_t edge;
+  int32_t nbx, nby, nbz;
+  float2 *minmax;
+  int device;
+};
+
+namespace vr {
+
+static thread_local std::string g_last_error;
+
+vr_status fail(vr_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+vr_status hip_fail(hipError_t e, const char *what) {
+  return fail(VR_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+static bool finite3(const double v[3]) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+vr_status check_volume(const vr_volume *v, VolConst *out) {
+  if (!v) return fail(VR_E_INVALID_ARG, "volume is NULL");
+  if (!v->data) return fail(VR_E_INVALID_ARG, "volume data is NULL");
+  if (v->dtype != VR_U16 && v->dtype != VR_I16 && v->dtype != VR_F32)
+    return fail(VR_E_INVALID_ARG, "unknown volume dtype %d", v->dtype);
+  if (v->nx <= 0 || v->ny <= 0 || v->nz <= 0)
+    return fail(VR_E_INVALID_ARG, "volume dims must be positive (%lld, %lld, %lld)", (long long)v->nx,
+                (long long)v->ny, (long long)v->nz);
+  if ((reinterpret_cast<uintptr_t>(v->data) & 3u) != 0)
+    return fail(VR_E_INVALID_ARG, "volume data must be 4-byte aligned");
+  const int64_t esz = v->dtype == VR_F32 ? 4 : 2;
+  const double bytes = (double)v->nx * (double)v->ny * (double)v->nz * (double)esz;
+  if (v->nx > (1 << 20) || v->ny > (1 << 20) || v->nz > (1 << 20) || bytes >= 4294967296.0)
+    return fail(VR_E_UNSUPPORTED, "volume of %.0f bytes exceeds the 4 GiB per-volume limit", bytes);
+  if (out) {
+    out->data = v->data;
+    out->dtype = v->dtype;
+    out->nx = (int32_t)v->nx;
+    out->ny = (int32_t)v->ny;
+    out->nz = (int32_t)v->nz;
+    out->bytes = (uint32_t)bytes;
+    out->minmax = nullptr;
+    out->nbx = out->nby = out->nbz = 0;
+    out->edge = 0;
+  }
+  return VR_OK;
+}
+
+vr_status check_tf_fields(const void *table, int32_t K, float v0, float v1, TfConst *out) {
+  if (!table) return fail(VR_E_INVALID_ARG, "TF table is NULL");
+  if (K < 2 || K > VR_MAX_TF_NODES) return fail(VR_E_INVALID_ARG, "TF node count K=%d outside [2, %d]", K, VR_MAX_TF_NODES);
+  if (!std::isfinite(v0) || !std::isfinite(v1) || !(v1 > v0))
+    return fail(VR_E_INVALID_ARG, "TF value range must be finite with v1 > v0 (%g, %g)", (double)v0, (double)v1);
+  if ((reinterpret_cast<uintptr_t>(table) & 15u) != 0) return fail(VR_E_INVALID_ARG, "TF table must be 16-byte aligned");
+  if (out) {
+    out->table = static_cast<const float *>(table);
+    out->K = K;
+    out->v0 = v0;
+    out->scale = (float)(K - 1) / (v1 - v0);
+  }
+  return VR_OK;
+}
+
+vr_status check_camera(const vr_camera *c, CamConst *out) {
+  if (!c) return fail(VR_E_INVALID_ARG, "camera is NULL");
+  if (c->width <= 0 || c->height <= 0 || c->width > 32768 || c->height > 32768)
+    return fail(VR_E_INVALID_ARG, "image size %dx%d outside [1, 32768]", c->width, c->height);
+  if (c->projection != 0 && c->projection != 1) return fail(VR_E_INVALID_ARG, "projection must be 0 or 1");
+  if (!finite3(c->eye) || !finite3(c->right) || !finite3(c->up) || !finite3(c->forward))
+    return fail(VR_E_INVALID_ARG, "camera vectors must be finite");
+  const double fn = c->forward[0] * c->forward[0] + c->forward[1] * c->forward[1] + c->forward[2] * c->forward[2];
+  if (!(fn > 0.0)) return fail(VR_E_INVALID_ARG, "camera forward vector is zero");
+  if (c->projection == 1) {
+    if (!std::isfinite(c->fov_y) || !(c->fov_y > 0.0) || !(c->fov_y < M_PI))
+      return fail(VR_E_INVALID_ARG, "fov_y must be in (0, pi)");
+  } else {
+    if (!std::isfinite(c->ortho_w) || !std::isfinite(c->ortho_h) || !(c->ortho_w > 0.0) || !(c->ortho_h > 0.0))
+      return fail(VR_E_INVALID_ARG, "ortho extents must be positive");
+  }
+  if (out) {
+    for (int k = 0; k < 3; ++k) {
+      out->eye[k] = c->eye[k];
+      out->right[k] = c->right[k];
+      out->up[k] = c->up[k];
+      out->fwd[k] = c->forward[k];
+    }
+    out->th = c->projection == 1 ? std::tan(0.5 * c->fov_y) : 0.0;
+    out->hw = 0.5 * c->ortho_w;
+    out->hh = 0.5 * c->ortho_h;
+    out->proj = c->projection;
+    out->W = c->width;
+    out->H = c->height;
+    out->pad = 0;
+  }
+  return VR_OK;
+}
+
+vr_status check_march(float step, float ert, int32_t use_skip, MarchConst *out) {
+  if (!std::isfinite(step) || !(step >= 1.0f / 1024.0f) || !(step <= 1024.0f))
+    return fail(VR_E_INVALID_ARG, "step must be finite and within [1/1024, 1024] voxels (got %g)", (double)step);
+  if (out) {
+    out->step = step;
+    out->ert = (ert > 0.0f && ert < 1.0f) ? ert : 0.0f;
+    out->skip = use_skip ? 1 : 0;
+    out->pad = 0;
+  }
+  return VR_OK;
+}
+
+vr_status attach_blocks(const vr_blocks *b, const vr_volume *v, VolConst *vc) {
+  if (!b) return fail(VR_E_INVALID_ARG, "use_skip needs blocks");
+  if (b->data != v->data || b->dtype != v->dtype || b->nx != v->nx || b->ny != v->ny || b->nz != v->nz)
+    return fail(VR_E_INVALID_ARG, "blocks were built for another volume");
+  vc->minmax = b->minmax;
+  vc->nbx = b->nbx;
+  vc->nby = b->nby;
+  vc->nbz = b->nbz;
+  vc->edge = b->edge;
+  return VR_OK;
+}
+
+// Validate the common arguments of vr_render / vr_render_backward and fill
+// the launch arguments (cameras excluded).
+static vr_status prepare(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,
+                         const vr_tf *tf, const vr_params *p, RenderArgs *a) {
+  memset(a, 0, sizeof(*a));
+  vr_status s = check_volume(vol, &a->vol);
+  if (s) return s;
+  if (!tf) return fail(VR_E_INVALID_ARG, "tf is NULL");
+  if ((s = check_tf_fields(tf->table, tf->K, tf->v0, tf->v1, &a->tf))) return s;
+  if (!p) return fail(VR_E_INVALID_ARG, "params is NULL");
+  if ((s = check_march(p->step, p->ert_threshold, p->use_skip, &a->mc))) return s;
+  if (!cams || n_cams <= 0) return fail(VR_E_INVALID_ARG, "need at least one camera");
+  for (int32_t i = 0; i < n_cams; ++i) {
+    if ((s = check_camera(&cams[i], nullptr))) return s;
+    if (cams[i].width != cams[0].width || cams[i].height != cams[0].height)
+      return fail(VR_E_INVALID_ARG, "all cameras must share one image size");
+  }
+  if (p->use_skip && (s = attach_blocks(blocks, vol, &a->vol))) return s;
+  a->counters = reinterpret_cast<unsigned long long *>(p->counters);
+  a->W = cams[0].width;
+  a->H = cams[0].height;
+  return VR_OK;
+}
+
+}  // namespace vr
+
+using namespace vr;
+
+extern "C" {
+
+const char *vr_last_error(void) { return g_last_error.c_str(); }
+
+int vr_abi_version(void) { return VR_ABI_VERSION; }
+
+vr_status vr_build_blocks(const vr_volume *vol, int32_t block_edge, void *stream, vr_blocks **out) {
+  if (!out) return fail(VR_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  VolConst vc;
+  vr_status s = check_volume(vol, &vc);
+  if (s) return s;
+  if (block_edge < 4 || block_edge > 64) return fail(VR_E_INVALID_ARG, "block edge %d outside [4, 64]", block_edge);
+  vr_blocks *b = new (std::nothrow) vr_blocks();
+  if (!b) return fail(VR_E_OOM, "host allocation failed");
+  b->data = vol->data;
+  b->dtype = vol->dtype;
+  b->nx = vol->nx;
+  b->ny = vol->ny;
+  b->nz = vol->nz;
+  b->edge = block_edge;
+  b->nbx = (int32_t)((vol->nx + block_edge - 1) / block_edge);
+  b->nby = (int32_t)((vol->ny + block_edge - 1) / block_edge);
+  b->nbz = (int32_t)((vol->nz + block_edge - 1) / block_edge);
+  (void)hipGetDevice(&b->device);
+  const size_t nb = (size_t)b->nbx * b->nby * b->nbz;
+  hipError_t e = hipMalloc(&b->minmax, nb * sizeof(float2));
+  if (e != hipSuccess) {
+    delete b;
+    return fail(VR_E_OOM, "hipMalloc of %zu block bytes: %s", nb * sizeof(float2), hipGetErrorString(e));
+  }
+  vc.nbx = b->nbx;
+  vc.nby = b->nby;
+  vc.nbz = b->nbz;
+  vc.edge = block_edge;
+  e = launch_block_minmax(vc, b->minmax, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    (void)hipFree(b->minmax);
+    delete b;
+    return hip_fail(e, "block min/max launch");
+  }
+  *out = b;
+  return VR_OK;
+}
+
+vr_status vr_blocks_info(const vr_blocks *b, int64_t dims_out[3], int32_t *edge_out) {
+  if (!b) return fail(VR_E_INVALID_ARG, "blocks is NULL");
+  if (dims_out) {
+    dims_out[0] = b->nbx;
+    dims_out[1] = b->nby;
+    dims_out[2] = b->nbz;
+  }
+  if (edge_out) *edge_out = b->edge;
+  return VR_OK;
+}
+
+vr_status vr_blocks_minmax(const vr_blocks *b, float *dst, int64_t dst_count, void *stream) {
+  if (!b || !dst) return fail(VR_E_INVALID_ARG, "blocks or destination is NULL");
+  const int64_t nb = (int64_t)b->nbx * b->nby * b->nbz;
+  if (dst_count < 2 * nb) return fail(VR_E_INVALID_ARG, "destination holds %lld floats, need %lld", (long long)dst_count, (long long)(2 * nb));
+  hipError_t e = hipMemcpyAsync(dst, b->minmax, (size_t)nb * sizeof(float2), hipMemcpyDeviceToDevice, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "copy block min/max");
+  return VR_OK;
+}
+
+vr_status vr_block_occupancy(const vr_blocks *b, const vr_tf *tf, uint8_t *occ, int64_t n, void *stream) {
+  if (!b || !tf || !occ) return fail(VR_E_INVALID_ARG, "blocks, tf or destination is NULL");
+  const int64_t nb = (int64_t)b->nbx * b->nby * b->nbz;
+  if (n < nb) return fail(VR_E_INVALID_ARG, "destination holds %lld bytes, need %lld", (long long)n, (long long)nb);
+  TfConst tc;
+  vr_status s = check_tf_fields(tf->table, tf->K, tf->v0, tf->v1, &tc);
+  if (s) return s;
+  VolConst vc;
+  memset(&vc, 0, sizeof(vc));
+  vc.minmax = b->minmax;
+  vc.nbx = b->nbx;
+  vc.nby = b->nby;
+  vc.nbz = b->nbz;
+  vc.edge = b->edge;
+  hipError_t e = launch_block_occupancy(vc, tc, occ, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "block occupancy launch");
+  return VR_OK;
+}
+
+void vr_blocks_free(vr_blocks *b) {
+  if (!b) return;
+  (void)hipFree(b->minmax);
+  delete b;
+}
+
+vr_status vr_render(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,
+                    const vr_tf *tf, const vr_params *p, float *out_rgba, void *stream) {
+  RenderArgs a;
+  vr_status s = prepare(vol, blocks, cams, n_cams, tf, p, &a);
+  if (s) return s;
+  if (!out_rgba) return fail(VR_E_INVALID_ARG, "out_rgba is NULL");
+  const size_t view_floats = (size_t)a.W * a.H * 4;
+  for (int32_t v0 = 0; v0 < n_cams; v0 += kMaxCamsPerLaunch) {
+    const int32_t n = std::min(kMaxCamsPerLaunch, n_cams - v0);
+    for (int32_t i = 0; i < n; ++i) check_camera(&cams[v0 + i], &a.cams[i]);
+    a.n_views = n;
+    a.out = out_rgba + (size_t)v0 * view_floats;
+    hipError_t e = launch_render(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "render launch");
+  }
+  return VR_OK;
+}
+
+vr_status vr_render_backward(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,
+                             const vr_tf *tf, const vr_params *p, const float *out_rgba, const float *grad_rgba,
+                             float *grad_volume, float *grad_tf, void *stream) {
+  BackwardArgs b;
+  vr_status s = prepare(vol, blocks, cams, n_cams, tf, p, &b.r);
+  if (s) return s;
+  if (!out_rgba || !grad_rgba) return fail(VR_E_INVALID_ARG, "out_rgba and grad_rgba are required");
+  if (grad_tf) b.r.mc.skip = 0;  // zero-extinction nodes still receive TF gradients
+  b.r.counters = nullptr;
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t nvox = (int64_t)vol->nx * vol->ny * vol->nz;
+  hipError_t e;
+  if (grad_volume && (e = launch_fill_zero(grad_volume, nvox, st)) != hipSuccess) return hip_fail(e, "zero grad_volume");
+  if (grad_tf && (e = launch_fill_zero(grad_tf, (int64_t)tf->K * 4, st)) != hipSuccess) return hip_fail(e, "zero grad_tf");
+  if (!grad_volume && !grad_tf) return VR_OK;
+  const size_t view_floats = (size_t)b.r.W * b.r.H * 4;
+  for (int32_t v0 = 0; v0 < n_cams; v0 += kMaxCamsPerLaunch) {
+    const int32_t n = std::min(kMaxCamsPerLaunch, n_cams - v0);
+    for (int32_t i = 0; i < n; ++i) check_camera(&cams[v0 + i], &b.r.cams[i]);
+    b.r.n_views = n;
+    b.r.out = nullptr;
+    b.out_rgba = out_rgba + (size_t)v0 * view_floats;
+    b.grad_rgba = grad_rgba + (size_t)v0 * view_floats;
+    b.grad_vol = grad_volume;
+    b.grad_tf = grad_tf;
+    e = launch_render_backward(b, st);
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
+  }
+  return VR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// blocks.hip -- block min/max build and TF-dependent block occupancy (gfx950).
+//
+// The paper decomposes the volume into fixed-size blocks (smaller at the far
+// faces) that overlap by the voxels a cubic stencil reads, and drops blocks
+// with nothing visible (Section 2, block decomposition, Fig. 3, "Pros" (a),
+// (b)).  Here a block is the cell range [bE, bE+E) per axis; its footprint
+// [bE-1, bE+E+1] (clamped) is every voxel a tricubic sample with its cell in
+// the block can read, and the per-block (min, max) over that footprint,
+// together with the TF, decides whether the block can hold a visible sample.
+#include "vr_internal.h"
+
+namespace vr {
+
+template <typename T>
+__device__ inline float load_voxel(const void *p, uint32_t i) {
+  return (float)reinterpret_cast<const T *>(p)[i];
+}
+
+// One workgroup per block streams its footprint and reduces it.
+template <typename T>
+__global__ __launch_bounds__(kWgSize) void k_block_minmax(const VolConst v, float2 *out) {
+  __shared__ float smin[kWgSize / kWaveSize], smax[kWgSize / kWaveSize];
+  const int64_t b = blockIdx.x;
+  const int bx = (int)(b % v.nbx), by = (int)((b / v.nbx) % v.nby), bz = (int)(b / ((int64_t)v.nbx * v.nby));
+  const int E = v.edge;
+  const int x0 = max(bx * E - 1, 0), x1 = min(bx * E + E + 1, v.nx - 1);
+  const int y0 = max(by * E - 1, 0), y1 = min(by * E + E + 1, v.ny - 1);
+  const int z0 = max(bz * E - 1, 0), z1 = min(bz * E + E + 1, v.nz - 1);
+  const int ex = x1 - x0 + 1, ey = y1 - y0 + 1, ez = z1 - z0 + 1;
+  const int count = ex * ey * ez;
+  float mn = INFINITY, mx = -INFINITY;
+  for (int i = threadIdx.x; i < count; i += kWgSize) {
+    int x = x0 + i % ex, y = y0 + (i / ex) % ey, z = z0 + i / (ex * ey);
+    uint32_t idx = ((uint32_t)z * (uint32_t)v.ny + (uint32_t)y) * (uint32_t)v.nx + (uint32_t)x;
+    float a = load_voxel<T>(v.data, idx);
+    mn = fminf(mn, a);
+    mx = fmaxf(mx, a);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    mn = fminf(mn, __shfl_xor(mn, off, kWaveSize));
+    mx = fmaxf(mx, __shfl_xor(mx, off, kWaveSize));
+  }
+  const int wave = threadIdx.x / kWaveSize, lane = threadIdx.x % kWaveSize;
+  if (lane == 0) {
+    smin[wave] = mn;
+    smax[wave] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kWgSize / kWaveSize; ++w) {
+      mn = fminf(mn, smin[w]);
+      mx = fmaxf(mx, smax[w]);
+    }
+    out[b] = make_float2(mn, mx);
+  }
+}
+
+hipError_t launch_block_minmax(const VolConst &v, float2 *out, hipStream_t s) {
+  int64_t nb = (int64_t)v.nbx * v.nby * v.nbz;
+  switch (v.dtype) {
+  case kU16: hipLaunchKernelGGL(k_block_minmax<uint16_t>, dim3((unsigned)nb), dim3(kWgSize), 0, s, v, out); break;
+  case kI16: hipLaunchKernelGGL(k_block_minmax<int16_t>, dim3((unsigned)nb), dim3(kWgSize), 0, s, v, out); break;
+  case kF32: hipLaunchKernelGGL(k_block_minmax<float>, dim3((unsigned)nb), dim3(kWgSize), 0, s, v, out); break;
+  default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// One thread per block; the TF and its prefix counts sit in LDS.  The same
+// decision (range_occupied) is taken on the fly by the render kernels.
+__global__ __launch_bounds__(kWgSize) void k_block_occupancy(const VolConst v, const TfConst tf, uint8_t *occ) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  TfShared s = carve_tf(lds, tf.K);
+  load_tf(s, tf);
+  const int64_t nb = (int64_t)v.nbx * v.nby * v.nbz;
+  const int64_t b = (int64_t)blockIdx.x * kWgSize + threadIdx.x;
+  if (b < nb) occ[b] = block_occupied(v, s, tf, (int)b) ? 1 : 0;
+}
+
+hipError_t launch_block_occupancy(const VolConst &v, const TfConst &tf, uint8_t *occ, hipStream_t s) {
+  int64_t nb = (int64_t)v.nbx * v.nby * v.nbz;
+  unsigned grid = (unsigned)((nb + kWgSize - 1) / kWgSize);
+  hipLaunchKernelGGL(k_block_occupancy, dim3(grid), dim3(kWgSize), tf_lds_bytes(tf.K), s, v, tf, occ);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kWgSize) void k_fill_zero(float *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kWgSize + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWgSize) p[i] = 0.0f;
+}
+
+hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t g = (n + kWgSize - 1) / kWgSize;
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)g), dim3(kWgSize), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace vr

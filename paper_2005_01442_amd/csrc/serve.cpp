@@ -1,0 +1,613 @@
+// serve.cpp -- continuous-batching render server behind vr_serve_*.
+//
+// The paper serves many clients from one rendering application in the cloud
+// (Section 2, "Cloud architecture": several clients share one application;
+// Section 3: interactive rendering of a large CT for remote clients).  Here
+// volumes and their block structures stay resident in HBM; clients submit
+// requests (volume, camera, TF, step) from any thread; a scheduler thread
+//   1. admits queued requests in FIFO order while a slot is free and the
+//      result image fits the HBM budget,
+//   2. cuts every admitted request into 16x16-pixel work items and fills each
+//      launch round-robin from all admitted requests (so requests of
+//      different volumes, image sizes and TFs share launches, and a request
+//      that arrives while others are on the GPU joins the next launch),
+//   3. keeps two launches in flight on two streams, each launch carrying its
+//      own copy of the request descriptors and TF tables (no cross-stream
+//      dependencies), and retires requests when their last item completes.
+// The per-pixel arithmetic is the whole-image kernel's, so a request's image
+// is the same alone and in any mix.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "vr.h"
+#include "vr_internal.h"
+
+using namespace vr;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double now_s() { return std::chrono::duration<double>(Clock::now().time_since_epoch()).count(); }
+
+enum class RState { Queued, Admitted, Done, Cancelled, Failed };
+
+struct Request {
+  uint64_t ticket = 0;
+  int32_t volume_id = 0;
+  CamConst cam{};
+  std::vector<float> tf;  // K*4, host copy
+  int32_t K = 0;
+  float v0 = 0, v1 = 1;
+  MarchConst mc{};
+  RState state = RState::Queued;
+  vr_status error = VR_OK;
+  double t_submit = 0, t_done = 0;
+  float *image = nullptr;
+  size_t image_bytes = 0;
+  int64_t items_total = 0, items_issued = 0, items_done = 0;
+  int32_t stx = 0, sty = 0;  // super-tile grid
+  bool released = false;
+};
+
+struct Volume {
+  vr_volume desc{};
+  VolConst vc{};
+  vr_blocks *blocks = nullptr;
+  size_t block_bytes = 0;
+  int64_t users = 0;  // queued + admitted requests
+};
+
+// A launch in flight.  Device layout of `dev`: ServeSlot[n_slots], then the
+// TF tables (K_i * 4 floats each, 16-byte aligned), then ServeItem[n_items].
+struct Batch {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  char *host = nullptr;  // pinned staging
+  char *dev = nullptr;
+  size_t cap = 0;
+  bool busy = false;
+  std::vector<std::pair<uint64_t, int32_t>> per_request;  // ticket, items in this batch
+  int64_t pixels = 0;
+};
+
+size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+}  // namespace
+
+struct vr_server {
+  vr_serve_config cfg{};
+  std::mutex mu;
+  std::condition_variable cv_work;   // scheduler wake-up
+  std::condition_variable cv_done;   // waiters
+  std::thread thread;
+  bool stop = false;
+  bool dead = false;
+  int waiters = 0;                   // threads inside vr_serve_wait
+  vr_status dead_status = VR_OK;
+
+  std::map<int32_t, Volume> volumes;
+  int32_t next_volume = 0;
+  std::unordered_map<uint64_t, std::unique_ptr<Request>> requests;
+  std::deque<uint64_t> queue;         // FIFO of queued tickets
+  std::vector<uint64_t> admitted;     // tickets holding a slot
+  uint64_t next_ticket = 1;
+  size_t rr = 0;                      // round-robin cursor over admitted
+
+  // HBM accounting (result images + blocks)
+  uint64_t hbm_used = 0, hbm_peak = 0;
+  std::multimap<size_t, float *> image_pool;  // free images by size
+
+  Batch batches[2];
+  int next_batch = 0;
+
+  // stats
+  uint64_t n_submitted = 0, n_admitted = 0, n_completed = 0, n_rejected = 0, n_launches = 0, n_items = 0;
+  std::vector<double> latencies_ms;
+  double busy_s = 0, busy_since = -1;
+  uint64_t pixels_done = 0;
+};
+
+namespace {
+
+void charge(vr_server *s, size_t bytes) {
+  s->hbm_used += bytes;
+  s->hbm_peak = std::max(s->hbm_peak, s->hbm_used);
+}
+
+// Get a result image of exactly `bytes`: from the pool, else a new
+// allocation if the budget allows (evicting pooled images of other sizes).
+// Called with the lock held.  Returns nullptr when the budget is full.
+float *acquire_image(vr_server *s, size_t bytes) {
+  auto it = s->image_pool.find(bytes);
+  if (it != s->image_pool.end()) {
+    float *p = it->second;
+    s->image_pool.erase(it);
+    return p;
+  }
+  while (s->hbm_used + bytes > s->cfg.hbm_budget_bytes && !s->image_pool.empty()) {
+    auto big = std::prev(s->image_pool.end());
+    (void)hipFree(big->second);
+    s->hbm_used -= big->first;
+    s->image_pool.erase(big);
+  }
+  if (s->hbm_used + bytes > s->cfg.hbm_budget_bytes) return nullptr;
+  float *p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  charge(s, bytes);
+  return p;
+}
+
+void release_image(vr_server *s, float *p, size_t bytes) {
+  if (p) s->image_pool.emplace(bytes, p);
+}
+
+size_t batch_capacity(const vr_serve_config &c) {
+  return (size_t)c.max_inflight * (align16(sizeof(ServeSlot)) + (size_t)VR_MAX_TF_NODES * 16) +
+         (size_t)c.max_batch_tiles * sizeof(ServeItem) + 64;
+}
+
+void fail_all(vr_server *s, vr_status st) {
+  s->dead = true;
+  s->dead_status = st;
+  for (auto &kv : s->requests) {
+    Request &r = *kv.second;
+    if (r.state == RState::Queued || r.state == RState::Admitted) {
+      r.state = RState::Failed;
+      r.error = st;
+      s->volumes[r.volume_id].users--;
+    }
+  }
+  s->queue.clear();
+  s->admitted.clear();
+  s->cv_done.notify_all();
+}
+
+// FIFO admission; lock held.
+void admit(vr_server *s) {
+  while (!s->queue.empty() && (int32_t)s->admitted.size() < s->cfg.max_inflight) {
+    Request &r = *s->requests[s->queue.front()];
+    float *img = acquire_image(s, r.image_bytes);
+    if (!img) break;  // head of line waits for memory
+    r.image = img;
+    r.state = RState::Admitted;
+    s->queue.pop_front();
+    s->admitted.push_back(r.ticket);
+    s->n_admitted++;
+  }
+}
+
+// Retire a finished batch; lock held.
+void retire(vr_server *s, Batch &b) {
+  double t = now_s();
+  for (auto &pr : b.per_request) {
+    auto it = s->requests.find(pr.first);
+    if (it == s->requests.end()) continue;
+    Request &r = *it->second;
+    r.items_done += pr.second;
+    if (r.state == RState::Admitted && r.items_done == r.items_total) {
+      r.state = RState::Done;
+      r.t_done = t;
+      s->latencies_ms.push_back((r.t_done - r.t_submit) * 1e3);
+      s->n_completed++;
+      s->pixels_done += (uint64_t)r.cam.W * r.cam.H;
+      s->admitted.erase(std::find(s->admitted.begin(), s->admitted.end(), r.ticket));
+      s->volumes[r.volume_id].users--;
+    }
+  }
+  b.per_request.clear();
+  b.busy = false;
+  s->cv_done.notify_all();
+}
+
+// Fill and launch batch `b` from the admitted requests; lock held.
+// Returns false if there was nothing to issue.
+bool issue(vr_server *s, Batch &b) {
+  std::vector<uint64_t> live;
+  for (uint64_t t : s->admitted) {
+    Request &r = *s->requests[t];
+    if (r.items_issued < r.items_total) live.push_back(t);
+  }
+  if (live.empty()) return false;
+  const int32_t cap_items = s->cfg.max_batch_tiles;
+  // items per request: round-robin shares of the launch
+  std::vector<int64_t> take(live.size(), 0);
+  int64_t left = cap_items;
+  bool progress = true;
+  const size_t n = live.size();
+  while (left > 0 && progress) {
+    progress = false;
+    int64_t share = std::max<int64_t>(1, left / (int64_t)n);
+    for (size_t q = 0; q < n && left > 0; ++q) {
+      size_t i = (s->rr + q) % n;
+      Request &r = *s->requests[live[i]];
+      int64_t rem = r.items_total - r.items_issued - take[i];
+      int64_t t = std::min<int64_t>({rem, share, left});
+      if (t > 0) {
+        take[i] += t;
+        left -= t;
+        progress = true;
+      }
+    }
+  }
+  s->rr = (s->rr + 1) % std::max<size_t>(1, n);
+  // lay out slots, TF tables and items in the pinned staging buffer
+  std::vector<size_t> slot_of;
+  size_t n_slots = 0;
+  for (size_t i = 0; i < n; ++i)
+    if (take[i] > 0) ++n_slots;
+  size_t off_slots = 0;
+  size_t off_tf = align16(n_slots * sizeof(ServeSlot));
+  size_t tf_bytes = 0;
+  for (size_t i = 0; i < n; ++i)
+    if (take[i] > 0) tf_bytes += align16((size_t)s->requests[live[i]]->K * 16);
+  size_t off_items = off_tf + tf_bytes;
+  int64_t n_items_total = cap_items - left;
+  size_t total = off_items + (size_t)n_items_total * sizeof(ServeItem);
+  if (total > b.cap) return false;  // cannot happen: capacity covers the worst case
+  ServeSlot *slots = reinterpret_cast<ServeSlot *>(b.host + off_slots);
+  ServeItem *items = reinterpret_cast<ServeItem *>(b.host + off_items);
+  size_t tf_cursor = off_tf;
+  int32_t slot = 0;
+  int64_t item = 0;
+  int32_t max_k = 2;
+  b.per_request.clear();
+  b.pixels = 0;
+  for (size_t i = 0; i < n; ++i) {
+    if (take[i] == 0) continue;
+    Request &r = *s->requests[live[i]];
+    Volume &v = s->volumes[r.volume_id];
+    ServeSlot &sl = slots[slot];
+    sl.vol = v.vc;
+    sl.cam = r.cam;
+    sl.mc = r.mc;
+    sl.out = r.image;
+    sl.tf.K = r.K;
+    max_k = std::max(max_k, r.K);
+    sl.tf.v0 = r.v0;
+    sl.tf.scale = (float)(r.K - 1) / (r.v1 - r.v0);
+    memcpy(b.host + tf_cursor, r.tf.data(), (size_t)r.K * 16);
+    sl.tf.table = reinterpret_cast<const float *>(b.dev + tf_cursor);
+    tf_cursor += align16((size_t)r.K * 16);
+    for (int64_t q = 0; q < take[i]; ++q) {
+      int64_t id = r.items_issued + q;
+      items[item].slot = slot;
+      items[item].sx = (int16_t)(id % r.stx);
+      items[item].sy = (int16_t)(id / r.stx);
+      ++item;
+    }
+    r.items_issued += take[i];
+    b.per_request.emplace_back(r.ticket, (int32_t)take[i]);
+    b.pixels += take[i] * kSuperEdge * kSuperEdge;
+    ++slot;
+  }
+  hipError_t e = hipMemcpyAsync(b.dev, b.host, total, hipMemcpyHostToDevice, b.stream);
+  if (e == hipSuccess)
+    e = launch_serve_batch(reinterpret_cast<const ServeSlot *>(b.dev + off_slots),
+                           reinterpret_cast<const ServeItem *>(b.dev + off_items), (int32_t)item, max_k,
+                           b.stream);
+  if (e == hipSuccess) e = hipEventRecord(b.done, b.stream);
+  if (e != hipSuccess) {
+    fail(VR_E_DEVICE, "serve launch: %s", hipGetErrorString(e));
+    fail_all(s, VR_E_DEVICE);
+    return false;
+  }
+  b.busy = true;
+  s->n_launches++;
+  s->n_items += (uint64_t)item;
+  return true;
+}
+
+void scheduler(vr_server *s) {
+  (void)hipSetDevice(s->cfg.device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  while (!s->stop) {
+    admit(s);
+    for (int q = 0; q < 2 && !s->dead; ++q) {
+      Batch &b = s->batches[s->next_batch];
+      if (b.busy || !issue(s, b)) break;
+      s->next_batch ^= 1;
+    }
+    bool retired = false;
+    for (Batch &b : s->batches) {
+      if (!b.busy) continue;
+      hipError_t e = hipEventQuery(b.done);
+      if (e == hipSuccess) {
+        retire(s, b);
+        retired = true;
+      } else if (e != hipErrorNotReady) {
+        fail(VR_E_DEVICE, "serve batch: %s", hipGetErrorString(e));
+        b.busy = false;
+        fail_all(s, VR_E_DEVICE);
+      }
+    }
+    const bool any_busy = s->batches[0].busy || s->batches[1].busy;
+    const double t = now_s();
+    if (any_busy && s->busy_since < 0) s->busy_since = t;
+    if (!any_busy && s->busy_since >= 0) {
+      s->busy_s += t - s->busy_since;
+      s->busy_since = -1;
+    }
+    if (retired) continue;
+    if (any_busy)
+      s->cv_work.wait_for(lk, std::chrono::microseconds(20));
+    else
+      s->cv_work.wait(lk);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+vr_status vr_serve_create(const vr_serve_config *cfg, vr_server **out) {
+  if (!cfg || !out) return fail(VR_E_INVALID_ARG, "config or out is NULL");
+  *out = nullptr;
+  if (cfg->max_inflight < 1 || cfg->max_inflight > 1024) return fail(VR_E_INVALID_ARG, "max_inflight outside [1, 1024]");
+  if (cfg->max_batch_tiles < 0 || cfg->max_batch_tiles > (1 << 20)) return fail(VR_E_INVALID_ARG, "max_batch_tiles outside [0, 2^20]");
+  if (cfg->hbm_budget_bytes == 0) return fail(VR_E_INVALID_ARG, "hbm_budget_bytes is zero");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev)
+    return fail(VR_E_INVALID_ARG, "device %d not available", cfg->device);
+  std::unique_ptr<vr_server> s(new (std::nothrow) vr_server());
+  if (!s) return fail(VR_E_OOM, "host allocation failed");
+  s->cfg = *cfg;
+  if (s->cfg.max_batch_tiles == 0) s->cfg.max_batch_tiles = 2048;
+  hipError_t e = hipSetDevice(cfg->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  const size_t cap = batch_capacity(s->cfg);
+  for (Batch &b : s->batches) {
+    b.cap = cap;
+    if ((e = hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+    if ((e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
+    if ((e = hipHostMalloc((void **)&b.host, cap, hipHostMallocDefault)) != hipSuccess) return hip_fail(e, "pinned staging");
+    if ((e = hipMalloc((void **)&b.dev, cap)) != hipSuccess) return fail(VR_E_OOM, "device staging: %s", hipGetErrorString(e));
+  }
+  vr_server *raw = s.release();
+  raw->thread = std::thread(scheduler, raw);
+  *out = raw;
+  return VR_OK;
+}
+
+vr_status vr_serve_add_volume(vr_server *s, const vr_volume *vol, int32_t block_edge, int32_t *volume_id) {
+  if (!s || !volume_id) return fail(VR_E_INVALID_ARG, "server or volume_id is NULL");
+  VolConst vc;
+  vr_status st = check_volume(vol, &vc);
+  if (st) return st;
+  vr_blocks *blocks = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return fail(VR_E_SHUTDOWN, "server is shutting down");
+  }
+  (void)hipSetDevice(s->cfg.device);
+  if ((st = vr_build_blocks(vol, block_edge, nullptr, &blocks))) return st;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    vr_blocks_free(blocks);
+    return hip_fail(e, "block build");
+  }
+  if ((st = attach_blocks(blocks, vol, &vc))) {
+    vr_blocks_free(blocks);
+    return st;
+  }
+  std::lock_guard<std::mutex> lk(s->mu);
+  size_t bb = (size_t)vc.nbx * vc.nby * vc.nbz * sizeof(float2);
+  if (s->hbm_used + bb > s->cfg.hbm_budget_bytes) {
+    vr_blocks_free(blocks);
+    return fail(VR_E_BUDGET, "blocks of %zu bytes exceed the HBM budget", bb);
+  }
+  charge(s, bb);
+  int32_t id = s->next_volume++;
+  Volume &v = s->volumes[id];
+  v.desc = *vol;
+  v.vc = vc;
+  v.blocks = blocks;
+  v.block_bytes = bb;
+  *volume_id = id;
+  return VR_OK;
+}
+
+vr_status vr_serve_remove_volume(vr_server *s, int32_t volume_id) {
+  if (!s) return fail(VR_E_INVALID_ARG, "server is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->volumes.find(volume_id);
+  if (it == s->volumes.end()) return fail(VR_E_NOT_FOUND, "unknown volume %d", volume_id);
+  if (it->second.users > 0) return fail(VR_E_BUSY, "volume %d has %lld requests queued or in flight", volume_id, (long long)it->second.users);
+  vr_blocks_free(it->second.blocks);
+  s->hbm_used -= it->second.block_bytes;
+  s->volumes.erase(it);
+  return VR_OK;
+}
+
+vr_status vr_serve_submit(vr_server *s, const vr_request *req, uint64_t *ticket) {
+  if (!s || !req || !ticket) return fail(VR_E_INVALID_ARG, "server, request or ticket is NULL");
+  std::unique_ptr<Request> r(new Request());
+  vr_status st = check_camera(&req->cam, &r->cam);
+  if (st) return st;
+  if (!req->tf_table_host) return fail(VR_E_INVALID_ARG, "tf_table_host is NULL");
+  if (req->K < 2 || req->K > VR_MAX_TF_NODES) return fail(VR_E_INVALID_ARG, "TF node count K=%d outside [2, %d]", req->K, VR_MAX_TF_NODES);
+  if (!std::isfinite(req->tf_v0) || !std::isfinite(req->tf_v1) || !(req->tf_v1 > req->tf_v0))
+    return fail(VR_E_INVALID_ARG, "TF value range must be finite with v1 > v0");
+  r->tf.assign(req->tf_table_host, req->tf_table_host + (size_t)req->K * 4);
+  for (int32_t j = 0; j < req->K; ++j) {
+    for (int c = 0; c < 4; ++c)
+      if (!std::isfinite(r->tf[4 * j + c])) return fail(VR_E_INVALID_ARG, "TF entry %d is not finite", j);
+    if (r->tf[4 * j + 3] < 0.0f) return fail(VR_E_INVALID_ARG, "TF node %d has negative extinction", j);
+  }
+  if ((st = check_march(req->step, req->ert_threshold, req->use_skip, &r->mc))) return st;
+  r->K = req->K;
+  r->v0 = req->tf_v0;
+  r->v1 = req->tf_v1;
+  r->volume_id = req->volume_id;
+  r->image_bytes = (size_t)req->cam.width * req->cam.height * 16;
+  r->stx = (req->cam.width + kSuperEdge - 1) / kSuperEdge;
+  r->sty = (req->cam.height + kSuperEdge - 1) / kSuperEdge;
+  if (r->stx > 32767 || r->sty > 32767) return fail(VR_E_UNSUPPORTED, "image too large for serving");
+  r->items_total = (int64_t)r->stx * r->sty;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stop) return fail(VR_E_SHUTDOWN, "server is shutting down");
+  if (s->dead) return fail(s->dead_status, "server failed earlier");
+  auto vit = s->volumes.find(req->volume_id);
+  if (vit == s->volumes.end()) {
+    s->n_rejected++;
+    return fail(VR_E_NOT_FOUND, "unknown volume %d", req->volume_id);
+  }
+  if (r->image_bytes > s->cfg.hbm_budget_bytes) {
+    s->n_rejected++;
+    return fail(VR_E_BUDGET, "result image of %zu bytes exceeds the HBM budget", r->image_bytes);
+  }
+  Volume &v = vit->second;
+  r->ticket = s->next_ticket++;
+  r->t_submit = now_s();
+  v.users++;
+  *ticket = r->ticket;
+  s->queue.push_back(r->ticket);
+  s->requests.emplace(r->ticket, std::move(r));
+  s->n_submitted++;
+  s->cv_work.notify_one();
+  return VR_OK;
+}
+
+vr_status vr_serve_wait(vr_server *s, uint64_t ticket, int64_t timeout_us, const float **rgba_device) {
+  if (!s) return fail(VR_E_INVALID_ARG, "server is NULL");
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->requests.find(ticket);
+  if (it == s->requests.end()) return fail(VR_E_NOT_FOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  Request *r = it->second.get();
+  auto ready = [&] { return r->state == RState::Done || r->state == RState::Cancelled || r->state == RState::Failed; };
+  s->waiters++;
+  bool ok = true;
+  if (timeout_us < 0)
+    s->cv_done.wait(lk, ready);
+  else
+    ok = s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready);
+  s->waiters--;
+  if (s->waiters == 0) s->cv_done.notify_all();
+  if (!ok)
+    return fail(VR_E_TIMEOUT, "ticket %llu not complete after %lld us", (unsigned long long)ticket, (long long)timeout_us);
+  if (r->state == RState::Cancelled) return fail(VR_E_SHUTDOWN, "ticket %llu cancelled by shutdown", (unsigned long long)ticket);
+  if (r->state == RState::Failed) return fail(r->error, "ticket %llu failed", (unsigned long long)ticket);
+  if (rgba_device) *rgba_device = r->image;
+  return VR_OK;
+}
+
+vr_status vr_serve_release(vr_server *s, uint64_t ticket) {
+  if (!s) return fail(VR_E_INVALID_ARG, "server is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->requests.find(ticket);
+  if (it == s->requests.end()) return fail(VR_E_NOT_FOUND, "unknown ticket %llu", (unsigned long long)ticket);
+  Request &r = *it->second;
+  if (r.state == RState::Queued || r.state == RState::Admitted)
+    return fail(VR_E_BUSY, "ticket %llu is not complete", (unsigned long long)ticket);
+  release_image(s, r.image, r.image_bytes);
+  s->requests.erase(it);
+  s->cv_work.notify_one();
+  return VR_OK;
+}
+
+vr_status vr_serve_stats_get(vr_server *s, vr_serve_stats *o) {
+  if (!s || !o) return fail(VR_E_INVALID_ARG, "server or out is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  memset(o, 0, sizeof(*o));
+  o->submitted = s->n_submitted;
+  o->admitted = s->n_admitted;
+  o->completed = s->n_completed;
+  o->rejected = s->n_rejected;
+  o->queued = s->queue.size();
+  o->inflight = s->admitted.size();
+  o->hbm_used = s->hbm_used;
+  o->hbm_peak = s->hbm_peak;
+  o->launches = s->n_launches;
+  o->tiles = s->n_items;
+  std::vector<double> l = s->latencies_ms;
+  if (!l.empty()) {
+    std::sort(l.begin(), l.end());
+    auto pct = [&](double p) {
+      double idx = p * (double)(l.size() - 1);
+      size_t lo = (size_t)std::floor(idx), hi = (size_t)std::ceil(idx);
+      return l[lo] + (l[hi] - l[lo]) * (idx - (double)lo);
+    };
+    o->p50_ms = pct(0.50);
+    o->p99_ms = pct(0.99);
+    double sum = 0;
+    for (double x : l) sum += x;
+    o->mean_ms = sum / (double)l.size();
+    o->max_ms = l.back();
+  }
+  double busy = s->busy_s + (s->busy_since >= 0 ? now_s() - s->busy_since : 0.0);
+  o->busy_s = busy;
+  o->rays_per_s = busy > 0 ? (double)s->pixels_done / busy : 0.0;
+  return VR_OK;
+}
+
+vr_status vr_serve_stats_reset(vr_server *s) {
+  if (!s) return fail(VR_E_INVALID_ARG, "server is NULL");
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->n_submitted = s->n_admitted = s->n_completed = s->n_rejected = s->n_launches = s->n_items = 0;
+  s->latencies_ms.clear();
+  s->busy_s = 0;
+  if (s->busy_since >= 0) s->busy_since = now_s();
+  s->pixels_done = 0;
+  s->hbm_peak = s->hbm_used;
+  return VR_OK;
+}
+
+vr_status vr_serve_destroy(vr_server *s) {
+  if (!s) return fail(VR_E_INVALID_ARG, "server is NULL");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    for (uint64_t t : s->queue) {
+      Request &r = *s->requests[t];
+      r.state = RState::Cancelled;
+      s->volumes[r.volume_id].users--;
+    }
+    s->queue.clear();
+    s->cv_work.notify_all();
+  }
+  if (s->thread.joinable()) s->thread.join();
+  (void)hipSetDevice(s->cfg.device);
+  for (Batch &b : s->batches) {
+    if (b.stream) (void)hipStreamSynchronize(b.stream);
+  }
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (Batch &b : s->batches)
+      if (b.busy) retire(s, b);
+    for (uint64_t t : s->admitted) {
+      Request &r = *s->requests[t];
+      r.state = RState::Cancelled;
+    }
+    s->admitted.clear();
+    s->cv_done.notify_all();
+  }
+  {
+    // let every waiter observe its final state before the server goes away
+    std::unique_lock<std::mutex> lk(s->mu);
+    s->cv_done.wait(lk, [&] { return s->waiters == 0; });
+  }
+  for (Batch &b : s->batches) {
+    if (b.done) (void)hipEventDestroy(b.done);
+    if (b.stream) (void)hipStreamDestroy(b.stream);
+    if (b.host) (void)hipHostFree(b.host);
+    if (b.dev) (void)hipFree(b.dev);
+  }
+  for (auto &kv : s->requests)
+    if (kv.second->image) (void)hipFree(kv.second->image);
+  for (auto &kv : s->image_pool) (void)hipFree(kv.second);
+  for (auto &kv : s->volumes) vr_blocks_free(kv.second.blocks);
+  delete s;
+  return VR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,492 @@
+// vr_device.h -- device building blocks of the gfx950 ray caster, shared by
+// the forward, adjoint and serving kernels.
+//
+// Ray casting per Section 2 of the paper: one ray per pixel from the
+// observer, fixed step, colour accumulated along the ray; the scalar is
+// reconstructed with cubic-spline (tricubic) interpolation and classified
+// after interpolation through the transfer function; rays stop once opaque and
+// blocks with nothing visible are skipped (block decomposition, "Pros" (b)).
+//
+// Work layout: a wavefront owns an 8x8 pixel tile (one ray per lane), a
+// workgroup of four wavefronts a 16x16 super-tile.  The transfer function and
+// its non-zero-extinction bitmask live in LDS.  Volume taps are fetched with
+// raw buffer loads (bounds-checked by the hardware): an x-row of four int16
+// taps is one dwordx3 load plus two v_alignbit, an fp32 row one dwordx4 load.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vr {
+
+constexpr int kTileEdge = 8;          // pixels per wavefront tile edge
+constexpr int kSuperEdge = 16;        // pixels per workgroup super-tile edge
+constexpr int kWaveSize = 64;
+constexpr int kWgSize = 256;
+constexpr int kMaxTf = 1024;          // max TF nodes (LDS: 16 KiB table)
+constexpr int kMaxCamsPerLaunch = 16; // cameras carried in kernel arguments
+constexpr int kXcds = 8;              // MI355X: 8 accelerator complex dies
+constexpr int kChunkEdge = 8;         // super-tiles per chunk edge (XCD mapping)
+
+enum Dtype : int32_t { kU16 = 0, kI16 = 1, kF32 = 2 };
+
+// Camera constants, FP64, precomputed on the host.
+struct CamConst {
+  double eye[3], right[3], up[3], fwd[3];
+  double th;      // tan(fov_y / 2), perspective
+  double hw, hh;  // ortho_w / 2, ortho_h / 2, orthographic
+  int32_t proj, W, H, pad;
+};
+
+struct VolConst {
+  const void *data;
+  int32_t dtype;
+  int32_t nx, ny, nz;
+  uint32_t bytes;           // total bytes (< 4 GiB)
+  const float2 *minmax;     // per-block (min, max) or nullptr
+  int32_t nbx, nby, nbz, edge;
+};
+
+struct TfConst {
+  const float *table;  // K x 4 fp32
+  int32_t K;
+  float v0, scale;     // u = (v - v0) * scale, scale = (K-1)/(v1-v0) in fp32
+};
+
+struct MarchConst {
+  float step;
+  float ert;        // in (0,1) enables early termination
+  int32_t skip;     // nonzero: skip samples in empty blocks
+  int32_t pad;
+};
+
+// ---------------------------------------------------------------------------
+// LDS state of a workgroup: the TF table and a prefix count of its non-zero
+// extinction nodes (block occupancy in O(1)).  Carved out of dynamic LDS,
+// sized by K.
+// ---------------------------------------------------------------------------
+struct TfShared {
+  float4 *node;                // K nodes (r, g, b, sigma)
+  int32_t *pref;               // K + 1: pref[j] = #{i < j : sigma_i != 0}
+  unsigned long long *mask;    // ceil(K / 64) ballot words
+};
+
+__host__ __device__ inline uint32_t tf_lds_bytes(int K) {
+  uint32_t a = (uint32_t)K * 16u;
+  uint32_t b = (((uint32_t)K + 1u) * 4u + 7u) & ~7u;
+  uint32_t c = (((uint32_t)K + 63u) / 64u) * 8u;
+  return a + b + c;
+}
+
+__device__ inline TfShared carve_tf(char *base, int K) {
+  TfShared s;
+  s.node = reinterpret_cast<float4 *>(base);
+  s.pref = reinterpret_cast<int32_t *>(base + (uint32_t)K * 16u);
+  s.mask = reinterpret_cast<unsigned long long *>(base + (uint32_t)K * 16u +
+                                                  ((((uint32_t)K + 1u) * 4u + 7u) & ~7u));
+  return s;
+}
+
+// Load the TF into LDS and build the prefix counts.  All 256 threads call it.
+// Negative or NaN extinction is read as zero.
+__device__ inline void load_tf(TfShared &s, const TfConst &tf) {
+  const int t = threadIdx.x;
+  const float4 *src = reinterpret_cast<const float4 *>(tf.table);
+  for (int j = t; j < tf.K; j += kWgSize) {
+    float4 n = src[j];
+    n.w = fmaxf(n.w, 0.0f);
+    s.node[j] = n;
+  }
+  __syncthreads();
+  const int words = (tf.K + 63) / 64;
+  const int wave = t / kWaveSize, lane = t % kWaveSize;
+  for (int w = wave; w < words; w += kWgSize / kWaveSize) {
+    int j = w * 64 + lane;
+    bool nz = (j < tf.K) && (s.node[j].w != 0.0f);
+    unsigned long long m = __ballot(nz);
+    if (lane == 0) s.mask[w] = m;
+  }
+  __syncthreads();
+  for (int j = t; j <= tf.K; j += kWgSize) {
+    int w = j / 64, b = j % 64;
+    int c = 0;
+    for (int q = 0; q < w; ++q) c += __popcll(s.mask[q]);
+    if (w < words && b) c += __popcll(s.mask[w] & ((1ull << b) - 1ull));
+    s.pref[j] = c;
+  }
+  __syncthreads();
+}
+
+// Occupancy of a block with value range [mn, mx]: some node in
+// [floor(u(mn)) - 1, ceil(u(mx)) + 1] (clamped) has non-zero extinction.
+__device__ inline bool range_occupied(const TfShared &s, int K, float v0, float scale, float mn, float mx) {
+  float ulo = (mn - v0) * scale;
+  float uhi = (mx - v0) * scale;
+  ulo = fminf(fmaxf(ulo, -2.0f), (float)K + 1.0f);
+  uhi = fminf(fmaxf(uhi, -2.0f), (float)K + 1.0f);
+  int jlo = (int)floorf(ulo) - 1;
+  int jhi = (int)ceilf(uhi) + 1;
+  jlo = min(max(jlo, 0), K - 1);
+  jhi = min(max(jhi, 0), K - 1);
+  return s.pref[jhi + 1] - s.pref[jlo] > 0;
+}
+
+// ---------------------------------------------------------------------------
+// Ray setup (FP64).  The expression order matches the camera definition in
+// vr.h term by term and no operation is contracted into an FMA, so the
+// lattice count -- an integer decided by floating point -- is reproducible.
+// ---------------------------------------------------------------------------
+struct Ray {
+  float p0[3];  // entry point o + t_in d, rounded to fp32
+  float d[3];   // unit direction, rounded to fp32
+  int32_t ns;   // lattice samples
+  bool hit;
+};
+
+__device__ inline Ray setup_ray(const CamConst &c, int col, int row, int nx, int ny, int nz, float step32) {
+#pragma clang fp contract(off)
+  Ray r;
+  r.hit = false;
+  r.ns = 0;
+  double sx = 2.0 * ((double)col + 0.5) / (double)c.W - 1.0;
+  double sy = 1.0 - 2.0 * ((double)row + 0.5) / (double)c.H;
+  double o[3], d[3];
+  if (c.proj != 0) {
+    double a = sx * c.th * ((double)c.W / (double)c.H);
+    double b = sy * c.th;
+    for (int k = 0; k < 3; ++k) {
+      o[k] = c.eye[k];
+      d[k] = c.fwd[k] + a * c.right[k] + b * c.up[k];
+    }
+  } else {
+    double a = sx * c.hw;
+    double b = sy * c.hh;
+    for (int k = 0; k < 3; ++k) {
+      o[k] = c.eye[k] + a * c.right[k] + b * c.up[k];
+      d[k] = c.fwd[k];
+    }
+  }
+  double n = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  for (int k = 0; k < 3; ++k) d[k] = d[k] / n;
+  // slab clip against [-1/2, n - 1/2]^3
+  double hi[3] = {(double)nx - 0.5, (double)ny - 0.5, (double)nz - 0.5};
+  double t0 = -INFINITY, t1 = INFINITY;
+  for (int a = 0; a < 3; ++a) {
+    if (d[a] == 0.0) {
+      if (o[a] < -0.5 || o[a] > hi[a]) return r;
+      continue;
+    }
+    double ta = (-0.5 - o[a]) / d[a];
+    double tb = (hi[a] - o[a]) / d[a];
+    if (ta > tb) {
+      double s = ta;
+      ta = tb;
+      tb = s;
+    }
+    if (ta > t0) t0 = ta;
+    if (tb < t1) t1 = tb;
+  }
+  double te = t0 > 0.0 ? t0 : 0.0;
+  if (!(t1 > te)) return r;
+  // lattice: #{k >= 0 : (k + 1/2) step < t1 - te}
+  double L = t1 - te;
+  double st = (double)step32;
+  double est = ceil(L / st - 0.5);
+  long long k = est > 0.0 ? (long long)est : 0;
+  while (k > 0 && ((double)(k - 1) + 0.5) * st >= L) --k;
+  while (((double)k + 0.5) * st < L) ++k;
+  r.ns = (int32_t)k;
+  r.hit = true;
+  for (int a = 0; a < 3; ++a) {
+    r.p0[a] = (float)(o[a] + te * d[a]);
+    r.d[a] = (float)d[a];
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Tricubic B-spline reconstruction.
+// ---------------------------------------------------------------------------
+__device__ inline void bspline_weights(float t, float w[4]) {
+  const float s = 1.0f - t;
+  const float t2 = t * t, t3 = t2 * t;
+  w[0] = (1.0f / 6.0f) * s * s * s;
+  w[3] = (1.0f / 6.0f) * t3;
+  w[1] = fmaf(0.5f, t3, (2.0f / 3.0f) - t2);
+  w[2] = 1.0f - w[0] - w[1] - w[3];
+}
+
+typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+  // raw buffer: stride 0, num_records in bytes; dword format word for gfx9
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <int DT> struct Vox;
+
+template <> struct Vox<kI16> {
+  static constexpr int kBytes = 2;
+  // four consecutive taps starting at element e; e_al = e & ~1 even
+  __device__ static inline void row(__amdgpu_buffer_rsrc_t r, uint32_t e, float t[4]) {
+    uint32_t ea = e & ~1u;
+    u32x3 v = __builtin_amdgcn_raw_buffer_load_b96(r, ea * 2u, 0, 0);
+    uint32_t sh = (e & 1u) * 16u;
+    uint32_t lo = __builtin_amdgcn_alignbit(v.y, v.x, sh);
+    uint32_t hi = __builtin_amdgcn_alignbit(v.z, v.y, sh);
+    t[0] = (float)(int16_t)(lo & 0xffffu);
+    t[1] = (float)((int32_t)lo >> 16);
+    t[2] = (float)(int16_t)(hi & 0xffffu);
+    t[3] = (float)((int32_t)hi >> 16);
+  }
+  __device__ static inline float one(__amdgpu_buffer_rsrc_t r, uint32_t e) {
+    return (float)(int16_t)__builtin_amdgcn_raw_buffer_load_b16(r, e * 2u, 0, 0);
+  }
+  // the dwordx3 window of the row starting at e lies inside the buffer
+  __device__ static inline bool window_ok(uint32_t e, uint32_t nvox) { return (e & ~1u) + 6u <= nvox; }
+};
+
+template <> struct Vox<kU16> {
+  static constexpr int kBytes = 2;
+  __device__ static inline void row(__amdgpu_buffer_rsrc_t r, uint32_t e, float t[4]) {
+    uint32_t ea = e & ~1u;
+    u32x3 v = __builtin_amdgcn_raw_buffer_load_b96(r, ea * 2u, 0, 0);
+    uint32_t sh = (e & 1u) * 16u;
+    uint32_t lo = __builtin_amdgcn_alignbit(v.y, v.x, sh);
+    uint32_t hi = __builtin_amdgcn_alignbit(v.z, v.y, sh);
+    t[0] = (float)(lo & 0xffffu);
+    t[1] = (float)(lo >> 16);
+    t[2] = (float)(hi & 0xffffu);
+    t[3] = (float)(hi >> 16);
+  }
+  __device__ static inline float one(__amdgpu_buffer_rsrc_t r, uint32_t e) {
+    return (float)(uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, e * 2u, 0, 0);
+  }
+  __device__ static inline bool window_ok(uint32_t e, uint32_t nvox) { return (e & ~1u) + 6u <= nvox; }
+};
+
+template <> struct Vox<kF32> {
+  static constexpr int kBytes = 4;
+  __device__ static inline void row(__amdgpu_buffer_rsrc_t r, uint32_t e, float t[4]) {
+    f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, e * 4u, 0, 0));
+    t[0] = v.x;
+    t[1] = v.y;
+    t[2] = v.z;
+    t[3] = v.w;
+  }
+  __device__ static inline float one(__amdgpu_buffer_rsrc_t r, uint32_t e) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, e * 4u, 0, 0));
+  }
+  __device__ static inline bool window_ok(uint32_t, uint32_t) { return true; }
+};
+
+// Stencil geometry of one sample: cell, fractional offsets, weights.
+struct Stencil {
+  int ix, iy, iz;
+  float wx[4], wy[4], wz[4];
+};
+
+__device__ inline Stencil make_stencil(float px, float py, float pz) {
+  Stencil s;
+  float fx = floorf(px), fy = floorf(py), fz = floorf(pz);
+  s.ix = (int)fx;
+  s.iy = (int)fy;
+  s.iz = (int)fz;
+  bspline_weights(px - fx, s.wx);
+  bspline_weights(py - fy, s.wy);
+  bspline_weights(pz - fz, s.wz);
+  return s;
+}
+
+// v = sum_c wz_c sum_b wy_b sum_a wx_a V[z_c][y_b][x_a], separable, with
+// clamp-to-edge addressing.  Interior stencils take the packed-row path.
+template <int DT>
+__device__ inline float reconstruct(__amdgpu_buffer_rsrc_t rs, const VolConst &v, const Stencil &s) {
+  const int nx = v.nx, ny = v.ny, nz = v.nz;
+  const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
+  const uint32_t nvox = nxy * (uint32_t)nz;
+  float acc = 0.0f;
+  bool inner = (s.ix >= 1) & (s.ix + 2 <= nx - 1) & (s.iy >= 1) & (s.iy + 2 <= ny - 1) & (s.iz >= 1) &
+               (s.iz + 2 <= nz - 1);
+  if (inner) {
+    uint32_t e0 = ((uint32_t)(s.iz - 1) * (uint32_t)ny + (uint32_t)(s.iy - 1)) * (uint32_t)nx + (uint32_t)(s.ix - 1);
+    inner = Vox<DT>::window_ok(e0 + 3u * nxy + 3u * (uint32_t)nx, nvox);
+    if (inner) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        float accy = 0.0f;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          float t[4];
+          Vox<DT>::row(rs, e0 + (uint32_t)c * nxy + (uint32_t)b * (uint32_t)nx, t);
+          float r = s.wx[0] * t[0];
+          r = fmaf(s.wx[1], t[1], r);
+          r = fmaf(s.wx[2], t[2], r);
+          r = fmaf(s.wx[3], t[3], r);
+          accy = fmaf(s.wy[b], r, accy);
+        }
+        acc = fmaf(s.wz[c], accy, acc);
+      }
+      return acc;
+    }
+  }
+  int xs[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) xs[a] = min(max(s.ix - 1 + a, 0), nx - 1);
+  for (int c = 0; c < 4; ++c) {
+    uint32_t z = (uint32_t)min(max(s.iz - 1 + c, 0), nz - 1);
+    float accy = 0.0f;
+    for (int b = 0; b < 4; ++b) {
+      uint32_t y = (uint32_t)min(max(s.iy - 1 + b, 0), ny - 1);
+      uint32_t rowb = (z * (uint32_t)ny + y) * (uint32_t)nx;
+      float r = 0.0f;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) r = fmaf(s.wx[a], Vox<DT>::one(rs, rowb + (uint32_t)xs[a]), r);
+      accy = fmaf(s.wy[b], r, accy);
+    }
+    acc = fmaf(s.wz[c], accy, acc);
+  }
+  return acc;
+}
+
+// Post-classification: (r, g, b, sigma) at value v; j and w of the segment;
+// `clamped` when u fell outside [0, K-1].
+struct Classified {
+  float4 c;
+  int j;
+  float w;
+  bool clamped;
+};
+
+__device__ inline Classified classify(const TfShared &s, int K, float v0, float scale, float v) {
+  Classified q;
+  float u = (v - v0) * scale;
+  q.clamped = !(u >= 0.0f && u <= (float)(K - 1));
+  u = fminf(fmaxf(u, 0.0f), (float)(K - 1));
+  int j = min((int)u, K - 2);
+  float w = u - (float)j;
+  float4 a = s.node[j], b = s.node[j + 1];
+  q.c.x = fmaf(w, b.x - a.x, a.x);
+  q.c.y = fmaf(w, b.y - a.y, a.y);
+  q.c.z = fmaf(w, b.z - a.z, a.z);
+  q.c.w = fmaf(w, b.w - a.w, a.w);
+  q.j = j;
+  q.w = w;
+  return q;
+}
+
+// exp(-x) for x >= 0 via the hardware exp2 (1 ulp); x = sigma * step.
+__device__ inline float transmit(float sigma, float step_log2e) {
+  return __builtin_amdgcn_exp2f(-sigma * step_log2e);
+}
+
+// ---------------------------------------------------------------------------
+// Empty-space leaping.  Block of the (clamped) cell of p, and the first
+// lattice index that may leave it.
+// ---------------------------------------------------------------------------
+__device__ inline int block_of(const VolConst &v, float px, float py, float pz, int bc[3]) {
+  int cx = min(max((int)floorf(px), 0), v.nx - 1);
+  int cy = min(max((int)floorf(py), 0), v.ny - 1);
+  int cz = min(max((int)floorf(pz), 0), v.nz - 1);
+  bc[0] = cx / v.edge;
+  bc[1] = cy / v.edge;
+  bc[2] = cz / v.edge;
+  return bc[0] + v.nbx * (bc[1] + v.nby * bc[2]);
+}
+
+// Every sample k' with k <= k' < result lies strictly inside the current
+// block: positions fl(fma(s, d, p0)) are monotone in s per axis, and the
+// bound is pulled in by 2^-9 voxel (more than the fp32 rounding of any
+// position below 8192) and by one more full step.  Computed in FP64.
+__device__ inline int leap_target(const VolConst &v, const Ray &r, const int bc[3], float step, int k) {
+  const int nb[3] = {v.nbx, v.nby, v.nbz};
+  double smin = INFINITY;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double da = (double)r.d[a];
+    double pa = (double)r.p0[a];
+    if (da > 0.0 && bc[a] < nb[a] - 1) {
+      double bound = (double)((bc[a] + 1) * v.edge) - 0x1p-9;
+      smin = fmin(smin, (bound - pa) / da);
+    } else if (da < 0.0 && bc[a] > 0) {
+      double bound = (double)(bc[a] * v.edge) + 0x1p-9;
+      smin = fmin(smin, (bound - pa) / da);
+    }
+  }
+  if (!(smin < 1e30)) return 0x7fffffff;
+  // first k with (k + 1/2) step >= smin, minus one step of margin
+  double kf = ceil(smin / (double)step - 0.5) - 1.0;
+  if (kf > 2.0e9) return 0x7fffffff;
+  int kt = (int)fmax(kf, 0.0);
+  return max(kt, k + 1);
+}
+
+// Blocks' minmax and TF decide occupancy.
+__device__ inline bool block_occupied(const VolConst &v, const TfShared &s, const TfConst &tf, int b) {
+  float2 mm = v.minmax[b];
+  return range_occupied(s, tf.K, tf.v0, tf.scale, mm.x, mm.y);
+}
+
+// ---------------------------------------------------------------------------
+// Tile mapping.  A workgroup owns a 16x16 super-tile; wavefront w the 8x8
+// sub-tile (w & 1, w >> 1); lane l the pixel (l & 7, l >> 3) of it.
+// Workgroups are dispatched round-robin over the XCDs; the mapping gives each
+// XCD whole 8x8-super-tile chunks (128x128 pixels) in turn, so a chunk's rays
+// share one L2 while the chunks of an image interleave over all XCDs.
+// ---------------------------------------------------------------------------
+struct SuperTile {
+  int view, sx, sy;  // super-tile coordinates within the view
+  bool valid;
+};
+
+__host__ __device__ inline int64_t chunk_count(int W, int H, int views) {
+  int stx = (W + kSuperEdge - 1) / kSuperEdge, sty = (H + kSuperEdge - 1) / kSuperEdge;
+  int cx = (stx + kChunkEdge - 1) / kChunkEdge, cy = (sty + kChunkEdge - 1) / kChunkEdge;
+  return (int64_t)cx * cy * views;
+}
+
+__host__ __device__ inline int64_t grid_size_for(int W, int H, int views) {
+  int64_t nc = chunk_count(W, H, views);
+  int64_t per = kChunkEdge * kChunkEdge;
+  return ((nc + kXcds - 1) / kXcds) * kXcds * per;
+}
+
+__device__ inline SuperTile map_workgroup(int64_t wg, int W, int H, int views) {
+  SuperTile st;
+  const int per = kChunkEdge * kChunkEdge;
+  int64_t xcd = wg % kXcds, r = wg / kXcds;
+  int64_t chunk = (r / per) * kXcds + xcd;
+  int pos = (int)(r % per);
+  int stx = (W + kSuperEdge - 1) / kSuperEdge, sty = (H + kSuperEdge - 1) / kSuperEdge;
+  int cx = (stx + kChunkEdge - 1) / kChunkEdge, cy = (sty + kChunkEdge - 1) / kChunkEdge;
+  int64_t nc = (int64_t)cx * cy * views;
+  st.valid = chunk < nc;
+  int64_t per_view = (int64_t)cx * cy;
+  st.view = (int)(chunk / per_view);
+  int64_t c = chunk % per_view;
+  st.sx = (int)(c % cx) * kChunkEdge + pos % kChunkEdge;
+  st.sy = (int)(c / cx) * kChunkEdge + pos / kChunkEdge;
+  st.valid = st.valid && st.sx < stx && st.sy < sty;
+  return st;
+}
+
+__device__ inline void pixel_of(int sx, int sy, int &col, int &row) {
+  int wave = threadIdx.x / kWaveSize, lane = threadIdx.x % kWaveSize;
+  col = sx * kSuperEdge + (wave & 1) * kTileEdge + (lane & 7);
+  row = sy * kSuperEdge + (wave >> 1) * kTileEdge + (lane >> 3);
+}
+
+// The kernel's by-value argument struct, read in place from the kernarg
+// segment (scalar loads; dynamic indexing then needs no private copy).
+template <class T> __device__ inline const T &kernarg() {
+  return *(const T *)__builtin_amdgcn_kernarg_segment_ptr();
+}
+
+// Sum a per-lane count over the wavefront and add it to a 64-bit counter.
+__device__ inline void wave_count(unsigned long long *ctr, uint32_t v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWaveSize);
+  if ((threadIdx.x % kWaveSize) == 0 && v) atomicAdd(ctr, (unsigned long long)v);
+}
+
+}  // namespace vr

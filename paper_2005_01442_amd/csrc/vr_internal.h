@@ -1,0 +1,66 @@
+// vr_internal.h -- host-side launch interface between the C ABI layer and the
+// HIP kernels.  Not installed; the public interface is include/vr.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vr.h"
+#include "vr_device.h"
+
+namespace vr {
+
+// Arguments of the whole-image render kernels (one launch covers up to
+// kMaxCamsPerLaunch views that share volume, TF and marching parameters).
+struct RenderArgs {
+  VolConst vol;
+  TfConst tf;
+  MarchConst mc;
+  float *out;                      // RGBA of the first view of this launch
+  unsigned long long *counters;    // optional [evaluated, lattice, hit, -]
+  int32_t W, H, n_views, pad;
+  CamConst cams[kMaxCamsPerLaunch];
+};
+
+struct BackwardArgs {
+  RenderArgs r;
+  const float *out_rgba;   // forward result of the first view of this launch
+  const float *grad_rgba;  // dL/dRGBA of the first view of this launch
+  float *grad_vol;         // nullptr or nx*ny*nz
+  float *grad_tf;          // nullptr or K*4
+};
+
+hipError_t launch_render(const RenderArgs &a, hipStream_t s);
+hipError_t launch_render_backward(const BackwardArgs &a, hipStream_t s);
+hipError_t launch_block_minmax(const VolConst &v, float2 *out, hipStream_t s);
+hipError_t launch_block_occupancy(const VolConst &v, const TfConst &tf, uint8_t *occ, hipStream_t s);
+hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s);
+
+// Serving: one work item is a 16x16 super-tile of one request slot.
+struct ServeSlot {
+  VolConst vol;
+  TfConst tf;
+  MarchConst mc;
+  CamConst cam;
+  float *out;
+};
+
+struct ServeItem {
+  int32_t slot;
+  int16_t sx, sy;
+};
+
+// Validation helpers of the ABI layer (api.cpp); each fills the kernel-side
+// constants and records vr_last_error on failure.
+vr_status fail(vr_status s, const char *fmt, ...);
+vr_status hip_fail(hipError_t e, const char *what);
+vr_status check_volume(const vr_volume *v, VolConst *out);
+vr_status check_tf_fields(const void *table, int32_t K, float v0, float v1, TfConst *out);
+vr_status check_camera(const vr_camera *c, CamConst *out);
+vr_status check_march(float step, float ert, int32_t use_skip, MarchConst *out);
+vr_status attach_blocks(const vr_blocks *b, const vr_volume *v, VolConst *vc);
+
+hipError_t launch_serve_batch(const ServeSlot *slots_dev, const ServeItem *items_dev, int32_t n_items,
+                              int32_t max_tf_k, hipStream_t s);
+
+}  // namespace vr

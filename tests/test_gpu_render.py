@@ -1,0 +1,206 @@
+"""GPU forward parity: the HIP ray caster (through the C ABI) against the FP64
+oracle, element by element, on seeded inputs.
+
+Bar: max |dRGBA| <= 2e-4 (fp32 kernel vs fp64 oracle); pixels where the oracle
+sees an early-termination tie (|1 - T - theta| < 1e-5) may differ by up to
+1 - theta more.  Integer results (block min/max, occupancy, lattice counts)
+must match exactly; skip vs no-skip must be bit-identical.
+"""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+import paper_2005_01442_amd as vr  # noqa: E402
+from gpu_util import compare_with_flags, gpu_render, log, upload_tf, upload_volume  # noqa: E402
+
+TOL = 2e-4
+
+
+def test_c0_full_frame_matches_oracle():
+    c = synth.config_c0()
+    log("c0: 64^3 u16 ortho 256^2")
+    img, ctr = gpu_render(c["volume"], c["cameras"], c["tf"], c["step"], counters=True)
+    ref = oracle.render(c["volume"], c["cameras"], c["tf"], c["step"])
+    d = np.abs(img - ref["rgba"]).max()
+    log(f"c0 max |dRGBA| = {d:.3e}")
+    assert d <= TOL
+    assert ctr[1] == ref["counts"][..., 0].sum() == 65536 * 128
+    assert ctr[0] == ctr[1]
+    assert ctr[2] == 65536
+
+
+def _small_ct(dims=(96, 80, 72), seed=31):
+    return synth.ct_phantom_i16(*dims, seed=seed, n_soft=6, n_bone=4)
+
+
+@pytest.mark.parametrize("ert", [0.0, 0.99])
+def test_ct_perspective_skip_and_ert_match_oracle(ert):
+    vol = _small_ct()
+    dims = (96, 80, 72)
+    cams = synth.orbit_cameras(dims, 3, 32, 60.0, 120, 104)  # ragged: not a multiple of 16
+    tf = synth.tf1()
+    log(f"ct 96x80x72 persp 120x104 x3 skip ert={ert}")
+    img = gpu_render(vol, cams, tf, 0.5, ert=ert, use_skip=True)
+    ref = oracle.render(vol, cams, tf, 0.5, ert=ert)
+    un, nflag = compare_with_flags(img, ref["rgba"], ref["flags"], ert if ert else 1.0)
+    log(f"max unflagged |dRGBA| = {un:.3e}, flagged = {nflag}")
+    assert nflag <= 1e-3 * img[..., 0].size + 2
+
+
+def test_skip_is_bit_identical_to_no_skip():
+    vol = _small_ct()
+    cams = synth.orbit_cameras((96, 80, 72), 4, 33, 60.0, 96, 96)
+    tf = synth.tf1()
+    v = upload_volume(vol)
+    a, ca = gpu_render(vol, cams, tf, 0.5, ert=0.99, use_skip=False, counters=True, vol=v)
+    b, cb = gpu_render(vol, cams, tf, 0.5, ert=0.99, use_skip=True, counters=True, vol=v)
+    assert np.array_equal(a, b)
+    assert cb[0] < ca[0]  # skipping evaluated fewer samples
+    assert ca[1] == cb[1]
+
+
+def test_lattice_counts_match_oracle_exactly():
+    dims = (96, 80, 72)
+    cams = synth.orbit_cameras(dims, 5, 34, 60.0, 64, 48) + [synth.ortho_axis_camera(96, 64, 48)]
+    vol = _small_ct()
+    tf = synth.tf1()
+    for step in (0.5, 0.3, 1.7):
+        _, ctr = gpu_render(vol, cams, tf, step, counters=True)
+        want = oracle.lattice(cams, dims, step)
+        assert ctr[1] == want.sum(), (step, ctr[1], want.sum())
+        assert ctr[2] == (want > 0).sum()
+
+
+@pytest.mark.parametrize("dtype", ["u16", "i16", "f32"])
+def test_dtypes_and_odd_row_lengths(dtype):
+    """Odd nx exercises the unaligned packed-row path; all dtypes."""
+    rng = np.random.default_rng(35)
+    dims = (37, 29, 23)
+    base = synth.ct_phantom_i16(*dims, seed=36, n_soft=3, n_bone=2)
+    if dtype == "u16":
+        vol = (base.astype(np.int32) + 1024).clip(0, 4095).astype(np.uint16)
+        tf = synth.tf_from_points([(v + 1024, c) for v, c in synth.TF1_POINTS], 256, 0.0, 4080.0)
+    elif dtype == "i16":
+        vol = base
+        tf = synth.tf1()
+    else:
+        vol = (base.astype(np.float32) + rng.standard_normal(base.shape).astype(np.float32))
+        tf = synth.tf1()
+    cams = synth.orbit_cameras(dims, 2, 37, 55.0, 40, 33)
+    cams.append(synth.Camera(0, np.array([18.0, 14.0, -50.0]), np.array([0.8, 0.6, 0.0]),
+                             np.array([-0.6, 0.8, 0.0]), np.array([0.0, 0.0, 1.0]), ortho_w=50.0, ortho_h=41.0,
+                             width=40, height=33))
+    img = gpu_render(vol, cams, tf, 0.4, use_skip=True)
+    ref = oracle.render(vol, cams, tf, 0.4)
+    d = np.abs(img - ref["rgba"]).max()
+    log(f"{dtype}: max |dRGBA| = {d:.3e}")
+    assert d <= TOL
+
+
+def test_blocks_and_occupancy_exact():
+    for dims, edge in (((96, 80, 72), 16), ((37, 29, 23), 8), ((50, 17, 33), 16)):
+        vol = synth.ct_phantom_i16(*dims, seed=38, n_soft=4, n_bone=3)
+        v = upload_volume(vol)
+        b = vr.vr_build_blocks(v, edge)
+        mm = vr.vr_blocks_minmax(b).cpu().numpy().astype(np.float64)
+        want = oracle.blocks(vol, edge)
+        assert np.array_equal(mm, want)
+        for tf in (synth.tf1(), synth.tf_from_points([(-1024, (0, 0, 0, 0)), (-900, (1, 1, 1, 0.1)),
+                                                     (0, (1, 1, 1, 0.0)), (3056, (1, 1, 1, 0.0))],
+                                                    64, -1024.0, 3056.0)):
+            occ = vr.vr_block_occupancy(b, upload_tf(tf)).cpu().numpy()
+            assert np.array_equal(occ, oracle.occupancy(want, tf))
+
+
+def test_camera_inside_volume_and_misses():
+    vol = _small_ct()
+    dims = (96, 80, 72)
+    tf = synth.tf1()
+    inside = synth.Camera(1, np.array([48.0, 40.0, 30.0]), np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0]),
+                          np.array([0.0, 0.0, 1.0]), fov_y=np.deg2rad(90.0), width=48, height=40)
+    away = synth.Camera(1, np.array([48.0, 40.0, -30.0]), np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0]),
+                        np.array([0.0, 0.0, -1.0]), fov_y=np.deg2rad(40.0), width=48, height=40)
+    for cam in (inside, away):
+        img = gpu_render(vol, [cam], tf, 0.5, ert=0.99, use_skip=True)
+        ref = oracle.render(vol, [cam], tf, 0.5, ert=0.99)
+        compare_with_flags(img, ref["rgba"], ref["flags"], 0.99)
+    assert np.all(gpu_render(vol, [away], tf, 0.5) == 0.0)
+
+
+def test_tiny_volumes_and_single_pixel():
+    tf = synth.tf1()
+    for dims in ((1, 1, 1), (2, 3, 4), (5, 1, 7)):
+        vol = np.arange(np.prod(dims), dtype=np.int16).reshape(dims[::-1]) * 200 - 100
+        cams = synth.orbit_cameras(dims, 2, 39, 70.0, 17, 9) + synth.orbit_cameras(dims, 1, 40, 10.0, 1, 1)
+        for cam_set in (cams[:2], cams[2:]):
+            img = gpu_render(vol, cam_set, tf, 0.25, use_skip=True, block_edge=4)
+            ref = oracle.render(vol, cam_set, tf, 0.25)
+            assert np.abs(img - ref["rgba"]).max() <= TOL
+
+
+def test_many_views_span_launches():
+    """More views than one launch carries (16) and a view count not a
+    multiple of it."""
+    vol = _small_ct((48, 40, 36), 41)
+    dims = (48, 40, 36)
+    cams = synth.orbit_cameras(dims, 19, 42, 60.0, 24, 20)
+    tf = synth.tf1()
+    img = gpu_render(vol, cams, tf, 0.5, ert=0.95, use_skip=True)
+    ref = oracle.render(vol, cams, tf, 0.5, ert=0.95)
+    compare_with_flags(img, ref["rgba"], ref["flags"], 0.95)
+
+
+def test_invalid_arguments_raise_and_enqueue_nothing():
+    vol = upload_volume(_small_ct((16, 16, 16), 43))
+    t = upload_tf(synth.tf1())
+    cam = synth.orbit_cameras((16, 16, 16), 1, 44, 60.0, 8, 8)[0]
+    with pytest.raises(vr.VrError, match="VR_E_INVALID_ARG"):
+        vr.vr_render(vol, None, [cam], t, 0.0)
+    with pytest.raises(vr.VrError, match="VR_E_INVALID_ARG"):
+        vr.vr_render(vol, None, [cam], t, 0.5, use_skip=True)  # skip without blocks
+    other = vr.vr_build_blocks(upload_volume(_small_ct((16, 16, 16), 45)))
+    with pytest.raises(vr.VrError, match="another volume"):
+        vr.vr_render(vol, other, [cam], t, 0.5, use_skip=True)
+    bad = synth.Camera(1, np.array([np.nan, 0, 0]), cam.right, cam.up, cam.forward, fov_y=1.0, width=8, height=8)
+    with pytest.raises(vr.VrError, match="finite"):
+        vr.vr_render(vol, None, [bad], t, 0.5)
+    t_bad = vr.TF(t.table, 5.0, 5.0)
+    with pytest.raises(vr.VrError, match="v1 > v0"):
+        vr.vr_render(vol, None, [cam], t_bad, 0.5)
+
+
+def test_c1_full_size_sampled_pixels_and_invariants():
+    """The metric configuration at full size (512x512x400 int16 -> 1024^2,
+    skip, ERT 0.99) in the launch configuration the benchmark times: sampled
+    pixels against the oracle, lattice counts of every pixel exactly, skip and
+    ERT invariants over the whole frame."""
+    c = synth.config_c1()
+    log("c1: building full-size inputs")
+    v = upload_volume(c["volume"])
+    blocks = vr.vr_build_blocks(v, 16)
+    img, ctr = gpu_render(None, c["cameras"], c["tf"], c["step"], ert=c["ert"], use_skip=True, counters=True,
+                          vol=v, blocks=blocks)
+    noskip = gpu_render(None, c["cameras"], c["tf"], c["step"], ert=c["ert"], use_skip=False, vol=v)
+    assert np.array_equal(img, noskip)
+    noert = gpu_render(None, c["cameras"], c["tf"], c["step"], ert=0.0, use_skip=True, vol=v, blocks=blocks)
+    assert np.abs(noert - img).max() <= (1 - c["ert"]) + 1e-6
+    lat = oracle.lattice(c["cameras"], (512, 512, 400), c["step"])
+    assert ctr[1] == lat.sum()
+    assert ctr[2] == (lat > 0).sum()
+    log(f"c1 evaluated={ctr[0]} lattice={ctr[1]} hit={ctr[2]}")
+    pix = synth.sample_pixels(1, 1024, 1024, 3000, seed=46)
+    hit_rows = pix[lat[0, pix[:, 1], pix[:, 2]] > 0]
+    ref = oracle.render(c["volume"], c["cameras"], c["tf"], c["step"], ert=c["ert"], pixels=hit_rows)
+    got = img[hit_rows[:, 0], hit_rows[:, 1], hit_rows[:, 2]]
+    un, nflag = compare_with_flags(got, ref["rgba"], ref["flags"], c["ert"])
+    log(f"c1 sampled {len(hit_rows)} hit pixels: max unflagged |dRGBA| = {un:.3e}, flagged = {nflag}")
+    # the image is not trivially empty or saturated
+    assert 0.05 < (img[..., 3] > 0.5).mean() < 0.95

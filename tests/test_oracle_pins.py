@@ -137,7 +137,7 @@ def test_beer_lambert_oblique_rays(oracle_lib):
     tf = _constant_tf((0.5, 0.125, 0.375), sigma0)
     u = np.array([0.3, -0.5, 0.81])
     cam = synth.orbit_camera((n, n, n), u, 50.0, 24, 24)
-    step = 0.37
+    step = 0.375
     out = oracle.render(vol, [cam], tf, step)
     ns = out["counts"][0][..., 0]
     assert ns.max() > 0 and (ns == 0).any()
@@ -189,9 +189,9 @@ def test_oracle_matches_brute_force_tiny_volume(oracle_lib):
     # three oblique perspective rays
     pcam = synth.orbit_camera((4, 4, 4), np.array([0.4, 0.7, -0.6]), 40.0, 16, 16)
     pix = [(5, 6), (8, 8), (10, 4)]
-    outp = oracle.render(vol, [pcam], tf, 0.3)
+    outp = oracle.render(vol, [pcam], tf, 0.3125)
     for row, col in pix:
-        want, n = brute.brute_pixel(lists, pcam, row, col, 0.3, classify)
+        want, n = brute.brute_pixel(lists, pcam, row, col, 0.3125, classify)
         assert n == outp["counts"][0, row, col, 0] and n > 0
         np.testing.assert_allclose(outp["rgba"][0, row, col], want, rtol=0, atol=1e-12)
 
@@ -342,7 +342,7 @@ def test_grad_volume_matches_central_differences(oracle_lib):
     linear TF, where several subgradients are correct) shows up as FD values
     that disagree between two step sizes; such voxels are re-drawn."""
     vol, tf, cams, g = _grad_case()
-    step = 0.45
+    step = 0.4375
     gv, _ = oracle.grad(vol, cams, tf, step, g)
     rng = np.random.default_rng(107)
     scale = max(1.0, abs(gv).max())
@@ -362,7 +362,7 @@ def test_grad_volume_matches_central_differences(oracle_lib):
 
 def test_grad_tf_matches_central_differences(oracle_lib):
     vol, tf, cams, g = _grad_case()
-    step = 0.45
+    step = 0.4375
     _, gt = oracle.grad(vol, cams, tf, step, g)
     h = 2.0 ** -10
     for j in range(tf.K):
@@ -401,7 +401,7 @@ def test_grad_closed_form_homogeneous_medium(oracle_lib):
 def test_grad_with_ert_matches_fd_with_fixed_stop(oracle_lib):
     vol, tf, cams, g = _grad_case()
     tf.table[:, 3] *= 4.0
-    step, ert = 0.45, 0.7
+    step, ert = 0.4375, 0.75
     gv, _ = oracle.grad(vol, cams, tf, step, g, ert=ert)
     assert oracle.render(vol, cams, tf, step, ert=ert)["rgba"][..., 3].max() >= ert
     rng = np.random.default_rng(108)
