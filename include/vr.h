@@ -107,8 +107,9 @@ typedef struct {
  *                  under the TF (needs a vr_blocks of this volume).  The
  *                  image is bit-identical to rendering without skipping.
  *   counters       optional DEVICE uint64_t[4] that the render ADDS to:
- *                  [0] evaluated samples, [1] lattice samples, [2] rays that
- *                  hit the box, [3] reserved.  NULL = not counted. */
+ *                  [0] evaluated samples, [1] lattice samples, [2] rays with
+ *                  at least one lattice sample, [3] reserved.  NULL = not
+ *                  counted. */
 typedef struct {
     float step;
     float ert_threshold;

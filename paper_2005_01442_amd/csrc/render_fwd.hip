@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kWgSize) void k_render(const RenderArgs args) {
       __amdgpu_buffer_rsrc_t rs = make_rsrc(a.vol.data, a.vol.bytes);
       rgba = march<DT>(a.vol, s, a.tf, a.mc, r, rs, evaluated);
       lattice = (uint32_t)r.ns;
-      hit = 1;
+      hit = r.ns > 0 ? 1u : 0u;
     }
     float4 *o = reinterpret_cast<float4 *>(a.out);
     o[((size_t)st.view * a.H + row) * a.W + col] = rgba;
