@@ -132,7 +132,8 @@ typedef struct {
  * stay alive and unchanged while the blocks are used. */
 typedef struct vr_blocks vr_blocks;
 
-/* Build the block min/max for `vol` with edge `block_edge` (4..64).
+/* Build the block min/max for `vol` with edge `block_edge` (a power of two
+ * in [4, 64]).
  * Enqueued on `stream`; *out is valid immediately and usable on the same
  * stream.  Allocates device memory (8 bytes per block).
  * Errors: VR_E_INVALID_ARG (null/invalid volume, edge out of range),

@@ -3,6 +3,7 @@
 // error reporting.  Kernels live in the .hip files.
 #include <cmath>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -64,6 +65,8 @@ vr_status check_volume(const vr_volume *v, VolConst *out) {
     out->minmax = nullptr;
     out->nbx = out->nby = out->nbz = 0;
     out->edge = 0;
+    out->edge_shift = 0;
+    out->row_even = (v->nx % 2) == 0 ? 1 : 0;
   }
   return VR_OK;
 }
@@ -138,7 +141,17 @@ vr_status attach_blocks(const vr_blocks *b, const vr_volume *v, VolConst *vc) {
   vc->nby = b->nby;
   vc->nbz = b->nbz;
   vc->edge = b->edge;
+  vc->edge_shift = __builtin_ctz((unsigned)b->edge);
   return VR_OK;
+}
+
+int32_t chunk_edge_setting() {
+  static const int32_t ce = [] {
+    const char *e = std::getenv("VR_CHUNK_EDGE");
+    int v = e ? std::atoi(e) : kDefaultChunkEdge;
+    return (v == 1 || v == 2 || v == 4 || v == 8) ? v : kDefaultChunkEdge;
+  }();
+  return ce;
 }
 
 // Validate the common arguments of vr_render / vr_render_backward and fill
@@ -162,6 +175,7 @@ static vr_status prepare(const vr_volume *vol, const vr_blocks *blocks, const vr
   a->counters = reinterpret_cast<unsigned long long *>(p->counters);
   a->W = cams[0].width;
   a->H = cams[0].height;
+  a->chunk_edge = chunk_edge_setting();
   return VR_OK;
 }
 
@@ -181,7 +195,8 @@ vr_status vr_build_blocks(const vr_volume *vol, int32_t block_edge, void *stream
   VolConst vc;
   vr_status s = check_volume(vol, &vc);
   if (s) return s;
-  if (block_edge < 4 || block_edge > 64) return fail(VR_E_INVALID_ARG, "block edge %d outside [4, 64]", block_edge);
+  if (block_edge < 4 || block_edge > 64 || (block_edge & (block_edge - 1)) != 0)
+    return fail(VR_E_INVALID_ARG, "block edge %d is not a power of two in [4, 64]", block_edge);
   vr_blocks *b = new (std::nothrow) vr_blocks();
   if (!b) return fail(VR_E_OOM, "host allocation failed");
   b->data = vol->data;
@@ -204,6 +219,7 @@ vr_status vr_build_blocks(const vr_volume *vol, int32_t block_edge, void *stream
   vc.nby = b->nby;
   vc.nbz = b->nbz;
   vc.edge = block_edge;
+  vc.edge_shift = __builtin_ctz((unsigned)block_edge);
   e = launch_block_minmax(vc, b->minmax, (hipStream_t)stream);
   if (e != hipSuccess) {
     (void)hipFree(b->minmax);
@@ -248,6 +264,7 @@ vr_status vr_block_occupancy(const vr_blocks *b, const vr_tf *tf, uint8_t *occ, 
   vc.nby = b->nby;
   vc.nbz = b->nbz;
   vc.edge = b->edge;
+  vc.edge_shift = __builtin_ctz((unsigned)b->edge);
   hipError_t e = launch_block_occupancy(vc, tc, occ, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "block occupancy launch");
   return VR_OK;

@@ -45,6 +45,8 @@ __device__ inline void march_backward(const VolConst &v, const TfShared &s, floa
   const float Tend = 1.0f - fin.w;
   const int ns = r.hit ? r.ns : 0;
   int k = 0;
+  int cur_block = -1;  // last block looked up and whether it is occupied
+  bool cur_occ = false;
   while (k < ns) {
     float sk = ((float)k + 0.5f) * mc.step;
     float px = fmaf(sk, r.d[0], r.p0[0]);
@@ -53,8 +55,11 @@ __device__ inline void march_backward(const VolConst &v, const TfShared &s, floa
     if (mc.skip) {
       int bc[3];
       int b = block_of(v, px, py, pz, bc);
-      bool occ = block_occupied(v, s, tf, b);
-      while (!occ) {
+      if (b != cur_block) {
+        cur_block = b;
+        cur_occ = block_occupied(v, s, tf, b);
+      }
+      while (!cur_occ) {
         k = leap_target(v, r, bc, mc.step, k);
         if (k >= ns) break;
         sk = ((float)k + 0.5f) * mc.step;
@@ -62,7 +67,10 @@ __device__ inline void march_backward(const VolConst &v, const TfShared &s, floa
         py = fmaf(sk, r.d[1], r.p0[1]);
         pz = fmaf(sk, r.d[2], r.p0[2]);
         b = block_of(v, px, py, pz, bc);
-        occ = block_occupied(v, s, tf, b);
+        if (b != cur_block) {
+          cur_block = b;
+          cur_occ = block_occupied(v, s, tf, b);
+        }
       }
       if (k >= ns) break;
     }
@@ -113,7 +121,7 @@ __global__ __launch_bounds__(kWgSize) void k_render_bwd(const BackwardArgs args)
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const BackwardArgs &a = kernarg<BackwardArgs>();
   const RenderArgs &ra = a.r;
-  SuperTile st = map_workgroup(blockIdx.x, ra.W, ra.H, ra.n_views);
+  SuperTile st = map_workgroup(blockIdx.x, ra.W, ra.H, ra.n_views, ra.chunk_edge);
   if (!st.valid) return;  // uniform over the workgroup
   const int K = ra.tf.K;
   float *sgtf = a.grad_tf ? reinterpret_cast<float *>(lds + tf_lds_bytes(K)) : nullptr;
@@ -146,7 +154,7 @@ __global__ __launch_bounds__(kWgSize) void k_render_bwd(const BackwardArgs args)
 
 hipError_t launch_render_backward(const BackwardArgs &a, hipStream_t s) {
   const RenderArgs &ra = a.r;
-  int64_t grid = grid_size_for(ra.W, ra.H, ra.n_views);
+  int64_t grid = grid_size_for(ra.W, ra.H, ra.n_views, ra.chunk_edge);
   uint32_t lds = tf_lds_bytes(ra.tf.K) + (a.grad_tf ? (uint32_t)ra.tf.K * 16u : 0u);
   switch (ra.vol.dtype) {
   case kU16: hipLaunchKernelGGL(k_render_bwd<kU16>, dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;

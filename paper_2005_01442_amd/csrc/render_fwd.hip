@@ -20,6 +20,8 @@ __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfCon
   const bool ert_on = mc.ert > 0.0f && mc.ert < 1.0f;
   const int ns = r.hit ? r.ns : 0;
   int k = 0;
+  int cur_block = -1;  // last block looked up and whether it is occupied
+  bool cur_occ = false;
   while (k < ns) {
     float sk = ((float)k + 0.5f) * mc.step;
     float px = fmaf(sk, r.d[0], r.p0[0]);
@@ -28,8 +30,11 @@ __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfCon
     if (mc.skip) {
       int bc[3];
       int b = block_of(v, px, py, pz, bc);
-      bool occ = block_occupied(v, s, tf, b);
-      while (!occ) {
+      if (b != cur_block) {
+        cur_block = b;
+        cur_occ = block_occupied(v, s, tf, b);
+      }
+      while (!cur_occ) {
         k = leap_target(v, r, bc, mc.step, k);
         if (k >= ns) break;
         sk = ((float)k + 0.5f) * mc.step;
@@ -37,7 +42,10 @@ __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfCon
         py = fmaf(sk, r.d[1], r.p0[1]);
         pz = fmaf(sk, r.d[2], r.p0[2]);
         b = block_of(v, px, py, pz, bc);
-        occ = block_occupied(v, s, tf, b);
+        if (b != cur_block) {
+          cur_block = b;
+          cur_occ = block_occupied(v, s, tf, b);
+        }
       }
       if (k >= ns) break;
     }
@@ -61,7 +69,7 @@ template <int DT>
 __global__ __launch_bounds__(kWgSize) void k_render(const RenderArgs args) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const RenderArgs &a = kernarg<RenderArgs>();
-  SuperTile st = map_workgroup(blockIdx.x, a.W, a.H, a.n_views);
+  SuperTile st = map_workgroup(blockIdx.x, a.W, a.H, a.n_views, a.chunk_edge);
   if (!st.valid) return;  // uniform over the workgroup
   TfShared s = carve_tf(lds, a.tf.K);
   load_tf(s, a.tf);
@@ -90,7 +98,7 @@ __global__ __launch_bounds__(kWgSize) void k_render(const RenderArgs args) {
 }
 
 hipError_t launch_render(const RenderArgs &a, hipStream_t s) {
-  int64_t grid = grid_size_for(a.W, a.H, a.n_views);
+  int64_t grid = grid_size_for(a.W, a.H, a.n_views, a.chunk_edge);
   uint32_t lds = tf_lds_bytes(a.tf.K);
   switch (a.vol.dtype) {
   case kU16: hipLaunchKernelGGL(k_render<kU16>, dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;

@@ -26,7 +26,7 @@ constexpr int kWgSize = 256;
 constexpr int kMaxTf = 1024;          // max TF nodes (LDS: 16 KiB table)
 constexpr int kMaxCamsPerLaunch = 16; // cameras carried in kernel arguments
 constexpr int kXcds = 8;              // MI355X: 8 accelerator complex dies
-constexpr int kChunkEdge = 8;         // super-tiles per chunk edge (XCD mapping)
+constexpr int kDefaultChunkEdge = 4;  // super-tiles per chunk edge (XCD mapping)
 
 enum Dtype : int32_t { kU16 = 0, kI16 = 1, kF32 = 2 };
 
@@ -45,6 +45,8 @@ struct VolConst {
   uint32_t bytes;           // total bytes (< 4 GiB)
   const float2 *minmax;     // per-block (min, max) or nullptr
   int32_t nbx, nby, nbz, edge;
+  int32_t edge_shift;       // log2(edge)
+  int32_t row_even;         // nx even: every x-row starts at an even element
 };
 
 struct TfConst {
@@ -228,6 +230,18 @@ template <int DT> struct Vox;
 
 template <> struct Vox<kI16> {
   static constexpr int kBytes = 2;
+  // even-length rows: byte offset of the pair-aligned window `voff` (per
+  // lane), row offset `soff` (uniform, in the SGPR soffset), shift `sh`
+  __device__ static inline void row_s(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t sh,
+                                      float t[4]) {
+    u32x3 v = __builtin_amdgcn_raw_buffer_load_b96(r, voff, soff, 0);
+    uint32_t lo = __builtin_amdgcn_alignbit(v.y, v.x, sh);
+    uint32_t hi = __builtin_amdgcn_alignbit(v.z, v.y, sh);
+    t[0] = (float)(int16_t)(lo & 0xffffu);
+    t[1] = (float)((int32_t)lo >> 16);
+    t[2] = (float)(int16_t)(hi & 0xffffu);
+    t[3] = (float)((int32_t)hi >> 16);
+  }
   // four consecutive taps starting at element e; e_al = e & ~1 even
   __device__ static inline void row(__amdgpu_buffer_rsrc_t r, uint32_t e, float t[4]) {
     uint32_t ea = e & ~1u;
@@ -249,6 +263,16 @@ template <> struct Vox<kI16> {
 
 template <> struct Vox<kU16> {
   static constexpr int kBytes = 2;
+  __device__ static inline void row_s(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t sh,
+                                      float t[4]) {
+    u32x3 v = __builtin_amdgcn_raw_buffer_load_b96(r, voff, soff, 0);
+    uint32_t lo = __builtin_amdgcn_alignbit(v.y, v.x, sh);
+    uint32_t hi = __builtin_amdgcn_alignbit(v.z, v.y, sh);
+    t[0] = (float)(lo & 0xffffu);
+    t[1] = (float)(lo >> 16);
+    t[2] = (float)(hi & 0xffffu);
+    t[3] = (float)(hi >> 16);
+  }
   __device__ static inline void row(__amdgpu_buffer_rsrc_t r, uint32_t e, float t[4]) {
     uint32_t ea = e & ~1u;
     u32x3 v = __builtin_amdgcn_raw_buffer_load_b96(r, ea * 2u, 0, 0);
@@ -268,6 +292,14 @@ template <> struct Vox<kU16> {
 
 template <> struct Vox<kF32> {
   static constexpr int kBytes = 4;
+  __device__ static inline void row_s(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t,
+                                      float t[4]) {
+    f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    t[0] = v.x;
+    t[1] = v.y;
+    t[2] = v.z;
+    t[3] = v.w;
+  }
   __device__ static inline void row(__amdgpu_buffer_rsrc_t r, uint32_t e, float t[4]) {
     f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, e * 4u, 0, 0));
     t[0] = v.x;
@@ -312,6 +344,30 @@ __device__ inline float reconstruct(__amdgpu_buffer_rsrc_t rs, const VolConst &v
   if (inner) {
     uint32_t e0 = ((uint32_t)(s.iz - 1) * (uint32_t)ny + (uint32_t)(s.iy - 1)) * (uint32_t)nx + (uint32_t)(s.ix - 1);
     inner = Vox<DT>::window_ok(e0 + 3u * nxy + 3u * (uint32_t)nx, nvox);
+    if (inner && (DT == kF32 || v.row_even)) {
+      // every row has e0's parity: one per-lane window offset, the row
+      // offsets are uniform and travel in the load's SGPR soffset
+      const uint32_t kb = (uint32_t)Vox<DT>::kBytes;
+      const uint32_t voff = (DT == kF32) ? e0 * 4u : (e0 & ~1u) * 2u;
+      const uint32_t sh = (e0 & 1u) * 16u;
+      const uint32_t rs_x = (uint32_t)nx * kb, rs_xy = nxy * kb;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        float accy = 0.0f;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          float t[4];
+          Vox<DT>::row_s(rs, voff, (uint32_t)c * rs_xy + (uint32_t)b * rs_x, sh, t);
+          float r = s.wx[0] * t[0];
+          r = fmaf(s.wx[1], t[1], r);
+          r = fmaf(s.wx[2], t[2], r);
+          r = fmaf(s.wx[3], t[3], r);
+          accy = fmaf(s.wy[b], r, accy);
+        }
+        acc = fmaf(s.wz[c], accy, acc);
+      }
+      return acc;
+    }
     if (inner) {
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
@@ -389,9 +445,9 @@ __device__ inline int block_of(const VolConst &v, float px, float py, float pz, 
   int cx = min(max((int)floorf(px), 0), v.nx - 1);
   int cy = min(max((int)floorf(py), 0), v.ny - 1);
   int cz = min(max((int)floorf(pz), 0), v.nz - 1);
-  bc[0] = cx / v.edge;
-  bc[1] = cy / v.edge;
-  bc[2] = cz / v.edge;
+  bc[0] = cx >> v.edge_shift;
+  bc[1] = cy >> v.edge_shift;
+  bc[2] = cz >> v.edge_shift;
   return bc[0] + v.nbx * (bc[1] + v.nby * bc[2]);
 }
 
@@ -431,43 +487,59 @@ __device__ inline bool block_occupied(const VolConst &v, const TfShared &s, cons
 // ---------------------------------------------------------------------------
 // Tile mapping.  A workgroup owns a 16x16 super-tile; wavefront w the 8x8
 // sub-tile (w & 1, w >> 1); lane l the pixel (l & 7, l >> 3) of it.
-// Workgroups are dispatched round-robin over the XCDs; the mapping gives each
-// XCD whole 8x8-super-tile chunks (128x128 pixels) in turn, so a chunk's rays
-// share one L2 while the chunks of an image interleave over all XCDs.
+// Super-tiles are grouped in chunks of ce x ce (ce = 4: 64x64 pixels).  The
+// hardware hands workgroup i to XCD i mod 8; workgroup i works on chunk
+// g = 8 (i / 8 / ce^2) + (i mod 8), so XCD x runs the chunks g = x (mod 8) one
+// after another and the workgroups of a chunk share that XCD's L2.  Chunks
+// are numbered along a Morton curve (over the chunk grid padded to a power of
+// two), so the chunks of one XCD are spread evenly over the image and every
+// XCD gets a similar share of the dense centre.
 // ---------------------------------------------------------------------------
 struct SuperTile {
   int view, sx, sy;  // super-tile coordinates within the view
   bool valid;
 };
 
-__host__ __device__ inline int64_t chunk_count(int W, int H, int views) {
-  int stx = (W + kSuperEdge - 1) / kSuperEdge, sty = (H + kSuperEdge - 1) / kSuperEdge;
-  int cx = (stx + kChunkEdge - 1) / kChunkEdge, cy = (sty + kChunkEdge - 1) / kChunkEdge;
-  return (int64_t)cx * cy * views;
+__host__ __device__ inline int pow2_at_least(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
 }
 
-__host__ __device__ inline int64_t grid_size_for(int W, int H, int views) {
-  int64_t nc = chunk_count(W, H, views);
-  int64_t per = kChunkEdge * kChunkEdge;
+__host__ __device__ inline int64_t grid_size_for(int W, int H, int views, int ce) {
+  int stx = (W + kSuperEdge - 1) / kSuperEdge, sty = (H + kSuperEdge - 1) / kSuperEdge;
+  int cx = (stx + ce - 1) / ce, cy = (sty + ce - 1) / ce;
+  int p = pow2_at_least(cx > cy ? cx : cy);
+  int64_t nc = (int64_t)p * p * views;
+  int64_t per = (int64_t)ce * ce;
   return ((nc + kXcds - 1) / kXcds) * kXcds * per;
 }
 
-__device__ inline SuperTile map_workgroup(int64_t wg, int W, int H, int views) {
+__host__ __device__ inline int compact_bits(uint32_t m) {
+  m &= 0x55555555u;
+  m = (m | (m >> 1)) & 0x33333333u;
+  m = (m | (m >> 2)) & 0x0f0f0f0fu;
+  m = (m | (m >> 4)) & 0x00ff00ffu;
+  m = (m | (m >> 8)) & 0x0000ffffu;
+  return (int)m;
+}
+
+__device__ inline SuperTile map_workgroup(int64_t wg, int W, int H, int views, int ce) {
   SuperTile st;
-  const int per = kChunkEdge * kChunkEdge;
-  int64_t xcd = wg % kXcds, r = wg / kXcds;
-  int64_t chunk = (r / per) * kXcds + xcd;
-  int pos = (int)(r % per);
-  int stx = (W + kSuperEdge - 1) / kSuperEdge, sty = (H + kSuperEdge - 1) / kSuperEdge;
-  int cx = (stx + kChunkEdge - 1) / kChunkEdge, cy = (sty + kChunkEdge - 1) / kChunkEdge;
-  int64_t nc = (int64_t)cx * cy * views;
-  st.valid = chunk < nc;
-  int64_t per_view = (int64_t)cx * cy;
-  st.view = (int)(chunk / per_view);
-  int64_t c = chunk % per_view;
-  st.sx = (int)(c % cx) * kChunkEdge + pos % kChunkEdge;
-  st.sy = (int)(c / cx) * kChunkEdge + pos / kChunkEdge;
-  st.valid = st.valid && st.sx < stx && st.sy < sty;
+  const int per = ce * ce;
+  const int64_t xcd = wg % kXcds, r = wg / kXcds;
+  const int64_t g = (r / per) * kXcds + xcd;
+  const int pos = (int)(r % per);
+  const int stx = (W + kSuperEdge - 1) / kSuperEdge, sty = (H + kSuperEdge - 1) / kSuperEdge;
+  const int cx = (stx + ce - 1) / ce, cy = (sty + ce - 1) / ce;
+  const int p = pow2_at_least(cx > cy ? cx : cy);
+  const int64_t per_view = (int64_t)p * p;
+  st.view = (int)(g / per_view);
+  const uint32_t m = (uint32_t)(g % per_view);
+  const int ccx = compact_bits(m), ccy = compact_bits(m >> 1);
+  st.sx = ccx * ce + pos % ce;
+  st.sy = ccy * ce + pos / ce;
+  st.valid = st.view < views && ccx < cx && ccy < cy && st.sx < stx && st.sy < sty;
   return st;
 }
 

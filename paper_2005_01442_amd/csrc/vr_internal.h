@@ -18,7 +18,7 @@ struct RenderArgs {
   MarchConst mc;
   float *out;                      // RGBA of the first view of this launch
   unsigned long long *counters;    // optional [evaluated, lattice, hit, -]
-  int32_t W, H, n_views, pad;
+  int32_t W, H, n_views, chunk_edge;
   CamConst cams[kMaxCamsPerLaunch];
 };
 
@@ -29,6 +29,10 @@ struct BackwardArgs {
   float *grad_vol;         // nullptr or nx*ny*nz
   float *grad_tf;          // nullptr or K*4
 };
+
+// Chunk edge of the workgroup -> tile mapping (VR_CHUNK_EDGE overrides: 1, 2,
+// 4 or 8).
+int32_t chunk_edge_setting();
 
 hipError_t launch_render(const RenderArgs &a, hipStream_t s);
 hipError_t launch_render_backward(const BackwardArgs &a, hipStream_t s);

@@ -113,6 +113,8 @@ def test_validation_without_device(abi):
     out = ctypes.c_void_p()
     rc = L.vr_build_blocks(ctypes.byref(abi.vr_volume(4096, abi.VR_I16, 0, 8, 8, 8)), 2, None, ctypes.byref(out))
     assert rc == 1 and b"block edge" in L.vr_last_error()
+    rc = L.vr_build_blocks(ctypes.byref(abi.vr_volume(4096, abi.VR_I16, 0, 8, 8, 8)), 12, None, ctypes.byref(out))
+    assert rc == 1 and b"power of two" in L.vr_last_error()
 
 
 def test_serve_config_validation_without_device(abi):
