@@ -61,6 +61,20 @@ def parse():
     return ap.parse_args()
 
 
+def kernel_source_hash():
+    """sha256 over the HIP sources; stored PMC traffic is valid only for them."""
+    import hashlib
+
+    d = os.path.join(ROOT, "paper_2005_01442_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
 def time_steps(fn, steps, warmup, torch):
     """W untimed steps, then exactly K steps bracketed by device syncs; per
     step HIP events on the current (launch) stream."""
@@ -265,7 +279,8 @@ def main():
     if os.path.exists(args.traffic_json):
         try:
             tj = json.load(open(args.traffic_json))
-            traffic = tj.get("bytes_per_launch")
+            if tj.get("kernel_source_sha256") == kernel_source_hash():
+                traffic = tj.get("bytes_per_launch")
         except Exception:
             traffic = None
     result["roofline"] = {
