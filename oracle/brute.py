@@ -118,10 +118,13 @@ def composite_ray(vol, o, d, step, classify, ert=0.0):
     tin, tout = hit
     C = [0.0, 0.0, 0.0]
     T = 1.0
+    # samples at t_k = (k + 1/2) step from the origin, t_in < t_k < t_out
     k = 0
+    while (k + 0.5) * step <= tin:
+        k += 1
     n = 0
-    while (k + 0.5) * step < tout - tin:
-        t = tin + (k + 0.5) * step
+    while (k + 0.5) * step < tout:
+        t = (k + 0.5) * step
         p = [o[c] + t * d[c] for c in range(3)]
         v = float(reconstruct(vol, p))
         r, g, b, sigma = classify(v)

@@ -292,14 +292,26 @@ typedef struct {
     int edge;
 } or_ctx;
 
-/* Sample lattice: midpoints t_k = t_in + (k + 1/2) step for every k >= 0    */
-/* with (k + 1/2) step < t_out - t_in.  Every segment has the full length.   */
+/* Sample lattice: the ray moves from its origin (the observer) with the     */
+/* fixed step, sampling at t_k = (k + 1/2) step; the samples of a ray are    */
+/* every k >= 0 with t_in < t_k < t_out.  Returns their count and the first  */
+/* index k0.  Rays of neighbouring pixels thus share sample distances.       */
+static long or_lattice(double tin, double tout, double step, long *k0_out)
+{
+    long k = (long)floor(tin / step - 0.5);
+    if (k < 0) k = 0;
+    while (k > 0 && ((double)(k - 1) + 0.5) * step > tin) --k;
+    while (((double)k + 0.5) * step <= tin) ++k;
+    long k0 = k;
+    while (((double)k + 0.5) * step < tout) ++k;
+    *k0_out = k0;
+    return k - k0;
+}
+
 static long or_lattice_count(double tin, double tout, double step)
 {
-    double L = tout - tin;
-    long k = 0;
-    while (((double)k + 0.5) * step < L) ++k;
-    return k;
+    long k0;
+    return or_lattice(tin, tout, step, &k0);
 }
 
 static int or_block_occupied(const or_ctx *cx, const double p[3])
@@ -324,13 +336,14 @@ static void or_trace(const or_ctx *cx, long view, long row, long col, double rgb
     const double *cam = cx->cams + 16 * view;
     or_ray(cam, cx->W, cx->H, col, row, o, d);
     if (!or_clip(o, d, cx->vol->nx, cx->vol->ny, cx->vol->nz, &tin, &tout)) return;
-    long ns = or_lattice_count(tin, tout, cx->step);
+    long k0;
+    long ns = or_lattice(tin, tout, cx->step, &k0);
     counts[0] = ns;
     int ert_on = cx->ert > 0.0 && cx->ert < 1.0;
     double C[3] = {0.0, 0.0, 0.0}, T = 1.0;
     or_sample s;
-    for (long k = 0; k < ns; ++k) {
-        double t = tin + ((double)k + 0.5) * cx->step;
+    for (long k = k0; k < k0 + ns; ++k) {
+        double t = ((double)k + 0.5) * cx->step;
         double p[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
         if (cx->occ && !or_block_occupied(cx, p)) continue;
         counts[1]++;
@@ -448,7 +461,8 @@ int oracle_grad(const void *data, int dtype, long nx, long ny, long nz, const do
             double o[3], d[3], tin, tout;
             or_ray(cams + 16 * view, W, H, col, row, o, d);
             if (!or_clip(o, d, nx, ny, nz, &tin, &tout)) continue;
-            long ns = or_lattice_count(tin, tout, step);
+            long k0;
+            long ns = or_lattice(tin, tout, step, &k0);
             if (ns > cap) {
                 free(rec);
                 cap = ns;
@@ -457,8 +471,8 @@ int oracle_grad(const void *data, int dtype, long nx, long ny, long nz, const do
             /* forward, storing every evaluated sample */
             long n = 0;
             double T = 1.0;
-            for (long k = 0; k < ns; ++k) {
-                double t = tin + ((double)k + 0.5) * step;
+            for (long k = k0; k < k0 + ns; ++k) {
+                double t = ((double)k + 0.5) * step;
                 double p[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
                 if (occ && !or_block_occupied(&cx, p)) continue;
                 or_rec *r = &rec[n++];

@@ -42,9 +42,9 @@ def sources():
     )
 
 
-def _compile(src):
-    obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *COMMON, "-c", src, "-o", obj]
+def _compile(src, extra=(), build_dir=BUILD_DIR):
+    obj = os.path.join(build_dir, os.path.basename(src) + ".o")
+    cmd = [HIPCC, *COMMON, *extra, "-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd += ["-pthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -56,20 +56,23 @@ def _compile(src):
     return obj, errs
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD_DIR, exist_ok=True)
+def build(verbose: bool = False, extra=(), out: str = LIB) -> str:
+    """Compile and link; ``extra`` adds compiler flags, ``out`` names the
+    library (tuning variants are built beside the default one)."""
+    build_dir = BUILD_DIR if out == LIB else os.path.join(BUILD_DIR, os.path.basename(out))
+    os.makedirs(build_dir, exist_ok=True)
     srcs = sources()
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        results = list(ex.map(_compile, srcs))
+        results = list(ex.map(lambda src: _compile(src, tuple(extra), build_dir), srcs))
     for _, errs in results:
         if verbose and errs.strip():
             print(errs, file=sys.stderr)
     objs = [o for o, _ in results]
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

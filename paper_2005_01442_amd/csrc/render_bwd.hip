@@ -43,37 +43,7 @@ __device__ inline void march_backward(const VolConst &v, const TfShared &s, floa
   const float sl2 = mc.step * 1.4426950408889634f;
   const bool ert_on = mc.ert > 0.0f && mc.ert < 1.0f;
   const float Tend = 1.0f - fin.w;
-  const int ns = r.hit ? r.ns : 0;
-  int k = 0;
-  int cur_block = -1;  // last block looked up and whether it is occupied
-  bool cur_occ = false;
-  while (k < ns) {
-    float sk = ((float)k + 0.5f) * mc.step;
-    float px = fmaf(sk, r.d[0], r.p0[0]);
-    float py = fmaf(sk, r.d[1], r.p0[1]);
-    float pz = fmaf(sk, r.d[2], r.p0[2]);
-    if (mc.skip) {
-      int bc[3];
-      int b = block_of(v, px, py, pz, bc);
-      if (b != cur_block) {
-        cur_block = b;
-        cur_occ = block_occupied(v, s, tf, b);
-      }
-      while (!cur_occ) {
-        k = leap_target(v, r, bc, mc.step, k);
-        if (k >= ns) break;
-        sk = ((float)k + 0.5f) * mc.step;
-        px = fmaf(sk, r.d[0], r.p0[0]);
-        py = fmaf(sk, r.d[1], r.p0[1]);
-        pz = fmaf(sk, r.d[2], r.p0[2]);
-        b = block_of(v, px, py, pz, bc);
-        if (b != cur_block) {
-          cur_block = b;
-          cur_occ = block_occupied(v, s, tf, b);
-        }
-      }
-      if (k >= ns) break;
-    }
+  auto visit = [&](int, float px, float py, float pz) -> bool {
     Stencil st = make_stencil(px, py, pz);
     float val = reconstruct<DT>(rs, v, st);
     Classified q = classify(s, tf.K, tf.v0, tf.scale, val);
@@ -111,9 +81,9 @@ __device__ inline void march_backward(const VolConst &v, const TfShared &s, floa
       dv *= tf.scale;
       if (dv != 0.0f) scatter_taps(grad_vol, v, st, dv);
     }
-    ++k;
-    if (ert_on && (1.0f - T) >= mc.ert) break;
-  }
+    return !(ert_on && (1.0f - T) >= mc.ert);
+  };
+  walk(v, s, tf, mc, r, visit);
 }
 
 template <int DT>
@@ -131,18 +101,23 @@ __global__ __launch_bounds__(kWgSize) void k_render_bwd(const BackwardArgs args)
   load_tf(s, ra.tf);  // ends with a barrier, which also orders the zeroing
   int col, row;
   pixel_of(st.sx, st.sy, col, row);
+  // every lane enters the march (it steps the wavefront in unison); lanes
+  // outside the image or without a gradient carry an empty ray
+  Ray r;
+  r.hit = false;
+  r.ns = 0;
+  r.k0 = 0;
+  float4 g = make_float4(0.0f, 0.0f, 0.0f, 0.0f), fin = g;
   if (col < ra.W && row < ra.H) {
     size_t pix = ((size_t)st.view * ra.H + row) * ra.W + col;
-    float4 g = reinterpret_cast<const float4 *>(a.grad_rgba)[pix];
+    g = reinterpret_cast<const float4 *>(a.grad_rgba)[pix];
     if (g.x != 0.0f || g.y != 0.0f || g.z != 0.0f || g.w != 0.0f) {
-      Ray r = setup_ray(ra.cams[st.view], col, row, ra.vol.nx, ra.vol.ny, ra.vol.nz, ra.mc.step);
-      if (r.hit) {
-        float4 fin = reinterpret_cast<const float4 *>(a.out_rgba)[pix];
-        __amdgpu_buffer_rsrc_t rs = make_rsrc(ra.vol.data, ra.vol.bytes);
-        march_backward<DT>(ra.vol, s, sgtf, ra.tf, ra.mc, r, rs, g, fin, a.grad_vol);
-      }
+      r = setup_ray(ra.cams[st.view], col, row, ra.vol.nx, ra.vol.ny, ra.vol.nz, ra.mc.step);
+      fin = reinterpret_cast<const float4 *>(a.out_rgba)[pix];
     }
   }
+  __amdgpu_buffer_rsrc_t rs = make_rsrc(ra.vol.data, ra.vol.bytes);
+  march_backward<DT>(ra.vol, s, sgtf, ra.tf, ra.mc, r, rs, g, fin, a.grad_vol);
   if (sgtf) {
     __syncthreads();
     for (int j = threadIdx.x; j < 4 * K; j += kWgSize) {

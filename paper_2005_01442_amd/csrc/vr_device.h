@@ -141,15 +141,23 @@ __device__ inline bool range_occupied(const TfShared &s, int K, float v0, float 
 struct Ray {
   float p0[3];  // entry point o + t_in d, rounded to fp32
   float d[3];   // unit direction, rounded to fp32
-  int32_t ns;   // lattice samples
+  float s0;     // t_{k0} - t_in, in (0, step]
+  int32_t k0;   // first lattice index: smallest k with (k + 1/2) step > t_in
+  int32_t ns;   // lattice samples: k0 <= k < k0 + ns
   bool hit;
 };
 
+// The ray moves from its origin with the fixed step; lattice samples sit at
+// t_k = (k + 1/2) step, every k >= 0 with t_in < t_k < t_out.  Rays of
+// neighbouring pixels share sample distances, so a wavefront's samples at one
+// k lie on a thin slab.  Sample k is at p0 + (s0 + (k - k0) step) d.
 __device__ inline Ray setup_ray(const CamConst &c, int col, int row, int nx, int ny, int nz, float step32) {
 #pragma clang fp contract(off)
   Ray r;
   r.hit = false;
   r.ns = 0;
+  r.k0 = 0;
+  r.s0 = 0.0f;
   double sx = 2.0 * ((double)col + 0.5) / (double)c.W - 1.0;
   double sy = 1.0 - 2.0 * ((double)row + 0.5) / (double)c.H;
   double o[3], d[3];
@@ -190,15 +198,22 @@ __device__ inline Ray setup_ray(const CamConst &c, int col, int row, int nx, int
   }
   double te = t0 > 0.0 ? t0 : 0.0;
   if (!(t1 > te)) return r;
-  // lattice: #{k >= 0 : (k + 1/2) step < t1 - te}
-  double L = t1 - te;
+  // lattice: smallest k >= 0 with (k + 1/2) step > te, then every k while
+  // (k + 1/2) step < t1 (the predicates of the definition, in FP64)
   double st = (double)step32;
-  double est = ceil(L / st - 0.5);
+  double est = floor(te / st - 0.5);
   long long k = est > 0.0 ? (long long)est : 0;
-  while (k > 0 && ((double)(k - 1) + 0.5) * st >= L) --k;
-  while (((double)k + 0.5) * st < L) ++k;
-  r.ns = (int32_t)k;
-  r.hit = true;
+  while (k > 0 && ((double)(k - 1) + 0.5) * st > te) --k;
+  while (((double)k + 0.5) * st <= te) ++k;
+  long long k0 = k;
+  double est1 = ceil(t1 / st - 0.5);
+  long long k1 = est1 > (double)k0 ? (long long)est1 : k0;
+  while (k1 > k0 && ((double)(k1 - 1) + 0.5) * st >= t1) --k1;
+  while (((double)k1 + 0.5) * st < t1) ++k1;
+  r.k0 = (int32_t)k0;
+  r.ns = (int32_t)(k1 - k0);
+  r.hit = r.ns > 0;
+  r.s0 = (float)(((double)k0 + 0.5) * st - te);
   for (int a = 0; a < 3; ++a) {
     r.p0[a] = (float)(o[a] + te * d[a]);
     r.d[a] = (float)d[a];
@@ -451,9 +466,9 @@ __device__ inline int block_of(const VolConst &v, float px, float py, float pz, 
   return bc[0] + v.nbx * (bc[1] + v.nby * bc[2]);
 }
 
-// Every sample k' with k <= k' < result lies strictly inside the current
-// block: positions fl(fma(s, d, p0)) are monotone in s per axis, and the
-// bound is pulled in by 2^-9 voxel (more than the fp32 rounding of any
+// Every lattice index k' with k <= k' < result samples strictly inside the
+// current block: positions fl(fma(s, d, p0)) are monotone in s per axis, and
+// the bound is pulled in by 2^-9 voxel (more than the fp32 rounding of any
 // position below 8192) and by one more full step.  Computed in FP64.
 __device__ inline int leap_target(const VolConst &v, const Ray &r, const int bc[3], float step, int k) {
   const int nb[3] = {v.nbx, v.nby, v.nbz};
@@ -463,22 +478,91 @@ __device__ inline int leap_target(const VolConst &v, const Ray &r, const int bc[
     double da = (double)r.d[a];
     double pa = (double)r.p0[a];
     if (da > 0.0 && bc[a] < nb[a] - 1) {
-      double bound = (double)((bc[a] + 1) * v.edge) - 0x1p-9;
+      double bound = (double)((bc[a] + 1) << v.edge_shift) - 0x1p-9;
       smin = fmin(smin, (bound - pa) / da);
     } else if (da < 0.0 && bc[a] > 0) {
-      double bound = (double)(bc[a] * v.edge) + 0x1p-9;
+      double bound = (double)(bc[a] << v.edge_shift) + 0x1p-9;
       smin = fmin(smin, (bound - pa) / da);
     }
   }
   if (!(smin < 1e30)) return 0x7fffffff;
-  // first k with (k + 1/2) step >= smin, minus one step of margin
-  double kf = ceil(smin / (double)step - 0.5) - 1.0;
-  if (kf > 2.0e9) return 0x7fffffff;
-  int kt = (int)fmax(kf, 0.0);
+  // first j with s0 + j step >= smin, minus one step of margin
+  double jf = ceil((smin - (double)r.s0) / (double)step) - 1.0;
+  if (jf > 2.0e9) return 0x7fffffff;
+  int kt = r.k0 + (int)fmax(jf, 0.0);
   return max(kt, k + 1);
 }
 
+// Position of lattice index k.
+__device__ inline void lattice_point(const Ray &r, float step, int k, float &px, float &py, float &pz) {
+  float sk = fmaf((float)(k - r.k0), step, r.s0);
+  px = fmaf(sk, r.d[0], r.p0[0]);
+  py = fmaf(sk, r.d[1], r.p0[1]);
+  pz = fmaf(sk, r.d[2], r.p0[2]);
+}
+
+__device__ inline int wave_min_i32(int x) {
+  for (int off = 32; off > 0; off >>= 1) x = min(x, __shfl_xor(x, off, kWaveSize));
+  return __builtin_amdgcn_readfirstlane(x);
+}
+
+__device__ inline int wave_max_i32(int x) {
+  for (int off = 32; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off, kWaveSize));
+  return __builtin_amdgcn_readfirstlane(x);
+}
+
 // Blocks' minmax and TF decide occupancy.
+__device__ inline bool block_occupied(const VolConst &v, const TfShared &s, const TfConst &tf, int b);
+
+// Walk one ray's lattice with the whole wavefront in step: all lanes look at
+// the same index k (a thin slab of the tile's rays).  A lane sits out when k
+// is outside its ray, after its ray terminated, or when its sample lies in a
+// block that is empty under the TF (such a sample would add exactly zero).
+// When no lane has a sample to evaluate, the wavefront leaps to the smallest
+// index any lane may need: its next lattice start, or the first index that
+// may leave its empty block.  visit(k, px, py, pz) evaluates one sample and
+// returns false to stop the ray.
+template <class Visit>
+__device__ inline void walk(const VolConst &v, const TfShared &s, const TfConst &tf, const MarchConst &mc,
+                            const Ray &r, Visit &visit) {
+  const int kb = r.hit ? r.k0 : 0x7fffffff;
+  const int ke = r.hit ? r.k0 + r.ns : 0;
+  bool alive = r.hit;
+  int k = wave_min_i32(kb);
+  const int kend = wave_max_i32(ke);
+  int cur_block = -1;
+  bool cur_occ = false;
+  int bc[3] = {0, 0, 0};
+  while (k < kend) {
+    const bool in = alive && k >= kb && k < ke;
+    bool want = in;
+    float px = 0.0f, py = 0.0f, pz = 0.0f;
+    if (in) {
+      lattice_point(r, mc.step, k, px, py, pz);
+      if (mc.skip) {
+        const int b = block_of(v, px, py, pz, bc);
+        if (b != cur_block) {
+          cur_block = b;
+          cur_occ = block_occupied(v, s, tf, b);
+        }
+        want = cur_occ;
+      }
+    }
+    if (__ballot(want) == 0ull) {
+      int prop = 0x7fffffff;
+      if (in)
+        prop = leap_target(v, r, bc, mc.step, k);
+      else if (alive && k < kb)
+        prop = kb;
+      const int m = wave_min_i32(prop);
+      k = m > k + 1 ? m : k + 1;
+      continue;
+    }
+    if (want && !visit(k, px, py, pz)) alive = false;
+    ++k;
+  }
+}
+
 __device__ inline bool block_occupied(const VolConst &v, const TfShared &s, const TfConst &tf, int b) {
   float2 mm = v.minmax[b];
   return range_occupied(s, tf.K, tf.v0, tf.scale, mm.x, mm.y);

@@ -144,7 +144,7 @@ def test_beer_lambert_oblique_rays(oracle_lib):
     T = np.exp(-sigma0 * step * ns)
     np.testing.assert_allclose(out["rgba"][0][..., 3], 1 - T, rtol=0, atol=1e-13)
     np.testing.assert_allclose(out["rgba"][0][..., 0], 0.5 * (1 - T), rtol=0, atol=1e-13)
-    # lattice count against the definition #{k : (k + 1/2) step < t_out - t_in},
+    # lattice count against the definition #{k >= 0 : t_in < (k + 1/2) step < t_out},
     # with t_in/t_out from the face-plane clip of the brute force
     for row, col in [(3, 5), (12, 12), (20, 7), (0, 0)]:
         o, d = brute.camera_ray(cam, row, col)
@@ -152,9 +152,9 @@ def test_beer_lambert_oblique_rays(oracle_lib):
         if hit is None:
             assert ns[row, col] == 0
             continue
-        L = hit[1] - hit[0]
-        want = math.ceil(L / step - 0.5)
-        assert ns[row, col] == want
+        k0 = max(math.floor(hit[0] / step - 0.5) + 1, 0)
+        k1 = math.ceil(hit[1] / step - 0.5)
+        assert ns[row, col] == k1 - k0
 
 
 # -------------------------------------------------------------- brute force --
