@@ -145,6 +145,14 @@ vr_status attach_blocks(const vr_blocks *b, const vr_volume *v, VolConst *vc) {
   return VR_OK;
 }
 
+uint32_t max_lds_per_workgroup() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536u;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+    return 65536u;
+  return (uint32_t)v;
+}
+
 int32_t chunk_edge_setting() {
   static const int32_t ce = [] {
     const char *e = std::getenv("VR_CHUNK_EDGE");
@@ -319,6 +327,8 @@ vr_status vr_render_backward(const vr_volume *vol, const vr_blocks *blocks, cons
     b.grad_rgba = grad_rgba + (size_t)v0 * view_floats;
     b.grad_vol = grad_volume;
     b.grad_tf = grad_tf;
+    b.use_box = 0;
+    b.pad = 0;
     e = launch_render_backward(b, st);
     if (e != hipSuccess) return hip_fail(e, "backward launch");
   }

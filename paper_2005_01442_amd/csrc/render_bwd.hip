@@ -35,14 +35,144 @@ __device__ inline void scatter_taps(float *g, const VolConst &v, const Stencil &
   }
 }
 
+// ---------------------------------------------------------------------------
+// Gradient box: each wavefront accumulates its grid-gradient scatter in a
+// kBox^3 fp32 box of LDS placed over the slab its lanes are sampling; when a
+// step's stencils leave the box, the box is flushed to global memory (one
+// atomic per touched voxel) and re-placed.  Steps whose stencils spread wider
+// than the box scatter straight to global memory.
+// ---------------------------------------------------------------------------
+constexpr int kBox = 16;
+constexpr int kBoxCells = kBox * kBox * kBox;
+
+struct GradBox {
+  float *cells;  // this wavefront's LDS cells, [z][y][x], zero outside use
+  int ox, oy, oz;
+  bool valid;
+};
+
+__device__ inline void box_flush(GradBox &b, float *grad, const VolConst &v) {
+  if (!b.valid) return;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const int lane = threadIdx.x % kWaveSize;
+  for (int i = lane; i < kBoxCells; i += kWaveSize) {
+    float val = b.cells[i];
+    if (val != 0.0f) {
+      int x = b.ox + (i % kBox), y = b.oy + ((i / kBox) % kBox), z = b.oz + i / (kBox * kBox);
+      if (x < v.nx && y < v.ny && z < v.nz)
+        unsafeAtomicAdd(grad + ((uint32_t)z * (uint32_t)v.ny + (uint32_t)y) * (uint32_t)v.nx + (uint32_t)x, val);
+      b.cells[i] = 0.0f;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  b.valid = false;
+}
+
+// Wavefront-wide: make the box cover every clamped stencil of this step's
+// sampling lanes, if they fit.
+__device__ inline void box_prepare(GradBox &b, float *grad, const VolConst &v, const Ray &r, bool want, float px,
+                                   float py, float pz) {
+  int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-1, -1, -1};
+  const int n[3] = {v.nx, v.ny, v.nz};
+  if (want) {
+    const float p[3] = {px, py, pz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      int f = (int)floorf(p[a]);
+      lo[a] = min(max(f - 1, 0), n[a] - 1);
+      hi[a] = min(max(f + 2, 0), n[a] - 1);
+    }
+  }
+  const int o[3] = {b.ox, b.oy, b.oz};
+  bool inside = true;
+  if (want)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) inside = inside && lo[a] >= o[a] && hi[a] < o[a] + kBox;
+  if (b.valid && __ballot(!inside) == 0ull) return;
+  box_flush(b, grad, v);
+  int mn[3], mx[3];
+  bool fits = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    mn[a] = wave_min_i32(lo[a]);
+    mx[a] = wave_max_i32(hi[a]);
+    fits = fits && (mx[a] - mn[a] < kBox);
+  }
+  if (!fits) return;  // this step scatters to global memory
+  // extend the box along the marching direction of the first sampling lane
+  const unsigned long long wm = __ballot(want);
+  const int first = __ffsll((long long)wm) - 1;
+  int org[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float da = __shfl(r.d[a], first, kWaveSize);
+    int oa = da >= 0.0f ? mn[a] : mx[a] - kBox + 1;
+    org[a] = max(oa, 0);
+  }
+  b.ox = __builtin_amdgcn_readfirstlane(org[0]);
+  b.oy = __builtin_amdgcn_readfirstlane(org[1]);
+  b.oz = __builtin_amdgcn_readfirstlane(org[2]);
+  b.valid = true;
+}
+
+// One lane's scatter of dv through its 64 weights into the box.
+__device__ inline void box_scatter(GradBox &b, const VolConst &v, const Stencil &st, float dv) {
+  const bool inner = (st.ix >= 1) & (st.ix + 2 <= v.nx - 1) & (st.iy >= 1) & (st.iy + 2 <= v.ny - 1) &
+                     (st.iz >= 1) & (st.iz + 2 <= v.nz - 1);
+  if (inner) {
+    float *base = b.cells + ((st.iz - 1 - b.oz) * kBox + (st.iy - 1 - b.oy)) * kBox + (st.ix - 1 - b.ox);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      float wc = dv * st.wz[c];
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) {
+        float wb = wc * st.wy[bb];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) atomicAdd(base + (c * kBox + bb) * kBox + a, wb * st.wx[a]);
+      }
+    }
+    return;
+  }
+  int xs[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) xs[a] = min(max(st.ix - 1 + a, 0), v.nx - 1) - b.ox;
+  for (int c = 0; c < 4; ++c) {
+    int z = min(max(st.iz - 1 + c, 0), v.nz - 1) - b.oz;
+    float wc = dv * st.wz[c];
+    for (int bb = 0; bb < 4; ++bb) {
+      int y = min(max(st.iy - 1 + bb, 0), v.ny - 1) - b.oy;
+      float wb = wc * st.wy[bb];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) atomicAdd(b.cells + (z * kBox + y) * kBox + xs[a], wb * st.wx[a]);
+    }
+  }
+}
+
 template <int DT>
-__device__ inline void march_backward(const VolConst &v, const TfShared &s, float *sgtf, const TfConst &tf,
-                                      const MarchConst &mc, const Ray &r, __amdgpu_buffer_rsrc_t rs, float4 g,
-                                      float4 fin, float *grad_vol) {
+__device__ inline void march_backward(const VolConst &v, const TfShared &s, float *sgtf, GradBox &box,
+                                      const TfConst &tf, const MarchConst &mc, const Ray &r,
+                                      __amdgpu_buffer_rsrc_t rs, float4 g, float4 fin, float *grad_vol) {
   float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, T = 1.0f;
   const float sl2 = mc.step * 1.4426950408889634f;
   const bool ert_on = mc.ert > 0.0f && mc.ert < 1.0f;
   const float Tend = 1.0f - fin.w;
+  // TF-gradient contributions of consecutive samples in one TF segment are
+  // summed in registers and written to LDS when the segment changes
+  int cj = -1;
+  float ga[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  auto flush_tf = [&]() {
+    if (cj >= 0) {
+      float *n0 = sgtf + 4 * cj;
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (ga[i] != 0.0f) atomicAdd(n0 + i, ga[i]);
+    }
+  };
+  auto prep = [&](bool want, float px, float py, float pz) {
+    if (grad_vol && box.cells) box_prepare(box, grad_vol, v, r, want, px, py, pz);
+  };
   auto visit = [&](int, float px, float py, float pz) -> bool {
     Stencil st = make_stencil(px, py, pz);
     float val = reconstruct<DT>(rs, v, st);
@@ -61,16 +191,21 @@ __device__ inline void march_backward(const VolConst &v, const TfShared &s, floa
     acc = fmaf(g.z, T * q.c.z - (fin.z - C2), acc);
     float dsig = mc.step * acc;
     if (sgtf) {
+      if (q.j != cj) {
+        flush_tf();
+        cj = q.j;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) ga[i] = 0.0f;
+      }
       float w1 = q.w, w0 = 1.0f - q.w;
-      float *n0 = sgtf + 4 * q.j;
-      atomicAdd(n0 + 0, w0 * dc0);
-      atomicAdd(n0 + 1, w0 * dc1);
-      atomicAdd(n0 + 2, w0 * dc2);
-      atomicAdd(n0 + 3, w0 * dsig);
-      atomicAdd(n0 + 4, w1 * dc0);
-      atomicAdd(n0 + 5, w1 * dc1);
-      atomicAdd(n0 + 6, w1 * dc2);
-      atomicAdd(n0 + 7, w1 * dsig);
+      ga[0] = fmaf(w0, dc0, ga[0]);
+      ga[1] = fmaf(w0, dc1, ga[1]);
+      ga[2] = fmaf(w0, dc2, ga[2]);
+      ga[3] = fmaf(w0, dsig, ga[3]);
+      ga[4] = fmaf(w1, dc0, ga[4]);
+      ga[5] = fmaf(w1, dc1, ga[5]);
+      ga[6] = fmaf(w1, dc2, ga[6]);
+      ga[7] = fmaf(w1, dsig, ga[7]);
     }
     if (grad_vol && !q.clamped) {
       float4 a = s.node[q.j], b = s.node[q.j + 1];
@@ -79,11 +214,18 @@ __device__ inline void march_backward(const VolConst &v, const TfShared &s, floa
       dv = fmaf(dc2, b.z - a.z, dv);
       dv = fmaf(dsig, b.w - a.w, dv);
       dv *= tf.scale;
-      if (dv != 0.0f) scatter_taps(grad_vol, v, st, dv);
+      if (dv != 0.0f) {
+        if (box.valid)
+          box_scatter(box, v, st, dv);
+        else
+          scatter_taps(grad_vol, v, st, dv);
+      }
     }
     return !(ert_on && (1.0f - T) >= mc.ert);
   };
-  walk(v, s, tf, mc, r, visit);
+  walk(v, s, tf, mc, r, visit, prep);
+  if (sgtf) flush_tf();
+  if (grad_vol) box_flush(box, grad_vol, v);
 }
 
 template <int DT>
@@ -94,9 +236,19 @@ __global__ __launch_bounds__(kWgSize) void k_render_bwd(const BackwardArgs args)
   SuperTile st = map_workgroup(blockIdx.x, ra.W, ra.H, ra.n_views, ra.chunk_edge);
   if (!st.valid) return;  // uniform over the workgroup
   const int K = ra.tf.K;
-  float *sgtf = a.grad_tf ? reinterpret_cast<float *>(lds + tf_lds_bytes(K)) : nullptr;
+  const uint32_t tf_bytes = tf_lds_bytes(K);
+  float *sgtf = a.grad_tf ? reinterpret_cast<float *>(lds + tf_bytes) : nullptr;
   if (sgtf)
     for (int j = threadIdx.x; j < 4 * K; j += kWgSize) sgtf[j] = 0.0f;
+  GradBox box;
+  box.valid = false;
+  box.ox = box.oy = box.oz = 0;
+  box.cells = nullptr;
+  if (a.grad_vol && a.use_box) {
+    float *boxes = reinterpret_cast<float *>(lds + tf_bytes + (a.grad_tf ? (uint32_t)K * 16u : 0u));
+    box.cells = boxes + (threadIdx.x / kWaveSize) * kBoxCells;
+    for (int i = threadIdx.x % kWaveSize; i < kBoxCells; i += kWaveSize) box.cells[i] = 0.0f;
+  }
   TfShared s = carve_tf(lds, K);
   load_tf(s, ra.tf);  // ends with a barrier, which also orders the zeroing
   int col, row;
@@ -117,7 +269,7 @@ __global__ __launch_bounds__(kWgSize) void k_render_bwd(const BackwardArgs args)
     }
   }
   __amdgpu_buffer_rsrc_t rs = make_rsrc(ra.vol.data, ra.vol.bytes);
-  march_backward<DT>(ra.vol, s, sgtf, ra.tf, ra.mc, r, rs, g, fin, a.grad_vol);
+  march_backward<DT>(ra.vol, s, sgtf, box, ra.tf, ra.mc, r, rs, g, fin, a.grad_vol);
   if (sgtf) {
     __syncthreads();
     for (int j = threadIdx.x; j < 4 * K; j += kWgSize) {
@@ -127,15 +279,27 @@ __global__ __launch_bounds__(kWgSize) void k_render_bwd(const BackwardArgs args)
   }
 }
 
-hipError_t launch_render_backward(const BackwardArgs &a, hipStream_t s) {
+hipError_t launch_render_backward(const BackwardArgs &a0, hipStream_t s) {
+  BackwardArgs a = a0;
   const RenderArgs &ra = a.r;
   int64_t grid = grid_size_for(ra.W, ra.H, ra.n_views, ra.chunk_edge);
   uint32_t lds = tf_lds_bytes(ra.tf.K) + (a.grad_tf ? (uint32_t)ra.tf.K * 16u : 0u);
+  const uint32_t box_bytes = (uint32_t)(kWgSize / kWaveSize) * kBoxCells * 4u;
+  a.use_box = (a.grad_vol && lds + box_bytes <= max_lds_per_workgroup()) ? 1 : 0;
+  if (a.use_box) lds += box_bytes;
+  const void *fn = nullptr;
+  switch (ra.vol.dtype) {
+  case kU16: fn = reinterpret_cast<const void *>(&k_render_bwd<kU16>); break;
+  case kI16: fn = reinterpret_cast<const void *>(&k_render_bwd<kI16>); break;
+  case kF32: fn = reinterpret_cast<const void *>(&k_render_bwd<kF32>); break;
+  default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
   switch (ra.vol.dtype) {
   case kU16: hipLaunchKernelGGL(k_render_bwd<kU16>, dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
   case kI16: hipLaunchKernelGGL(k_render_bwd<kI16>, dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
-  case kF32: hipLaunchKernelGGL(k_render_bwd<kF32>, dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
-  default: return hipErrorInvalidValue;
+  default: hipLaunchKernelGGL(k_render_bwd<kF32>, dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
   }
   return hipGetLastError();
 }

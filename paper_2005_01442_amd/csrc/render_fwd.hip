@@ -31,7 +31,8 @@ __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfCon
     ++evaluated;
     return !(ert_on && (1.0f - T) >= mc.ert);
   };
-  walk(v, s, tf, mc, r, visit);
+  NoPrep prep;
+  walk(v, s, tf, mc, r, visit, prep);
   return make_float4(C0, C1, C2, 1.0f - T);
 }
 

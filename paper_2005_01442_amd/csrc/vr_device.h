@@ -520,11 +520,16 @@ __device__ inline bool block_occupied(const VolConst &v, const TfShared &s, cons
 // block that is empty under the TF (such a sample would add exactly zero).
 // When no lane has a sample to evaluate, the wavefront leaps to the smallest
 // index any lane may need: its next lattice start, or the first index that
-// may leave its empty block.  visit(k, px, py, pz) evaluates one sample and
-// returns false to stop the ray.
-template <class Visit>
+// may leave its empty block.  prep(want, px, py, pz) runs on every lane of the
+// wavefront before the samples of a step (for wavefront-wide staging);
+// visit(k, px, py, pz) evaluates one sample and returns false to stop the ray.
+struct NoPrep {
+  __device__ inline void operator()(bool, float, float, float) const {}
+};
+
+template <class Visit, class Prep>
 __device__ inline void walk(const VolConst &v, const TfShared &s, const TfConst &tf, const MarchConst &mc,
-                            const Ray &r, Visit &visit) {
+                            const Ray &r, Visit &visit, Prep &prep) {
   const int kb = r.hit ? r.k0 : 0x7fffffff;
   const int ke = r.hit ? r.k0 + r.ns : 0;
   bool alive = r.hit;
@@ -558,6 +563,7 @@ __device__ inline void walk(const VolConst &v, const TfShared &s, const TfConst 
       k = m > k + 1 ? m : k + 1;
       continue;
     }
+    prep(want, px, py, pz);
     if (want && !visit(k, px, py, pz)) alive = false;
     ++k;
   }

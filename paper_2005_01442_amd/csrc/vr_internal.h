@@ -28,7 +28,12 @@ struct BackwardArgs {
   const float *grad_rgba;  // dL/dRGBA of the first view of this launch
   float *grad_vol;         // nullptr or nx*ny*nz
   float *grad_tf;          // nullptr or K*4
+  int32_t use_box;         // stage the grid-gradient scatter in LDS boxes
+  int32_t pad;
 };
+
+// Largest dynamic LDS a workgroup may allocate on the current device.
+uint32_t max_lds_per_workgroup();
 
 // Chunk edge of the workgroup -> tile mapping (VR_CHUNK_EDGE overrides: 1, 2,
 // 4 or 8).
