@@ -43,10 +43,22 @@ __device__ inline void scatter_taps(float *g, const VolConst &v, const Stencil &
 // than the box scatter straight to global memory.
 // ---------------------------------------------------------------------------
 constexpr int kBox = 16;
-constexpr int kBoxCells = kBox * kBox * kBox;
+// z stride of a box: kBox^2 + 4, so that the 64 taps (a + 16 b + kBoxZ c,
+// a, b, c < 4) of one stencil fall in 64 distinct LDS banks
+constexpr int kBoxZ = kBox * kBox + 4;
+constexpr int kBoxCells = kBox * kBoxZ;
+constexpr int kRec = 16;  // dwords per staged scatter record
+
+// LDS layout of the adjoint: TF + prefix counts, TF gradient (4K floats, when
+// requested), then 16-byte aligned per-wavefront boxes and record areas.
+__host__ __device__ inline uint32_t box_lds_offset(int K, bool with_tf_grad) {
+  uint32_t o = tf_lds_bytes(K) + (with_tf_grad ? (uint32_t)K * 16u : 0u);
+  return (o + 15u) & ~15u;
+}
 
 struct GradBox {
   float *cells;  // this wavefront's LDS cells, [z][y][x], zero outside use
+  float *recs;   // this wavefront's staged scatter records, kRec dwords per lane
   int ox, oy, oz;
   bool valid;
 };
@@ -56,13 +68,15 @@ __device__ inline void box_flush(GradBox &b, float *grad, const VolConst &v) {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
   const int lane = threadIdx.x % kWaveSize;
-  for (int i = lane; i < kBoxCells; i += kWaveSize) {
-    float val = b.cells[i];
+  for (int i = lane; i < kBox * kBox * kBox; i += kWaveSize) {
+    const int cx = i % kBox, cy = (i / kBox) % kBox, cz = i / (kBox * kBox);
+    const int cell = cz * kBoxZ + cy * kBox + cx;
+    float val = b.cells[cell];
     if (val != 0.0f) {
-      int x = b.ox + (i % kBox), y = b.oy + ((i / kBox) % kBox), z = b.oz + i / (kBox * kBox);
+      int x = b.ox + cx, y = b.oy + cy, z = b.oz + cz;
       if (x < v.nx && y < v.ny && z < v.nz)
         unsafeAtomicAdd(grad + ((uint32_t)z * (uint32_t)v.ny + (uint32_t)y) * (uint32_t)v.nx + (uint32_t)x, val);
-      b.cells[i] = 0.0f;
+      b.cells[cell] = 0.0f;
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -117,23 +131,24 @@ __device__ inline void box_prepare(GradBox &b, float *grad, const VolConst &v, c
   b.valid = true;
 }
 
-// One lane's scatter of dv through its 64 weights into the box.
-__device__ inline void box_scatter(GradBox &b, const VolConst &v, const Stencil &st, float dv) {
+// A lane whose stencil is interior stages its scatter record (x, y, z weights
+// with dv folded into the z weights, and the box cell of tap (0, 0, 0)); the
+// wavefront then applies the staged records one sample at a time with the
+// lanes transposed onto the 64 taps (box_apply).  Clamped stencils, whose taps
+// can coincide, add their taps with LDS atomics right away.
+__device__ inline bool box_stage(GradBox &b, const VolConst &v, const Stencil &st, float dv) {
   const bool inner = (st.ix >= 1) & (st.ix + 2 <= v.nx - 1) & (st.iy >= 1) & (st.iy + 2 <= v.ny - 1) &
                      (st.iz >= 1) & (st.iz + 2 <= v.nz - 1);
   if (inner) {
-    float *base = b.cells + ((st.iz - 1 - b.oz) * kBox + (st.iy - 1 - b.oy)) * kBox + (st.ix - 1 - b.ox);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      float wc = dv * st.wz[c];
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb) {
-        float wb = wc * st.wy[bb];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) atomicAdd(base + (c * kBox + bb) * kBox + a, wb * st.wx[a]);
-      }
-    }
-    return;
+    float *rec = b.recs + (threadIdx.x % kWaveSize) * kRec;
+    f32x4 wx = {st.wx[0], st.wx[1], st.wx[2], st.wx[3]};
+    f32x4 wy = {st.wy[0], st.wy[1], st.wy[2], st.wy[3]};
+    f32x4 wz = {dv * st.wz[0], dv * st.wz[1], dv * st.wz[2], dv * st.wz[3]};
+    *reinterpret_cast<f32x4 *>(rec + 0) = wx;
+    *reinterpret_cast<f32x4 *>(rec + 4) = wy;
+    *reinterpret_cast<f32x4 *>(rec + 8) = wz;
+    reinterpret_cast<int *>(rec)[12] = (st.iz - 1 - b.oz) * kBoxZ + (st.iy - 1 - b.oy) * kBox + (st.ix - 1 - b.ox);
+    return true;
   }
   int xs[4];
 #pragma unroll
@@ -145,9 +160,32 @@ __device__ inline void box_scatter(GradBox &b, const VolConst &v, const Stencil 
       int y = min(max(st.iy - 1 + bb, 0), v.ny - 1) - b.oy;
       float wb = wc * st.wy[bb];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) atomicAdd(b.cells + (z * kBox + y) * kBox + xs[a], wb * st.wx[a]);
+      for (int a = 0; a < 4; ++a) atomicAdd(b.cells + z * kBoxZ + y * kBox + xs[a], wb * st.wx[a]);
     }
   }
+  return false;
+}
+
+// Wavefront-wide: apply the records of the lanes in `staged`.  For one record
+// the 64 lanes update 64 distinct cells, so plain read-add-write is exact;
+// records are applied in order.
+__device__ inline void box_apply(GradBox &b, unsigned long long staged) {
+  if (staged == 0ull) return;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const int l = threadIdx.x % kWaveSize;
+  const int ta = l & 3, tb = (l >> 2) & 3, tc = l >> 4;
+  const int off = tc * kBoxZ + tb * kBox + ta;
+  while (staged) {
+    const int sl = __ffsll((long long)staged) - 1;
+    staged &= staged - 1ull;
+    const float *rec = b.recs + sl * kRec;
+    const float w = rec[ta] * rec[4 + tb] * rec[8 + tc];
+    const int cell = reinterpret_cast<const int *>(rec)[12] + off;
+    b.cells[cell] += w;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
 template <int DT>
@@ -170,8 +208,13 @@ __device__ inline void march_backward(const VolConst &v, const TfShared &s, floa
         if (ga[i] != 0.0f) atomicAdd(n0 + i, ga[i]);
     }
   };
+  bool staged = false;
   auto prep = [&](bool want, float px, float py, float pz) {
     if (grad_vol && box.cells) box_prepare(box, grad_vol, v, r, want, px, py, pz);
+  };
+  auto post = [&]() {
+    if (grad_vol && box.cells) box_apply(box, __ballot(staged));
+    staged = false;
   };
   auto visit = [&](int, float px, float py, float pz) -> bool {
     Stencil st = make_stencil(px, py, pz);
@@ -216,14 +259,14 @@ __device__ inline void march_backward(const VolConst &v, const TfShared &s, floa
       dv *= tf.scale;
       if (dv != 0.0f) {
         if (box.valid)
-          box_scatter(box, v, st, dv);
+          staged = box_stage(box, v, st, dv);
         else
           scatter_taps(grad_vol, v, st, dv);
       }
     }
     return !(ert_on && (1.0f - T) >= mc.ert);
   };
-  walk(v, s, tf, mc, r, visit, prep);
+  walk(v, s, tf, mc, r, visit, prep, post);
   if (sgtf) flush_tf();
   if (grad_vol) box_flush(box, grad_vol, v);
 }
@@ -245,8 +288,10 @@ __global__ __launch_bounds__(kWgSize) void k_render_bwd(const BackwardArgs args)
   box.ox = box.oy = box.oz = 0;
   box.cells = nullptr;
   if (a.grad_vol && a.use_box) {
-    float *boxes = reinterpret_cast<float *>(lds + tf_bytes + (a.grad_tf ? (uint32_t)K * 16u : 0u));
-    box.cells = boxes + (threadIdx.x / kWaveSize) * kBoxCells;
+    float *boxes = reinterpret_cast<float *>(lds + box_lds_offset(K, a.grad_tf != nullptr));
+    const int wave = threadIdx.x / kWaveSize;
+    box.cells = boxes + wave * (kBoxCells + kWaveSize * kRec);
+    box.recs = box.cells + kBoxCells;
     for (int i = threadIdx.x % kWaveSize; i < kBoxCells; i += kWaveSize) box.cells[i] = 0.0f;
   }
   TfShared s = carve_tf(lds, K);
@@ -284,9 +329,10 @@ hipError_t launch_render_backward(const BackwardArgs &a0, hipStream_t s) {
   const RenderArgs &ra = a.r;
   int64_t grid = grid_size_for(ra.W, ra.H, ra.n_views, ra.chunk_edge);
   uint32_t lds = tf_lds_bytes(ra.tf.K) + (a.grad_tf ? (uint32_t)ra.tf.K * 16u : 0u);
-  const uint32_t box_bytes = (uint32_t)(kWgSize / kWaveSize) * kBoxCells * 4u;
-  a.use_box = (a.grad_vol && lds + box_bytes <= max_lds_per_workgroup()) ? 1 : 0;
-  if (a.use_box) lds += box_bytes;
+  const uint32_t box_bytes = (uint32_t)(kWgSize / kWaveSize) * (kBoxCells + kWaveSize * kRec) * 4u;
+  const uint32_t with_box = box_lds_offset(ra.tf.K, a.grad_tf != nullptr) + box_bytes;
+  a.use_box = (a.grad_vol && with_box <= max_lds_per_workgroup()) ? 1 : 0;
+  if (a.use_box) lds = with_box;
   const void *fn = nullptr;
   switch (ra.vol.dtype) {
   case kU16: fn = reinterpret_cast<const void *>(&k_render_bwd<kU16>); break;

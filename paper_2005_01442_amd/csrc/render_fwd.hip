@@ -32,7 +32,8 @@ __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfCon
     return !(ert_on && (1.0f - T) >= mc.ert);
   };
   NoPrep prep;
-  walk(v, s, tf, mc, r, visit, prep);
+  NoPost post;
+  walk(v, s, tf, mc, r, visit, prep, post);
   return make_float4(C0, C1, C2, 1.0f - T);
 }
 

@@ -523,13 +523,17 @@ __device__ inline bool block_occupied(const VolConst &v, const TfShared &s, cons
 // may leave its empty block.  prep(want, px, py, pz) runs on every lane of the
 // wavefront before the samples of a step (for wavefront-wide staging);
 // visit(k, px, py, pz) evaluates one sample and returns false to stop the ray.
+// post() runs on every lane after the samples of a step.
 struct NoPrep {
   __device__ inline void operator()(bool, float, float, float) const {}
 };
+struct NoPost {
+  __device__ inline void operator()() const {}
+};
 
-template <class Visit, class Prep>
+template <class Visit, class Prep, class Post>
 __device__ inline void walk(const VolConst &v, const TfShared &s, const TfConst &tf, const MarchConst &mc,
-                            const Ray &r, Visit &visit, Prep &prep) {
+                            const Ray &r, Visit &visit, Prep &prep, Post &post) {
   const int kb = r.hit ? r.k0 : 0x7fffffff;
   const int ke = r.hit ? r.k0 + r.ns : 0;
   bool alive = r.hit;
@@ -565,6 +569,7 @@ __device__ inline void walk(const VolConst &v, const TfShared &s, const TfConst 
     }
     prep(want, px, py, pz);
     if (want && !visit(k, px, py, pz)) alive = false;
+    post();
     ++k;
   }
 }
