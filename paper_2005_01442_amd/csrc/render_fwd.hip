@@ -14,13 +14,16 @@ namespace vr {
 // result is bit-identical to marching every sample.
 template <int DT>
 __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfConst &tf, const MarchConst &mc,
-                               const Ray &r, __amdgpu_buffer_rsrc_t rs, uint32_t &evaluated) {
+                               const Ray &r, __amdgpu_buffer_rsrc_t rs, ValBox &box, uint32_t &evaluated) {
   float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, T = 1.0f;
   const float sl2 = mc.step * 1.4426950408889634f;
   const bool ert_on = mc.ert > 0.0f && mc.ert < 1.0f;
+  auto prep = [&](bool want, float px, float py, float pz) {
+    if (box.cells) vbox_prepare<DT>(box, rs, v, r, want, px, py, pz);
+  };
   auto visit = [&](int, float px, float py, float pz) -> bool {
     Stencil st = make_stencil(px, py, pz);
-    float val = reconstruct<DT>(rs, v, st);
+    float val = box.valid ? reconstruct_box(box, st) : reconstruct<DT>(rs, v, st);
     Classified q = classify(s, tf.K, tf.v0, tf.scale, val);
     float e = transmit(q.c.w, sl2);
     float ta = T * (1.0f - e);
@@ -31,7 +34,6 @@ __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfCon
     ++evaluated;
     return !(ert_on && (1.0f - T) >= mc.ert);
   };
-  NoPrep prep;
   NoPost post;
   walk(v, s, tf, mc, r, visit, prep, post);
   return make_float4(C0, C1, C2, 1.0f - T);
@@ -63,7 +65,13 @@ void k_render(const RenderArgs args) {
   r.k0 = 0;
   if (inside) r = setup_ray(cam, col, row, a.vol.nx, a.vol.ny, a.vol.nz, a.mc.step);
   __amdgpu_buffer_rsrc_t rs = make_rsrc(a.vol.data, a.vol.bytes);
-  float4 rgba = march<DT>(a.vol, s, a.tf, a.mc, r, rs, evaluated);
+  ValBox box;
+  box.valid = false;
+  box.ox = box.oy = box.oz = 0;
+  box.cells = a.use_box ? reinterpret_cast<float *>(lds + vbox_lds_offset(a.tf.K)) +
+                              (threadIdx.x / kWaveSize) * kVBoxCells
+                        : nullptr;
+  float4 rgba = march<DT>(a.vol, s, a.tf, a.mc, r, rs, box, evaluated);
   if (inside) {
     float4 *o = reinterpret_cast<float4 *>(a.out);
     o[((size_t)st.view * a.H + row) * a.W + col] = rgba;
@@ -75,14 +83,26 @@ void k_render(const RenderArgs args) {
   }
 }
 
-hipError_t launch_render(const RenderArgs &a, hipStream_t s) {
+hipError_t launch_render(const RenderArgs &a0, hipStream_t s) {
+  RenderArgs a = a0;
   int64_t grid = grid_size_for(a.W, a.H, a.n_views, a.chunk_edge);
   uint32_t lds = tf_lds_bytes(a.tf.K);
+  const uint32_t with_box = vbox_lds_offset(a.tf.K) + vbox_lds_bytes();
+  a.use_box = with_box <= max_lds_per_workgroup() ? 1 : 0;
+  if (a.use_box) lds = with_box;
+  const void *fn = nullptr;
+  switch (a.vol.dtype) {
+  case kU16: fn = reinterpret_cast<const void *>(&k_render<kU16>); break;
+  case kI16: fn = reinterpret_cast<const void *>(&k_render<kI16>); break;
+  case kF32: fn = reinterpret_cast<const void *>(&k_render<kF32>); break;
+  default: return hipErrorInvalidValue;
+  }
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
   switch (a.vol.dtype) {
   case kU16: hipLaunchKernelGGL(k_render<kU16>, dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
   case kI16: hipLaunchKernelGGL(k_render<kI16>, dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
-  case kF32: hipLaunchKernelGGL(k_render<kF32>, dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
-  default: return hipErrorInvalidValue;
+  default: hipLaunchKernelGGL(k_render<kF32>, dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
   }
   return hipGetLastError();
 }
@@ -91,7 +111,8 @@ hipError_t launch_render(const RenderArgs &a, hipStream_t s) {
 // request; the items of a launch may come from many requests of different
 // volumes, sizes and TFs.  The per-ray arithmetic is the whole-image
 // kernel's, so a request's pixels do not depend on what it is batched with.
-__global__ __launch_bounds__(kWgSize) void k_serve(const ServeSlot *slots, const ServeItem *items) {
+__global__ __launch_bounds__(kWgSize) void k_serve(const ServeSlot *slots, const ServeItem *items, int lds_k,
+                                                   int use_box) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const ServeItem it = items[blockIdx.x];
   const ServeSlot &sl = slots[it.slot];
@@ -107,11 +128,16 @@ __global__ __launch_bounds__(kWgSize) void k_serve(const ServeSlot *slots, const
   if (inside) r = setup_ray(sl.cam, col, row, sl.vol.nx, sl.vol.ny, sl.vol.nz, sl.mc.step);
   __amdgpu_buffer_rsrc_t rs = make_rsrc(sl.vol.data, sl.vol.bytes);
   uint32_t evaluated = 0;
+  ValBox box;
+  box.valid = false;
+  box.ox = box.oy = box.oz = 0;
+  box.cells = use_box ? reinterpret_cast<float *>(lds + vbox_lds_offset(lds_k)) + (threadIdx.x / kWaveSize) * kVBoxCells
+                      : nullptr;
   float4 rgba;
   switch (sl.vol.dtype) {  // uniform over the workgroup
-  case kU16: rgba = march<kU16>(sl.vol, s, sl.tf, sl.mc, r, rs, evaluated); break;
-  case kI16: rgba = march<kI16>(sl.vol, s, sl.tf, sl.mc, r, rs, evaluated); break;
-  default: rgba = march<kF32>(sl.vol, s, sl.tf, sl.mc, r, rs, evaluated); break;
+  case kU16: rgba = march<kU16>(sl.vol, s, sl.tf, sl.mc, r, rs, box, evaluated); break;
+  case kI16: rgba = march<kI16>(sl.vol, s, sl.tf, sl.mc, r, rs, box, evaluated); break;
+  default: rgba = march<kF32>(sl.vol, s, sl.tf, sl.mc, r, rs, box, evaluated); break;
   }
   if (inside) reinterpret_cast<float4 *>(sl.out)[(size_t)row * sl.cam.W + col] = rgba;
 }
@@ -119,8 +145,15 @@ __global__ __launch_bounds__(kWgSize) void k_serve(const ServeSlot *slots, const
 hipError_t launch_serve_batch(const ServeSlot *slots_dev, const ServeItem *items_dev, int32_t n_items,
                               int32_t max_tf_k, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_serve, dim3((unsigned)n_items), dim3(kWgSize), tf_lds_bytes(max_tf_k), s, slots_dev,
-                     items_dev);
+  uint32_t lds = tf_lds_bytes(max_tf_k);
+  const uint32_t with_box = vbox_lds_offset(max_tf_k) + vbox_lds_bytes();
+  const int use_box = with_box <= max_lds_per_workgroup() ? 1 : 0;
+  if (use_box) lds = with_box;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_serve),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_serve, dim3((unsigned)n_items), dim3(kWgSize), lds, s, slots_dev, items_dev, max_tf_k,
+                     use_box);
   return hipGetLastError();
 }
 

@@ -30,6 +30,18 @@ constexpr int kDefaultChunkEdge = 4;  // super-tiles per chunk edge (XCD mapping
 
 enum Dtype : int32_t { kU16 = 0, kI16 = 1, kF32 = 2 };
 
+// Wavefront-wide min / max, returned as a uniform (scalar) value.
+__device__ inline int wave_min_i32(int x) {
+  for (int off = 32; off > 0; off >>= 1) x = min(x, __shfl_xor(x, off, kWaveSize));
+  return __builtin_amdgcn_readfirstlane(x);
+}
+
+__device__ inline int wave_max_i32(int x) {
+  for (int off = 32; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off, kWaveSize));
+  return __builtin_amdgcn_readfirstlane(x);
+}
+
+
 // Camera constants, FP64, precomputed on the host.
 struct CamConst {
   double eye[3], right[3], up[3], fwd[3];
@@ -234,6 +246,7 @@ __device__ inline void bspline_weights(float t, float w[4]) {
 }
 
 typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
@@ -274,6 +287,21 @@ template <> struct Vox<kI16> {
   }
   // the dwordx3 window of the row starting at e lies inside the buffer
   __device__ static inline bool window_ok(uint32_t e, uint32_t nvox) { return (e & ~1u) + 6u <= nvox; }
+  // 16 consecutive voxels from element e (9-dword window from e & ~1)
+  __device__ static inline bool row16_ok(uint32_t e, uint32_t nvox) { return (e & ~1u) + 18u <= nvox; }
+  __device__ static inline void row16(__amdgpu_buffer_rsrc_t r, uint32_t e, float t[16]) {
+    const uint32_t b = (e & ~1u) * 2u, sh = (e & 1u) * 16u;
+    const u32x4 p = __builtin_amdgcn_raw_buffer_load_b128(r, b, 0, 0);
+    const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(r, b + 16u, 0, 0);
+    const uint32_t z = __builtin_amdgcn_raw_buffer_load_b32(r, b + 32u, 0, 0);
+    const uint32_t d[9] = {p.x, p.y, p.z, p.w, q.x, q.y, q.z, q.w, z};
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      uint32_t w = __builtin_amdgcn_alignbit(d[j + 1], d[j], sh);
+      t[2 * j] = (float)(int16_t)(w & 0xffffu);
+      t[2 * j + 1] = (float)((int32_t)w >> 16);
+    }
+  }
 };
 
 template <> struct Vox<kU16> {
@@ -303,6 +331,20 @@ template <> struct Vox<kU16> {
     return (float)(uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, e * 2u, 0, 0);
   }
   __device__ static inline bool window_ok(uint32_t e, uint32_t nvox) { return (e & ~1u) + 6u <= nvox; }
+  __device__ static inline bool row16_ok(uint32_t e, uint32_t nvox) { return (e & ~1u) + 18u <= nvox; }
+  __device__ static inline void row16(__amdgpu_buffer_rsrc_t r, uint32_t e, float t[16]) {
+    const uint32_t b = (e & ~1u) * 2u, sh = (e & 1u) * 16u;
+    const u32x4 p = __builtin_amdgcn_raw_buffer_load_b128(r, b, 0, 0);
+    const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(r, b + 16u, 0, 0);
+    const uint32_t z = __builtin_amdgcn_raw_buffer_load_b32(r, b + 32u, 0, 0);
+    const uint32_t d[9] = {p.x, p.y, p.z, p.w, q.x, q.y, q.z, q.w, z};
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      uint32_t w = __builtin_amdgcn_alignbit(d[j + 1], d[j], sh);
+      t[2 * j] = (float)(w & 0xffffu);
+      t[2 * j + 1] = (float)(w >> 16);
+    }
+  }
 };
 
 template <> struct Vox<kF32> {
@@ -326,6 +368,17 @@ template <> struct Vox<kF32> {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, e * 4u, 0, 0));
   }
   __device__ static inline bool window_ok(uint32_t, uint32_t) { return true; }
+  __device__ static inline bool row16_ok(uint32_t, uint32_t) { return true; }
+  __device__ static inline void row16(__amdgpu_buffer_rsrc_t r, uint32_t e, float t[16]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, (e + 4u * j) * 4u, 0, 0));
+      t[4 * j] = v.x;
+      t[4 * j + 1] = v.y;
+      t[4 * j + 2] = v.z;
+      t[4 * j + 3] = v.w;
+    }
+  }
 };
 
 // Stencil geometry of one sample: cell, fractional offsets, weights.
@@ -421,6 +474,122 @@ __device__ inline float reconstruct(__amdgpu_buffer_rsrc_t rs, const VolConst &v
   return acc;
 }
 
+// ---------------------------------------------------------------------------
+// Value box: each wavefront stages in LDS a kVBox^3 box of the volume over the
+// slab its lanes are sampling, converted to fp32 with clamp-to-edge applied
+// while filling.  A step whose stencils all lie in the box reads its 64 taps
+// per sample from LDS, with the same FMA order as the global path (the value
+// is bit-identical).  When a step's stencils leave the box, the box is
+// refilled around them, extended along the marching direction; a step whose
+// stencils spread wider than the box reads from global memory.
+// ---------------------------------------------------------------------------
+constexpr int kVBox = 16;
+constexpr int kVBoxZ = kVBox * kVBox + 4;  // padded z stride (LDS banks)
+constexpr int kVBoxCells = kVBox * kVBoxZ;
+
+struct ValBox {
+  float *cells;  // this wavefront's LDS cells or nullptr (no staging)
+  int ox, oy, oz;
+  bool valid;
+};
+
+template <int DT>
+__device__ inline void vbox_fill(ValBox &b, __amdgpu_buffer_rsrc_t rs, const VolConst &v) {
+  const int lane = threadIdx.x % kWaveSize;
+  const uint32_t nvox = (uint32_t)v.nx * (uint32_t)v.ny * (uint32_t)v.nz;
+#pragma unroll 1
+  for (int row = lane; row < kVBox * kVBox; row += kWaveSize) {
+    const int cy = row % kVBox, cz = row / kVBox;
+    const uint32_t y = (uint32_t)min(max(b.oy + cy, 0), v.ny - 1);
+    const uint32_t z = (uint32_t)min(max(b.oz + cz, 0), v.nz - 1);
+    const uint32_t rowbase = (z * (uint32_t)v.ny + y) * (uint32_t)v.nx;
+    float t[kVBox];
+    if (b.ox >= 0 && b.ox + kVBox - 1 <= v.nx - 1 && Vox<DT>::row16_ok(rowbase + (uint32_t)b.ox, nvox)) {
+      Vox<DT>::row16(rs, rowbase + (uint32_t)b.ox, t);
+    } else {
+#pragma unroll
+      for (int i = 0; i < kVBox; ++i) t[i] = Vox<DT>::one(rs, rowbase + (uint32_t)min(max(b.ox + i, 0), v.nx - 1));
+    }
+    f32x4 *dst = reinterpret_cast<f32x4 *>(b.cells + cz * kVBoxZ + cy * kVBox);
+#pragma unroll
+    for (int j = 0; j < kVBox / 4; ++j) dst[j] = f32x4{t[4 * j], t[4 * j + 1], t[4 * j + 2], t[4 * j + 3]};
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Wavefront-wide, before the samples of a step.
+template <int DT>
+__device__ inline void vbox_prepare(ValBox &b, __amdgpu_buffer_rsrc_t rs, const VolConst &v, const Ray &r,
+                                    bool want, float px, float py, float pz) {
+  int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
+  if (want) {
+    lo[0] = (int)floorf(px) - 1;
+    lo[1] = (int)floorf(py) - 1;
+    lo[2] = (int)floorf(pz) - 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) hi[a] = lo[a] + 3;
+  }
+  const int o[3] = {b.ox, b.oy, b.oz};
+  bool inside = true;
+  if (want)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) inside = inside && lo[a] >= o[a] && hi[a] < o[a] + kVBox;
+  if (b.valid && __ballot(!inside) == 0ull) return;
+  int mn[3], mx[3];
+  bool fits = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    mn[a] = wave_min_i32(lo[a]);
+    mx[a] = wave_max_i32(hi[a]);
+    fits = fits && (mx[a] - mn[a] < kVBox);
+  }
+  if (!fits) {
+    b.valid = false;  // this step reads from global memory
+    return;
+  }
+  const unsigned long long wm = __ballot(want);
+  const int first = __ffsll((long long)wm) - 1;
+  int org[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float da = __shfl(r.d[a], first, kWaveSize);
+    org[a] = da >= 0.0f ? mn[a] : mx[a] - kVBox + 1;
+  }
+  // the lanes may still read the previous contents: order the refill after them
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  b.ox = __builtin_amdgcn_readfirstlane(org[0]);
+  b.oy = __builtin_amdgcn_readfirstlane(org[1]);
+  b.oz = __builtin_amdgcn_readfirstlane(org[2]);
+  vbox_fill<DT>(b, rs, v);
+  b.valid = true;
+}
+
+__device__ inline float reconstruct_box(const ValBox &b, const Stencil &s) {
+  const float *base = b.cells + (s.iz - 1 - b.oz) * kVBoxZ + (s.iy - 1 - b.oy) * kVBox + (s.ix - 1 - b.ox);
+  float acc = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    float accy = 0.0f;
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) {
+      const float *t = base + c * kVBoxZ + bb * kVBox;
+      float r = s.wx[0] * t[0];
+      r = fmaf(s.wx[1], t[1], r);
+      r = fmaf(s.wx[2], t[2], r);
+      r = fmaf(s.wx[3], t[3], r);
+      accy = fmaf(s.wy[bb], r, accy);
+    }
+    acc = fmaf(s.wz[c], accy, acc);
+  }
+  return acc;
+}
+
+// LDS bytes of the TF staging rounded up to 16, where the value boxes begin.
+__host__ __device__ inline uint32_t vbox_lds_offset(int K) { return (tf_lds_bytes(K) + 15u) & ~15u; }
+__host__ __device__ inline uint32_t vbox_lds_bytes() { return (uint32_t)(kWgSize / kWaveSize) * kVBoxCells * 4u; }
+
 // Post-classification: (r, g, b, sigma) at value v; j and w of the segment;
 // `clamped` when u fell outside [0, K-1].
 struct Classified {
@@ -499,16 +668,6 @@ __device__ inline void lattice_point(const Ray &r, float step, int k, float &px,
   px = fmaf(sk, r.d[0], r.p0[0]);
   py = fmaf(sk, r.d[1], r.p0[1]);
   pz = fmaf(sk, r.d[2], r.p0[2]);
-}
-
-__device__ inline int wave_min_i32(int x) {
-  for (int off = 32; off > 0; off >>= 1) x = min(x, __shfl_xor(x, off, kWaveSize));
-  return __builtin_amdgcn_readfirstlane(x);
-}
-
-__device__ inline int wave_max_i32(int x) {
-  for (int off = 32; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off, kWaveSize));
-  return __builtin_amdgcn_readfirstlane(x);
 }
 
 // Blocks' minmax and TF decide occupancy.

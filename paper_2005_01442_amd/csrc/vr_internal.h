@@ -19,6 +19,8 @@ struct RenderArgs {
   float *out;                      // RGBA of the first view of this launch
   unsigned long long *counters;    // optional [evaluated, lattice, hit, -]
   int32_t W, H, n_views, chunk_edge;
+  int32_t use_box;                 // stage volume boxes in LDS (set at launch)
+  int32_t pad2;
   CamConst cams[kMaxCamsPerLaunch];
 };
 
@@ -31,6 +33,8 @@ struct BackwardArgs {
   int32_t use_box;         // stage the grid-gradient scatter in LDS boxes
   int32_t pad;
 };
+
+
 
 // Largest dynamic LDS a workgroup may allocate on the current device.
 uint32_t max_lds_per_workgroup();
