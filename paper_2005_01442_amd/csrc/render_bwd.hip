@@ -42,10 +42,11 @@ __device__ inline void scatter_taps(float *g, const VolConst &v, const Stencil &
 // atomic per touched voxel) and re-placed.  Steps whose stencils spread wider
 // than the box scatter straight to global memory.
 // ---------------------------------------------------------------------------
-constexpr int kBox = 16;
-// z stride of a box: kBox^2 + 4, so that the 64 taps (a + 16 b + kBoxZ c,
-// a, b, c < 4) of one stencil fall in 64 distinct LDS banks
-constexpr int kBoxZ = kBox * kBox + 4;
+constexpr int kBox = 14;   // box extent per axis
+constexpr int kBoxY = 16;  // y stride
+// z stride: with y stride 16 and z stride 228 the 64 taps a + 16 b + 228 c
+// (a, b, c < 4) of one stencil fall in 64 distinct LDS banks
+constexpr int kBoxZ = kBoxY * kBox + 4;
 constexpr int kBoxCells = kBox * kBoxZ;
 constexpr int kRec = 16;  // dwords per staged scatter record
 
@@ -70,7 +71,7 @@ __device__ inline void box_flush(GradBox &b, float *grad, const VolConst &v) {
   const int lane = threadIdx.x % kWaveSize;
   for (int i = lane; i < kBox * kBox * kBox; i += kWaveSize) {
     const int cx = i % kBox, cy = (i / kBox) % kBox, cz = i / (kBox * kBox);
-    const int cell = cz * kBoxZ + cy * kBox + cx;
+    const int cell = cz * kBoxZ + cy * kBoxY + cx;
     float val = b.cells[cell];
     if (val != 0.0f) {
       int x = b.ox + cx, y = b.oy + cy, z = b.oz + cz;
@@ -147,7 +148,7 @@ __device__ inline bool box_stage(GradBox &b, const VolConst &v, const Stencil &s
     *reinterpret_cast<f32x4 *>(rec + 0) = wx;
     *reinterpret_cast<f32x4 *>(rec + 4) = wy;
     *reinterpret_cast<f32x4 *>(rec + 8) = wz;
-    reinterpret_cast<int *>(rec)[12] = (st.iz - 1 - b.oz) * kBoxZ + (st.iy - 1 - b.oy) * kBox + (st.ix - 1 - b.ox);
+    reinterpret_cast<int *>(rec)[12] = (st.iz - 1 - b.oz) * kBoxZ + (st.iy - 1 - b.oy) * kBoxY + (st.ix - 1 - b.ox);
     return true;
   }
   int xs[4];
@@ -160,7 +161,7 @@ __device__ inline bool box_stage(GradBox &b, const VolConst &v, const Stencil &s
       int y = min(max(st.iy - 1 + bb, 0), v.ny - 1) - b.oy;
       float wb = wc * st.wy[bb];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) atomicAdd(b.cells + z * kBoxZ + y * kBox + xs[a], wb * st.wx[a]);
+      for (int a = 0; a < 4; ++a) atomicAdd(b.cells + z * kBoxZ + y * kBoxY + xs[a], wb * st.wx[a]);
     }
   }
   return false;
@@ -175,7 +176,7 @@ __device__ inline void box_apply(GradBox &b, unsigned long long staged) {
   __builtin_amdgcn_wave_barrier();
   const int l = threadIdx.x % kWaveSize;
   const int ta = l & 3, tb = (l >> 2) & 3, tc = l >> 4;
-  const int off = tc * kBoxZ + tb * kBox + ta;
+  const int off = tc * kBoxZ + tb * kBoxY + ta;
   while (staged) {
     const int sl = __ffsll((long long)staged) - 1;
     staged &= staged - 1ull;

@@ -39,12 +39,13 @@ __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfCon
   return make_float4(C0, C1, C2, 1.0f - T);
 }
 
-#ifndef VR_FWD_WAVES_PER_EU
-#define VR_FWD_WAVES_PER_EU 1
+// The LDS value boxes bound the workgroups per CU (14^3 boxes: three, i.e.
+// three wavefronts per SIMD); the register budget is set to match.
+#ifndef VR_FWD_MAX_WAVES
+#define VR_FWD_MAX_WAVES 3
 #endif
-
 template <int DT>
-__global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(VR_FWD_WAVES_PER_EU)))
+__global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(1, VR_FWD_MAX_WAVES)))
 void k_render(const RenderArgs args) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const RenderArgs &a = kernarg<RenderArgs>();

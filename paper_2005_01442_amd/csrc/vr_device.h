@@ -483,8 +483,12 @@ __device__ inline float reconstruct(__amdgpu_buffer_rsrc_t rs, const VolConst &v
 // refilled around them, extended along the marching direction; a step whose
 // stencils spread wider than the box reads from global memory.
 // ---------------------------------------------------------------------------
-constexpr int kVBox = 16;
+#ifndef VR_VBOX_EDGE
+#define VR_VBOX_EDGE 14
+#endif
+constexpr int kVBox = VR_VBOX_EDGE;
 constexpr int kVBoxZ = kVBox * kVBox + 4;  // padded z stride (LDS banks)
+static_assert(kVBox % 2 == 0 && kVBox >= 4 && kVBox <= 16, "box rows are filled in pairs from a 16-voxel window");
 constexpr int kVBoxCells = kVBox * kVBoxZ;
 
 struct ValBox {
@@ -503,16 +507,16 @@ __device__ inline void vbox_fill(ValBox &b, __amdgpu_buffer_rsrc_t rs, const Vol
     const uint32_t y = (uint32_t)min(max(b.oy + cy, 0), v.ny - 1);
     const uint32_t z = (uint32_t)min(max(b.oz + cz, 0), v.nz - 1);
     const uint32_t rowbase = (z * (uint32_t)v.ny + y) * (uint32_t)v.nx;
-    float t[kVBox];
-    if (b.ox >= 0 && b.ox + kVBox - 1 <= v.nx - 1 && Vox<DT>::row16_ok(rowbase + (uint32_t)b.ox, nvox)) {
+    float t[16];  // a 16-voxel window; the first kVBox are stored
+    if (b.ox >= 0 && b.ox + 15 <= v.nx - 1 && Vox<DT>::row16_ok(rowbase + (uint32_t)b.ox, nvox)) {
       Vox<DT>::row16(rs, rowbase + (uint32_t)b.ox, t);
     } else {
 #pragma unroll
       for (int i = 0; i < kVBox; ++i) t[i] = Vox<DT>::one(rs, rowbase + (uint32_t)min(max(b.ox + i, 0), v.nx - 1));
     }
-    f32x4 *dst = reinterpret_cast<f32x4 *>(b.cells + cz * kVBoxZ + cy * kVBox);
+    float2 *dst = reinterpret_cast<float2 *>(b.cells + cz * kVBoxZ + cy * kVBox);
 #pragma unroll
-    for (int j = 0; j < kVBox / 4; ++j) dst[j] = f32x4{t[4 * j], t[4 * j + 1], t[4 * j + 2], t[4 * j + 3]};
+    for (int j = 0; j < kVBox / 2; ++j) dst[j] = make_float2(t[2 * j], t[2 * j + 1]);
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -568,17 +572,32 @@ __device__ inline void vbox_prepare(ValBox &b, __amdgpu_buffer_rsrc_t rs, const 
 
 __device__ inline float reconstruct_box(const ValBox &b, const Stencil &s) {
   const float *base = b.cells + (s.iz - 1 - b.oz) * kVBoxZ + (s.iy - 1 - b.oy) * kVBox + (s.ix - 1 - b.ox);
+  // all 64 taps first (one base per z slice keeps the row offsets within the
+  // immediate offsets of paired LDS reads), then the separable FMA chain in
+  // the order of the global path
+  typedef __attribute__((address_space(3))) const float lds_float;
+  float t[4][4][4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    lds_float *zb = (lds_float *)(base + c * kVBoxZ);
+    // keep each slice base in its own register (otherwise rows past the
+    // 255-dword immediate range get one address add per LDS read)
+    asm volatile("" : "+v"(zb));
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) t[c][bb][a] = zb[bb * kVBox + a];
+  }
   float acc = 0.0f;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     float accy = 0.0f;
 #pragma unroll
     for (int bb = 0; bb < 4; ++bb) {
-      const float *t = base + c * kVBoxZ + bb * kVBox;
-      float r = s.wx[0] * t[0];
-      r = fmaf(s.wx[1], t[1], r);
-      r = fmaf(s.wx[2], t[2], r);
-      r = fmaf(s.wx[3], t[3], r);
+      float r = s.wx[0] * t[c][bb][0];
+      r = fmaf(s.wx[1], t[c][bb][1], r);
+      r = fmaf(s.wx[2], t[c][bb][2], r);
+      r = fmaf(s.wx[3], t[c][bb][3], r);
       accy = fmaf(s.wy[bb], r, accy);
     }
     acc = fmaf(s.wz[c], accy, acc);

@@ -204,3 +204,27 @@ def test_c1_full_size_sampled_pixels_and_invariants():
     log(f"c1 sampled {len(hit_rows)} hit pixels: max unflagged |dRGBA| = {un:.3e}, flagged = {nflag}")
     # the image is not trivially empty or saturated
     assert 0.05 < (img[..., 3] > 0.5).mean() < 0.95
+
+
+def test_c2_full_size_sampled_pixels():
+    """The large configuration (1024^3 int16, 2 GiB, to 2048^2, step 0.25,
+    skip, ERT 0.99) in the launch configuration of a full frame: sampled hit
+    pixels against the oracle, every pixel's lattice count exactly, skip vs
+    no-skip bit-identical over the frame."""
+    c = synth.config_c2()
+    log("c2: 1024^3 int16 -> 2048^2")
+    v = upload_volume(c["volume"])
+    blocks = vr.vr_build_blocks(v, 16)
+    img, ctr = gpu_render(None, c["cameras"], c["tf"], c["step"], ert=c["ert"], use_skip=True, counters=True,
+                          vol=v, blocks=blocks)
+    noskip = gpu_render(None, c["cameras"], c["tf"], c["step"], ert=c["ert"], use_skip=False, vol=v)
+    assert np.array_equal(img, noskip)
+    lat = oracle.lattice(c["cameras"], (1024, 1024, 1024), c["step"])
+    assert ctr[1] == lat.sum() and ctr[2] == (lat > 0).sum()
+    log(f"c2 evaluated={ctr[0]} lattice={ctr[1]} hit={ctr[2]}")
+    pix = synth.sample_pixels(1, 2048, 2048, 4000, seed=47)
+    hit_rows = pix[lat[0, pix[:, 1], pix[:, 2]] > 0][:2000]
+    ref = oracle.render(c["volume"], c["cameras"], c["tf"], c["step"], ert=c["ert"], pixels=hit_rows)
+    got = img[hit_rows[:, 0], hit_rows[:, 1], hit_rows[:, 2]]
+    un, nflag = compare_with_flags(got, ref["rgba"], ref["flags"], c["ert"])
+    log(f"c2 sampled {len(hit_rows)} hit pixels: max unflagged |dRGBA| = {un:.3e}, flagged = {nflag}")
