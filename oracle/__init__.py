@@ -49,12 +49,33 @@ def build(force: bool = True) -> str:
 _lib = None
 
 
+def load(path: str):
+    """Load an oracle shared library from ``path`` with its prototypes."""
+    L = ctypes.CDLL(path)
+    _prototypes(L)
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             build()
-        L = ctypes.CDLL(_LIB_PATH)
+        _lib = load(_LIB_PATH)
+    return _lib
+
+
+def use(library):
+    """Make ``library`` (a handle from ``load``) the one every call goes
+    through; returns the previous one.  Used by the mutation tests."""
+    global _lib
+    prev = _lib
+    _lib = library
+    return prev
+
+
+def _prototypes(L):
+    if True:
         P = ctypes.c_void_p
         i64 = ctypes.c_long
         i32 = ctypes.c_int
@@ -79,8 +100,6 @@ def lib():
         L.oracle_weights.restype = None
         L.oracle_lattice.argtypes = [P, i32, i32, i32, i64, i64, i64, f64, P]
         L.oracle_lattice.restype = i32
-        _lib = L
-    return _lib
 
 
 def f32(x) -> float:

@@ -1,0 +1,74 @@
+"""Strength of the oracle pins: plausible mistakes planted in copies of
+oracle.c (on the CPU) must each make at least one pin fail."""
+
+import os
+import subprocess
+
+import pytest
+
+import oracle
+import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
+
+MUTANTS = {
+    "bspline_w1_w2_swapped": (
+        "w[1] = (3.0 * f * f * f - 6.0 * f * f + 4.0) / 6.0;\n    w[2] = (-3.0 * f * f * f + 3.0 * f * f + 3.0 * f + 1.0) / 6.0;",
+        "w[2] = (3.0 * f * f * f - 6.0 * f * f + 4.0) / 6.0;\n    w[1] = (-3.0 * f * f * f + 3.0 * f * f + 3.0 * f + 1.0) / 6.0;",
+    ),
+    "bspline_w2_sign": ("w[2] = (-3.0 * f * f * f", "w[2] = (3.0 * f * f * f"),
+    "bspline_w0_w3_swapped": ("w[0] = g * g * g / 6.0;", "w[0] = f * f * f / 6.0;"),
+    "tf_weights_swapped": (
+        "out[c] = (1.0 - w) * (double)tf[4 * j + c] + w * (double)tf[4 * (j + 1) + c];",
+        "out[c] = w * (double)tf[4 * j + c] + (1.0 - w) * (double)tf[4 * (j + 1) + c];",
+    ),
+    "opacity_without_step": ("double alpha = -expm1(-val[3] * cx->step);", "double alpha = -expm1(-val[3]);"),
+    "sample_at_segment_start": ("double t = ((double)k + 0.5) * cx->step;", "double t = ((double)k) * cx->step;"),
+    "camera_axes_transposed": ("d[k] = f[k] + a * r[k] + b * u[k];", "d[k] = f[k] + a * u[k] + b * r[k];"),
+    "ert_late": ("if (1.0 - T >= cx->ert) break;", "if (1.0 - T >= cx->ert + 0.05) break;"),
+    "adjoint_drops_suffix": ("ds += g[c] * (Tnext * r->val[c] - S[c]);", "ds += g[c] * (Tnext * r->val[c]);"),
+    "adjoint_alpha_sign": ("dval[c] = g[c] * r->Tk * r->alpha;", "dval[c] = -g[c] * r->Tk * r->alpha;"),
+    "footprint_low_apron_dropped": ("long x0 = or_clampl(bx * edge - 1, 0, nx - 1)", "long x0 = or_clampl(bx * edge, 0, nx - 1)"),
+    "occupancy_margin_dropped": ("long jlo = (long)floorf(ulo) - 1, jhi = (long)ceilf(uhi) + 1;",
+                                 "long jlo = (long)floorf(ulo), jhi = (long)ceilf(uhi);"),
+}
+
+PINS = [
+    pins.test_bspline_weights_worked_values,
+    pins.test_bspline_weights_match_kernel_everywhere,
+    pins.test_clamp_edge_worked_examples,
+    pins.test_reconstruction_matches_rational_brute_force,
+    pins.test_beer_lambert_axis_aligned_slab,
+    pins.test_beer_lambert_oblique_rays,
+    pins.test_oracle_matches_brute_force_tiny_volume,
+    pins.test_oracle_matches_brute_force_table_tf_and_ert,
+    pins.test_blocks_match_numpy_footprint,
+    pins.test_occupancy_perturbation,
+    pins.test_grad_closed_form_homogeneous_medium,
+    pins.test_grad_volume_matches_central_differences,
+    pins.test_grad_tf_matches_central_differences,
+]
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site of {name} not found exactly once"
+    mutant_c = tmp_path / "oracle_mutant.c"
+    mutant_c.write_text(src.replace(old, new))
+    so = tmp_path / "liboracle_mutant.so"
+    subprocess.run(["gcc", "-O1", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off", "-o", str(so),
+                    str(mutant_c), "-lm"], check=True)
+    prev = oracle.use(oracle.load(str(so)))
+    caught = []
+    try:
+        for pin in PINS:
+            try:
+                pin(None)
+            except AssertionError:
+                caught.append(pin.__name__)
+                break
+    finally:
+        oracle.use(prev)
+    assert caught, f"no pin caught the planted mistake {name}"

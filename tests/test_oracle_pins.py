@@ -285,6 +285,15 @@ def test_occupancy_perturbation(oracle_lib):
             t2 = synth.TransferFunction(tf.table.copy(), tf.v0, tf.v1)
             t2.table[jj, 3] = 0.01
             assert oracle.occupancy(mm, t2)[b] == 1
+    # the one-node margin on each side of the range is part of the definition
+    for b in empties[:5]:
+        ulo = (np.float32(mm[b, 0]) - np.float32(tf.v0)) * scale
+        uhi = (np.float32(mm[b, 1]) - np.float32(tf.v0)) * scale
+        for jj in (int(np.floor(ulo)) - 1, int(np.ceil(uhi)) + 1):
+            if 0 <= jj < tf.K:
+                t2 = synth.TransferFunction(tf.table.copy(), tf.v0, tf.v1)
+                t2.table[jj, 3] = 0.01
+                assert oracle.occupancy(mm, t2)[b] == 1
     # a node far above every block's range changes nothing
     t3 = synth.TransferFunction(tf.table.copy(), tf.v0, tf.v1)
     t3.table[250, 3] = 0.0
