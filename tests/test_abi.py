@@ -107,6 +107,10 @@ def test_validation_without_device(abi):
     p.use_skip = 1
     rc = L.vr_render(ctypes.byref(vol), None, ctypes.byref(cam), 1, ctypes.byref(tf), ctypes.byref(p), None, None)
     assert rc == 1 and b"use_skip needs blocks" in L.vr_last_error()
+    p.use_skip = 0
+    rc = L.vr_render(ctypes.byref(vol), None, ctypes.byref(cam), 0, ctypes.byref(tf), ctypes.byref(p), None, None)
+    assert rc == 1 and b"at least one camera" in L.vr_last_error()
+    p.use_skip = 1
     vol.nx = 1 << 21
     rc = L.vr_render(ctypes.byref(vol), None, ctypes.byref(cam), 1, ctypes.byref(tf), ctypes.byref(p), None, None)
     assert rc == 2  # VR_E_UNSUPPORTED: over the per-volume size limit

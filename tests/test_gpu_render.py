@@ -228,3 +228,41 @@ def test_c2_full_size_sampled_pixels():
     got = img[hit_rows[:, 0], hit_rows[:, 1], hit_rows[:, 2]]
     un, nflag = compare_with_flags(got, ref["rgba"], ref["flags"], c["ert"])
     log(f"c2 sampled {len(hit_rows)} hit pixels: max unflagged |dRGBA| = {un:.3e}, flagged = {nflag}")
+
+
+def test_degenerate_transfer_functions_and_parameters():
+    """All-transparent TF (every block empty: the march leaps through the whole
+    volume and the image is exactly zero), near-opaque TF with ERT, the
+    smallest (K = 2) and largest (K = 1024) tables, a step longer than the
+    volume, an ERT threshold just above zero, a camera on a box face."""
+    vol = _small_ct((40, 36, 32), 48)
+    dims = (40, 36, 32)
+    cams = synth.orbit_cameras(dims, 2, 49, 60.0, 32, 24)
+    empty = synth.tf_from_points([(-1024, (1, 1, 1, 0)), (3056, (1, 1, 1, 0))], 256, -1024.0, 3056.0)
+    img, ctr = gpu_render(vol, cams, empty, 0.5, ert=0.99, use_skip=True, counters=True)
+    assert np.all(img == 0.0) and ctr[0] == 0 and ctr[1] > 0
+    opaque = synth.tf_from_points([(-1024, (0.2, 0.3, 0.4, 50.0)), (3056, (0.9, 0.1, 0.5, 50.0))], 16,
+                                  -1024.0, 3056.0)
+    k2 = synth.tf_from_points([(-1024, (0, 0, 0, 0)), (3056, (1, 0.5, 0.25, 0.02))], 2, -1024.0, 3056.0)
+    k1024 = synth.tf_from_points(synth.TF1_POINTS, 1024, -1024.0, 3056.0)
+    face = synth.Camera(1, np.array([19.5, 17.5, -0.5]), np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0]),
+                        np.array([0.0, 0.0, 1.0]), fov_y=np.deg2rad(70.0), width=32, height=24)
+    cases = [
+        (opaque, cams, 0.5, 0.99),
+        (k2, cams, 0.5, 0.0),
+        (k1024, cams, 0.5, 0.99),
+        (synth.tf1(), cams, 200.0, 0.0),
+        (opaque, cams, 0.5, 1e-6),
+        (synth.tf1(), [face], 0.5, 0.99),
+    ]
+    for tf, cs, step, ert in cases:
+        img = gpu_render(vol, cs, tf, step, ert=ert, use_skip=True)
+        ref = oracle.render(vol, cs, tf, step, ert=ert)
+        compare_with_flags(img, ref["rgba"], ref["flags"], ert if ert else 1.0)
+
+
+def test_empty_view_list_is_rejected():
+    vol = upload_volume(_small_ct((16, 16, 16), 50))
+    t = upload_tf(synth.tf1())
+    with pytest.raises((vr.VrError, IndexError)):
+        vr.vr_render(vol, None, [], t, 0.5)
