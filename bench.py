@@ -58,6 +58,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "render_fwd_c1_traffic.json"))
+    ap.add_argument("--no-c3", action="store_true", help="skip the differentiable 256^3 x 64-view measurement")
     return ap.parse_args()
 
 
@@ -121,6 +122,49 @@ def cpu_baseline(c, lattice, seconds):
         cores=oracle.num_threads(),
         kind="oracle",
         sample=f"{n} seeded hit pixels of the 1024^2 frame (skip + ERT 0.99), FP64, OpenMP over pixels",
+    )
+
+
+def differentiable_c3(vr, torch, steps=3):
+    """Forward + adjoint of the differentiable workload: 256^3 fp32 density
+    grid, 64 views of 512^2, step 0.5, no skipping (the TF gradient needs
+    every sample), loss = MSE against renders of a perturbed grid."""
+    import synth
+    from synth.configs import c3_perturbed_grid
+
+    c = synth.config_c3()
+    target_grid = torch.from_numpy(c["volume"]).cuda()
+    grid = torch.from_numpy(c3_perturbed_grid(c["volume"])).cuda()
+    table = torch.from_numpy(c["tf"].table).cuda()
+    tf = vr.TF(table, c["tf"].v0, c["tf"].v1)
+    cams = c["cameras"]
+    target = vr.vr_render(vr.Volume(target_grid), None, cams, tf, c["step"])
+    vol = vr.Volume(grid)
+    ctr = torch.zeros(4, dtype=torch.int64, device="cuda")
+    vr.vr_render(vol, None, cams, tf, c["step"], counters=ctr)
+    torch.cuda.synchronize()
+    lattice = int(ctr[1].item())
+
+    def step():
+        img = vr.vr_render(vol, None, cams, tf, c["step"])
+        g = (img - target) * (2.0 / img.numel())
+        return vr.vr_render_backward(vol, None, cams, tf, c["step"], 0.0, False, img, g)
+
+    def fwd():
+        vr.vr_render(vol, None, cams, tf, c["step"])
+
+    wall_f, _ = time_steps(fwd, steps, 1, torch)
+    wall_fb, _ = time_steps(step, steps, 1, torch)
+    rays = len(cams) * cams[0].width * cams[0].height
+    return dict(
+        workload="c3_density256_f32_64x512x512_step0.5",
+        lattice_samples_per_step=lattice,
+        fwd_ms=wall_f / steps * 1e3,
+        fwd_bwd_ms=wall_fb / steps * 1e3,
+        fwd_samples_per_s=lattice / (wall_f / steps),
+        fwd_bwd_samples_per_s=lattice / (wall_fb / steps),
+        fwd_bwd_rays_per_s=rays / (wall_fb / steps),
+        note="all lattice samples evaluated (no skipping: TF gradient requested); loss = MSE vs perturbed-grid renders",
     )
 
 
@@ -229,8 +273,9 @@ def main():
     ctr = torch.zeros(4, dtype=torch.int64, device="cuda")
     vr.vr_render(vol, blocks, cams, tf, c["step"], c["ert"], True, out=out, counters=ctr)
     torch.cuda.synchronize()
-    evaluated, lattice_total, hit = (int(x) for x in ctr.cpu().numpy()[:3])
-    log(f"frame: evaluated {evaluated:.4g} samples, lattice {lattice_total:.4g}, hit rays {hit}")
+    evaluated, lattice_total, hit, unstaged = (int(x) for x in ctr.cpu().numpy()[:4])
+    log(f"frame: evaluated {evaluated:.4g} samples, lattice {lattice_total:.4g}, hit rays {hit}, "
+        f"unstaged {unstaged / max(evaluated, 1):.3f}")
 
     def fwd():
         vr.vr_render(vol, blocks, cams, tf, c["step"], c["ert"], True, out=out)
@@ -272,6 +317,7 @@ def main():
         "evaluated_samples_per_frame": evaluated,
         "lattice_samples_per_frame": lattice_total,
         "hit_rays_per_frame": hit,
+        "unstaged_sample_fraction": unstaged / max(evaluated, 1),
         "kernel_ms": kern_ms,
         "block_build_ms": float(np.mean(ev_b)),
     }
@@ -312,6 +358,11 @@ def main():
         }
         log(f"fwd+bwd: {ms_fb:.3f} ms/step")
         del gv_holder
+
+    if not args.no_c3:
+        log("differentiable 256^3 fp32, 64 views of 512^2")
+        result["c3_fwd_bwd"] = differentiable_c3(vr, torch)
+        log(f"c3: fwd {result['c3_fwd_bwd']['fwd_ms']:.2f} ms, fwd+bwd {result['c3_fwd_bwd']['fwd_bwd_ms']:.2f} ms")
 
     if not args.no_serve:
         log("serving mix")

@@ -108,8 +108,9 @@ typedef struct {
  *                  image is bit-identical to rendering without skipping.
  *   counters       optional DEVICE uint64_t[4] that the render ADDS to:
  *                  [0] evaluated samples, [1] lattice samples, [2] rays with
- *                  at least one lattice sample, [3] reserved.  NULL = not
- *                  counted. */
+ *                  at least one lattice sample, [3] evaluated samples whose
+ *                  taps were read from global memory rather than from an
+ *                  LDS-staged box.  NULL = not counted. */
 typedef struct {
     float step;
     float ert_threshold;

@@ -176,7 +176,8 @@ def vr_render(volume: Volume, blocks, cameras, tf: TF, step: float, ert: float =
               out: torch.Tensor | None = None, counters: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """Render len(cameras) views; returns (views, H, W, 4) fp32 premultiplied RGBA.
     ``counters``: optional int64 CUDA tensor of 4 that the kernel adds
-    [evaluated samples, lattice samples, hit rays, 0] to."""
+    [evaluated samples, lattice samples, rays with samples, samples read from
+    global memory instead of an LDS box] to."""
     W, H = int(cameras[0].width), int(cameras[0].height)
     if out is None:
         out = torch.empty((len(cameras), H, W, 4), dtype=torch.float32, device=volume.tensor.device)

@@ -14,7 +14,8 @@ namespace vr {
 // result is bit-identical to marching every sample.
 template <int DT>
 __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfConst &tf, const MarchConst &mc,
-                               const Ray &r, __amdgpu_buffer_rsrc_t rs, ValBox &box, uint32_t &evaluated) {
+                               const Ray &r, __amdgpu_buffer_rsrc_t rs, ValBox &box, uint32_t &evaluated,
+                               uint32_t &unstaged) {
   float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, T = 1.0f;
   const float sl2 = mc.step * 1.4426950408889634f;
   const bool ert_on = mc.ert > 0.0f && mc.ert < 1.0f;
@@ -23,7 +24,13 @@ __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfCon
   };
   auto visit = [&](int, float px, float py, float pz) -> bool {
     Stencil st = make_stencil(px, py, pz);
-    float val = box.valid ? reconstruct_box(box, st) : reconstruct<DT>(rs, v, st);
+    float val;
+    if (box.valid) {
+      val = reconstruct_box(box, st);
+    } else {
+      val = reconstruct<DT>(rs, v, st);
+      ++unstaged;
+    }
     Classified q = classify(s, tf.K, tf.v0, tf.scale, val);
     float e = transmit(q.c.w, sl2);
     float ta = T * (1.0f - e);
@@ -57,7 +64,7 @@ void k_render(const RenderArgs args) {
   pixel_of(st.sx, st.sy, col, row);
   const bool inside = col < a.W && row < a.H;
   const CamConst &cam = a.cams[st.view];
-  uint32_t evaluated = 0;
+  uint32_t evaluated = 0, unstaged = 0;
   // every lane enters the march (it steps the wavefront in unison); pixels
   // outside the image carry an empty ray
   Ray r;
@@ -72,7 +79,7 @@ void k_render(const RenderArgs args) {
   box.cells = a.use_box ? reinterpret_cast<float *>(lds + vbox_lds_offset(a.tf.K)) +
                               (threadIdx.x / kWaveSize) * kVBoxCells
                         : nullptr;
-  float4 rgba = march<DT>(a.vol, s, a.tf, a.mc, r, rs, box, evaluated);
+  float4 rgba = march<DT>(a.vol, s, a.tf, a.mc, r, rs, box, evaluated, unstaged);
   if (inside) {
     float4 *o = reinterpret_cast<float4 *>(a.out);
     o[((size_t)st.view * a.H + row) * a.W + col] = rgba;
@@ -81,6 +88,7 @@ void k_render(const RenderArgs args) {
     wave_count(a.counters + 0, evaluated);
     wave_count(a.counters + 1, (uint32_t)r.ns);
     wave_count(a.counters + 2, r.hit ? 1u : 0u);
+    wave_count(a.counters + 3, unstaged);
   }
 }
 
@@ -128,7 +136,7 @@ __global__ __launch_bounds__(kWgSize) void k_serve(const ServeSlot *slots, const
   r.k0 = 0;
   if (inside) r = setup_ray(sl.cam, col, row, sl.vol.nx, sl.vol.ny, sl.vol.nz, sl.mc.step);
   __amdgpu_buffer_rsrc_t rs = make_rsrc(sl.vol.data, sl.vol.bytes);
-  uint32_t evaluated = 0;
+  uint32_t evaluated = 0, unstaged = 0;
   ValBox box;
   box.valid = false;
   box.ox = box.oy = box.oz = 0;
@@ -136,9 +144,9 @@ __global__ __launch_bounds__(kWgSize) void k_serve(const ServeSlot *slots, const
                       : nullptr;
   float4 rgba;
   switch (sl.vol.dtype) {  // uniform over the workgroup
-  case kU16: rgba = march<kU16>(sl.vol, s, sl.tf, sl.mc, r, rs, box, evaluated); break;
-  case kI16: rgba = march<kI16>(sl.vol, s, sl.tf, sl.mc, r, rs, box, evaluated); break;
-  default: rgba = march<kF32>(sl.vol, s, sl.tf, sl.mc, r, rs, box, evaluated); break;
+  case kU16: rgba = march<kU16>(sl.vol, s, sl.tf, sl.mc, r, rs, box, evaluated, unstaged); break;
+  case kI16: rgba = march<kI16>(sl.vol, s, sl.tf, sl.mc, r, rs, box, evaluated, unstaged); break;
+  default: rgba = march<kF32>(sl.vol, s, sl.tf, sl.mc, r, rs, box, evaluated, unstaged); break;
   }
   if (inside) reinterpret_cast<float4 *>(sl.out)[(size_t)row * sl.cam.W + col] = rgba;
 }
