@@ -100,6 +100,13 @@ def _prototypes(L):
         L.oracle_weights.restype = None
         L.oracle_lattice.argtypes = [P, i32, i32, i32, i64, i64, i64, f64, P]
         L.oracle_lattice.restype = i32
+        L.oracle_render_shaded.argtypes = [P, i32, i64, i64, i64, P, i32, i32, i32, P, i32, f64, f64, f64, f64,
+                                           P, i32, P, P, i64, P, P, P]
+        L.oracle_render_shaded.restype = i32
+        L.oracle_gradient.argtypes = [P, i32, i64, i64, i64, f64, f64, f64, P]
+        L.oracle_gradient.restype = None
+        L.oracle_dweights.argtypes = [f64, P]
+        L.oracle_dweights.restype = None
 
 
 def f32(x) -> float:
@@ -158,9 +165,20 @@ def occupancy(minmax, tf) -> np.ndarray:
     return occ
 
 
-def render(vol, cameras, tf, step, ert=0.0, occ=None, edge=16, pixels=None):
+def shade_params(sh) -> np.ndarray:
+    """The oracle's 9 lighting doubles (ambient, diffuse, specular, shininess,
+    light x, y, z, headlight flag, grad_min) from a mapping or an object with
+    those fields; the scalars are rounded to the fp32 the GPU ABI carries."""
+    get = (lambda k: sh[k]) if isinstance(sh, dict) else (lambda k: getattr(sh, k))
+    light = [f32(x) for x in get("light")]
+    return np.array([f32(get("ambient")), f32(get("diffuse")), f32(get("specular")), f32(get("shininess")),
+                     *light, 1.0 if get("headlight") else 0.0, f32(get("grad_min"))], dtype=np.float64)
+
+
+def render(vol, cameras, tf, step, ert=0.0, occ=None, edge=16, pixels=None, shading=None):
     """FP64 render.  Returns dict(rgba, flags, counts); rgba is (views, H, W, 4)
-    for a full render or (n, 4) for a pixel list."""
+    for a full render or (n, 4) for a pixel list.  ``shading`` (see
+    ``shade_params``) switches on local lighting."""
     vol, dt, nx, ny, nz = _vol(vol)
     cams = pack_cameras(cameras)
     W, H = int(cameras[0].width), int(cameras[0].height)
@@ -177,11 +195,19 @@ def render(vol, cameras, tf, step, ert=0.0, occ=None, edge=16, pixels=None):
     rgba = np.zeros(shape + (4,), dtype=np.float64)
     flags = np.zeros(shape, dtype=np.uint8)
     counts = np.zeros(shape + (2,), dtype=np.int64)
-    rc = lib().oracle_render(
-        _ptr(vol), dt, nx, ny, nz, _ptr(cams), len(cameras), W, H, _ptr(table), table.shape[0],
-        f32(tf.v0), f32(tf.v1), f32(step), f32(ert), _ptr(occ_a), int(edge), _ptr(pix), n,
-        _ptr(rgba), _ptr(flags), _ptr(counts),
-    )
+    if shading is None:
+        rc = lib().oracle_render(
+            _ptr(vol), dt, nx, ny, nz, _ptr(cams), len(cameras), W, H, _ptr(table), table.shape[0],
+            f32(tf.v0), f32(tf.v1), f32(step), f32(ert), _ptr(occ_a), int(edge), _ptr(pix), n,
+            _ptr(rgba), _ptr(flags), _ptr(counts),
+        )
+    else:
+        sp = shade_params(shading)
+        rc = lib().oracle_render_shaded(
+            _ptr(vol), dt, nx, ny, nz, _ptr(cams), len(cameras), W, H, _ptr(table), table.shape[0],
+            f32(tf.v0), f32(tf.v1), f32(step), f32(ert), _ptr(occ_a), int(edge), _ptr(sp), _ptr(pix), n,
+            _ptr(rgba), _ptr(flags), _ptr(counts),
+        )
     if rc:
         raise ValueError("oracle_render rejected its arguments")
     return dict(rgba=rgba, flags=flags, counts=counts)
@@ -241,3 +267,18 @@ def weights(f) -> np.ndarray:
     w = np.zeros(4, dtype=np.float64)
     lib().oracle_weights(float(f), _ptr(w))
     return w
+
+
+def dweights(f) -> np.ndarray:
+    """Derivatives of the four B-spline weights at fractional offset f."""
+    d = np.zeros(4, dtype=np.float64)
+    lib().oracle_dweights(float(f), _ptr(d))
+    return d
+
+
+def gradient(vol, p) -> np.ndarray:
+    """Analytic gradient of the tricubic reconstruction of ``vol`` at p."""
+    vol, dt, nx, ny, nz = _vol(vol)
+    g = np.zeros(3, dtype=np.float64)
+    lib().oracle_gradient(_ptr(vol), dt, nx, ny, nz, float(p[0]), float(p[1]), float(p[2]), _ptr(g))
+    return g

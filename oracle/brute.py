@@ -12,7 +12,9 @@ to differ from ``oracle.c``:
     that lie on the box (not by the slab method);
   * the transfer function is evaluated either as an explicit function of the
     value, or by a linear search for the node interval of the table;
-  * compositing uses alpha = 1 - exp(-sigma step) and T <- T (1 - alpha).
+  * compositing uses alpha = 1 - exp(-sigma step) and T <- T (1 - alpha);
+  * the gradient for local lighting differentiates the kernel sum exactly
+    (beta' in rationals), not the per-offset weight polynomials.
 Only exp and the square root of the direction normalisation are floating
 point; positions are converted exactly to rationals.
 """
@@ -50,6 +52,56 @@ def reconstruct(vol, p):
                 zc = min(max(z, 0), nz - 1)
                 total += wx * wy * wz * Fraction(vol[zc][yc][xc])
     return total
+
+
+def bspline_kernel_deriv(x: Fraction) -> Fraction:
+    """beta'(x): -2x + 3x|x|/2 for |x| < 1, -sign(x) (2 - |x|)^2 / 2 for 1 <= |x| < 2."""
+    ax = abs(x)
+    sgn = 1 if x > 0 else (-1 if x < 0 else 0)
+    if ax < 1:
+        return -2 * x + Fraction(3, 2) * x * ax
+    if ax < 2:
+        return -sgn * (2 - ax) ** 2 / 2
+    return Fraction(0)
+
+
+def gradient(vol, p):
+    """Exact gradient of the tricubic B-spline reconstruction at p (d/dp of
+    the 64-term kernel sum), clamp-to-edge addressing; three Fractions."""
+    nz, ny, nx = len(vol), len(vol[0]), len(vol[0][0])
+    px, py, pz = (Fraction(c) for c in p)
+    fx, fy, fz = math.floor(px), math.floor(py), math.floor(pz)
+    g = [Fraction(0)] * 3
+    for z in range(fz - 1, fz + 3):
+        for y in range(fy - 1, fy + 3):
+            for x in range(fx - 1, fx + 3):
+                v = Fraction(vol[min(max(z, 0), nz - 1)][min(max(y, 0), ny - 1)][min(max(x, 0), nx - 1)])
+                kx, ky, kz = bspline_kernel(px - x), bspline_kernel(py - y), bspline_kernel(pz - z)
+                g[0] += bspline_kernel_deriv(px - x) * ky * kz * v
+                g[1] += kx * bspline_kernel_deriv(py - y) * kz * v
+                g[2] += kx * ky * bspline_kernel_deriv(pz - z) * v
+    return g
+
+
+def lit_colour(sh, d, g, c):
+    """Blinn-Phong two-sided lighting of colour c (3 floats) at a sample with
+    ray direction d and field gradient g; sh = (ka, kd, ks, shininess,
+    (lx, ly, lz), headlight, grad_min)."""
+    ka, kd, ks, shin, light, headlight, gmin = sh
+    eye = [-x for x in d]
+    if headlight:
+        L = list(eye)
+    else:
+        ln = math.sqrt(sum(x * x for x in light))
+        L = [x / ln for x in light]
+    half = [L[k] + eye[k] for k in range(3)]
+    hn = math.sqrt(sum(x * x for x in half))
+    gn = math.sqrt(sum(float(x) ** 2 for x in g))
+    scale = max(gn, gmin)
+    normal = [-float(x) / scale for x in g]
+    diffuse = abs(sum(normal[k] * L[k] for k in range(3)))
+    spec = 0.0 if hn <= 1e-12 else abs(sum(normal[k] * half[k] for k in range(3)) / hn) ** shin
+    return [c[k] * (ka + kd * diffuse) + ks * spec for k in range(3)]
 
 
 def camera_ray(cam, row, col):
@@ -109,8 +161,9 @@ def tf_table_lookup(table, v0, v1, v):
     return list(table[K - 1])
 
 
-def composite_ray(vol, o, d, step, classify, ert=0.0):
-    """Front-to-back emission-absorption along one ray; returns (rgba, n_samples)."""
+def composite_ray(vol, o, d, step, classify, ert=0.0, shade=None):
+    """Front-to-back emission-absorption along one ray; returns (rgba, n_samples).
+    ``shade`` (the tuple of ``lit_colour``) lights every sample's colour."""
     dims = (len(vol[0][0]), len(vol[0]), len(vol))
     hit = clip_planes(o, d, dims)
     if hit is None:
@@ -128,6 +181,8 @@ def composite_ray(vol, o, d, step, classify, ert=0.0):
         p = [o[c] + t * d[c] for c in range(3)]
         v = float(reconstruct(vol, p))
         r, g, b, sigma = classify(v)
+        if shade is not None:
+            r, g, b = lit_colour(shade, d, gradient(vol, p), (r, g, b))
         alpha = 1.0 - math.exp(-sigma * step)
         C = [C[0] + T * alpha * r, C[1] + T * alpha * g, C[2] + T * alpha * b]
         T = T * (1.0 - alpha)
@@ -138,6 +193,6 @@ def composite_ray(vol, o, d, step, classify, ert=0.0):
     return [C[0], C[1], C[2], 1.0 - T], n
 
 
-def brute_pixel(vol, cam, row, col, step, classify, ert=0.0):
+def brute_pixel(vol, cam, row, col, step, classify, ert=0.0, shade=None):
     o, d = camera_ray(cam, row, col)
-    return composite_ray(vol, o, d, step, classify, ert)
+    return composite_ray(vol, o, d, step, classify, ert, shade)

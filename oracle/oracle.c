@@ -256,6 +256,80 @@ static void or_reconstruct(const or_vol *vol, const double p[3], or_sample *s)
     s->v = v;
 }
 
+/* Derivative with respect to f of the four B-spline weights above: the     */
+/* paper computes the gradient for local lighting with the same cubic       */
+/* filter (Section 2, the three-voxel block overlap paragraph), i.e. the    */
+/* gradient of the reconstructed field itself.                             */
+static void or_bspline_deriv(double f, double d[4])
+{
+    double g = 1.0 - f;
+    d[0] = -g * g / 2.0;
+    d[1] = (9.0 * f * f - 12.0 * f) / 6.0;
+    d[2] = (-9.0 * f * f + 6.0 * f + 3.0) / 6.0;
+    d[3] = f * f / 2.0;
+}
+
+/* Analytic gradient of the tricubic reconstruction at p: per axis, the     */
+/* explicit 64-term sum with that axis' weights replaced by derivative      */
+/* weights (clamp-to-edge addressing as in the value).                      */
+static void or_gradient(const or_vol *vol, const double p[3], double g[3])
+{
+    long ix = (long)floor(p[0]), iy = (long)floor(p[1]), iz = (long)floor(p[2]);
+    double w[3][4], dw[3][4];
+    long base[3] = {ix, iy, iz};
+    for (int a = 0; a < 3; ++a) {
+        or_bspline(p[a] - (double)base[a], w[a]);
+        or_bspline_deriv(p[a] - (double)base[a], dw[a]);
+    }
+    g[0] = g[1] = g[2] = 0.0;
+    for (int c = 0; c < 4; ++c)
+        for (int b = 0; b < 4; ++b)
+            for (int a = 0; a < 4; ++a) {
+                long x = or_clampl(ix - 1 + a, 0, vol->nx - 1);
+                long y = or_clampl(iy - 1 + b, 0, vol->ny - 1);
+                long z = or_clampl(iz - 1 + c, 0, vol->nz - 1);
+                double V = or_voxel(vol, x, y, z);
+                g[0] += dw[0][a] * w[1][b] * w[2][c] * V;
+                g[1] += w[0][a] * dw[1][b] * w[2][c] * V;
+                g[2] += w[0][a] * w[1][b] * dw[2][c] * V;
+            }
+}
+
+/* Local lighting (Section 2: Phong's model, with the gradient of the      */
+/* cubic reconstruction as the surface normal).  shade = 9 doubles: ka, kd, */
+/* ks, shininess, light direction (3, towards the light, any length),      */
+/* headlight flag (nonzero: the light sits at the eye), grad_min.          */
+/* The sample colour c becomes                                              */
+/*   c (ka + kd |n.L|) + ks |n.H|^shininess                                 */
+/* with V = -d the direction to the eye, L = V for a headlight, else the    */
+/* normalised light direction, H = (L + V)/|L + V| (no specular when L = -V) */
+/* and n = -g / max(|g|, grad_min): the unit normal where the gradient is  */
+/* at least grad_min, shrinking to zero with it below (flat regions get    */
+/* ambient light only).  |.| makes the lighting two-sided.  Opacity is      */
+/* unchanged.                                                               */
+static void or_shade_colour(const double *sh, const double d[3], const double g[3], double c[3])
+{
+    double V[3] = {-d[0], -d[1], -d[2]}, L[3];
+    if (sh[7] != 0.0) {
+        for (int a = 0; a < 3; ++a) L[a] = V[a];
+    } else {
+        double ln = sqrt(sh[4] * sh[4] + sh[5] * sh[5] + sh[6] * sh[6]);
+        for (int a = 0; a < 3; ++a) L[a] = sh[4 + a] / ln;
+    }
+    double Hs[3] = {L[0] + V[0], L[1] + V[1], L[2] + V[2]};
+    double hn = sqrt(Hs[0] * Hs[0] + Hs[1] * Hs[1] + Hs[2] * Hs[2]);
+    double gm = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    double m = gm > sh[8] ? gm : sh[8];
+    double n[3] = {-g[0] / m, -g[1] / m, -g[2] / m};
+    double nl = fabs(n[0] * L[0] + n[1] * L[1] + n[2] * L[2]);
+    double spec = 0.0;
+    if (hn > 1e-12) {
+        double nh = fabs(n[0] * Hs[0] + n[1] * Hs[1] + n[2] * Hs[2]) / hn;
+        spec = pow(nh, sh[3]);
+    }
+    for (int a = 0; a < 3; ++a) c[a] = c[a] * (sh[0] + sh[1] * nl) + sh[2] * spec;
+}
+
 /* Post-classification: T(V) on the interpolated value.  Node j sits at      */
 /* v0 + j (v1 - v0)/(K-1); u is clamped to [0, K-1]; linear between nodes.   */
 /* Outputs (r, g, b, sigma), the segment j, its weight w and whether u was   */
@@ -290,6 +364,7 @@ typedef struct {
     double v0, v1, step, ert;
     const uint8_t *occ; /* NULL: no skipping */
     int edge;
+    const double *shade; /* NULL: no local lighting */
 } or_ctx;
 
 /* Sample lattice: the ray moves from its origin (the observer) with the     */
@@ -352,6 +427,11 @@ static void or_trace(const or_ctx *cx, long view, long row, long col, double rgb
         long j;
         int cl;
         or_classify(cx->tf, cx->K, cx->v0, cx->v1, s.v, val, &j, &w, &cl);
+        if (cx->shade) {
+            double g[3];
+            or_gradient(cx->vol, p, g);
+            or_shade_colour(cx->shade, d, g, val);
+        }
         double alpha = -expm1(-val[3] * cx->step);
         for (int c = 0; c < 3; ++c) C[c] += T * alpha * val[c];
         T *= exp(-val[3] * cx->step);
@@ -375,16 +455,17 @@ static void or_trace(const or_ctx *cx, long view, long row, long col, double rgb
 /* out_counts (optional): 2 longs (lattice, evaluated).                      */
 /* occ (optional): one byte per block from oracle_occupancy; NULL = no skip. */
 /* ------------------------------------------------------------------------ */
-int oracle_render(const void *data, int dtype, long nx, long ny, long nz, const double *cams, int n_cams, int W,
-                  int H, const float *tf, int K, double v0, double v1, double step, double ert,
-                  const uint8_t *occ, int edge, const long *pix, long n_pix, double *out_rgba,
-                  uint8_t *out_flags, long *out_counts)
+static int or_render(const void *data, int dtype, long nx, long ny, long nz, const double *cams, int n_cams, int W,
+                     int H, const float *tf, int K, double v0, double v1, double step, double ert,
+                     const uint8_t *occ, int edge, const double *shade, const long *pix, long n_pix,
+                     double *out_rgba, uint8_t *out_flags, long *out_counts)
 {
     if (!data || !cams || !tf || !out_rgba || n_cams <= 0 || W <= 0 || H <= 0 || K < 2 || !(v1 > v0) ||
         !(step > 0.0))
         return 1;
+    if (shade && !(shade[8] > 0.0 && shade[3] >= 1.0)) return 1;
     or_vol vol = {data, dtype, nx, ny, nz};
-    or_ctx cx = {&vol, cams, W, H, tf, K, v0, v1, step, ert, occ, edge};
+    or_ctx cx = {&vol, cams, W, H, tf, K, v0, v1, step, ert, occ, edge, shade};
     long total = pix ? n_pix : (long)n_cams * W * H;
 #pragma omp parallel for schedule(dynamic, 16)
     for (long q = 0; q < total; ++q) {
@@ -410,6 +491,26 @@ int oracle_render(const void *data, int dtype, long nx, long ny, long nz, const 
         }
     }
     return 0;
+}
+
+int oracle_render(const void *data, int dtype, long nx, long ny, long nz, const double *cams, int n_cams, int W,
+                  int H, const float *tf, int K, double v0, double v1, double step, double ert,
+                  const uint8_t *occ, int edge, const long *pix, long n_pix, double *out_rgba,
+                  uint8_t *out_flags, long *out_counts)
+{
+    return or_render(data, dtype, nx, ny, nz, cams, n_cams, W, H, tf, K, v0, v1, step, ert, occ, edge, NULL, pix,
+                     n_pix, out_rgba, out_flags, out_counts);
+}
+
+/* Forward render with local lighting; shade as in or_shade_colour.         */
+int oracle_render_shaded(const void *data, int dtype, long nx, long ny, long nz, const double *cams, int n_cams,
+                         int W, int H, const float *tf, int K, double v0, double v1, double step, double ert,
+                         const uint8_t *occ, int edge, const double *shade, const long *pix, long n_pix,
+                         double *out_rgba, uint8_t *out_flags, long *out_counts)
+{
+    if (!shade) return 1;
+    return or_render(data, dtype, nx, ny, nz, cams, n_cams, W, H, tf, K, v0, v1, step, ert, occ, edge, shade, pix,
+                     n_pix, out_rgba, out_flags, out_counts);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -445,7 +546,7 @@ int oracle_grad(const void *data, int dtype, long nx, long ny, long nz, const do
         !(step > 0.0))
         return 1;
     or_vol vol = {data, dtype, nx, ny, nz};
-    or_ctx cx = {&vol, cams, W, H, tf, K, v0, v1, step, ert, occ, edge};
+    or_ctx cx = {&vol, cams, W, H, tf, K, v0, v1, step, ert, occ, edge, NULL};
     long total = (long)n_cams * W * H;
     double slope_scale = (double)(K - 1) / (v1 - v0);
     int ert_on = ert > 0.0 && ert < 1.0;
@@ -551,6 +652,17 @@ double oracle_sample(const void *data, int dtype, long nx, long ny, long nz, dou
 
 /* B-spline weights at fractional offset f (exposed for the weight pins).   */
 void oracle_weights(double f, double w[4]) { or_bspline(f, w); }
+
+void oracle_dweights(double f, double d[4]) { or_bspline_deriv(f, d); }
+
+/* Gradient of the reconstructed field at (px, py, pz). */
+void oracle_gradient(const void *data, int dtype, long nx, long ny, long nz, double px, double py, double pz,
+                     double g[3])
+{
+    or_vol vol = {data, dtype, nx, ny, nz};
+    double p[3] = {px, py, pz};
+    or_gradient(&vol, p, g);
+}
 
 /* Lattice sample count of every pixel of every view (ray setup and clip     */
 /* only; exposed so that integer counts can be compared at full size).       */

@@ -486,8 +486,12 @@ __device__ inline float reconstruct(__amdgpu_buffer_rsrc_t rs, const VolConst &v
 #ifndef VR_VBOX_EDGE
 #define VR_VBOX_EDGE 14
 #endif
+#ifndef VR_VBOX_ZPAD
+#define VR_VBOX_ZPAD 4
+#endif
 constexpr int kVBox = VR_VBOX_EDGE;
-constexpr int kVBoxZ = kVBox * kVBox + 4;  // padded z stride (LDS banks)
+constexpr int kVBoxZ = kVBox * kVBox + VR_VBOX_ZPAD;  // padded z stride (LDS banks)
+static_assert(VR_VBOX_ZPAD % 2 == 0, "slices hold float2 pairs");
 static_assert(kVBox % 2 == 0 && kVBox >= 4 && kVBox <= 16, "box rows are filled in pairs from a 16-voxel window");
 constexpr int kVBoxCells = kVBox * kVBoxZ;
 

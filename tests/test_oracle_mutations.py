@@ -8,6 +8,7 @@ import pytest
 
 import oracle
 import test_oracle_pins as pins
+import test_oracle_shading as shading
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
 
@@ -31,7 +32,20 @@ MUTANTS = {
     "footprint_low_apron_dropped": ("long x0 = or_clampl(bx * edge - 1, 0, nx - 1)", "long x0 = or_clampl(bx * edge, 0, nx - 1)"),
     "occupancy_margin_dropped": ("long jlo = (long)floorf(ulo) - 1, jhi = (long)ceilf(uhi) + 1;",
                                  "long jlo = (long)floorf(ulo), jhi = (long)ceilf(uhi);"),
+    "dweight_d1_wrong": ("d[1] = (9.0 * f * f - 12.0 * f) / 6.0;", "d[1] = (9.0 * f * f - 6.0 * f) / 6.0;"),
+    "gradient_y_takes_x_derivative": ("g[1] += w[0][a] * dw[1][b] * w[2][c] * V;",
+                                      "g[1] += dw[0][a] * w[1][b] * w[2][c] * V;"),
+    "light_one_sided": ("double nl = fabs(n[0] * L[0] + n[1] * L[1] + n[2] * L[2]);",
+                        "double nl = fmax(n[0] * L[0] + n[1] * L[1] + n[2] * L[2], 0.0);"),
+    "specular_dropped": ("c[a] = c[a] * (sh[0] + sh[1] * nl) + sh[2] * spec;", "c[a] = c[a] * (sh[0] + sh[1] * nl);"),
+    "normal_not_shrunk": ("double m = gm > sh[8] ? gm : sh[8];", "double m = gm;"),
+    "half_vector_not_normalised": ("double nh = fabs(n[0] * Hs[0] + n[1] * Hs[1] + n[2] * Hs[2]) / hn;",
+                                   "double nh = fabs(n[0] * Hs[0] + n[1] * Hs[1] + n[2] * Hs[2]);"),
 }
+
+
+def _lit_single_sample_half_slope(lib):
+    shading.test_lit_single_sample_closed_form(lib, 0.5)
 
 PINS = [
     pins.test_bspline_weights_worked_values,
@@ -47,6 +61,11 @@ PINS = [
     pins.test_grad_closed_form_homogeneous_medium,
     pins.test_grad_volume_matches_central_differences,
     pins.test_grad_tf_matches_central_differences,
+    shading.test_derivative_weights_match_the_kernel_derivative,
+    shading.test_gradient_of_quadratic_field_is_exact,
+    shading.test_gradient_matches_rational_brute_force,
+    _lit_single_sample_half_slope,
+    shading.test_lit_render_matches_brute_force,
 ]
 
 
