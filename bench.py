@@ -59,6 +59,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "render_fwd_c1_traffic.json"))
     ap.add_argument("--no-c3", action="store_true", help="skip the differentiable 256^3 x 64-view measurement")
+    ap.add_argument("--no-lit", action="store_true", help="skip the lit (local lighting) forward measurement")
     return ap.parse_args()
 
 
@@ -336,9 +337,33 @@ def main():
         "unit": "GB/s",
         "frac": achieved_gbs / HBM_PEAK_GBS,
         "traffic": traffic,
-        "kernel": "k_render<kI16>",
+        "kernel": "k_render<kI16, unlit>",
         "bytes_per_launch": evaluated * TAPS_BYTES_I16,
     }
+
+    if not args.no_lit:
+        shade = vr.Shading(**synth.SHADE_CT)
+        lit_ctr = torch.zeros(4, dtype=torch.int64, device="cuda")
+        vr.vr_render(vol, blocks, cams, tf, c["step"], c["ert"], True, out=out, counters=lit_ctr, shading=shade)
+        torch.cuda.synchronize()
+        lit_eval = int(lit_ctr[0].item())
+
+        def fwd_lit():
+            vr.vr_render(vol, blocks, cams, tf, c["step"], c["ert"], True, out=out, shading=shade)
+
+        wall_l, ev_l = time_steps(fwd_lit, args.steps, args.warmup, torch)
+        ms_l = wall_l / args.steps * 1e3
+        log(f"fwd lit: {ms_l:.3f} ms/frame wall, {float(np.mean(ev_l)):.3f} ms/launch events")
+        result["c1_lit"] = {
+            "ms_per_step": ms_l,
+            "kernel_ms": float(np.mean(ev_l)),
+            "samples_per_s": lit_eval / (wall_l / args.steps),
+            "rays_per_s": W * H / (wall_l / args.steps),
+            "evaluated_samples_per_frame": lit_eval,
+            "shading": dict(synth.SHADE_CT),
+            "note": "same frame with local lighting: gradient of the cubic reconstruction from the same 64 taps, "
+                    "two-sided Blinn-Phong; opacity and samples as the unlit frame",
+        }
 
     if not args.no_bwd:
         gv_holder = {}

@@ -13,6 +13,7 @@ Importing this package loads ``libvr.so`` and raises if it has not been built.
 from __future__ import annotations
 
 import ctypes
+from dataclasses import dataclass
 
 import torch
 
@@ -29,6 +30,7 @@ __all__ = [
     "vr_block_occupancy",
     "vr_render",
     "vr_render_backward",
+    "Shading",
     "render",
     "VolumeRender",
     "Server",
@@ -172,12 +174,39 @@ def _params(step, ert, use_skip, counters):
     return p
 
 
+@dataclass
+class Shading:
+    """Local lighting of ``vr_render_shaded``: every sample's colour c becomes
+    c (ambient + diffuse |n.L|) + specular |n.H|^shininess with the normal n
+    from the gradient of the cubic reconstruction (two-sided Blinn-Phong)."""
+
+    ambient: float = 0.3
+    diffuse: float = 0.7
+    specular: float = 0.3
+    shininess: float = 16.0
+    light: tuple = (0.0, 0.0, -1.0)
+    headlight: bool = True
+    grad_min: float = 1.0
+
+    def struct(self) -> _abi.vr_shading:
+        c = _abi.vr_shading()
+        c.ambient, c.diffuse, c.specular, c.shininess = (float(self.ambient), float(self.diffuse),
+                                                         float(self.specular), float(self.shininess))
+        for a in range(3):
+            c.light[a] = float(self.light[a])
+        c.headlight = 1 if self.headlight else 0
+        c.grad_min = float(self.grad_min)
+        return c
+
+
 def vr_render(volume: Volume, blocks, cameras, tf: TF, step: float, ert: float = 0.0, use_skip: bool = False,
-              out: torch.Tensor | None = None, counters: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+              out: torch.Tensor | None = None, counters: torch.Tensor | None = None, stream=None,
+              shading: Shading | None = None) -> torch.Tensor:
     """Render len(cameras) views; returns (views, H, W, 4) fp32 premultiplied RGBA.
     ``counters``: optional int64 CUDA tensor of 4 that the kernel adds
     [evaluated samples, lattice samples, rays with samples, samples read from
-    global memory instead of an LDS box] to."""
+    global memory instead of an LDS box] to.  ``shading`` switches on local
+    lighting (``vr_render_shaded``)."""
     W, H = int(cameras[0].width), int(cameras[0].height)
     if out is None:
         out = torch.empty((len(cameras), H, W, 4), dtype=torch.float32, device=volume.tensor.device)
@@ -185,8 +214,15 @@ def vr_render(volume: Volume, blocks, cameras, tf: TF, step: float, ert: float =
         raise ValueError("counters must be an int64 CUDA tensor of at least 4 elements")
     cams = _cameras(cameras)
     p = _params(step, ert, use_skip, counters)
-    check(lib().vr_render(ctypes.byref(volume.c), None if blocks is None else blocks.ptr, cams, len(cameras),
-                          ctypes.byref(tf.c), ctypes.byref(p), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    if shading is None:
+        check(lib().vr_render(ctypes.byref(volume.c), None if blocks is None else blocks.ptr, cams, len(cameras),
+                              ctypes.byref(tf.c), ctypes.byref(p), ctypes.c_void_p(out.data_ptr()),
+                              _stream_ptr(stream)))
+    else:
+        sh = shading.struct()
+        check(lib().vr_render_shaded(ctypes.byref(volume.c), None if blocks is None else blocks.ptr, cams,
+                                     len(cameras), ctypes.byref(tf.c), ctypes.byref(p), ctypes.byref(sh),
+                                     ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out
 
 

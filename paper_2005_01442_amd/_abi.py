@@ -57,6 +57,11 @@ class vr_params(ctypes.Structure):
                 ("counters", c_void_p)]
 
 
+class vr_shading(ctypes.Structure):
+    _fields_ = [("ambient", c_float), ("diffuse", c_float), ("specular", c_float), ("shininess", c_float),
+                ("light", c_float * 3), ("headlight", c_int32), ("grad_min", c_float), ("reserved", c_int32)]
+
+
 class vr_serve_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", c_uint64), ("max_inflight", c_int32), ("max_batch_tiles", c_int32),
                 ("device", c_int32), ("reserved", c_int32)]
@@ -86,6 +91,8 @@ PROTOTYPES = {
     "vr_blocks_free": ([c_void_p], None),
     "vr_render": ([POINTER(vr_volume), c_void_p, POINTER(vr_camera), c_int32, POINTER(vr_tf), POINTER(vr_params),
                    c_void_p, c_void_p], c_int32),
+    "vr_render_shaded": ([POINTER(vr_volume), c_void_p, POINTER(vr_camera), c_int32, POINTER(vr_tf),
+                          POINTER(vr_params), POINTER(vr_shading), c_void_p, c_void_p], c_int32),
     "vr_render_backward": ([POINTER(vr_volume), c_void_p, POINTER(vr_camera), c_int32, POINTER(vr_tf),
                             POINTER(vr_params), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p], c_int32),
     "vr_serve_create": ([POINTER(vr_serve_config), POINTER(c_void_p)], c_int32),

@@ -132,6 +132,39 @@ vr_status check_march(float step, float ert, int32_t use_skip, MarchConst *out) 
   return VR_OK;
 }
 
+vr_status check_shading(const vr_shading *sh, ShadeConst *out) {
+  if (!sh) return fail(VR_E_INVALID_ARG, "shading is NULL");
+  const float k[3] = {sh->ambient, sh->diffuse, sh->specular};
+  for (float x : k)
+    if (!std::isfinite(x) || x < 0.0f) return fail(VR_E_INVALID_ARG, "ambient/diffuse/specular must be finite and >= 0");
+  if (!std::isfinite(sh->shininess) || !(sh->shininess >= 1.0f) || !(sh->shininess <= 1024.0f))
+    return fail(VR_E_INVALID_ARG, "shininess must be within [1, 1024] (got %g)", (double)sh->shininess);
+  if (!std::isfinite(sh->grad_min) || !(sh->grad_min > 0.0f))
+    return fail(VR_E_INVALID_ARG, "grad_min must be finite and > 0");
+  double L[3] = {0.0, 0.0, 0.0};
+  if (!sh->headlight) {
+    double n = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      if (!std::isfinite(sh->light[a])) return fail(VR_E_INVALID_ARG, "light direction is not finite");
+      n += (double)sh->light[a] * (double)sh->light[a];
+    }
+    if (!(n > 1e-30)) return fail(VR_E_INVALID_ARG, "light direction has zero length");
+    n = std::sqrt(n);
+    for (int a = 0; a < 3; ++a) L[a] = (double)sh->light[a] / n;
+  }
+  if (out) {
+    out->ka = sh->ambient;
+    out->kd = sh->diffuse;
+    out->ks = sh->specular;
+    out->shininess = sh->shininess;
+    for (int a = 0; a < 3; ++a) out->light[a] = (float)L[a];
+    out->headlight = sh->headlight ? 1 : 0;
+    out->grad_min = sh->grad_min;
+    out->pad = 0;
+  }
+  return VR_OK;
+}
+
 vr_status attach_blocks(const vr_blocks *b, const vr_volume *v, VolConst *vc) {
   if (!b) return fail(VR_E_INVALID_ARG, "use_skip needs blocks");
   if (b->data != v->data || b->dtype != v->dtype || b->nx != v->nx || b->ny != v->ny || b->nz != v->nz)
@@ -284,12 +317,7 @@ void vr_blocks_free(vr_blocks *b) {
   delete b;
 }
 
-vr_status vr_render(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,
-                    const vr_tf *tf, const vr_params *p, float *out_rgba, void *stream) {
-  RenderArgs a;
-  vr_status s = prepare(vol, blocks, cams, n_cams, tf, p, &a);
-  if (s) return s;
-  if (!out_rgba) return fail(VR_E_INVALID_ARG, "out_rgba is NULL");
+static vr_status render_views(RenderArgs &a, const vr_camera *cams, int32_t n_cams, float *out_rgba, void *stream) {
   const size_t view_floats = (size_t)a.W * a.H * 4;
   for (int32_t v0 = 0; v0 < n_cams; v0 += kMaxCamsPerLaunch) {
     const int32_t n = std::min(kMaxCamsPerLaunch, n_cams - v0);
@@ -300,6 +328,27 @@ vr_status vr_render(const vr_volume *vol, const vr_blocks *blocks, const vr_came
     if (e != hipSuccess) return hip_fail(e, "render launch");
   }
   return VR_OK;
+}
+
+vr_status vr_render(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,
+                    const vr_tf *tf, const vr_params *p, float *out_rgba, void *stream) {
+  RenderArgs a;
+  vr_status s = prepare(vol, blocks, cams, n_cams, tf, p, &a);
+  if (s) return s;
+  if (!out_rgba) return fail(VR_E_INVALID_ARG, "out_rgba is NULL");
+  return render_views(a, cams, n_cams, out_rgba, stream);
+}
+
+vr_status vr_render_shaded(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,
+                           const vr_tf *tf, const vr_params *p, const vr_shading *shading, float *out_rgba,
+                           void *stream) {
+  RenderArgs a;
+  vr_status s = prepare(vol, blocks, cams, n_cams, tf, p, &a);
+  if (s) return s;
+  if ((s = check_shading(shading, &a.shade))) return s;
+  if (!out_rgba) return fail(VR_E_INVALID_ARG, "out_rgba is NULL");
+  a.shaded = 1;
+  return render_views(a, cams, n_cams, out_rgba, stream);
 }
 
 vr_status vr_render_backward(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,

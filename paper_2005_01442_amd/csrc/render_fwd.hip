@@ -11,27 +11,47 @@ namespace vr {
 
 // March one ray front to back.  Skipped samples are exactly those whose block
 // is empty under the TF; such a sample would contribute a = 0 exactly, so the
-// result is bit-identical to marching every sample.
-template <int DT>
+// result is bit-identical to marching every sample.  SHADE adds local
+// lighting: the same 64 taps also give the gradient, which lights the
+// classified colour (the value, hence opacity and termination, is unchanged).
+template <int DT, bool SHADE>
 __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfConst &tf, const MarchConst &mc,
-                               const Ray &r, __amdgpu_buffer_rsrc_t rs, ValBox &box, uint32_t &evaluated,
-                               uint32_t &unstaged) {
+                               const ShadeConst &sc, const Ray &r, __amdgpu_buffer_rsrc_t rs, ValBox &box,
+                               uint32_t &evaluated, uint32_t &unstaged) {
   float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, T = 1.0f;
   const float sl2 = mc.step * 1.4426950408889634f;
   const bool ert_on = mc.ert > 0.0f && mc.ert < 1.0f;
+  RayLight rl;
+  if constexpr (SHADE) rl = ray_light(sc, r.d);
   auto prep = [&](bool want, float px, float py, float pz) {
     if (box.cells) vbox_prepare<DT>(box, rs, v, r, want, px, py, pz);
   };
   auto visit = [&](int, float px, float py, float pz) -> bool {
-    Stencil st = make_stencil(px, py, pz);
-    float val;
-    if (box.valid) {
-      val = reconstruct_box(box, st);
+    Classified q;
+    if constexpr (SHADE) {
+      StencilG sg = make_stencil_grad(px, py, pz);
+      float4 vg;
+      if (box.valid) {
+        float t[4][4][4];
+        load_taps_box(box, sg.s, t);
+        vg = combine_grad(sg, t);
+      } else {
+        vg = reconstruct_grad<DT>(rs, v, sg);
+        ++unstaged;
+      }
+      q = classify(s, tf.K, tf.v0, tf.scale, vg.x);
+      light_colour(sc, rl, vg, q.c);
     } else {
-      val = reconstruct<DT>(rs, v, st);
-      ++unstaged;
+      Stencil st = make_stencil(px, py, pz);
+      float val;
+      if (box.valid) {
+        val = reconstruct_box(box, st);
+      } else {
+        val = reconstruct<DT>(rs, v, st);
+        ++unstaged;
+      }
+      q = classify(s, tf.K, tf.v0, tf.scale, val);
     }
-    Classified q = classify(s, tf.K, tf.v0, tf.scale, val);
     float e = transmit(q.c.w, sl2);
     float ta = T * (1.0f - e);
     C0 = fmaf(ta, q.c.x, C0);
@@ -51,8 +71,8 @@ __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfCon
 #ifndef VR_FWD_MAX_WAVES
 #define VR_FWD_MAX_WAVES 3
 #endif
-template <int DT>
-__global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(1, VR_FWD_MAX_WAVES)))
+template <int DT, bool SHADE>
+__global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(SHADE ? VR_FWD_MAX_WAVES : 1, VR_FWD_MAX_WAVES)))
 void k_render(const RenderArgs args) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const RenderArgs &a = kernarg<RenderArgs>();
@@ -79,7 +99,7 @@ void k_render(const RenderArgs args) {
   box.cells = a.use_box ? reinterpret_cast<float *>(lds + vbox_lds_offset(a.tf.K)) +
                               (threadIdx.x / kWaveSize) * kVBoxCells
                         : nullptr;
-  float4 rgba = march<DT>(a.vol, s, a.tf, a.mc, r, rs, box, evaluated, unstaged);
+  float4 rgba = march<DT, SHADE>(a.vol, s, a.tf, a.mc, a.shade, r, rs, box, evaluated, unstaged);
   if (inside) {
     float4 *o = reinterpret_cast<float4 *>(a.out);
     o[((size_t)st.view * a.H + row) * a.W + col] = rgba;
@@ -92,6 +112,21 @@ void k_render(const RenderArgs args) {
   }
 }
 
+template <bool SHADE>
+static hipError_t launch_render_as(const RenderArgs &a, int64_t grid, uint32_t lds, hipStream_t s) {
+  const void *fn = a.vol.dtype == kU16   ? reinterpret_cast<const void *>(&k_render<kU16, SHADE>)
+                   : a.vol.dtype == kI16 ? reinterpret_cast<const void *>(&k_render<kI16, SHADE>)
+                                         : reinterpret_cast<const void *>(&k_render<kF32, SHADE>);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  switch (a.vol.dtype) {
+  case kU16: hipLaunchKernelGGL((k_render<kU16, SHADE>), dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
+  case kI16: hipLaunchKernelGGL((k_render<kI16, SHADE>), dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
+  default: hipLaunchKernelGGL((k_render<kF32, SHADE>), dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_render(const RenderArgs &a0, hipStream_t s) {
   RenderArgs a = a0;
   int64_t grid = grid_size_for(a.W, a.H, a.n_views, a.chunk_edge);
@@ -99,21 +134,8 @@ hipError_t launch_render(const RenderArgs &a0, hipStream_t s) {
   const uint32_t with_box = vbox_lds_offset(a.tf.K) + vbox_lds_bytes();
   a.use_box = with_box <= max_lds_per_workgroup() ? 1 : 0;
   if (a.use_box) lds = with_box;
-  const void *fn = nullptr;
-  switch (a.vol.dtype) {
-  case kU16: fn = reinterpret_cast<const void *>(&k_render<kU16>); break;
-  case kI16: fn = reinterpret_cast<const void *>(&k_render<kI16>); break;
-  case kF32: fn = reinterpret_cast<const void *>(&k_render<kF32>); break;
-  default: return hipErrorInvalidValue;
-  }
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  switch (a.vol.dtype) {
-  case kU16: hipLaunchKernelGGL(k_render<kU16>, dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
-  case kI16: hipLaunchKernelGGL(k_render<kI16>, dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
-  default: hipLaunchKernelGGL(k_render<kF32>, dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
-  }
-  return hipGetLastError();
+  if (a.vol.dtype != kU16 && a.vol.dtype != kI16 && a.vol.dtype != kF32) return hipErrorInvalidValue;
+  return a.shaded ? launch_render_as<true>(a, grid, lds, s) : launch_render_as<false>(a, grid, lds, s);
 }
 
 // Serving: one workgroup per work item, a 16x16 super-tile of one admitted
@@ -144,9 +166,9 @@ __global__ __launch_bounds__(kWgSize) void k_serve(const ServeSlot *slots, const
                       : nullptr;
   float4 rgba;
   switch (sl.vol.dtype) {  // uniform over the workgroup
-  case kU16: rgba = march<kU16>(sl.vol, s, sl.tf, sl.mc, r, rs, box, evaluated, unstaged); break;
-  case kI16: rgba = march<kI16>(sl.vol, s, sl.tf, sl.mc, r, rs, box, evaluated, unstaged); break;
-  default: rgba = march<kF32>(sl.vol, s, sl.tf, sl.mc, r, rs, box, evaluated, unstaged); break;
+  case kU16: rgba = march<kU16, false>(sl.vol, s, sl.tf, sl.mc, ShadeConst{}, r, rs, box, evaluated, unstaged); break;
+  case kI16: rgba = march<kI16, false>(sl.vol, s, sl.tf, sl.mc, ShadeConst{}, r, rs, box, evaluated, unstaged); break;
+  default: rgba = march<kF32, false>(sl.vol, s, sl.tf, sl.mc, ShadeConst{}, r, rs, box, evaluated, unstaged); break;
   }
   if (inside) reinterpret_cast<float4 *>(sl.out)[(size_t)row * sl.cam.W + col] = rgba;
 }

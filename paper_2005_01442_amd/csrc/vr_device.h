@@ -399,14 +399,14 @@ __device__ inline Stencil make_stencil(float px, float py, float pz) {
   return s;
 }
 
-// v = sum_c wz_c sum_b wy_b sum_a wx_a V[z_c][y_b][x_a], separable, with
-// clamp-to-edge addressing.  Interior stencils take the packed-row path.
-template <int DT>
-__device__ inline float reconstruct(__amdgpu_buffer_rsrc_t rs, const VolConst &v, const Stencil &s) {
+// Visit the 16 x-rows of a stencil's taps, row(c, b, t) with t[a] =
+// V[iz-1+c][iy-1+b][ix-1+a] under clamp-to-edge addressing, in the order
+// c = 0..3, b = 0..3.  Interior stencils take the packed-row loads.
+template <int DT, class Row>
+__device__ inline void for_rows(__amdgpu_buffer_rsrc_t rs, const VolConst &v, const Stencil &s, Row &row) {
   const int nx = v.nx, ny = v.ny, nz = v.nz;
   const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
   const uint32_t nvox = nxy * (uint32_t)nz;
-  float acc = 0.0f;
   bool inner = (s.ix >= 1) & (s.ix + 2 <= nx - 1) & (s.iy >= 1) & (s.iy + 2 <= ny - 1) & (s.iz >= 1) &
                (s.iz + 2 <= nz - 1);
   if (inner) {
@@ -420,39 +420,25 @@ __device__ inline float reconstruct(__amdgpu_buffer_rsrc_t rs, const VolConst &v
       const uint32_t sh = (e0 & 1u) * 16u;
       const uint32_t rs_x = (uint32_t)nx * kb, rs_xy = nxy * kb;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        float accy = 0.0f;
+      for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           float t[4];
           Vox<DT>::row_s(rs, voff, (uint32_t)c * rs_xy + (uint32_t)b * rs_x, sh, t);
-          float r = s.wx[0] * t[0];
-          r = fmaf(s.wx[1], t[1], r);
-          r = fmaf(s.wx[2], t[2], r);
-          r = fmaf(s.wx[3], t[3], r);
-          accy = fmaf(s.wy[b], r, accy);
+          row(c, b, t);
         }
-        acc = fmaf(s.wz[c], accy, acc);
-      }
-      return acc;
+      return;
     }
     if (inner) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        float accy = 0.0f;
+      for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           float t[4];
           Vox<DT>::row(rs, e0 + (uint32_t)c * nxy + (uint32_t)b * (uint32_t)nx, t);
-          float r = s.wx[0] * t[0];
-          r = fmaf(s.wx[1], t[1], r);
-          r = fmaf(s.wx[2], t[2], r);
-          r = fmaf(s.wx[3], t[3], r);
-          accy = fmaf(s.wy[b], r, accy);
+          row(c, b, t);
         }
-        acc = fmaf(s.wz[c], accy, acc);
-      }
-      return acc;
+      return;
     }
   }
   int xs[4];
@@ -460,18 +446,116 @@ __device__ inline float reconstruct(__amdgpu_buffer_rsrc_t rs, const VolConst &v
   for (int a = 0; a < 4; ++a) xs[a] = min(max(s.ix - 1 + a, 0), nx - 1);
   for (int c = 0; c < 4; ++c) {
     uint32_t z = (uint32_t)min(max(s.iz - 1 + c, 0), nz - 1);
-    float accy = 0.0f;
     for (int b = 0; b < 4; ++b) {
       uint32_t y = (uint32_t)min(max(s.iy - 1 + b, 0), ny - 1);
       uint32_t rowb = (z * (uint32_t)ny + y) * (uint32_t)nx;
-      float r = 0.0f;
+      float t[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) r = fmaf(s.wx[a], Vox<DT>::one(rs, rowb + (uint32_t)xs[a]), r);
-      accy = fmaf(s.wy[b], r, accy);
+      for (int a = 0; a < 4; ++a) t[a] = Vox<DT>::one(rs, rowb + (uint32_t)xs[a]);
+      row(c, b, t);
     }
+  }
+}
+
+// v = sum_c wz_c sum_b wy_b sum_a wx_a V[z_c][y_b][x_a], separable (16
+// x-rows, 4 y-sums, 1 z-sum).  Every reconstruction path keeps this order, so
+// a value does not depend on where its taps came from.
+__device__ inline float row_sum(const float w[4], const float t[4]) {
+  float r = w[0] * t[0];
+  r = fmaf(w[1], t[1], r);
+  r = fmaf(w[2], t[2], r);
+  return fmaf(w[3], t[3], r);
+}
+
+struct ValueRows {
+  const Stencil &s;
+  float acc, accy;
+  __device__ inline void operator()(int c, int b, const float t[4]) {
+    if (b == 0) accy = 0.0f;
+    accy = fmaf(s.wy[b], row_sum(s.wx, t), accy);
+    if (b == 3) acc = fmaf(s.wz[c], accy, acc);
+  }
+};
+
+template <int DT>
+__device__ inline float reconstruct(__amdgpu_buffer_rsrc_t rs, const VolConst &v, const Stencil &s) {
+  ValueRows f{s, 0.0f, 0.0f};
+  for_rows<DT>(rs, v, s, f);
+  return f.acc;
+}
+
+__device__ inline float combine(const Stencil &s, const float t[4][4][4]) {
+  float acc = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    float accy = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) accy = fmaf(s.wy[b], row_sum(s.wx, t[c][b]), accy);
     acc = fmaf(s.wz[c], accy, acc);
   }
   return acc;
+}
+
+// Derivatives of the B-spline weights with respect to the offset t.
+__device__ inline void bspline_dweights(float t, float d[4]) {
+  const float s = 1.0f - t;
+  d[0] = -0.5f * s * s;
+  d[1] = t * fmaf(1.5f, t, -2.0f);
+  d[2] = fmaf(t, fmaf(-1.5f, t, 1.0f), 0.5f);
+  d[3] = 0.5f * t * t;
+}
+
+// A stencil with derivative weights: the gradient of the reconstructed field
+// (the cubic filter's own gradient, used for local lighting).
+struct StencilG {
+  Stencil s;
+  float dx[4], dy[4], dz[4];
+};
+
+__device__ inline StencilG make_stencil_grad(float px, float py, float pz) {
+  StencilG g;
+  g.s = make_stencil(px, py, pz);
+  bspline_dweights(px - floorf(px), g.dx);
+  bspline_dweights(py - floorf(py), g.dy);
+  bspline_dweights(pz - floorf(pz), g.dz);
+  return g;
+}
+
+// (value, dv/dx, dv/dy, dv/dz).  The value is combine()'s, bit for bit; each
+// derivative swaps one axis' weights for derivative weights in the same
+// separable order.
+struct GradRows {
+  const StencilG &g;
+  float acc, ax, ay, az, accy, accx, accd;
+  __device__ inline void operator()(int c, int b, const float t[4]) {
+    if (b == 0) accy = accx = accd = 0.0f;
+    const float r = row_sum(g.s.wx, t), rd = row_sum(g.dx, t);
+    accy = fmaf(g.s.wy[b], r, accy);
+    accx = fmaf(g.s.wy[b], rd, accx);
+    accd = fmaf(g.dy[b], r, accd);
+    if (b == 3) {
+      acc = fmaf(g.s.wz[c], accy, acc);
+      ax = fmaf(g.s.wz[c], accx, ax);
+      ay = fmaf(g.s.wz[c], accd, ay);
+      az = fmaf(g.dz[c], accy, az);
+    }
+  }
+};
+
+template <int DT>
+__device__ inline float4 reconstruct_grad(__amdgpu_buffer_rsrc_t rs, const VolConst &v, const StencilG &g) {
+  GradRows f{g, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  for_rows<DT>(rs, v, g.s, f);
+  return make_float4(f.acc, f.ax, f.ay, f.az);
+}
+
+__device__ inline float4 combine_grad(const StencilG &g, const float t[4][4][4]) {
+  GradRows f{g, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) f(c, b, t[c][b]);
+  return make_float4(f.acc, f.ax, f.ay, f.az);
 }
 
 // ---------------------------------------------------------------------------
@@ -574,13 +658,11 @@ __device__ inline void vbox_prepare(ValBox &b, __amdgpu_buffer_rsrc_t rs, const 
   b.valid = true;
 }
 
-__device__ inline float reconstruct_box(const ValBox &b, const Stencil &s) {
+__device__ inline void load_taps_box(const ValBox &b, const Stencil &s, float t[4][4][4]) {
   const float *base = b.cells + (s.iz - 1 - b.oz) * kVBoxZ + (s.iy - 1 - b.oy) * kVBox + (s.ix - 1 - b.ox);
-  // all 64 taps first (one base per z slice keeps the row offsets within the
-  // immediate offsets of paired LDS reads), then the separable FMA chain in
-  // the order of the global path
+  // one base per z slice keeps the row offsets within the immediate offsets
+  // of paired LDS reads
   typedef __attribute__((address_space(3))) const float lds_float;
-  float t[4][4][4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     lds_float *zb = (lds_float *)(base + c * kVBoxZ);
@@ -592,26 +674,68 @@ __device__ inline float reconstruct_box(const ValBox &b, const Stencil &s) {
 #pragma unroll
       for (int a = 0; a < 4; ++a) t[c][bb][a] = zb[bb * kVBox + a];
   }
-  float acc = 0.0f;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    float accy = 0.0f;
-#pragma unroll
-    for (int bb = 0; bb < 4; ++bb) {
-      float r = s.wx[0] * t[c][bb][0];
-      r = fmaf(s.wx[1], t[c][bb][1], r);
-      r = fmaf(s.wx[2], t[c][bb][2], r);
-      r = fmaf(s.wx[3], t[c][bb][3], r);
-      accy = fmaf(s.wy[bb], r, accy);
-    }
-    acc = fmaf(s.wz[c], accy, acc);
-  }
-  return acc;
+}
+
+// All 64 taps from the box first, then the separable FMA chain of the
+// global path (the value is bit-identical).
+__device__ inline float reconstruct_box(const ValBox &b, const Stencil &s) {
+  float t[4][4][4];
+  load_taps_box(b, s, t);
+  return combine(s, t);
 }
 
 // LDS bytes of the TF staging rounded up to 16, where the value boxes begin.
 __host__ __device__ inline uint32_t vbox_lds_offset(int K) { return (tf_lds_bytes(K) + 15u) & ~15u; }
 __host__ __device__ inline uint32_t vbox_lds_bytes() { return (uint32_t)(kWgSize / kWaveSize) * kVBoxCells * 4u; }
+
+// ---------------------------------------------------------------------------
+// Local lighting (Phong's model in the Blinn half-vector form, two-sided),
+// with the gradient of the cubic reconstruction as the surface normal:
+//   c' = c (ka + kd |n.L|) + ks |n.H|^shininess,
+// n = -grad / max(|grad|, grad_min), V = -d, L = V for a headlight, H =
+// (L + V) / |L + V| (0 when L = -V).  Opacity is not changed.
+// ---------------------------------------------------------------------------
+struct ShadeConst {
+  float ka, kd, ks, shininess;
+  float light[3];      // unit, towards the light (unused with a headlight)
+  int32_t headlight;
+  float grad_min;      // > 0
+  int32_t pad;
+};
+
+struct RayLight {
+  float L[3], H[3];
+};
+
+__device__ inline RayLight ray_light(const ShadeConst &sc, const float d[3]) {
+  RayLight q;
+  float h[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    q.L[a] = sc.headlight ? -d[a] : sc.light[a];
+    h[a] = q.L[a] - d[a];
+  }
+  const float hn = sqrtf(fmaf(h[0], h[0], fmaf(h[1], h[1], h[2] * h[2])));
+  const float inv = hn > 1e-12f ? 1.0f / hn : 0.0f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) q.H[a] = h[a] * inv;
+  return q;
+}
+
+// Light colour c of a sample with gradient (g.y, g.z, g.w) (g.x is the value).
+__device__ inline void light_colour(const ShadeConst &sc, const RayLight &q, const float4 &g, float4 &c) {
+  const float gm = sqrtf(fmaf(g.y, g.y, fmaf(g.z, g.z, g.w * g.w)));
+  const float inv = -1.0f / fmaxf(gm, sc.grad_min);
+  const float n0 = g.y * inv, n1 = g.z * inv, n2 = g.w * inv;
+  const float nl = fabsf(fmaf(n0, q.L[0], fmaf(n1, q.L[1], n2 * q.L[2])));
+  const float nh = fabsf(fmaf(n0, q.H[0], fmaf(n1, q.H[1], n2 * q.H[2])));
+  // nh^shininess through the hardware log2/exp2 (nh = 0 gives exp2(-inf) = 0)
+  const float spec = sc.ks * __builtin_amdgcn_exp2f(sc.shininess * __builtin_amdgcn_logf(nh));
+  const float f = fmaf(sc.kd, nl, sc.ka);
+  c.x = fmaf(c.x, f, spec);
+  c.y = fmaf(c.y, f, spec);
+  c.z = fmaf(c.z, f, spec);
+}
 
 // Post-classification: (r, g, b, sigma) at value v; j and w of the segment;
 // `clamped` when u fell outside [0, K-1].

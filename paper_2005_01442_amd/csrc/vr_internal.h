@@ -20,7 +20,8 @@ struct RenderArgs {
   unsigned long long *counters;    // optional [evaluated, lattice, hit, -]
   int32_t W, H, n_views, chunk_edge;
   int32_t use_box;                 // stage volume boxes in LDS (set at launch)
-  int32_t pad2;
+  int32_t shaded;                  // nonzero: local lighting with `shade`
+  ShadeConst shade;
   CamConst cams[kMaxCamsPerLaunch];
 };
 
@@ -71,6 +72,7 @@ vr_status check_volume(const vr_volume *v, VolConst *out);
 vr_status check_tf_fields(const void *table, int32_t K, float v0, float v1, TfConst *out);
 vr_status check_camera(const vr_camera *c, CamConst *out);
 vr_status check_march(float step, float ert, int32_t use_skip, MarchConst *out);
+vr_status check_shading(const vr_shading *sh, ShadeConst *out);
 vr_status attach_blocks(const vr_blocks *b, const vr_volume *v, VolConst *vc);
 
 hipError_t launch_serve_batch(const ServeSlot *slots_dev, const ServeItem *items_dev, int32_t n_items,

@@ -43,4 +43,7 @@ from .configs import (  # noqa: F401
     config_c4_volumes,
     c4_arrivals,
     sample_pixels,
+    SHADE_CT,
+    SHADE_CT_HEADLIGHT,
+    SHADE_C0,
 )

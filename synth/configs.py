@@ -155,3 +155,14 @@ __all__ = [
     "sample_pixels",
     "orbit_directions",
 ]
+
+
+# Local-lighting parameter sets (plain numbers; the lighting arithmetic lives
+# in the oracle and the GPU library).  Gradient magnitudes are in value units
+# per voxel: CT soft-tissue noise gives about 5-10 HU/voxel, bone edges
+# hundreds, so grad_min = 20 keeps noise from acting as a surface.
+SHADE_CT = dict(ambient=0.25, diffuse=0.7, specular=0.35, shininess=24.0, light=(-0.3, 0.4, -0.87),
+                headlight=False, grad_min=20.0)
+SHADE_CT_HEADLIGHT = dict(SHADE_CT, headlight=True, light=(0.0, 0.0, 1.0))
+SHADE_C0 = dict(ambient=0.3, diffuse=0.6, specular=0.4, shininess=12.0, light=(0.5, -0.5, -0.7071),
+                headlight=False, grad_min=50.0)

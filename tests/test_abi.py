@@ -52,6 +52,7 @@ def test_struct_layout_matches_the_header(abi, tmp_path):
         "vr_camera": ["projection", "width", "eye", "forward", "fov_y", "ortho_h"],
         "vr_tf": ["table", "K", "v0", "v1"],
         "vr_params": ["step", "ert_threshold", "use_skip", "counters"],
+        "vr_shading": ["ambient", "shininess", "light", "headlight", "grad_min"],
         "vr_serve_config": ["hbm_budget_bytes", "max_inflight", "max_batch_tiles", "device"],
         "vr_request": ["volume_id", "K", "tf_table_host", "tf_v1", "cam", "step", "use_skip"],
         "vr_serve_stats": ["submitted", "tiles", "p50_ms", "p99_ms", "busy_s"],
@@ -129,3 +130,34 @@ def test_serve_config_validation_without_device(abi):
     cfg = abi.vr_serve_config(1 << 20, 0, 0, 0, 0)
     assert L.vr_serve_create(ctypes.byref(cfg), ctypes.byref(out)) == 1
     assert b"max_inflight" in L.vr_last_error()
+
+
+def test_shading_validation_without_device(abi):
+    L = abi.lib()
+    vol = abi.vr_volume(4096, abi.VR_I16, 0, 8, 8, 8)
+    cam = abi.vr_camera()
+    cam.width = cam.height = 8
+    cam.projection = 1
+    cam.forward[2] = 1.0
+    cam.right[0] = 1.0
+    cam.up[1] = 1.0
+    cam.fov_y = 1.0
+    tf = abi.vr_tf(4096, 256, 0.0, 1.0)
+    p = abi.vr_params(0.5, 0.0, 0, 0, None)
+    args = lambda sh: (ctypes.byref(vol), None, ctypes.byref(cam), 1, ctypes.byref(tf), ctypes.byref(p),  # noqa: E731
+                       sh, None, None)
+    assert L.vr_render_shaded(*args(None)) == 1 and b"shading is NULL" in L.vr_last_error()
+    sh = abi.vr_shading(0.3, 0.7, 0.3, 16.0, (ctypes.c_float * 3)(0.0, 0.0, 0.0), 0, 1.0, 0)
+    assert L.vr_render_shaded(*args(ctypes.byref(sh))) == 1 and b"zero length" in L.vr_last_error()
+    sh.headlight = 1
+    sh.shininess = 0.5
+    assert L.vr_render_shaded(*args(ctypes.byref(sh))) == 1 and b"shininess" in L.vr_last_error()
+    sh.shininess = 16.0
+    sh.grad_min = 0.0
+    assert L.vr_render_shaded(*args(ctypes.byref(sh))) == 1 and b"grad_min" in L.vr_last_error()
+    sh.grad_min = 1.0
+    sh.specular = float("nan")
+    assert L.vr_render_shaded(*args(ctypes.byref(sh))) == 1 and b"specular" in L.vr_last_error()
+    sh.specular = 0.3
+    # a valid shading reaches the output check (nothing is enqueued)
+    assert L.vr_render_shaded(*args(ctypes.byref(sh))) == 1 and b"out_rgba is NULL" in L.vr_last_error()
