@@ -107,6 +107,11 @@ def _prototypes(L):
         L.oracle_gradient.restype = None
         L.oracle_dweights.argtypes = [f64, P]
         L.oracle_dweights.restype = None
+        L.oracle_preint_table.argtypes = [P, i32, f64, P]
+        L.oracle_preint_table.restype = i32
+        L.oracle_render_preint.argtypes = [P, i32, i64, i64, i64, P, i32, i32, i32, P, i32, f64, f64, P, f64, f64,
+                                           P, i32, P, i64, P, P, P]
+        L.oracle_render_preint.restype = i32
 
 
 def f32(x) -> float:
@@ -282,3 +287,46 @@ def gradient(vol, p) -> np.ndarray:
     g = np.zeros(3, dtype=np.float64)
     lib().oracle_gradient(_ptr(vol), dt, nx, ny, nz, float(p[0]), float(p[1]), float(p[2]), _ptr(g))
     return g
+
+
+def preint_table(tf, step) -> np.ndarray:
+    """Pre-integrated segment table (K, K, 4): entry (i, j) = (C_r, C_g, C_b,
+    alpha) of a segment of length ``step`` whose value rises linearly from TF
+    node i to node j."""
+    table = np.ascontiguousarray(tf.table, dtype=np.float32)
+    K = table.shape[0]
+    out = np.zeros((K, K, 4), dtype=np.float64)
+    if lib().oracle_preint_table(_ptr(table), K, f32(step), _ptr(out)):
+        raise ValueError("oracle_preint_table rejected its arguments")
+    return out
+
+
+def render_preint(vol, cameras, tf, step, ert=0.0, minmax=None, edge=16, pixels=None, table=None):
+    """FP64 pre-integrated render (cells between lattice boundaries, table
+    lookup per cell).  ``minmax`` (per-block, from ``blocks``) enables the
+    pair-of-blocks skip rule.  Returns dict(rgba, flags, counts) as ``render``."""
+    vol, dt, nx, ny, nz = _vol(vol)
+    cams = pack_cameras(cameras)
+    W, H = int(cameras[0].width), int(cameras[0].height)
+    tf_tab = np.ascontiguousarray(tf.table, dtype=np.float32)
+    tab = preint_table(tf, step) if table is None else np.ascontiguousarray(table, dtype=np.float64)
+    mm = None if minmax is None else np.ascontiguousarray(minmax, dtype=np.float64)
+    if pixels is None:
+        n = len(cameras) * W * H
+        pix = None
+        shape = (len(cameras), H, W)
+    else:
+        pix = np.ascontiguousarray(pixels, dtype=np.int64)
+        n = pix.shape[0]
+        shape = (n,)
+    rgba = np.zeros(shape + (4,), dtype=np.float64)
+    flags = np.zeros(shape, dtype=np.uint8)
+    counts = np.zeros(shape + (2,), dtype=np.int64)
+    rc = lib().oracle_render_preint(
+        _ptr(vol), dt, nx, ny, nz, _ptr(cams), len(cameras), W, H, _ptr(tf_tab), tf_tab.shape[0], f32(tf.v0),
+        f32(tf.v1), _ptr(tab), f32(step), f32(ert), _ptr(mm), int(edge), _ptr(pix), n, _ptr(rgba), _ptr(flags),
+        _ptr(counts),
+    )
+    if rc:
+        raise ValueError("oracle_render_preint rejected its arguments")
+    return dict(rgba=rgba, flags=flags, counts=counts)

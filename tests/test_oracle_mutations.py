@@ -9,6 +9,7 @@ import pytest
 import oracle
 import test_oracle_pins as pins
 import test_oracle_shading as shading
+import test_oracle_preint as preint
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
 
@@ -41,6 +42,17 @@ MUTANTS = {
     "normal_not_shrunk": ("double m = gm > sh[8] ? gm : sh[8];", "double m = gm;"),
     "half_vector_not_normalised": ("double nh = fabs(n[0] * Hs[0] + n[1] * Hs[1] + n[2] * Hs[2]) / hn;",
                                    "double nh = fabs(n[0] * Hs[0] + n[1] * Hs[1] + n[2] * Hs[2]);"),
+    "preint_tau_quadratic_dropped": ("double t = tau + ea[3] * xs[r] + 0.5 * (eb[3] - ea[3]) * xs[r] * xs[r] / piece;",
+                                     "double t = tau + ea[3] * xs[r];"),
+    "preint_lookup_front_back_swapped": ("or_preint_lookup(tab, K, (sf.v - v0) * scale, (sb.v - v0) * scale, seg);",
+                                         "or_preint_lookup(tab, K, (sb.v - v0) * scale, (sf.v - v0) * scale, seg);"),
+    "preint_back_value_at_midpoint": ("double tf_ = (double)k * step, tb = (double)(k + 1) * step;",
+                                      "double tf_ = (double)k * step, tb = ((double)k + 0.5) * step;"),
+    "preint_skip_front_block_only": (
+        "double lo = fmin(minmax[2 * bf], minmax[2 * bb]), hi = fmax(minmax[2 * bf + 1], minmax[2 * bb + 1]);",
+        "double lo = minmax[2 * bf], hi = minmax[2 * bf + 1];"),
+    "preint_bilinear_corners_swapped": ("w[0] * (1.0 - w[1]) * p10 + (1.0 - w[0]) * w[1] * p01",
+                                        "w[0] * (1.0 - w[1]) * p01 + (1.0 - w[0]) * w[1] * p10"),
 }
 
 
@@ -66,6 +78,12 @@ PINS = [
     shading.test_gradient_matches_rational_brute_force,
     _lit_single_sample_half_slope,
     shading.test_lit_render_matches_brute_force,
+    preint.test_table_linear_extinction_closed_form,
+    preint.test_table_matches_adaptive_quadrature,
+    lambda lib: preint.test_preint_skip_is_lossless(lib, 0.5, 8),
+    lambda lib: preint.test_preint_skip_is_lossless(lib, 2.5, 4),
+    preint.test_preint_skip_joins_both_blocks,
+    preint.test_preint_render_matches_brute_force,
 ]
 
 
