@@ -208,6 +208,51 @@ vr_status vr_render_shaded(const vr_volume *vol, const vr_blocks *blocks, const 
                            const vr_tf *tf, const vr_params *p, const vr_shading *shading, float *out_rgba,
                            void *stream);
 
+/* Pre-integrated classification.  The paper combines its ray caster with
+ * tables of previously integrated rendering (Section 2, the proposed method;
+ * the conclusion's pre-integrated rendering against sampling artefacts).
+ * A segment of length `step` along which the value rises linearly from TF
+ * node i to node j has, with u(x) = i + (j - i) x / step and
+ * tau(x) = integral_0^x sigma(u) dx',
+ *   alpha(i, j) = 1 - exp(-tau(step)),
+ *   C(i, j)     = integral_0^step c(u(x)) sigma(u(x)) exp(-tau(x)) dx
+ * (premultiplied).  The table holds (C_r, C_g, C_b, alpha) for every node
+ * pair, integrated in FP64 (pieces between node crossings, Gauss-Legendre on
+ * sub-intervals of optical depth <= 1/32) and stored as fp32.
+ * Opaque, library-owned; it remembers the TF (pointer, K, v0, v1) and step it
+ * was built for.  Negative or NaN extinction reads as zero. */
+typedef struct vr_preint vr_preint;
+
+/* Build the K x K table for `tf` (HOST struct; its DEVICE table is read by
+ * the enqueued kernel) and `step` (range of vr_params.step).  Enqueued on
+ * `stream`; allocates K*K*16 bytes of device memory.
+ * Errors: VR_E_INVALID_ARG, VR_E_OOM, VR_E_DEVICE. */
+vr_status vr_preint_build(const vr_tf *tf, float step, void *stream, vr_preint **out);
+
+/* Copy the table (K*K*4 floats, entry (i, j) at 4 (i K + j)) into dst_device
+ * (DEVICE, at least K*K*4 floats).  Enqueued on `stream`. */
+vr_status vr_preint_table(const vr_preint *table, float *dst_device, int64_t dst_count, void *stream);
+
+void vr_preint_free(vr_preint *table);
+
+/* Pre-integrated render.  The ray's lattice cells (cell k between t = k step
+ * and (k+1) step, for the k whose midpoints are vr_render's samples) are the
+ * segments: the value is reconstructed at every cell boundary (a boundary may
+ * lie up to half a step outside the box; clamp-to-edge defines the field
+ * there) and each cell takes the table's bilinear lookup at (u(front),
+ * u(back)), u clamped to [0, K-1]; front to back C += T C_cell, T *= 1 -
+ * alpha_cell; early termination after the cell whose opacity reaches the
+ * threshold.  With use_skip, a cell is skipped iff no value in the union of
+ * its two boundary points' block ranges can meet non-zero extinction (the
+ * image is bit-identical to rendering every cell).
+ * table: built by vr_preint_build from this tf (same table pointer, K, v0,
+ * v1) and p->step, else VR_E_INVALID_ARG.  The TF contents must not have
+ * changed since.  counters as vr_render with cells for samples ([3] counts
+ * boundary values read from global memory).  Otherwise as vr_render. */
+vr_status vr_render_preint(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,
+                           const vr_tf *tf, const vr_params *p, const vr_preint *table, float *out_rgba,
+                           void *stream);
+
 /* Adjoint of vr_render: gradients of L with respect to the voxel values and
  * the TF table, given g = dL/dRGBA.  Per ray the forward march is recomputed
  * front to back (no per-sample state is stored); the stopping sample of

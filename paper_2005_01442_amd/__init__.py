@@ -31,6 +31,10 @@ __all__ = [
     "vr_render",
     "vr_render_backward",
     "Shading",
+    "PreintTable",
+    "vr_preint_build",
+    "vr_preint_table",
+    "vr_render_preint",
     "render",
     "VolumeRender",
     "Server",
@@ -223,6 +227,55 @@ def vr_render(volume: Volume, blocks, cameras, tf: TF, step: float, ert: float =
         check(lib().vr_render_shaded(ctypes.byref(volume.c), None if blocks is None else blocks.ptr, cams,
                                      len(cameras), ctypes.byref(tf.c), ctypes.byref(p), ctypes.byref(sh),
                                      ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+class PreintTable:
+    """Library-owned pre-integrated segment table of one TF and step."""
+
+    def __init__(self, ptr, tf: TF, step: float):
+        self.ptr = ptr
+        self.tf = tf  # keeps the TF table memory alive
+        self.step = float(step)
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            try:
+                lib().vr_preint_free(self.ptr)
+            except Exception:
+                pass
+            self.ptr = None
+
+
+def vr_preint_build(tf: TF, step: float, stream=None) -> PreintTable:
+    out = ctypes.c_void_p()
+    check(lib().vr_preint_build(ctypes.byref(tf.c), float(step), _stream_ptr(stream), ctypes.byref(out)))
+    return PreintTable(out, tf, step)
+
+
+def vr_preint_table(table: PreintTable, stream=None) -> torch.Tensor:
+    """(K, K, 4) fp32 copy of the table: entry (i, j) = (C_r, C_g, C_b, alpha)."""
+    K = table.tf.K
+    dst = torch.empty((K, K, 4), dtype=torch.float32, device=table.tf.table.device)
+    check(lib().vr_preint_table(table.ptr, ctypes.c_void_p(dst.data_ptr()), dst.numel(), _stream_ptr(stream)))
+    return dst
+
+
+def vr_render_preint(volume: Volume, blocks, cameras, tf: TF, table: PreintTable, step: float, ert: float = 0.0,
+                     use_skip: bool = False, out: torch.Tensor | None = None, counters: torch.Tensor | None = None,
+                     stream=None) -> torch.Tensor:
+    """Pre-integrated render of len(cameras) views; (views, H, W, 4) fp32
+    premultiplied RGBA.  ``counters`` as vr_render, counting lattice cells."""
+    W, H = int(cameras[0].width), int(cameras[0].height)
+    if out is None:
+        out = torch.empty((len(cameras), H, W, 4), dtype=torch.float32, device=volume.tensor.device)
+    if counters is not None and (counters.dtype != torch.int64 or counters.numel() < 4 or not counters.is_cuda):
+        raise ValueError("counters must be an int64 CUDA tensor of at least 4 elements")
+    cams = _cameras(cameras)
+    p = _params(step, ert, use_skip, counters)
+    check(lib().vr_render_preint(ctypes.byref(volume.c), None if blocks is None else blocks.ptr, cams, len(cameras),
+                                 ctypes.byref(tf.c), ctypes.byref(p), table.ptr, ctypes.c_void_p(out.data_ptr()),
+                                 _stream_ptr(stream)))
     return out
 
 

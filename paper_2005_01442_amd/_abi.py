@@ -93,6 +93,11 @@ PROTOTYPES = {
                    c_void_p, c_void_p], c_int32),
     "vr_render_shaded": ([POINTER(vr_volume), c_void_p, POINTER(vr_camera), c_int32, POINTER(vr_tf),
                           POINTER(vr_params), POINTER(vr_shading), c_void_p, c_void_p], c_int32),
+    "vr_preint_build": ([POINTER(vr_tf), c_float, c_void_p, POINTER(c_void_p)], c_int32),
+    "vr_preint_table": ([c_void_p, c_void_p, c_int64, c_void_p], c_int32),
+    "vr_preint_free": ([c_void_p], None),
+    "vr_render_preint": ([POINTER(vr_volume), c_void_p, POINTER(vr_camera), c_int32, POINTER(vr_tf),
+                          POINTER(vr_params), c_void_p, c_void_p, c_void_p], c_int32),
     "vr_render_backward": ([POINTER(vr_volume), c_void_p, POINTER(vr_camera), c_int32, POINTER(vr_tf),
                             POINTER(vr_params), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p], c_int32),
     "vr_serve_create": ([POINTER(vr_serve_config), POINTER(c_void_p)], c_int32),

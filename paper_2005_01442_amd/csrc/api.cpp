@@ -21,6 +21,13 @@ struct vr_blocks {
   int device;
 };
 
+struct vr_preint {
+  float4 *table;  // K x K (C_r, C_g, C_b, alpha), entry (i, j) at i K + j
+  int32_t K;
+  float step, v0, v1;
+  const float *tf_table;  // the TF it was built from (checked at render)
+};
+
 namespace vr {
 
 static thread_local std::string g_last_error;
@@ -317,14 +324,15 @@ void vr_blocks_free(vr_blocks *b) {
   delete b;
 }
 
-static vr_status render_views(RenderArgs &a, const vr_camera *cams, int32_t n_cams, float *out_rgba, void *stream) {
+static vr_status render_views(RenderArgs &a, const vr_camera *cams, int32_t n_cams, float *out_rgba, void *stream,
+                              const float4 *preint = nullptr) {
   const size_t view_floats = (size_t)a.W * a.H * 4;
   for (int32_t v0 = 0; v0 < n_cams; v0 += kMaxCamsPerLaunch) {
     const int32_t n = std::min(kMaxCamsPerLaunch, n_cams - v0);
     for (int32_t i = 0; i < n; ++i) check_camera(&cams[v0 + i], &a.cams[i]);
     a.n_views = n;
     a.out = out_rgba + (size_t)v0 * view_floats;
-    hipError_t e = launch_render(a, (hipStream_t)stream);
+    hipError_t e = preint ? launch_render_preint(a, preint, (hipStream_t)stream) : launch_render(a, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "render launch");
   }
   return VR_OK;
@@ -349,6 +357,67 @@ vr_status vr_render_shaded(const vr_volume *vol, const vr_blocks *blocks, const 
   if (!out_rgba) return fail(VR_E_INVALID_ARG, "out_rgba is NULL");
   a.shaded = 1;
   return render_views(a, cams, n_cams, out_rgba, stream);
+}
+
+vr_status vr_preint_build(const vr_tf *tf, float step, void *stream, vr_preint **out) {
+  if (!out) return fail(VR_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!tf) return fail(VR_E_INVALID_ARG, "tf is NULL");
+  TfConst tc;
+  vr_status s = check_tf_fields(tf->table, tf->K, tf->v0, tf->v1, &tc);
+  if (s) return s;
+  MarchConst mc;
+  if ((s = check_march(step, 0.0f, 0, &mc))) return s;
+  vr_preint *t = new (std::nothrow) vr_preint();
+  if (!t) return fail(VR_E_OOM, "host allocation failed");
+  t->K = tf->K;
+  t->step = step;
+  t->v0 = tf->v0;
+  t->v1 = tf->v1;
+  t->tf_table = tf->table;
+  const size_t bytes = (size_t)tf->K * tf->K * sizeof(float4);
+  hipError_t e = hipMalloc(&t->table, bytes);
+  if (e != hipSuccess) {
+    delete t;
+    return fail(VR_E_OOM, "hipMalloc of %zu table bytes: %s", bytes, hipGetErrorString(e));
+  }
+  e = launch_preint_table(tf->table, tf->K, step, t->table, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    (void)hipFree(t->table);
+    delete t;
+    return hip_fail(e, "pre-integration table launch");
+  }
+  *out = t;
+  return VR_OK;
+}
+
+vr_status vr_preint_table(const vr_preint *t, float *dst, int64_t dst_count, void *stream) {
+  if (!t || !dst) return fail(VR_E_INVALID_ARG, "table or destination is NULL");
+  const int64_t n = (int64_t)t->K * t->K * 4;
+  if (dst_count < n) return fail(VR_E_INVALID_ARG, "destination holds %lld floats, need %lld", (long long)dst_count, (long long)n);
+  hipError_t e = hipMemcpyAsync(dst, t->table, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "copy pre-integration table");
+  return VR_OK;
+}
+
+void vr_preint_free(vr_preint *t) {
+  if (!t) return;
+  (void)hipFree(t->table);
+  delete t;
+}
+
+vr_status vr_render_preint(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,
+                           const vr_tf *tf, const vr_params *p, const vr_preint *table, float *out_rgba,
+                           void *stream) {
+  RenderArgs a;
+  vr_status s = prepare(vol, blocks, cams, n_cams, tf, p, &a);
+  if (s) return s;
+  if (!table) return fail(VR_E_INVALID_ARG, "pre-integration table is NULL");
+  if (table->K != tf->K || table->v0 != tf->v0 || table->v1 != tf->v1 || table->tf_table != tf->table ||
+      table->step != p->step)
+    return fail(VR_E_INVALID_ARG, "the pre-integration table was built for another TF or step");
+  if (!out_rgba) return fail(VR_E_INVALID_ARG, "out_rgba is NULL");
+  return render_views(a, cams, n_cams, out_rgba, stream, table->table);
 }
 
 vr_status vr_render_backward(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,

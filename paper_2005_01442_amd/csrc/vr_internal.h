@@ -49,6 +49,8 @@ hipError_t launch_render_backward(const BackwardArgs &a, hipStream_t s);
 hipError_t launch_block_minmax(const VolConst &v, float2 *out, hipStream_t s);
 hipError_t launch_block_occupancy(const VolConst &v, const TfConst &tf, uint8_t *occ, hipStream_t s);
 hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s);
+hipError_t launch_preint_table(const float *tf, int K, float step, float4 *out, hipStream_t s);
+hipError_t launch_render_preint(const RenderArgs &a, const float4 *tab, hipStream_t s);
 
 // Serving: one work item is a 16x16 super-tile of one request slot.
 struct ServeSlot {
