@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "render_fwd_c1_traffic.json"))
     ap.add_argument("--no-c3", action="store_true", help="skip the differentiable 256^3 x 64-view measurement")
     ap.add_argument("--no-lit", action="store_true", help="skip the lit (local lighting) forward measurement")
+    ap.add_argument("--no-preint", action="store_true",
+                    help="skip the pre-integrated forward and the step-artefact measurement")
     return ap.parse_args()
 
 
@@ -239,6 +241,84 @@ def serve_mix(vr, torch, n_req, n_warm, rate):
     )
 
 
+SPIKE_POINTS = [(-1024.0, (0, 0, 0, 0)), (-16.0, (0, 0, 0, 0)), (0.0, (0.8, 0.3, 0.2, 0.01)),
+                (96.0, (0.8, 0.3, 0.2, 0.01)), (112.0, (0, 0, 0, 0)), (336.0, (0, 0, 0, 0)),
+                (352.0, (1.0, 0.9, 0.8, 0.6)), (368.0, (0, 0, 0, 0)), (3056.0, (0, 0, 0, 0))]
+
+
+def _psnr(a, b, np):
+    return float(10.0 * np.log10(1.0 / np.mean((a - b) ** 2)))
+
+
+def _ssim(a, b, np):
+    """Mean SSIM over the RGBA channels (Gaussian window sigma 1.5, data range 1)."""
+    from scipy.ndimage import gaussian_filter
+
+    c1, c2 = 0.01 ** 2, 0.03 ** 2
+    vals = []
+    for ch in range(a.shape[-1]):
+        x, y = a[..., ch], b[..., ch]
+        mx, my = gaussian_filter(x, 1.5), gaussian_filter(y, 1.5)
+        sxx = gaussian_filter(x * x, 1.5) - mx * mx
+        syy = gaussian_filter(y * y, 1.5) - my * my
+        sxy = gaussian_filter(x * y, 1.5) - mx * my
+        s = ((2 * mx * my + c1) * (2 * sxy + c2)) / ((mx * mx + my * my + c1) * (sxx + syy + c2))
+        vals.append(float(s.mean()))
+    return float(np.mean(vals))
+
+
+def preint_measurements(vr, torch, np, synth, c, vol, blocks, cams, tf, out, args):
+    """Pre-integrated C1 frame (TF1, step 0.5, skip, ERT) timed like the
+    forward; then the step-artefact metric: a one-node extinction spike TF
+    rendered at coarse steps, post-classified and pre-integrated, against a
+    post-classified reference at step 1/8 (PSNR and SSIM over RGBA)."""
+    W, H = cams[0].width, cams[0].height
+    table = vr.vr_preint_build(tf, c["step"])
+    ctr = torch.zeros(4, dtype=torch.int64, device="cuda")
+    vr.vr_render_preint(vol, blocks, cams, tf, table, c["step"], c["ert"], True, out=out, counters=ctr)
+    torch.cuda.synchronize()
+    cells = int(ctr[0].item())
+
+    def fwd_pre():
+        vr.vr_render_preint(vol, blocks, cams, tf, table, c["step"], c["ert"], True, out=out)
+
+    wall, ev = time_steps(fwd_pre, args.steps, args.warmup, torch)
+    ms = wall / args.steps * 1e3
+    log(f"fwd pre-integrated: {ms:.3f} ms/frame wall, {float(np.mean(ev)):.3f} ms/launch events")
+    t0 = time.perf_counter()
+    tbl = vr.vr_preint_build(tf, c["step"])
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    del tbl
+    stf = synth.tf_from_points(SPIKE_POINTS, 256, -1024.0, 3056.0)
+    spike = vr.TF(torch.from_numpy(stf.table).cuda(), stf.v0, stf.v1)
+    ref = vr.vr_render(vol, blocks, cams, spike, 0.125, 0.0, True).cpu().numpy().astype(np.float64)
+    artefacts = []
+    for st in (1.0, 2.0, 4.0):
+        post = vr.vr_render(vol, blocks, cams, spike, st, 0.0, True).cpu().numpy().astype(np.float64)
+        tb = vr.vr_preint_build(spike, st)
+        pre = vr.vr_render_preint(vol, blocks, cams, spike, tb, st, 0.0, True).cpu().numpy().astype(np.float64)
+        row = {"step": st, "psnr_post_db": _psnr(post, ref, np), "psnr_preint_db": _psnr(pre, ref, np),
+               "ssim_post": _ssim(post[0], ref[0], np), "ssim_preint": _ssim(pre[0], ref[0], np)}
+        log(f"step {st}: PSNR post {row['psnr_post_db']:.2f} dB, pre-integrated {row['psnr_preint_db']:.2f} dB; "
+            f"SSIM {row['ssim_post']:.4f} / {row['ssim_preint']:.4f}")
+        artefacts.append(row)
+    return {
+        "ms_per_step": ms,
+        "kernel_ms": float(np.mean(ev)),
+        "cells_per_s": cells / (wall / args.steps),
+        "rays_per_s": W * H / (wall / args.steps),
+        "evaluated_cells_per_frame": cells,
+        "table_build_ms": build_ms,
+        "step_artefacts": {
+            "tf": "one-node extinction spike at 352 HU + soft tissue band (K=256)",
+            "reference": "post-classified, step 1/8",
+            "rows": artefacts,
+        },
+        "note": "same frame, TF1, step 0.5, skip + ERT 0.99: cells between lattice boundaries, K x K table lookup",
+    }
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -364,6 +444,9 @@ def main():
             "note": "same frame with local lighting: gradient of the cubic reconstruction from the same 64 taps, "
                     "two-sided Blinn-Phong; opacity and samples as the unlit frame",
         }
+
+    if not args.no_preint:
+        result["c1_preint"] = preint_measurements(vr, torch, np, synth, c, vol, blocks, cams, tf, out, args)
 
     if not args.no_bwd:
         gv_holder = {}
