@@ -253,6 +253,62 @@ vr_status vr_render_preint(const vr_volume *vol, const vr_blocks *blocks, const 
                            const vr_tf *tf, const vr_params *p, const vr_preint *table, float *out_rgba,
                            void *stream);
 
+/* ---------------------------------------------------------------------- */
+/* Out-of-core rendering: the paper's block decomposition of volumes that  */
+/* do not fit GPU memory (Section 2: blocks overlapping by the voxels a    */
+/* cubic stencil reads, smaller blocks at the far faces, empty blocks      */
+/* excluded, blocks rendered in order from the observer; Fig. 3).          */
+/* ---------------------------------------------------------------------- */
+
+/* Opaque, library-owned: a volume kept in pinned host memory as bricks (the
+ * footprint [bE-1, bE+E+1] per axis of every E^3 block, edge-clamped, (E+3)^3
+ * voxels each) plus a device pool of whole bricks with a page table. */
+typedef struct vr_bricked vr_bricked;
+
+typedef struct {
+    uint64_t passes;            /* rendering passes so far                     */
+    uint64_t bricks_total;      /* bricks of the volume                        */
+    uint64_t bricks_occupied;   /* occupied under the last TF                  */
+    uint64_t bricks_uploaded;   /* host -> device brick copies so far          */
+    uint64_t bytes_uploaded;
+    uint64_t bricks_resident;   /* bricks in the pool after the last render    */
+    uint64_t pool_slots;        /* bricks the pool holds                       */
+    uint64_t brick_bytes;       /* bytes of one brick (padded to 256)          */
+} vr_bricked_stats;
+
+/* Copy `host_vol` (its data is a HOST pointer here, read during the call
+ * only; dims up to 2^20 per axis, no 4 GiB limit) into pinned host bricks of
+ * edge `brick_edge` (a power of two in [8, 128]) with their min/max, and
+ * allocate a device pool of floor(pool_bytes / brick bytes) bricks (at least
+ * one).  Synchronous.  Errors: VR_E_INVALID_ARG, VR_E_OOM, VR_E_DEVICE. */
+vr_status vr_bricked_create(const vr_volume *host_vol, int32_t brick_edge, uint64_t pool_bytes, vr_bricked **out);
+
+/* Render n_cams views (one image size) of a bricked volume into out_rgba
+ * (DEVICE, layout of vr_render).  Per view: the TF occupancy of every brick
+ * (the test of vr_block_occupancy), the occupied bricks in front-to-back
+ * order for the camera, then passes over consecutive runs of that order, as
+ * many bricks as the pool holds (bricks already resident are reused, the
+ * others copied from pinned memory on `stream`); each pass continues every
+ * ray, in lattice order, through its bricks.  The image is bit-identical to
+ * vr_render with skipping and blocks of the same edge (p->use_skip is
+ * implied: empty bricks are never loaded).  The host waits for the stream
+ * between passes (and once for the occupancy).  Not thread-safe per
+ * vr_bricked.  Errors as vr_render, VR_E_OOM. */
+vr_status vr_bricked_render(vr_bricked *bricked, const vr_camera *cams, int32_t n_cams, const vr_tf *tf,
+                            const vr_params *p, float *out_rgba, void *stream);
+
+vr_status vr_bricked_stats_get(const vr_bricked *bricked, vr_bricked_stats *out);
+
+/* Front-to-back order of all bricks of edge `brick_edge` of a dims[0] x
+ * dims[1] x dims[2] volume for `cam`: brick indices (x fastest) into
+ * order_out (HOST, at least the brick count).  Host only; no device use.
+ * Every ray of the camera meets its bricks in this order. */
+vr_status vr_brick_order(const int64_t dims[3], int32_t brick_edge, const vr_camera *cam, int64_t *order_out,
+                         int64_t n);
+
+/* Waits for the device, then frees the pinned bricks and the pool. */
+void vr_bricked_free(vr_bricked *bricked);
+
 /* Adjoint of vr_render: gradients of L with respect to the voxel values and
  * the TF table, given g = dL/dRGBA.  Per ray the forward march is recomputed
  * front to back (no per-sample state is stored); the stopping sample of

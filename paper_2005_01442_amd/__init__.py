@@ -32,6 +32,8 @@ __all__ = [
     "vr_render_backward",
     "Shading",
     "PreintTable",
+    "BrickedVolume",
+    "vr_brick_order",
     "vr_preint_build",
     "vr_preint_table",
     "vr_render_preint",
@@ -276,6 +278,69 @@ def vr_render_preint(volume: Volume, blocks, cameras, tf: TF, table: PreintTable
     check(lib().vr_render_preint(ctypes.byref(volume.c), None if blocks is None else blocks.ptr, cams, len(cameras),
                                  ctypes.byref(tf.c), ctypes.byref(p), table.ptr, ctypes.c_void_p(out.data_ptr()),
                                  _stream_ptr(stream)))
+    return out
+
+
+_NP_DTYPES = {"uint16": VR_U16, "int16": VR_I16, "float32": VR_F32}
+
+
+class BrickedVolume:
+    """A volume kept in pinned host memory as bricks, rendered through a
+    device brick pool of ``pool_bytes`` (``vr_bricked_*``).  ``host_array`` is
+    a C-contiguous NumPy array (nz, ny, nx) of uint16, int16 or float32, copied
+    at construction."""
+
+    def __init__(self, host_array, brick_edge: int = 64, pool_bytes: int = 1 << 30):
+        import numpy as np
+
+        arr = np.ascontiguousarray(host_array)
+        if str(arr.dtype) not in _NP_DTYPES or arr.ndim != 3:
+            raise ValueError("host_array must be a 3-D uint16, int16 or float32 array")
+        nz, ny, nx = arr.shape
+        hv = _abi.vr_volume(arr.ctypes.data, _NP_DTYPES[str(arr.dtype)], 0, nx, ny, nz)
+        out = ctypes.c_void_p()
+        check(lib().vr_bricked_create(ctypes.byref(hv), int(brick_edge), int(pool_bytes), ctypes.byref(out)))
+        self.ptr = out
+        self.shape = arr.shape
+        self.brick_edge = int(brick_edge)
+
+    def render(self, cameras, tf: TF, step: float, ert: float = 0.0, out: torch.Tensor | None = None,
+               stream=None) -> torch.Tensor:
+        W, H = int(cameras[0].width), int(cameras[0].height)
+        if out is None:
+            out = torch.empty((len(cameras), H, W, 4), dtype=torch.float32, device=tf.table.device)
+        cams = _cameras(cameras)
+        p = _params(step, ert, True, None)
+        check(lib().vr_bricked_render(self.ptr, cams, len(cameras), ctypes.byref(tf.c), ctypes.byref(p),
+                                      ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+        return out
+
+    def stats(self) -> dict:
+        st = _abi.vr_bricked_stats()
+        check(lib().vr_bricked_stats_get(self.ptr, ctypes.byref(st)))
+        return {name: int(getattr(st, name)) for name, _ in st._fields_}
+
+    def __del__(self):
+        if getattr(self, "ptr", None):
+            try:
+                lib().vr_bricked_free(self.ptr)
+            except Exception:
+                pass
+            self.ptr = None
+
+
+def vr_brick_order(dims_xyz, brick_edge: int, camera):
+    """Front-to-back brick order (host only): brick indices, x fastest."""
+    import numpy as np
+
+    nb = 1
+    for d in dims_xyz:
+        nb *= -(-int(d) // int(brick_edge))
+    dims = (ctypes.c_int64 * 3)(*[int(d) for d in dims_xyz])
+    out = np.zeros(nb, dtype=np.int64)
+    cam = camera_struct(camera)
+    check(lib().vr_brick_order(dims, int(brick_edge), ctypes.byref(cam),
+                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), nb))
     return out
 
 

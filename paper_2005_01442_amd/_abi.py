@@ -62,6 +62,12 @@ class vr_shading(ctypes.Structure):
                 ("light", c_float * 3), ("headlight", c_int32), ("grad_min", c_float), ("reserved", c_int32)]
 
 
+class vr_bricked_stats(ctypes.Structure):
+    _fields_ = [("passes", c_uint64), ("bricks_total", c_uint64), ("bricks_occupied", c_uint64),
+                ("bricks_uploaded", c_uint64), ("bytes_uploaded", c_uint64), ("bricks_resident", c_uint64),
+                ("pool_slots", c_uint64), ("brick_bytes", c_uint64)]
+
+
 class vr_serve_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", c_uint64), ("max_inflight", c_int32), ("max_batch_tiles", c_int32),
                 ("device", c_int32), ("reserved", c_int32)]
@@ -98,6 +104,12 @@ PROTOTYPES = {
     "vr_preint_free": ([c_void_p], None),
     "vr_render_preint": ([POINTER(vr_volume), c_void_p, POINTER(vr_camera), c_int32, POINTER(vr_tf),
                           POINTER(vr_params), c_void_p, c_void_p, c_void_p], c_int32),
+    "vr_bricked_create": ([POINTER(vr_volume), c_int32, c_uint64, POINTER(c_void_p)], c_int32),
+    "vr_bricked_render": ([c_void_p, POINTER(vr_camera), c_int32, POINTER(vr_tf), POINTER(vr_params), c_void_p,
+                           c_void_p], c_int32),
+    "vr_bricked_stats_get": ([c_void_p, POINTER(vr_bricked_stats)], c_int32),
+    "vr_brick_order": ([POINTER(c_int64), c_int32, POINTER(vr_camera), POINTER(c_int64), c_int64], c_int32),
+    "vr_bricked_free": ([c_void_p], None),
     "vr_render_backward": ([POINTER(vr_volume), c_void_p, POINTER(vr_camera), c_int32, POINTER(vr_tf),
                             POINTER(vr_params), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p], c_int32),
     "vr_serve_create": ([POINTER(vr_serve_config), POINTER(c_void_p)], c_int32),

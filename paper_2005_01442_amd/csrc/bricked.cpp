@@ -1,0 +1,365 @@
+// bricked.cpp -- out-of-core volumes: host-resident bricks, a device brick
+// pool with a page table, and front-to-back rendering passes.
+//
+// The paper's block decomposition renders volumes that do not fit GPU memory
+// one block at a time (Section 2: blocks overlapping by the voxels a cubic
+// stencil reads, smaller blocks at the far faces, completely empty blocks
+// excluded; Fig. 3 and the pros and cons that follow).  A brick here is a
+// block's footprint, copied once into pinned host memory.  Rendering a view:
+//   1. TF occupancy of every brick (the blocks' min/max test, on the device);
+//   2. the occupied bricks in a front-to-back order for the camera: along
+//      each axis a ray moves away from the eye's slab, so the sum over the
+//      axes of |brick index - eye slab index| grows at every brick a ray
+//      enters (orthographic: the sum of sign(d_a) * index); sorting by it
+//      orders the bricks of every ray;
+//   3. passes over consecutive runs of that order, as many bricks as the pool
+//      holds: bricks already resident stay, missing ones are copied in, the
+//      page table lists the pass's bricks, and the pass kernel continues every
+//      ray through them from the state earlier passes left;
+//   4. the RGBA image from the final state.
+// Empty bricks are never copied; their samples add exactly zero.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "vr_internal.h"
+
+struct vr_bricked {
+  int32_t dtype;
+  int64_t nx, ny, nz;
+  int32_t E, S;
+  int32_t nbx, nby, nbz;
+  int64_t nbricks;
+  int64_t esz;
+  int64_t slot_bytes;
+  char *host_bricks;       // pinned, nbricks * slot_bytes
+  float2 *minmax_dev;      // nbricks
+  uint8_t *occ_dev;
+  uint8_t *occ_host;       // pinned
+  int32_t *page_dev;
+  int32_t *page_host;      // pinned
+  char *pool;
+  int64_t nslots;
+  std::vector<int64_t> slot_brick;  // slot -> brick or -1
+  std::vector<int64_t> brick_slot;  // brick -> slot or -1
+  float4 *state;
+  int32_t *next;
+  int64_t state_cap;
+  vr_bricked_stats stats;
+};
+
+namespace vr {
+
+static inline int64_t clampl(int64_t a, int64_t lo, int64_t hi) { return a < lo ? lo : (a > hi ? hi : a); }
+
+// Copy brick (bx, by, bz)'s footprint into dst (S^3 elements, x fastest) and
+// return its (min, max).
+template <class T>
+static float2 gather_brick(const T *src, int64_t nx, int64_t ny, int64_t nz, int E, int S, int64_t bx, int64_t by,
+                           int64_t bz, T *dst) {
+  float mn = INFINITY, mx = -INFINITY;
+  const int64_t ox = bx * E - 1, oy = by * E - 1, oz = bz * E - 1;
+  for (int zl = 0; zl < S; ++zl) {
+    const int64_t z = clampl(oz + zl, 0, nz - 1);
+    for (int yl = 0; yl < S; ++yl) {
+      const int64_t y = clampl(oy + yl, 0, ny - 1);
+      const T *row = src + (z * ny + y) * nx;
+      T *out = dst + ((int64_t)zl * S + yl) * S;
+      for (int xl = 0; xl < S; ++xl) {
+        const T v = row[clampl(ox + xl, 0, nx - 1)];
+        out[xl] = v;
+        const float f = (float)v;
+        mn = f < mn ? f : mn;
+        mx = f > mx ? f : mx;
+      }
+    }
+  }
+  return make_float2(mn, mx);
+}
+
+// Front-to-back rank of brick (i, j, k) for a camera (see the file comment).
+static int64_t brick_rank(const CamConst &c, int E, int64_t i, int64_t j, int64_t k) {
+  const int64_t idx[3] = {i, j, k};
+  int64_t r = 0;
+  for (int a = 0; a < 3; ++a) {
+    if (c.proj != 0) {
+      const int64_t e = (int64_t)std::floor(c.eye[a] / (double)E);
+      r += std::llabs(idx[a] - e);
+    } else {
+      const double d = c.fwd[a];
+      r += d > 0.0 ? idx[a] : (d < 0.0 ? -idx[a] : 0);
+    }
+  }
+  return r;
+}
+
+static void order_bricks(const CamConst &c, int E, int32_t nbx, int32_t nby, int32_t nbz, const uint8_t *occ,
+                         std::vector<int64_t> &out) {
+  std::vector<std::pair<int64_t, int64_t>> keyed;
+  const int64_t nb = (int64_t)nbx * nby * nbz;
+  keyed.reserve((size_t)nb);
+  for (int64_t b = 0; b < nb; ++b) {
+    if (occ && !occ[b]) continue;
+    const int64_t i = b % nbx, j = (b / nbx) % nby, k = b / ((int64_t)nbx * nby);
+    keyed.emplace_back(brick_rank(c, E, i, j, k), b);
+  }
+  std::sort(keyed.begin(), keyed.end());
+  out.clear();
+  for (auto &kv : keyed) out.push_back(kv.second);
+}
+
+static void destroy(vr_bricked *v) {
+  if (!v) return;
+  if (v->host_bricks) (void)hipHostFree(v->host_bricks);
+  if (v->occ_host) (void)hipHostFree(v->occ_host);
+  if (v->page_host) (void)hipHostFree(v->page_host);
+  (void)hipFree(v->minmax_dev);
+  (void)hipFree(v->occ_dev);
+  (void)hipFree(v->page_dev);
+  (void)hipFree(v->pool);
+  (void)hipFree(v->state);
+  (void)hipFree(v->next);
+  delete v;
+}
+
+}  // namespace vr
+
+using namespace vr;
+
+extern "C" {
+
+vr_status vr_bricked_create(const vr_volume *host_vol, int32_t brick_edge, uint64_t pool_bytes, vr_bricked **out) {
+  if (!out) return fail(VR_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!host_vol || !host_vol->data) return fail(VR_E_INVALID_ARG, "host volume or its data is NULL");
+  if (host_vol->dtype != VR_U16 && host_vol->dtype != VR_I16 && host_vol->dtype != VR_F32)
+    return fail(VR_E_INVALID_ARG, "unknown volume dtype %d", host_vol->dtype);
+  if (host_vol->nx <= 0 || host_vol->ny <= 0 || host_vol->nz <= 0 || host_vol->nx > (1 << 20) ||
+      host_vol->ny > (1 << 20) || host_vol->nz > (1 << 20))
+    return fail(VR_E_INVALID_ARG, "volume dims must be in [1, 2^20]");
+  if (brick_edge < 8 || brick_edge > 128 || (brick_edge & (brick_edge - 1)) != 0)
+    return fail(VR_E_INVALID_ARG, "brick edge %d is not a power of two in [8, 128]", brick_edge);
+  vr_bricked *v = new (std::nothrow) vr_bricked();
+  if (!v) return fail(VR_E_OOM, "host allocation failed");
+  v->dtype = host_vol->dtype;
+  v->nx = host_vol->nx;
+  v->ny = host_vol->ny;
+  v->nz = host_vol->nz;
+  v->E = brick_edge;
+  v->S = brick_edge + 3;
+  v->nbx = (int32_t)((v->nx + brick_edge - 1) / brick_edge);
+  v->nby = (int32_t)((v->ny + brick_edge - 1) / brick_edge);
+  v->nbz = (int32_t)((v->nz + brick_edge - 1) / brick_edge);
+  v->nbricks = (int64_t)v->nbx * v->nby * v->nbz;
+  v->esz = v->dtype == VR_F32 ? 4 : 2;
+  v->slot_bytes = (((int64_t)v->S * v->S * v->S * v->esz) + 255) & ~(int64_t)255;
+  v->nslots = (int64_t)(pool_bytes / (uint64_t)v->slot_bytes);
+  if (v->nslots < 1) {
+    delete v;
+    return fail(VR_E_INVALID_ARG, "pool of %llu bytes holds no brick of %lld bytes", (unsigned long long)pool_bytes,
+                (long long)v->slot_bytes);
+  }
+  v->nslots = std::min<int64_t>(v->nslots, v->nbricks);
+  hipError_t e = hipHostMalloc((void **)&v->host_bricks, (size_t)(v->nbricks * v->slot_bytes), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    v->host_bricks = nullptr;
+    destroy(v);
+    return fail(VR_E_OOM, "pinned host allocation of %lld brick bytes: %s", (long long)(v->nbricks * v->slot_bytes),
+                hipGetErrorString(e));
+  }
+  // gather every footprint (and its min/max) with the host's threads
+  std::vector<float2> mm((size_t)v->nbricks);
+  const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> pool;
+  for (unsigned t = 0; t < nt; ++t)
+    pool.emplace_back([&, t]() {
+      for (int64_t b = t; b < v->nbricks; b += nt) {
+        const int64_t i = b % v->nbx, j = (b / v->nbx) % v->nby, k = b / ((int64_t)v->nbx * v->nby);
+        char *dst = v->host_bricks + b * v->slot_bytes;
+        if (v->dtype == VR_F32)
+          mm[b] = gather_brick((const float *)host_vol->data, v->nx, v->ny, v->nz, v->E, v->S, i, j, k, (float *)dst);
+        else if (v->dtype == VR_I16)
+          mm[b] = gather_brick((const int16_t *)host_vol->data, v->nx, v->ny, v->nz, v->E, v->S, i, j, k,
+                               (int16_t *)dst);
+        else
+          mm[b] = gather_brick((const uint16_t *)host_vol->data, v->nx, v->ny, v->nz, v->E, v->S, i, j, k,
+                               (uint16_t *)dst);
+      }
+    });
+  for (auto &th : pool) th.join();
+  const size_t nb = (size_t)v->nbricks;
+  if ((e = hipMalloc(&v->minmax_dev, nb * sizeof(float2))) != hipSuccess ||
+      (e = hipMalloc(&v->occ_dev, nb)) != hipSuccess || (e = hipMalloc(&v->page_dev, nb * sizeof(int32_t))) != hipSuccess ||
+      (e = hipMalloc(&v->pool, (size_t)(v->nslots * v->slot_bytes))) != hipSuccess) {
+    destroy(v);
+    return fail(VR_E_OOM, "device allocation for the brick pool: %s", hipGetErrorString(e));
+  }
+  if ((e = hipHostMalloc((void **)&v->occ_host, nb, hipHostMallocDefault)) != hipSuccess ||
+      (e = hipHostMalloc((void **)&v->page_host, nb * sizeof(int32_t), hipHostMallocDefault)) != hipSuccess) {
+    destroy(v);
+    return fail(VR_E_OOM, "pinned host allocation: %s", hipGetErrorString(e));
+  }
+  if ((e = hipMemcpy(v->minmax_dev, mm.data(), nb * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess) {
+    destroy(v);
+    return hip_fail(e, "copy brick min/max");
+  }
+  v->slot_brick.assign((size_t)v->nslots, -1);
+  v->brick_slot.assign(nb, -1);
+  memset(&v->stats, 0, sizeof(v->stats));
+  v->stats.bricks_total = (uint64_t)v->nbricks;
+  v->stats.pool_slots = (uint64_t)v->nslots;
+  v->stats.brick_bytes = (uint64_t)v->slot_bytes;
+  *out = v;
+  return VR_OK;
+}
+
+vr_status vr_brick_order(const int64_t dims[3], int32_t brick_edge, const vr_camera *cam, int64_t *order_out,
+                         int64_t n) {
+  if (!dims || !cam || !order_out) return fail(VR_E_INVALID_ARG, "dims, camera or output is NULL");
+  if (brick_edge < 1) return fail(VR_E_INVALID_ARG, "brick edge must be positive");
+  if (dims[0] <= 0 || dims[1] <= 0 || dims[2] <= 0) return fail(VR_E_INVALID_ARG, "dims must be positive");
+  CamConst c;
+  vr_status s = check_camera(cam, &c);
+  if (s) return s;
+  const int32_t nbx = (int32_t)((dims[0] + brick_edge - 1) / brick_edge);
+  const int32_t nby = (int32_t)((dims[1] + brick_edge - 1) / brick_edge);
+  const int32_t nbz = (int32_t)((dims[2] + brick_edge - 1) / brick_edge);
+  const int64_t nb = (int64_t)nbx * nby * nbz;
+  if (n < nb) return fail(VR_E_INVALID_ARG, "output holds %lld entries, need %lld", (long long)n, (long long)nb);
+  std::vector<int64_t> order;
+  order_bricks(c, brick_edge, nbx, nby, nbz, nullptr, order);
+  std::copy(order.begin(), order.end(), order_out);
+  return VR_OK;
+}
+
+vr_status vr_bricked_render(vr_bricked *v, const vr_camera *cams, int32_t n_cams, const vr_tf *tf,
+                            const vr_params *p, float *out_rgba, void *stream) {
+  if (!v) return fail(VR_E_INVALID_ARG, "bricked volume is NULL");
+  if (!tf || !p || !out_rgba) return fail(VR_E_INVALID_ARG, "tf, params or out_rgba is NULL");
+  BrickedArgs a;
+  memset(&a, 0, sizeof(a));
+  vr_status s = check_tf_fields(tf->table, tf->K, tf->v0, tf->v1, &a.tf);
+  if (s) return s;
+  if ((s = check_march(p->step, p->ert_threshold, 1, &a.mc))) return s;
+  if (!cams || n_cams <= 0) return fail(VR_E_INVALID_ARG, "need at least one camera");
+  for (int32_t i = 0; i < n_cams; ++i) {
+    if ((s = check_camera(&cams[i], nullptr))) return s;
+    if (cams[i].width != cams[0].width || cams[i].height != cams[0].height)
+      return fail(VR_E_INVALID_ARG, "all cameras must share one image size");
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t npix = (int64_t)cams[0].width * cams[0].height;
+  hipError_t e;
+  if (npix > v->state_cap) {
+    (void)hipFree(v->state);
+    (void)hipFree(v->next);
+    v->state = nullptr;
+    v->next = nullptr;
+    v->state_cap = 0;
+    if ((e = hipMalloc(&v->state, (size_t)npix * sizeof(float4))) != hipSuccess ||
+        (e = hipMalloc(&v->next, (size_t)npix * sizeof(int32_t))) != hipSuccess)
+      return fail(VR_E_OOM, "ray state allocation: %s", hipGetErrorString(e));
+    v->state_cap = npix;
+  }
+  VolConst &vc = a.vol;
+  vc.data = nullptr;
+  vc.dtype = v->dtype;
+  vc.nx = (int32_t)v->nx;
+  vc.ny = (int32_t)v->ny;
+  vc.nz = (int32_t)v->nz;
+  vc.minmax = v->minmax_dev;
+  vc.nbx = v->nbx;
+  vc.nby = v->nby;
+  vc.nbz = v->nbz;
+  vc.edge = v->E;
+  vc.edge_shift = __builtin_ctz((unsigned)v->E);
+  // 1. occupancy under this TF
+  if ((e = launch_block_occupancy(vc, a.tf, v->occ_dev, st)) != hipSuccess) return hip_fail(e, "occupancy launch");
+  if ((e = hipMemcpyAsync(v->occ_host, v->occ_dev, (size_t)v->nbricks, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess)
+    return hip_fail(e, "occupancy readback");
+  a.pool = v->pool;
+  a.page = v->page_dev;
+  a.occ = v->occ_dev;
+  a.state = v->state;
+  a.next = v->next;
+  a.slot_bytes = v->slot_bytes;
+  a.slot_edge = v->S;
+  a.W = cams[0].width;
+  a.H = cams[0].height;
+  std::vector<int64_t> order;
+  std::vector<char> in_pass((size_t)v->nbricks, 0);
+  for (int32_t view = 0; view < n_cams; ++view) {
+    check_camera(&cams[view], &a.cam);
+    // 2. front-to-back order of the occupied bricks
+    order_bricks(a.cam, v->E, v->nbx, v->nby, v->nbz, v->occ_host, order);
+    // 3. passes
+    const int64_t nocc = (int64_t)order.size();
+    int64_t pos = 0;
+    a.first = 1;
+    do {
+      const int64_t end = std::min(nocc, pos + v->nslots);
+      for (int64_t q = pos; q < end; ++q) in_pass[(size_t)order[q]] = 1;
+      // free the slots of resident bricks outside this pass
+      std::vector<int64_t> free_slots;
+      for (int64_t sl = 0; sl < v->nslots; ++sl) {
+        const int64_t b = v->slot_brick[(size_t)sl];
+        if (b >= 0 && !in_pass[(size_t)b]) {
+          v->brick_slot[(size_t)b] = -1;
+          v->slot_brick[(size_t)sl] = -1;
+        }
+        if (v->slot_brick[(size_t)sl] < 0) free_slots.push_back(sl);
+      }
+      // the previous pass's page-table copy has been consumed once the stream is idle
+      if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "pass synchronisation");
+      for (int64_t b = 0; b < v->nbricks; ++b) v->page_host[b] = -1;
+      size_t fi = 0;
+      for (int64_t q = pos; q < end; ++q) {
+        const int64_t b = order[q];
+        int64_t sl = v->brick_slot[(size_t)b];
+        if (sl < 0) {
+          sl = free_slots[fi++];
+          e = hipMemcpyAsync(v->pool + sl * v->slot_bytes, v->host_bricks + b * v->slot_bytes, (size_t)v->slot_bytes,
+                             hipMemcpyHostToDevice, st);
+          if (e != hipSuccess) return hip_fail(e, "brick upload");
+          v->brick_slot[(size_t)b] = sl;
+          v->slot_brick[(size_t)sl] = b;
+          v->stats.bricks_uploaded++;
+          v->stats.bytes_uploaded += (uint64_t)v->slot_bytes;
+        }
+        v->page_host[b] = (int32_t)sl;
+      }
+      e = hipMemcpyAsync(v->page_dev, v->page_host, (size_t)v->nbricks * sizeof(int32_t), hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) return hip_fail(e, "page table upload");
+      if ((e = launch_bricked_pass(a, st)) != hipSuccess) return hip_fail(e, "pass launch");
+      v->stats.passes++;
+      a.first = 0;
+      for (int64_t q = pos; q < end; ++q) in_pass[(size_t)order[q]] = 0;
+      pos = end;
+    } while (pos < nocc);
+    v->stats.bricks_occupied = (uint64_t)nocc;
+    // 4. image
+    float4 *dst = reinterpret_cast<float4 *>(out_rgba) + (size_t)view * (size_t)npix;
+    if ((e = launch_bricked_finish(v->state, dst, npix, st)) != hipSuccess) return hip_fail(e, "finish launch");
+  }
+  uint64_t resident = 0;
+  for (int64_t sl = 0; sl < v->nslots; ++sl) resident += v->slot_brick[(size_t)sl] >= 0;
+  v->stats.bricks_resident = resident;
+  return VR_OK;
+}
+
+vr_status vr_bricked_stats_get(const vr_bricked *v, vr_bricked_stats *out) {
+  if (!v || !out) return fail(VR_E_INVALID_ARG, "bricked volume or output is NULL");
+  *out = v->stats;
+  return VR_OK;
+}
+
+void vr_bricked_free(vr_bricked *v) {
+  if (v) (void)hipDeviceSynchronize();
+  destroy(v);
+}
+
+}  // extern "C"

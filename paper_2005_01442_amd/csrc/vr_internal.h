@@ -37,6 +37,24 @@ struct BackwardArgs {
 
 
 
+// Out-of-core pass over one view: bricks of edge E (the blocks' footprints,
+// (E+3)^3 voxels each) resident in pool slots listed by the page table.
+struct BrickedArgs {
+  VolConst vol;            // dims, block grid, edge, edge_shift (no data)
+  TfConst tf;
+  MarchConst mc;
+  CamConst cam;
+  const char *pool;        // slot i at pool + i * slot_bytes
+  const int32_t *page;     // per brick: slot in this pass, or -1
+  const uint8_t *occ;      // per brick: TF occupancy
+  float4 *state;           // per pixel: (C_r, C_g, C_b, T)
+  int32_t *next;           // per pixel: next lattice index, -1 when finished
+  int64_t slot_bytes;
+  int32_t slot_edge;       // E + 3
+  int32_t W, H;
+  int32_t first;           // initialise the ray state
+};
+
 // Largest dynamic LDS a workgroup may allocate on the current device.
 uint32_t max_lds_per_workgroup();
 
@@ -49,6 +67,8 @@ hipError_t launch_render_backward(const BackwardArgs &a, hipStream_t s);
 hipError_t launch_block_minmax(const VolConst &v, float2 *out, hipStream_t s);
 hipError_t launch_block_occupancy(const VolConst &v, const TfConst &tf, uint8_t *occ, hipStream_t s);
 hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s);
+hipError_t launch_bricked_pass(const BrickedArgs &a, hipStream_t s);
+hipError_t launch_bricked_finish(const float4 *state, float4 *out, int64_t n, hipStream_t s);
 hipError_t launch_preint_table(const float *tf, int K, float step, float4 *out, hipStream_t s);
 hipError_t launch_render_preint(const RenderArgs &a, const float4 *tab, hipStream_t s);
 
