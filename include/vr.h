@@ -273,7 +273,7 @@ typedef struct {
     uint64_t bytes_uploaded;
     uint64_t bricks_resident;   /* bricks in the pool after the last render    */
     uint64_t pool_slots;        /* bricks the pool holds                       */
-    uint64_t brick_bytes;       /* bytes of one brick (padded to 256)          */
+    uint64_t brick_bytes;       /* bytes of one pool slot (brick + 16, to 256) */
 } vr_bricked_stats;
 
 /* Copy `host_vol` (its data is a HOST pointer here, read during the call

@@ -155,7 +155,8 @@ vr_status vr_bricked_create(const vr_volume *host_vol, int32_t brick_edge, uint6
   v->nbz = (int32_t)((v->nz + brick_edge - 1) / brick_edge);
   v->nbricks = (int64_t)v->nbx * v->nby * v->nbz;
   v->esz = v->dtype == VR_F32 ? 4 : 2;
-  v->slot_bytes = (((int64_t)v->S * v->S * v->S * v->esz) + 255) & ~(int64_t)255;
+  // 16 bytes of padding keep the kernel's 12-byte row windows inside the slot
+  v->slot_bytes = (((int64_t)v->S * v->S * v->S * v->esz) + 16 + 255) & ~(int64_t)255;
   v->nslots = (int64_t)(pool_bytes / (uint64_t)v->slot_bytes);
   if (v->nslots < 1) {
     delete v;

@@ -23,6 +23,7 @@ template <int DT>
 __device__ inline float reconstruct_slot(const char *slot, int S, int ox, int oy, int oz, int nx, int ny, int nz,
                                          const Stencil &s) {
   float t[4][4][4];
+  const bool xrow = DT != kF32 && s.ix >= 1 && s.ix + 2 <= nx - 1;  // the 4 x taps are one contiguous run
   int xs[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) xs[a] = min(max(s.ix - 1 + a, 0), nx - 1) - ox;
@@ -33,6 +34,26 @@ __device__ inline float reconstruct_slot(const char *slot, int S, int ox, int oy
     for (int b = 0; b < 4; ++b) {
       const int y = min(max(s.iy - 1 + b, 0), ny - 1) - oy;
       const size_t row = ((size_t)z * S + y) * S;
+      if (xrow) {
+        // 16-bit taps: the dword-aligned 12-byte window holding them, shifted
+        // by the run's parity (the slot padding keeps the window inside)
+        const size_t e = row + xs[0];
+        const uint32_t *w = reinterpret_cast<const uint32_t *>(slot + (e & ~(size_t)1) * 2);
+        const uint32_t sh = (uint32_t)(e & 1) * 16u;
+        const uint32_t lo = __builtin_amdgcn_alignbit(w[1], w[0], sh), hi = __builtin_amdgcn_alignbit(w[2], w[1], sh);
+        if (DT == kI16) {
+          t[c][b][0] = (float)(int16_t)(lo & 0xffffu);
+          t[c][b][1] = (float)((int32_t)lo >> 16);
+          t[c][b][2] = (float)(int16_t)(hi & 0xffffu);
+          t[c][b][3] = (float)((int32_t)hi >> 16);
+        } else {
+          t[c][b][0] = (float)(lo & 0xffffu);
+          t[c][b][1] = (float)(lo >> 16);
+          t[c][b][2] = (float)(hi & 0xffffu);
+          t[c][b][3] = (float)(hi >> 16);
+        }
+        continue;
+      }
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         const size_t e = row + xs[a];
