@@ -177,6 +177,20 @@ void vr_blocks_free(vr_blocks *blocks);
 vr_status vr_render(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,
                     const vr_tf *tf, const vr_params *p, float *out_rgba, void *stream);
 
+/* Interpolating cubic B-spline.  The paper compares reconstruction filters
+ * (Section 2, the filter comparison of Fig. 4); the plain cubic B-spline
+ * smooths, its prefiltered form interpolates.  Writes to coeff_out (DEVICE,
+ * nx*ny*nz fp32, layout of the volume; may not alias vol->data) the
+ * coefficients c whose B-spline reconstruction (clamp-to-edge addressing)
+ * passes through every voxel value: along every axis line
+ *   (c[i-1] + 4 c[i] + c[i+1]) / 6 = v[i],  c[-1] = c[0], c[n] = c[n-1],
+ * solved along x, then y, then z (fp32 elimination with FP64-derived
+ * pivots).  Render the coefficient volume (VR_F32) with vr_render; its
+ * vr_build_blocks min/max bound the reconstructed values exactly, so skipping
+ * stays exact.  Enqueued on `stream` (the host waits once for a small pivot
+ * table).  Errors: VR_E_INVALID_ARG, VR_E_UNSUPPORTED, VR_E_OOM, VR_E_DEVICE. */
+vr_status vr_prefilter_bspline(const vr_volume *vol, float *coeff_out, void *stream);
+
 /* Local lighting.  The paper lights its renderings with Phong's model, the
  * gradient for the normal taken with the same cubic filter as the value
  * (Section 2, the paragraph on the three-voxel block overlap).  Here every

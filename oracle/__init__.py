@@ -84,10 +84,10 @@ def _prototypes(L):
         L.oracle_num_threads.restype = i32
         L.oracle_blocks.argtypes = [P, i32, i64, i64, i64, i32, P]
         L.oracle_blocks.restype = i32
-        L.oracle_occupancy.argtypes = [P, i64, P, i32, f32, f32, P]
+        L.oracle_occupancy.argtypes = [P, i64, P, i32, f32, f32, f32, P]
         L.oracle_occupancy.restype = i32
         L.oracle_render.argtypes = [P, i32, i64, i64, i64, P, i32, i32, i32, P, i32, f64, f64, f64, f64,
-                                    P, i32, P, i64, P, P, P]
+                                    P, i32, i32, P, i64, P, P, P]
         L.oracle_render.restype = i32
         L.oracle_grad.argtypes = [P, i32, i64, i64, i64, P, i32, i32, i32, P, i32, f64, f64, f64, f64,
                                   P, i32, P, P, P]
@@ -112,6 +112,12 @@ def _prototypes(L):
         L.oracle_render_preint.argtypes = [P, i32, i64, i64, i64, P, i32, i32, i32, P, i32, f64, f64, P, f64, f64,
                                            P, i32, P, i64, P, P, P]
         L.oracle_render_preint.restype = i32
+        L.oracle_prefilter.argtypes = [P, i32, i64, i64, i64, P]
+        L.oracle_prefilter.restype = i32
+        L.oracle_sample_filter.argtypes = [P, i32, i64, i64, i64, f64, f64, f64, i32]
+        L.oracle_sample_filter.restype = f64
+        L.oracle_catmull_rom.argtypes = [f64, P]
+        L.oracle_catmull_rom.restype = None
 
 
 def f32(x) -> float:
@@ -158,13 +164,18 @@ def blocks(vol, edge: int = 16) -> np.ndarray:
     return out
 
 
-def occupancy(minmax, tf) -> np.ndarray:
-    """One byte per block: 1 when the block can hold a visible sample under tf."""
+CATMULL_ROM_WIDEN = 0.4765625  # ((1 + 2/8)^3 - 1) / 2
+
+
+def occupancy(minmax, tf, filter=0) -> np.ndarray:
+    """One byte per block: 1 when the block can hold a visible sample under tf
+    (filter 1, Catmull-Rom: over the widened range of ``oracle_occupancy``)."""
     mm = np.ascontiguousarray(minmax, dtype=np.float64)
     nb = mm.size // 2
     occ = np.zeros(mm.shape[:-1], dtype=np.uint8)
     table = np.ascontiguousarray(tf.table, dtype=np.float32)
-    rc = lib().oracle_occupancy(_ptr(mm), nb, _ptr(table), table.shape[0], f32(tf.v0), f32(tf.v1), _ptr(occ))
+    widen = CATMULL_ROM_WIDEN if filter == 1 else 0.0
+    rc = lib().oracle_occupancy(_ptr(mm), nb, _ptr(table), table.shape[0], f32(tf.v0), f32(tf.v1), widen, _ptr(occ))
     if rc:
         raise ValueError("oracle_occupancy rejected its arguments")
     return occ
@@ -180,10 +191,11 @@ def shade_params(sh) -> np.ndarray:
                      *light, 1.0 if get("headlight") else 0.0, f32(get("grad_min"))], dtype=np.float64)
 
 
-def render(vol, cameras, tf, step, ert=0.0, occ=None, edge=16, pixels=None, shading=None):
+def render(vol, cameras, tf, step, ert=0.0, occ=None, edge=16, pixels=None, shading=None, filter=0):
     """FP64 render.  Returns dict(rgba, flags, counts); rgba is (views, H, W, 4)
     for a full render or (n, 4) for a pixel list.  ``shading`` (see
-    ``shade_params``) switches on local lighting."""
+    ``shade_params``) switches on local lighting; ``filter`` 1 reconstructs
+    with Catmull-Rom instead of the cubic B-spline (unlit only)."""
     vol, dt, nx, ny, nz = _vol(vol)
     cams = pack_cameras(cameras)
     W, H = int(cameras[0].width), int(cameras[0].height)
@@ -203,10 +215,12 @@ def render(vol, cameras, tf, step, ert=0.0, occ=None, edge=16, pixels=None, shad
     if shading is None:
         rc = lib().oracle_render(
             _ptr(vol), dt, nx, ny, nz, _ptr(cams), len(cameras), W, H, _ptr(table), table.shape[0],
-            f32(tf.v0), f32(tf.v1), f32(step), f32(ert), _ptr(occ_a), int(edge), _ptr(pix), n,
+            f32(tf.v0), f32(tf.v1), f32(step), f32(ert), _ptr(occ_a), int(edge), int(filter), _ptr(pix), n,
             _ptr(rgba), _ptr(flags), _ptr(counts),
         )
     else:
+        if filter != 0:
+            raise ValueError("local lighting is defined for the cubic B-spline only")
         sp = shade_params(shading)
         rc = lib().oracle_render_shaded(
             _ptr(vol), dt, nx, ny, nz, _ptr(cams), len(cameras), W, H, _ptr(table), table.shape[0],
@@ -262,10 +276,20 @@ def ray(camera, row, col, dims_xyz, step):
     return out[:3].copy(), out[3:6].copy(), float(out[6]), float(out[7]), int(ns.value), bool(hit)
 
 
-def sample(vol, p) -> float:
-    """Tricubic B-spline value of ``vol`` at point p = (x, y, z)."""
+def sample(vol, p, filter=0) -> float:
+    """Tricubic value of ``vol`` at point p = (x, y, z): cubic B-spline
+    (filter 0) or Catmull-Rom (filter 1)."""
     vol, dt, nx, ny, nz = _vol(vol)
-    return float(lib().oracle_sample(_ptr(vol), dt, nx, ny, nz, float(p[0]), float(p[1]), float(p[2])))
+    if filter == 0:
+        return float(lib().oracle_sample(_ptr(vol), dt, nx, ny, nz, float(p[0]), float(p[1]), float(p[2])))
+    return float(lib().oracle_sample_filter(_ptr(vol), dt, nx, ny, nz, float(p[0]), float(p[1]), float(p[2]),
+                                            int(filter)))
+
+
+def catmull_rom_weights(f) -> np.ndarray:
+    w = np.zeros(4, dtype=np.float64)
+    lib().oracle_catmull_rom(float(f), _ptr(w))
+    return w
 
 
 def weights(f) -> np.ndarray:
@@ -330,3 +354,13 @@ def render_preint(vol, cameras, tf, step, ert=0.0, minmax=None, edge=16, pixels=
     if rc:
         raise ValueError("oracle_render_preint rejected its arguments")
     return dict(rgba=rgba, flags=flags, counts=counts)
+
+
+def prefilter(vol) -> np.ndarray:
+    """Interpolating cubic B-spline coefficients of ``vol`` (FP64, same shape):
+    the B-spline of the result passes through every voxel value."""
+    vol, dt, nx, ny, nz = _vol(vol)
+    out = np.zeros(vol.shape, dtype=np.float64)
+    if lib().oracle_prefilter(_ptr(vol), dt, nx, ny, nz, _ptr(out)):
+        raise ValueError("oracle_prefilter rejected its arguments")
+    return out

@@ -54,6 +54,16 @@ def reconstruct(vol, p):
     return total
 
 
+def catmull_rom_kernel(x: Fraction) -> Fraction:
+    """Catmull-Rom: 3|x|^3/2 - 5x^2/2 + 1 for |x| < 1, -|x|^3/2 + 5x^2/2 - 4|x| + 2 for 1 <= |x| < 2."""
+    ax = abs(x)
+    if ax < 1:
+        return Fraction(3, 2) * ax ** 3 - Fraction(5, 2) * ax ** 2 + 1
+    if ax < 2:
+        return -Fraction(1, 2) * ax ** 3 + Fraction(5, 2) * ax ** 2 - 4 * ax + 2
+    return Fraction(0)
+
+
 def bspline_kernel_deriv(x: Fraction) -> Fraction:
     """beta'(x): -2x + 3x|x|/2 for |x| < 1, -sign(x) (2 - |x|)^2 / 2 for 1 <= |x| < 2."""
     ax = abs(x)

@@ -142,13 +142,25 @@ static int or_range_occupied(const float *tf, int K, float v0, float scale, floa
     return 0;
 }
 
-int oracle_occupancy(const double *minmax, long nblocks, const float *tf, int K, float v0, float v1,
+/* widen >= 0: the range tested is [lo - widen (hi - lo), hi + widen (hi -  */
+/* lo)] in fp32 fused multiply-adds, for filters whose samples can leave     */
+/* the range of their taps (Catmull-Rom: the sum of the negative weights of  */
+/* the 4x4x4 tensor product is at most ((1 + 2/8)^3 - 1)/2 = 0.4765625).     */
+int oracle_occupancy(const double *minmax, long nblocks, const float *tf, int K, float v0, float v1, float widen,
                      uint8_t *occ)
 {
-    if (!minmax || !tf || !occ || K < 2 || !(v1 > v0)) return 1;
+    if (!minmax || !tf || !occ || K < 2 || !(v1 > v0) || !(widen >= 0.0f)) return 1;
     float scale = (float)(K - 1) / (v1 - v0);
-    for (long b = 0; b < nblocks; ++b)
-        occ[b] = (uint8_t)or_range_occupied(tf, K, v0, scale, (float)minmax[2 * b], (float)minmax[2 * b + 1]);
+    for (long b = 0; b < nblocks; ++b) {
+        float lo = (float)minmax[2 * b], hi = (float)minmax[2 * b + 1];
+        if (widen > 0.0f) {
+            float d = hi - lo;
+            float wlo = fmaf(-widen, d, lo), whi = fmaf(widen, d, hi);
+            lo = wlo;
+            hi = whi;
+        }
+        occ[b] = (uint8_t)or_range_occupied(tf, K, v0, scale, lo, hi);
+    }
     return 0;
 }
 
@@ -227,6 +239,17 @@ static void or_bspline(double f, double w[4])
     w[3] = f * f * f / 6.0;
 }
 
+/* Catmull-Rom weights (the interpolating cubic of the paper's filter        */
+/* comparison, Fig. 4 discussion) for the same four taps.  Two of them are   */
+/* negative: a sample can leave the range of its taps.                      */
+static void or_catmull_rom(double f, double w[4])
+{
+    w[0] = (-f * f * f + 2.0 * f * f - f) / 2.0;
+    w[1] = (3.0 * f * f * f - 5.0 * f * f + 2.0) / 2.0;
+    w[2] = (-3.0 * f * f * f + 4.0 * f * f + f) / 2.0;
+    w[3] = (f * f * f - f * f) / 2.0;
+}
+
 /* One reconstructed sample: the 64 taps, their weights and the value.      */
 typedef struct {
     long tap[64];
@@ -236,13 +259,15 @@ typedef struct {
 
 /* Tricubic reconstruction at p: the explicit 64-term sum over the 4x4x4     */
 /* stencil, clamp-to-edge addressing.                                        */
-static void or_reconstruct(const or_vol *vol, const double p[3], or_sample *s)
+/* filter: 0 cubic B-spline, 1 Catmull-Rom.                                 */
+static void or_reconstruct_f(const or_vol *vol, const double p[3], or_sample *s, int filter)
 {
     long ix = (long)floor(p[0]), iy = (long)floor(p[1]), iz = (long)floor(p[2]);
     double wx[4], wy[4], wz[4];
-    or_bspline(p[0] - (double)ix, wx);
-    or_bspline(p[1] - (double)iy, wy);
-    or_bspline(p[2] - (double)iz, wz);
+    void (*weights)(double, double *) = filter == 1 ? or_catmull_rom : or_bspline;
+    weights(p[0] - (double)ix, wx);
+    weights(p[1] - (double)iy, wy);
+    weights(p[2] - (double)iz, wz);
     double v = 0.0;
     int n = 0;
     for (int c = 0; c < 4; ++c)
@@ -259,6 +284,8 @@ static void or_reconstruct(const or_vol *vol, const double p[3], or_sample *s)
             }
     s->v = v;
 }
+
+static void or_reconstruct(const or_vol *vol, const double p[3], or_sample *s) { or_reconstruct_f(vol, p, s, 0); }
 
 /* Derivative with respect to f of the four B-spline weights above: the     */
 /* paper computes the gradient for local lighting with the same cubic       */
@@ -376,6 +403,7 @@ typedef struct {
     const uint8_t *occ; /* NULL: no skipping */
     int edge;
     const double *shade; /* NULL: no local lighting */
+    int filter;          /* 0 cubic B-spline, 1 Catmull-Rom */
 } or_ctx;
 
 /* Sample lattice: the ray moves from its origin (the observer) with the     */
@@ -433,7 +461,7 @@ static void or_trace(const or_ctx *cx, long view, long row, long col, double rgb
         double p[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
         if (cx->occ && !or_block_occupied(cx, p)) continue;
         counts[1]++;
-        or_reconstruct(cx->vol, p, &s);
+        or_reconstruct_f(cx->vol, p, &s, cx->filter);
         double val[4], w;
         long j;
         int cl;
@@ -468,7 +496,7 @@ static void or_trace(const or_ctx *cx, long view, long row, long col, double rgb
 /* ------------------------------------------------------------------------ */
 static int or_render(const void *data, int dtype, long nx, long ny, long nz, const double *cams, int n_cams, int W,
                      int H, const float *tf, int K, double v0, double v1, double step, double ert,
-                     const uint8_t *occ, int edge, const double *shade, const long *pix, long n_pix,
+                     const uint8_t *occ, int edge, const double *shade, int filter, const long *pix, long n_pix,
                      double *out_rgba, uint8_t *out_flags, long *out_counts)
 {
     if (!data || !cams || !tf || !out_rgba || n_cams <= 0 || W <= 0 || H <= 0 || K < 2 || !(v1 > v0) ||
@@ -476,7 +504,8 @@ static int or_render(const void *data, int dtype, long nx, long ny, long nz, con
         return 1;
     if (shade && !(shade[8] > 0.0 && shade[3] >= 1.0)) return 1;
     or_vol vol = {data, dtype, nx, ny, nz};
-    or_ctx cx = {&vol, cams, W, H, tf, K, v0, v1, step, ert, occ, edge, shade};
+    if (filter != 0 && filter != 1) return 1;
+    or_ctx cx = {&vol, cams, W, H, tf, K, v0, v1, step, ert, occ, edge, shade, filter};
     long total = pix ? n_pix : (long)n_cams * W * H;
 #pragma omp parallel for schedule(dynamic, 16)
     for (long q = 0; q < total; ++q) {
@@ -504,13 +533,15 @@ static int or_render(const void *data, int dtype, long nx, long ny, long nz, con
     return 0;
 }
 
+/* filter: 0 cubic B-spline (the default reading), 1 Catmull-Rom; occ must */
+/* then come from oracle_occupancy with the Catmull-Rom widening.          */
 int oracle_render(const void *data, int dtype, long nx, long ny, long nz, const double *cams, int n_cams, int W,
                   int H, const float *tf, int K, double v0, double v1, double step, double ert,
-                  const uint8_t *occ, int edge, const long *pix, long n_pix, double *out_rgba,
+                  const uint8_t *occ, int edge, int filter, const long *pix, long n_pix, double *out_rgba,
                   uint8_t *out_flags, long *out_counts)
 {
-    return or_render(data, dtype, nx, ny, nz, cams, n_cams, W, H, tf, K, v0, v1, step, ert, occ, edge, NULL, pix,
-                     n_pix, out_rgba, out_flags, out_counts);
+    return or_render(data, dtype, nx, ny, nz, cams, n_cams, W, H, tf, K, v0, v1, step, ert, occ, edge, NULL, filter,
+                     pix, n_pix, out_rgba, out_flags, out_counts);
 }
 
 /* Forward render with local lighting; shade as in or_shade_colour.         */
@@ -520,8 +551,8 @@ int oracle_render_shaded(const void *data, int dtype, long nx, long ny, long nz,
                          double *out_rgba, uint8_t *out_flags, long *out_counts)
 {
     if (!shade) return 1;
-    return or_render(data, dtype, nx, ny, nz, cams, n_cams, W, H, tf, K, v0, v1, step, ert, occ, edge, shade, pix,
-                     n_pix, out_rgba, out_flags, out_counts);
+    return or_render(data, dtype, nx, ny, nz, cams, n_cams, W, H, tf, K, v0, v1, step, ert, occ, edge, shade, 0,
+                     pix, n_pix, out_rgba, out_flags, out_counts);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -557,7 +588,7 @@ int oracle_grad(const void *data, int dtype, long nx, long ny, long nz, const do
         !(step > 0.0))
         return 1;
     or_vol vol = {data, dtype, nx, ny, nz};
-    or_ctx cx = {&vol, cams, W, H, tf, K, v0, v1, step, ert, occ, edge, NULL};
+    or_ctx cx = {&vol, cams, W, H, tf, K, v0, v1, step, ert, occ, edge, NULL, 0};
     long total = (long)n_cams * W * H;
     double slope_scale = (double)(K - 1) / (v1 - v0);
     int ert_on = ert > 0.0 && ert < 1.0;
@@ -660,6 +691,18 @@ double oracle_sample(const void *data, int dtype, long nx, long ny, long nz, dou
     or_reconstruct(&vol, p, &s);
     return s.v;
 }
+
+double oracle_sample_filter(const void *data, int dtype, long nx, long ny, long nz, double px, double py, double pz,
+                            int filter)
+{
+    or_vol vol = {data, dtype, nx, ny, nz};
+    double p[3] = {px, py, pz};
+    or_sample s;
+    or_reconstruct_f(&vol, p, &s, filter);
+    return s.v;
+}
+
+void oracle_catmull_rom(double f, double w[4]) { or_catmull_rom(f, w); }
 
 /* B-spline weights at fractional offset f (exposed for the weight pins).   */
 void oracle_weights(double f, double w[4]) { or_bspline(f, w); }
@@ -892,5 +935,57 @@ int oracle_render_preint(const void *data, int dtype, long nx, long ny, long nz,
             out_counts[2 * q + 1] = nev;
         }
     }
+    return 0;
+}
+
+
+/* ------------------------------------------------------------------------ */
+/* Interpolating cubic B-spline (the prefiltered spline of the paper's      */
+/* filter comparison, Fig. 4 discussion): coefficients c such that the      */
+/* B-spline reconstruction with clamp-to-edge addressing passes through     */
+/* every voxel value.  Per axis line the condition is                       */
+/*   (c[i-1] + 4 c[i] + c[i+1]) / 6 = v[i],  c[-1] = c[0], c[n] = c[n-1],   */
+/* a tridiagonal system (diagonal 5 in the first and last rows, for n >= 2; */
+/* c = v for n = 1), solved along x, then y, then z (the tensor-product     */
+/* condition separates), each line by plain Gaussian elimination of the     */
+/* tridiagonal matrix.  out: nx*ny*nz doubles, layout of the volume.        */
+/* ------------------------------------------------------------------------ */
+static void or_tridiag_line(double *x, long n, long stride, double *sub, double *diag, double *sup, double *rhs)
+{
+    if (n == 1) return;
+    for (long i = 0; i < n; ++i) {
+        sub[i] = i > 0 ? 1.0 : 0.0;
+        sup[i] = i < n - 1 ? 1.0 : 0.0;
+        diag[i] = (i == 0 || i == n - 1) ? 5.0 : 4.0;
+        rhs[i] = 6.0 * x[i * stride];
+    }
+    for (long i = 1; i < n; ++i) {
+        double m = sub[i] / diag[i - 1];
+        diag[i] -= m * sup[i - 1];
+        rhs[i] -= m * rhs[i - 1];
+    }
+    x[(n - 1) * stride] = rhs[n - 1] / diag[n - 1];
+    for (long i = n - 2; i >= 0; --i) x[i * stride] = (rhs[i] - sup[i] * x[(i + 1) * stride]) / diag[i];
+}
+
+int oracle_prefilter(const void *data, int dtype, long nx, long ny, long nz, double *out)
+{
+    if (!data || !out || nx <= 0 || ny <= 0 || nz <= 0) return 1;
+    or_vol vol = {data, dtype, nx, ny, nz};
+    for (long z = 0; z < nz; ++z)
+        for (long y = 0; y < ny; ++y)
+            for (long x = 0; x < nx; ++x) out[x + nx * (y + ny * z)] = or_voxel(&vol, x, y, z);
+    long nmax = nx > ny ? nx : ny;
+    if (nz > nmax) nmax = nz;
+    double *work = (double *)malloc(sizeof(double) * 4 * (size_t)nmax);
+    if (!work) return 1;
+    double *sub = work, *diag = work + nmax, *sup = work + 2 * nmax, *rhs = work + 3 * nmax;
+    for (long z = 0; z < nz; ++z)
+        for (long y = 0; y < ny; ++y) or_tridiag_line(out + nx * (y + ny * z), nx, 1, sub, diag, sup, rhs);
+    for (long z = 0; z < nz; ++z)
+        for (long x = 0; x < nx; ++x) or_tridiag_line(out + x + nx * ny * z, ny, nx, sub, diag, sup, rhs);
+    for (long y = 0; y < ny; ++y)
+        for (long x = 0; x < nx; ++x) or_tridiag_line(out + x + nx * y, nz, nx * ny, sub, diag, sup, rhs);
+    free(work);
     return 0;
 }

@@ -32,6 +32,7 @@ __all__ = [
     "vr_render_backward",
     "Shading",
     "PreintTable",
+    "vr_prefilter_bspline",
     "BrickedVolume",
     "vr_brick_order",
     "vr_preint_build",
@@ -230,6 +231,14 @@ def vr_render(volume: Volume, blocks, cameras, tf: TF, step: float, ert: float =
                                      len(cameras), ctypes.byref(tf.c), ctypes.byref(p), ctypes.byref(sh),
                                      ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out
+
+
+def vr_prefilter_bspline(volume: Volume, stream=None) -> Volume:
+    """Interpolating cubic B-spline coefficients of ``volume`` as a new fp32
+    Volume (render it with ``vr_render`` for an interpolating filter)."""
+    out = torch.empty(volume.tensor.shape, dtype=torch.float32, device=volume.tensor.device)
+    check(lib().vr_prefilter_bspline(ctypes.byref(volume.c), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return Volume(out)
 
 
 class PreintTable:

@@ -110,6 +110,7 @@ PROTOTYPES = {
     "vr_bricked_stats_get": ([c_void_p, POINTER(vr_bricked_stats)], c_int32),
     "vr_brick_order": ([POINTER(c_int64), c_int32, POINTER(vr_camera), POINTER(c_int64), c_int64], c_int32),
     "vr_bricked_free": ([c_void_p], None),
+    "vr_prefilter_bspline": ([POINTER(vr_volume), c_void_p, c_void_p], c_int32),
     "vr_render_backward": ([POINTER(vr_volume), c_void_p, POINTER(vr_camera), c_int32, POINTER(vr_tf),
                             POINTER(vr_params), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p], c_int32),
     "vr_serve_create": ([POINTER(vr_serve_config), POINTER(c_void_p)], c_int32),

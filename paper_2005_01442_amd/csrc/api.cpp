@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "vr.h"
 #include "vr_internal.h"
@@ -418,6 +419,41 @@ vr_status vr_render_preint(const vr_volume *vol, const vr_blocks *blocks, const 
     return fail(VR_E_INVALID_ARG, "the pre-integration table was built for another TF or step");
   if (!out_rgba) return fail(VR_E_INVALID_ARG, "out_rgba is NULL");
   return render_views(a, cams, n_cams, out_rgba, stream, table->table);
+}
+
+vr_status vr_prefilter_bspline(const vr_volume *vol, float *coeff_out, void *stream) {
+  VolConst vc;
+  vr_status s = check_volume(vol, &vc);
+  if (s) return s;
+  if (!coeff_out) return fail(VR_E_INVALID_ARG, "coeff_out is NULL");
+  // pivots of tridiag(1, 4, 1) with end diagonals 5, per axis length (FP64,
+  // rounded once); the table travels with the launch in a small device buffer
+  const int64_t dims[3] = {vol->nx, vol->ny, vol->nz};
+  std::vector<float> coef;
+  for (int a = 0; a < 3; ++a) {
+    const int64_t n = dims[a];
+    std::vector<double> piv((size_t)n), sup((size_t)n, 0.0);
+    for (int64_t i = 0; i < n; ++i) {
+      const double diag = (i == 0 || i == n - 1) ? 5.0 : 4.0;
+      piv[(size_t)i] = i == 0 ? diag : diag - sup[(size_t)i - 1];
+      sup[(size_t)i] = i < n - 1 ? 1.0 / piv[(size_t)i] : 0.0;
+    }
+    for (int64_t i = 0; i < n; ++i) coef.push_back((float)(1.0 / piv[(size_t)i]));
+    for (int64_t i = 0; i < n; ++i) coef.push_back((float)sup[(size_t)i]);
+  }
+  float *dcoef = nullptr;
+  hipError_t e = hipMallocAsync((void **)&dcoef, coef.size() * sizeof(float), (hipStream_t)stream);
+  if (e != hipSuccess) return fail(VR_E_OOM, "prefilter table allocation: %s", hipGetErrorString(e));
+  if ((e = hipMemcpyAsync(dcoef, coef.data(), coef.size() * sizeof(float), hipMemcpyHostToDevice,
+                          (hipStream_t)stream)) != hipSuccess ||
+      (e = hipStreamSynchronize((hipStream_t)stream)) != hipSuccess) {
+    (void)hipFreeAsync(dcoef, (hipStream_t)stream);
+    return hip_fail(e, "prefilter table upload");
+  }
+  e = launch_prefilter(vc, coeff_out, dcoef, (hipStream_t)stream);
+  (void)hipFreeAsync(dcoef, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "prefilter launch");
+  return VR_OK;
 }
 
 vr_status vr_render_backward(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,

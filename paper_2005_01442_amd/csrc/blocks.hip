@@ -97,3 +97,83 @@ hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s) {
 }
 
 }  // namespace vr
+
+namespace vr {
+
+// Interpolating cubic B-spline prefilter, one axis: every line solves
+// (c[i-1] + 4 c[i] + c[i+1]) / 6 = v[i] with c[-1] = c[0], c[n] = c[n-1]
+// (diagonal 5 in the end rows).  The elimination's pivots depend only on the
+// line length, so they come precomputed (inv_piv[i] = 1 / pivot i, sup[i] the
+// eliminated super-diagonal); a thread sweeps one line forward and back, in
+// place.  Lines along y and z are coalesced across a wavefront's lanes.
+__global__ __launch_bounds__(kWgSize) void k_prefilter_axis(float *vol, int nx, int ny, int nz, int axis,
+                                                            const float *inv_piv, const float *sup) {
+  const int64_t line = (int64_t)blockIdx.x * kWgSize + threadIdx.x;
+  int64_t base, stride;
+  int n;
+  if (axis == 0) {
+    if (line >= (int64_t)ny * nz) return;
+    base = line * nx;
+    stride = 1;
+    n = nx;
+  } else if (axis == 1) {
+    if (line >= (int64_t)nx * nz) return;
+    const int64_t x = line % nx, z = line / nx;
+    base = z * (int64_t)nx * ny + x;
+    stride = nx;
+    n = ny;
+  } else {
+    if (line >= (int64_t)nx * ny) return;
+    base = line;
+    stride = (int64_t)nx * ny;
+    n = nz;
+  }
+  if (n == 1) return;
+  float *p = vol + base;
+  float prev = 6.0f * p[0] * inv_piv[0];
+  p[0] = prev;
+  for (int i = 1; i < n; ++i) {
+    prev = (6.0f * p[(int64_t)i * stride] - prev) * inv_piv[i];
+    p[(int64_t)i * stride] = prev;
+  }
+  float next = prev;
+  for (int i = n - 2; i >= 0; --i) {
+    next = p[(int64_t)i * stride] - sup[i] * next;
+    p[(int64_t)i * stride] = next;
+  }
+}
+
+// Copy a volume of any dtype into fp32.
+template <int DT>
+__global__ __launch_bounds__(kWgSize) void k_to_f32(const void *src, float *dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kWgSize + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWgSize) {
+    if (DT == kF32)
+      dst[i] = reinterpret_cast<const float *>(src)[i];
+    else if (DT == kI16)
+      dst[i] = (float)reinterpret_cast<const int16_t *>(src)[i];
+    else
+      dst[i] = (float)reinterpret_cast<const uint16_t *>(src)[i];
+  }
+}
+
+hipError_t launch_prefilter(const VolConst &v, float *out, const float *coef, hipStream_t s) {
+  const int64_t n = (int64_t)v.nx * v.ny * v.nz;
+  int64_t g = (n + kWgSize - 1) / kWgSize;
+  if (g > 65536) g = 65536;
+  switch (v.dtype) {
+  case kU16: hipLaunchKernelGGL(k_to_f32<kU16>, dim3((unsigned)g), dim3(kWgSize), 0, s, v.data, out, n); break;
+  case kI16: hipLaunchKernelGGL(k_to_f32<kI16>, dim3((unsigned)g), dim3(kWgSize), 0, s, v.data, out, n); break;
+  default: hipLaunchKernelGGL(k_to_f32<kF32>, dim3((unsigned)g), dim3(kWgSize), 0, s, v.data, out, n); break;
+  }
+  const int dims[3] = {v.nx, v.ny, v.nz};
+  int64_t off = 0;
+  for (int axis = 0; axis < 3; ++axis) {
+    const int64_t lines = n / dims[axis];
+    hipLaunchKernelGGL(k_prefilter_axis, dim3((unsigned)((lines + kWgSize - 1) / kWgSize)), dim3(kWgSize), 0, s, out,
+                       v.nx, v.ny, v.nz, axis, coef + off, coef + off + dims[axis]);
+    off += 2 * (int64_t)dims[axis];
+  }
+  return hipGetLastError();
+}
+
+}  // namespace vr

@@ -67,6 +67,9 @@ hipError_t launch_render_backward(const BackwardArgs &a, hipStream_t s);
 hipError_t launch_block_minmax(const VolConst &v, float2 *out, hipStream_t s);
 hipError_t launch_block_occupancy(const VolConst &v, const TfConst &tf, uint8_t *occ, hipStream_t s);
 hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s);
+// coef: per axis (x, y, z) 2 n floats: 1 / pivot[i], then the eliminated
+// super-diagonal sup[i] of the prefilter's tridiagonal system.
+hipError_t launch_prefilter(const VolConst &v, float *out, const float *coef, hipStream_t s);
 hipError_t launch_bricked_pass(const BrickedArgs &a, hipStream_t s);
 hipError_t launch_bricked_finish(const float4 *state, float4 *out, int64_t n, hipStream_t s);
 hipError_t launch_preint_table(const float *tf, int K, float step, float4 *out, hipStream_t s);

@@ -1,0 +1,117 @@
+"""Pins of the oracle's filter variants (the paper's filter comparison,
+Fig. 4 discussion): the interpolating (prefiltered) cubic B-spline and the
+Catmull-Rom cubic with its widened skip test."""
+
+import numpy as np
+import pytest
+from scipy.linalg import solve_banded
+
+from fractions import Fraction
+
+import oracle
+from oracle import brute
+import synth
+
+
+@pytest.mark.parametrize("shape,dtype", [((5, 6, 7), np.float64), ((1, 2, 9), np.float32), ((4, 1, 3), np.uint16),
+                                         ((3, 5, 2), np.int16)])
+def test_prefiltered_spline_interpolates_every_voxel(oracle_lib, shape, dtype):
+    rng = np.random.default_rng(501)
+    vol = (rng.normal(0, 500, shape) + (2000 if dtype == np.uint16 else 0)).astype(dtype)
+    c = oracle.prefilter(vol)
+    nz, ny, nx = shape
+    worst = max(abs(oracle.sample(c, (x, y, z)) - float(vol[z, y, x]))
+                for z in range(nz) for y in range(ny) for x in range(nx))
+    assert worst < 1e-9 * max(1.0, float(np.abs(vol).max()))
+
+
+def test_prefilter_line_matches_a_banded_solver(oracle_lib):
+    """Along one axis the coefficients solve tridiag(1, 4, 1) / 6 with the
+    clamped ends (diagonal 5): scipy's banded LU as an independent solver."""
+    rng = np.random.default_rng(502)
+    for n in (2, 3, 8, 33):
+        v = rng.normal(size=n)
+        ab = np.zeros((3, n))
+        ab[0, 1:] = 1.0
+        ab[1, :] = 4.0
+        ab[1, 0] = ab[1, -1] = 5.0
+        ab[2, :-1] = 1.0
+        want = solve_banded((1, 1), ab, 6.0 * v)
+        got = oracle.prefilter(v.reshape(1, 1, n))[0, 0]
+        np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
+
+
+def test_prefilter_keeps_constants(oracle_lib):
+    vol = np.full((4, 5, 6), 1234, dtype=np.int16)
+    np.testing.assert_allclose(oracle.prefilter(vol), 1234.0, rtol=0, atol=1e-10)
+
+
+# ------------------------------------------------------------ Catmull-Rom --
+
+def test_catmull_rom_weights_match_the_kernel(oracle_lib):
+    rng = np.random.default_rng(503)
+    for f in list(rng.uniform(0, 1, 100)) + [0.0, 0.5, 0.25]:
+        w = oracle.catmull_rom_weights(f)
+        for a in range(4):
+            assert abs(w[a] - float(brute.catmull_rom_kernel(Fraction(f) + 1 - a))) < 1e-14
+        assert abs(w.sum() - 1.0) < 1e-14
+
+
+def test_catmull_rom_interpolates_and_reproduces_quadratics(oracle_lib):
+    rng = np.random.default_rng(504)
+    vol = rng.normal(0, 100, (6, 7, 8))
+    for z in range(6):
+        for y in range(7):
+            for x in range(8):
+                assert abs(oracle.sample(vol, (x, y, z), filter=1) - vol[z, y, x]) < 1e-11
+    z_, y_, x_ = np.meshgrid(np.arange(12.0), np.arange(12.0), np.arange(12.0), indexing="ij")
+    q = x_ * x_ - 2.0 * y_ * z_ + 3.0 * z_
+    for _ in range(20):
+        p = rng.uniform(2.0, 8.99, 3)
+        want = p[0] ** 2 - 2 * p[1] * p[2] + 3 * p[2]
+        assert abs(oracle.sample(q, p, filter=1) - want) < 1e-10
+
+
+def test_catmull_rom_overshoot_bound_is_tight(oracle_lib):
+    """Samples stay within [lo - w (hi - lo), hi + w (hi - lo)], w = 0.4765625,
+    and a checkerboard of the negative taps reaches the bound."""
+    rng = np.random.default_rng(505)
+    vol = rng.integers(0, 2, (6, 6, 6)).astype(np.float64) * 1000.0
+    w = oracle.CATMULL_ROM_WIDEN
+    for _ in range(300):
+        p = rng.uniform(1.0, 3.999, 3)
+        v = oracle.sample(vol, p, filter=1)
+        assert -w * 1000.0 - 1e-9 <= v <= 1000.0 + w * 1000.0 + 1e-9
+    # taps at offsets -1 and +2 (negative weights at f = 1/2) high, others low,
+    # on every axis: the product's negative weights all meet 1000
+    chk = np.zeros((4, 4, 4))
+    for c in range(4):
+        for b in range(4):
+            for a in range(4):
+                neg = ((a in (0, 3)) + (b in (0, 3)) + (c in (0, 3))) % 2 == 1
+                chk[c, b, a] = 1000.0 if neg else 0.0
+    assert abs(oracle.sample(chk, (1.5, 1.5, 1.5), filter=1) - (-w * 1000.0)) < 1e-9
+
+
+def _undershoot_case():
+    """Step edges 0 -> 1000 whose Catmull-Rom undershoot reaches values that
+    only a TF band below -40 makes visible; the blocks' own ranges [0, 1000]
+    never touch that band."""
+    vol = np.zeros((16, 16, 32), dtype=np.int16)
+    vol[:, :, 16:] = 1000
+    vol[:, 8:, :] = np.where(vol[:, 8:, :] == 0, 1000, 0)
+    pts = [(-500.0, (0, 0, 0, 0)), (-50.0, (0.2, 0.9, 0.4, 0.8)), (-40.0, (0, 0, 0, 0)), (1500.0, (0, 0, 0, 0))]
+    tf = synth.tf_from_points(pts, 201, -500.0, 1500.0)
+    cams = synth.orbit_cameras((32, 16, 16), 2, 506, 50.0, 24, 20)
+    return vol, tf, cams
+
+
+def test_catmull_rom_skip_is_lossless_with_widened_ranges(oracle_lib):
+    vol, tf, cams = _undershoot_case()
+    mm = oracle.blocks(vol, 8)
+    full = oracle.render(vol, cams, tf, 0.5, filter=1)
+    assert full["rgba"][..., 3].max() > 0.01  # the undershoot band is visible
+    skip = oracle.render(vol, cams, tf, 0.5, filter=1, occ=oracle.occupancy(mm, tf, filter=1), edge=8)
+    np.testing.assert_array_equal(skip["rgba"], full["rgba"])
+    # the B-spline never undershoots: same volume, nothing visible
+    assert oracle.render(vol, cams, tf, 0.5)["rgba"].max() == 0.0

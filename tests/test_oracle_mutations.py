@@ -4,12 +4,14 @@ oracle.c (on the CPU) must each make at least one pin fail."""
 import os
 import subprocess
 
+import numpy as np
 import pytest
 
 import oracle
 import test_oracle_pins as pins
 import test_oracle_shading as shading
 import test_oracle_preint as preint
+import test_oracle_filters as filters
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
 
@@ -18,7 +20,7 @@ MUTANTS = {
         "w[1] = (3.0 * f * f * f - 6.0 * f * f + 4.0) / 6.0;\n    w[2] = (-3.0 * f * f * f + 3.0 * f * f + 3.0 * f + 1.0) / 6.0;",
         "w[2] = (3.0 * f * f * f - 6.0 * f * f + 4.0) / 6.0;\n    w[1] = (-3.0 * f * f * f + 3.0 * f * f + 3.0 * f + 1.0) / 6.0;",
     ),
-    "bspline_w2_sign": ("w[2] = (-3.0 * f * f * f", "w[2] = (3.0 * f * f * f"),
+    "bspline_w2_sign": ("w[2] = (-3.0 * f * f * f + 3.0 * f * f", "w[2] = (3.0 * f * f * f + 3.0 * f * f"),
     "bspline_w0_w3_swapped": ("w[0] = g * g * g / 6.0;", "w[0] = f * f * f / 6.0;"),
     "tf_weights_swapped": (
         "out[c] = (1.0 - w) * (double)tf[4 * j + c] + w * (double)tf[4 * (j + 1) + c];",
@@ -53,6 +55,13 @@ MUTANTS = {
         "double lo = minmax[2 * bf], hi = minmax[2 * bf + 1];"),
     "preint_bilinear_corners_swapped": ("w[0] * (1.0 - w[1]) * p10 + (1.0 - w[0]) * w[1] * p01",
                                         "w[0] * (1.0 - w[1]) * p01 + (1.0 - w[0]) * w[1] * p10"),
+    "prefilter_end_rows_unclamped": ("diag[i] = (i == 0 || i == n - 1) ? 5.0 : 4.0;", "diag[i] = 4.0;"),
+    "prefilter_without_z_pass": ("for (long x = 0; x < nx; ++x) or_tridiag_line(out + x + nx * y, nz, nx * ny, sub, diag, sup, rhs);",
+                                 "for (long x = 0; x < nx; ++x) (void)0;"),
+    "catmull_rom_w1_wrong": ("w[1] = (3.0 * f * f * f - 5.0 * f * f + 2.0) / 2.0;",
+                             "w[1] = (3.0 * f * f * f - 4.0 * f * f + 2.0) / 2.0;"),
+    "catmull_rom_range_not_widened": ("if (widen > 0.0f) {", "if (widen > 1e30f) {"),
+    "catmull_rom_widened_low_end_wrong_way": ("float wlo = fmaf(-widen, d, lo)", "float wlo = fmaf(widen, d, lo)"),
 }
 
 
@@ -84,6 +93,11 @@ PINS = [
     lambda lib: preint.test_preint_skip_is_lossless(lib, 2.5, 4),
     preint.test_preint_skip_joins_both_blocks,
     preint.test_preint_render_matches_brute_force,
+    lambda lib: filters.test_prefiltered_spline_interpolates_every_voxel(lib, (5, 6, 7), np.float64),
+    filters.test_prefilter_line_matches_a_banded_solver,
+    filters.test_catmull_rom_weights_match_the_kernel,
+    filters.test_catmull_rom_interpolates_and_reproduces_quadratics,
+    filters.test_catmull_rom_skip_is_lossless_with_widened_ranges,
 ]
 
 
