@@ -63,6 +63,7 @@ def parse():
     ap.add_argument("--no-preint", action="store_true",
                     help="skip the pre-integrated forward and the step-artefact measurement")
     ap.add_argument("--no-bricked", action="store_true", help="skip the out-of-core (brick pool) measurement")
+    ap.add_argument("--no-filters", action="store_true", help="skip the Catmull-Rom / interpolating-spline frames")
     return ap.parse_args()
 
 
@@ -458,7 +459,7 @@ def main():
         "unit": "GB/s",
         "frac": achieved_gbs / HBM_PEAK_GBS,
         "traffic": traffic,
-        "kernel": "k_render<kI16, unlit>",
+        "kernel": "k_render<kI16, unlit, B-spline>",
         "bytes_per_launch": evaluated * TAPS_BYTES_I16,
     }
 
@@ -488,6 +489,33 @@ def main():
 
     if not args.no_preint:
         result["c1_preint"] = preint_measurements(vr, torch, np, synth, c, vol, blocks, cams, tf, out, args)
+
+    if not args.no_filters:
+        def fwd_cr():
+            vr.vr_render(vol, blocks, cams, tf, c["step"], c["ert"], True, out=out, filter=vr.VR_FILTER_CATMULL_ROM)
+
+        wall_cr, ev_cr = time_steps(fwd_cr, args.steps, args.warmup, torch)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        coef = vr.vr_prefilter_bspline(vol)
+        torch.cuda.synchronize()
+        pre_ms = (time.perf_counter() - t0) * 1e3
+        cblocks = vr.vr_build_blocks(coef, 16)
+
+        def fwd_interp():
+            vr.vr_render(coef, cblocks, cams, tf, c["step"], c["ert"], True, out=out)
+
+        wall_ip, ev_ip = time_steps(fwd_interp, args.steps, args.warmup, torch)
+        result["c1_filters"] = {
+            "catmull_rom_ms": wall_cr / args.steps * 1e3,
+            "interpolating_bspline_ms": wall_ip / args.steps * 1e3,
+            "prefilter_ms": pre_ms,
+            "note": "same frame; Catmull-Rom with widened block ranges; interpolating cubic B-spline = prefiltered "
+                    "fp32 coefficient volume (256 B of taps per sample) rendered with the default filter",
+        }
+        log(f"filters: Catmull-Rom {wall_cr / args.steps * 1e3:.3f} ms, interpolating B-spline "
+            f"{wall_ip / args.steps * 1e3:.3f} ms (+ prefilter {pre_ms:.2f} ms once)")
+        del coef, cblocks
 
     if not args.no_bricked:
         result["c1_out_of_core"] = bricked_measurements(vr, torch, np, c, cams, tf, out, args)

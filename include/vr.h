@@ -115,9 +115,21 @@ typedef struct {
     float step;
     float ert_threshold;
     int32_t use_skip;
-    int32_t reserved;
+    int32_t filter;      /* VR_FILTER_*; vr_render only, 0 elsewhere */
     uint64_t *counters;
 } vr_params;
+
+/* Reconstruction filters (the paper's filter comparison, Fig. 4 discussion).
+ * VR_FILTER_BSPLINE: the uniform cubic B-spline (the default reading).
+ * VR_FILTER_CATMULL_ROM: the interpolating Catmull-Rom cubic on the same 64
+ *   taps, weights (-t^3+2t^2-t)/2, (3t^3-5t^2+2)/2, (-3t^3+4t^2+t)/2,
+ *   (t^3-t^2)/2.  Its samples can leave their taps' range by at most
+ *   w = ((1 + 2/8)^3 - 1)/2 = 0.4765625 of it, so its block test widens every
+ *   block's range to [lo - w (hi - lo), hi + w (hi - lo)] (fp32 fused
+ *   multiply-adds) and skipping stays exact.
+ * (The interpolating cubic B-spline is vr_prefilter_bspline + this default.) */
+#define VR_FILTER_BSPLINE 0
+#define VR_FILTER_CATMULL_ROM 1
 
 /* ---------------------------------------------------------------------- */
 /* Blocks: the auxiliary structure for empty-space leaping (Section 2,     */
@@ -136,7 +148,8 @@ typedef struct vr_blocks vr_blocks;
 /* Build the block min/max for `vol` with edge `block_edge` (a power of two
  * in [4, 64]).
  * Enqueued on `stream`; *out is valid immediately and usable on the same
- * stream.  Allocates device memory (8 bytes per block).
+ * stream.  Allocates device memory (16 bytes per block: the ranges and
+ * their Catmull-Rom widening).
  * Errors: VR_E_INVALID_ARG (null/invalid volume, edge out of range),
  * VR_E_OOM, VR_E_DEVICE. */
 vr_status vr_build_blocks(const vr_volume *vol, int32_t block_edge, void *stream, vr_blocks **out);

@@ -18,7 +18,7 @@ from dataclasses import dataclass
 import torch
 
 from . import _abi
-from ._abi import VrError, VR_F32, VR_I16, VR_U16, check, lib
+from ._abi import VrError, VR_F32, VR_FILTER_BSPLINE, VR_FILTER_CATMULL_ROM, VR_I16, VR_U16, check, lib
 
 __all__ = [
     "VrError",
@@ -172,11 +172,12 @@ def vr_block_occupancy(blocks: Blocks, tf: TF, stream=None) -> torch.Tensor:
     return dst
 
 
-def _params(step, ert, use_skip, counters):
+def _params(step, ert, use_skip, counters, filter=0):
     p = _abi.vr_params()
     p.step = float(step)
     p.ert_threshold = float(ert)
     p.use_skip = 1 if use_skip else 0
+    p.filter = int(filter)
     p.counters = None if counters is None else counters.data_ptr()
     return p
 
@@ -208,19 +209,20 @@ class Shading:
 
 def vr_render(volume: Volume, blocks, cameras, tf: TF, step: float, ert: float = 0.0, use_skip: bool = False,
               out: torch.Tensor | None = None, counters: torch.Tensor | None = None, stream=None,
-              shading: Shading | None = None) -> torch.Tensor:
+              shading: Shading | None = None, filter: int = 0) -> torch.Tensor:
     """Render len(cameras) views; returns (views, H, W, 4) fp32 premultiplied RGBA.
     ``counters``: optional int64 CUDA tensor of 4 that the kernel adds
     [evaluated samples, lattice samples, rays with samples, samples read from
     global memory instead of an LDS box] to.  ``shading`` switches on local
-    lighting (``vr_render_shaded``)."""
+    lighting (``vr_render_shaded``); ``filter`` selects the reconstruction
+    (VR_FILTER_BSPLINE, VR_FILTER_CATMULL_ROM)."""
     W, H = int(cameras[0].width), int(cameras[0].height)
     if out is None:
         out = torch.empty((len(cameras), H, W, 4), dtype=torch.float32, device=volume.tensor.device)
     if counters is not None and (counters.dtype != torch.int64 or counters.numel() < 4 or not counters.is_cuda):
         raise ValueError("counters must be an int64 CUDA tensor of at least 4 elements")
     cams = _cameras(cameras)
-    p = _params(step, ert, use_skip, counters)
+    p = _params(step, ert, use_skip, counters, filter)
     if shading is None:
         check(lib().vr_render(ctypes.byref(volume.c), None if blocks is None else blocks.ptr, cams, len(cameras),
                               ctypes.byref(tf.c), ctypes.byref(p), ctypes.c_void_p(out.data_ptr()),

@@ -27,6 +27,7 @@ STATUS_NAMES = {
     9: "VR_E_SHUTDOWN",
 }
 VR_U16, VR_I16, VR_F32 = 0, 1, 2
+VR_FILTER_BSPLINE, VR_FILTER_CATMULL_ROM = 0, 1
 VR_MAX_TF_NODES = 1024
 
 
@@ -53,7 +54,7 @@ class vr_tf(ctypes.Structure):
 
 
 class vr_params(ctypes.Structure):
-    _fields_ = [("step", c_float), ("ert_threshold", c_float), ("use_skip", c_int32), ("reserved", c_int32),
+    _fields_ = [("step", c_float), ("ert_threshold", c_float), ("use_skip", c_int32), ("filter", c_int32),
                 ("counters", c_void_p)]
 
 

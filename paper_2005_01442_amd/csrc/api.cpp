@@ -19,6 +19,7 @@ struct vr_blocks {
   int32_t edge;
   int32_t nbx, nby, nbz;
   float2 *minmax;
+  float2 *minmax_cr;  // ranges widened for Catmull-Rom samples
   int device;
 };
 
@@ -220,7 +221,11 @@ static vr_status prepare(const vr_volume *vol, const vr_blocks *blocks, const vr
     if (cams[i].width != cams[0].width || cams[i].height != cams[0].height)
       return fail(VR_E_INVALID_ARG, "all cameras must share one image size");
   }
+  if (p->filter != VR_FILTER_BSPLINE && p->filter != VR_FILTER_CATMULL_ROM)
+    return fail(VR_E_INVALID_ARG, "unknown filter %d", p->filter);
   if (p->use_skip && (s = attach_blocks(blocks, vol, &a->vol))) return s;
+  a->filter = p->filter;
+  if (p->use_skip && p->filter == VR_FILTER_CATMULL_ROM) a->vol.minmax = blocks->minmax_cr;
   a->counters = reinterpret_cast<unsigned long long *>(p->counters);
   a->W = cams[0].width;
   a->H = cams[0].height;
@@ -259,17 +264,19 @@ vr_status vr_build_blocks(const vr_volume *vol, int32_t block_edge, void *stream
   b->nbz = (int32_t)((vol->nz + block_edge - 1) / block_edge);
   (void)hipGetDevice(&b->device);
   const size_t nb = (size_t)b->nbx * b->nby * b->nbz;
-  hipError_t e = hipMalloc(&b->minmax, nb * sizeof(float2));
+  hipError_t e = hipMalloc(&b->minmax, 2 * nb * sizeof(float2));
   if (e != hipSuccess) {
     delete b;
-    return fail(VR_E_OOM, "hipMalloc of %zu block bytes: %s", nb * sizeof(float2), hipGetErrorString(e));
+    return fail(VR_E_OOM, "hipMalloc of %zu block bytes: %s", 2 * nb * sizeof(float2), hipGetErrorString(e));
   }
+  b->minmax_cr = b->minmax + nb;
   vc.nbx = b->nbx;
   vc.nby = b->nby;
   vc.nbz = b->nbz;
   vc.edge = block_edge;
   vc.edge_shift = __builtin_ctz((unsigned)block_edge);
   e = launch_block_minmax(vc, b->minmax, (hipStream_t)stream);
+  if (e == hipSuccess) e = launch_widen_minmax(b->minmax, b->minmax_cr, (int64_t)nb, kCatmullRomWiden, (hipStream_t)stream);
   if (e != hipSuccess) {
     (void)hipFree(b->minmax);
     delete b;
@@ -354,6 +361,7 @@ vr_status vr_render_shaded(const vr_volume *vol, const vr_blocks *blocks, const 
   RenderArgs a;
   vr_status s = prepare(vol, blocks, cams, n_cams, tf, p, &a);
   if (s) return s;
+  if (p->filter != VR_FILTER_BSPLINE) return fail(VR_E_UNSUPPORTED, "local lighting uses the cubic B-spline only");
   if ((s = check_shading(shading, &a.shade))) return s;
   if (!out_rgba) return fail(VR_E_INVALID_ARG, "out_rgba is NULL");
   a.shaded = 1;
@@ -413,6 +421,7 @@ vr_status vr_render_preint(const vr_volume *vol, const vr_blocks *blocks, const 
   RenderArgs a;
   vr_status s = prepare(vol, blocks, cams, n_cams, tf, p, &a);
   if (s) return s;
+  if (p->filter != VR_FILTER_BSPLINE) return fail(VR_E_UNSUPPORTED, "pre-integration uses the cubic B-spline only");
   if (!table) return fail(VR_E_INVALID_ARG, "pre-integration table is NULL");
   if (table->K != tf->K || table->v0 != tf->v0 || table->v1 != tf->v1 || table->tf_table != tf->table ||
       table->step != p->step)
@@ -462,6 +471,7 @@ vr_status vr_render_backward(const vr_volume *vol, const vr_blocks *blocks, cons
   BackwardArgs b;
   vr_status s = prepare(vol, blocks, cams, n_cams, tf, p, &b.r);
   if (s) return s;
+  if (p->filter != VR_FILTER_BSPLINE) return fail(VR_E_UNSUPPORTED, "the adjoint is of the cubic B-spline render");
   if (!out_rgba || !grad_rgba) return fail(VR_E_INVALID_ARG, "out_rgba and grad_rgba are required");
   if (grad_tf) b.r.mc.skip = 0;  // zero-extinction nodes still receive TF gradients
   b.r.counters = nullptr;

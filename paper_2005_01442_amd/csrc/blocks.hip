@@ -84,6 +84,22 @@ hipError_t launch_block_occupancy(const VolConst &v, const TfConst &tf, uint8_t 
   return hipGetLastError();
 }
 
+// Widened block ranges [lo - w (hi - lo), hi + w (hi - lo)] (fused, fp32).
+__global__ __launch_bounds__(kWgSize) void k_widen_minmax(const float2 *in, float2 *out, int64_t n, float w) {
+  const int64_t i = (int64_t)blockIdx.x * kWgSize + threadIdx.x;
+  if (i < n) {
+    const float2 m = in[i];
+    const float d = m.y - m.x;
+    out[i] = make_float2(fmaf(-w, d, m.x), fmaf(w, d, m.y));
+  }
+}
+
+hipError_t launch_widen_minmax(const float2 *in, float2 *out, int64_t n, float w, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_widen_minmax, dim3((unsigned)((n + kWgSize - 1) / kWgSize)), dim3(kWgSize), 0, s, in, out, n, w);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(kWgSize) void k_fill_zero(float *p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * kWgSize + threadIdx.x; i < n; i += (int64_t)gridDim.x * kWgSize) p[i] = 0.0f;
 }

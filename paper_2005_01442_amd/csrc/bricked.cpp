@@ -245,6 +245,7 @@ vr_status vr_bricked_render(vr_bricked *v, const vr_camera *cams, int32_t n_cams
   vr_status s = check_tf_fields(tf->table, tf->K, tf->v0, tf->v1, &a.tf);
   if (s) return s;
   if ((s = check_march(p->step, p->ert_threshold, 1, &a.mc))) return s;
+  if (p->filter != VR_FILTER_BSPLINE) return fail(VR_E_UNSUPPORTED, "out-of-core rendering uses the cubic B-spline only");
   if (!cams || n_cams <= 0) return fail(VR_E_INVALID_ARG, "need at least one camera");
   for (int32_t i = 0; i < n_cams; ++i) {
     if ((s = check_camera(&cams[i], nullptr))) return s;

@@ -14,7 +14,7 @@ namespace vr {
 // result is bit-identical to marching every sample.  SHADE adds local
 // lighting: the same 64 taps also give the gradient, which lights the
 // classified colour (the value, hence opacity and termination, is unchanged).
-template <int DT, bool SHADE>
+template <int DT, bool SHADE, int F = 0>
 __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfConst &tf, const MarchConst &mc,
                                const ShadeConst &sc, const Ray &r, __amdgpu_buffer_rsrc_t rs, ValBox &box,
                                uint32_t &evaluated, uint32_t &unstaged) {
@@ -42,7 +42,7 @@ __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfCon
       q = classify(s, tf.K, tf.v0, tf.scale, vg.x);
       light_colour(sc, rl, vg, q.c);
     } else {
-      Stencil st = make_stencil(px, py, pz);
+      Stencil st = make_stencil_f<F>(px, py, pz);
       float val;
       if (box.valid) {
         val = reconstruct_box(box, st);
@@ -71,7 +71,7 @@ __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfCon
 #ifndef VR_FWD_MAX_WAVES
 #define VR_FWD_MAX_WAVES 3
 #endif
-template <int DT, bool SHADE>
+template <int DT, bool SHADE, int F>
 __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(SHADE ? VR_FWD_MAX_WAVES : 1, VR_FWD_MAX_WAVES)))
 void k_render(const RenderArgs args) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
@@ -99,7 +99,7 @@ void k_render(const RenderArgs args) {
   box.cells = a.use_box ? reinterpret_cast<float *>(lds + vbox_lds_offset(a.tf.K)) +
                               (threadIdx.x / kWaveSize) * kVBoxCells
                         : nullptr;
-  float4 rgba = march<DT, SHADE>(a.vol, s, a.tf, a.mc, a.shade, r, rs, box, evaluated, unstaged);
+  float4 rgba = march<DT, SHADE, F>(a.vol, s, a.tf, a.mc, a.shade, r, rs, box, evaluated, unstaged);
   if (inside) {
     float4 *o = reinterpret_cast<float4 *>(a.out);
     o[((size_t)st.view * a.H + row) * a.W + col] = rgba;
@@ -112,17 +112,17 @@ void k_render(const RenderArgs args) {
   }
 }
 
-template <bool SHADE>
+template <bool SHADE, int F>
 static hipError_t launch_render_as(const RenderArgs &a, int64_t grid, uint32_t lds, hipStream_t s) {
-  const void *fn = a.vol.dtype == kU16   ? reinterpret_cast<const void *>(&k_render<kU16, SHADE>)
-                   : a.vol.dtype == kI16 ? reinterpret_cast<const void *>(&k_render<kI16, SHADE>)
-                                         : reinterpret_cast<const void *>(&k_render<kF32, SHADE>);
+  const void *fn = a.vol.dtype == kU16   ? reinterpret_cast<const void *>(&k_render<kU16, SHADE, F>)
+                   : a.vol.dtype == kI16 ? reinterpret_cast<const void *>(&k_render<kI16, SHADE, F>)
+                                         : reinterpret_cast<const void *>(&k_render<kF32, SHADE, F>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   switch (a.vol.dtype) {
-  case kU16: hipLaunchKernelGGL((k_render<kU16, SHADE>), dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
-  case kI16: hipLaunchKernelGGL((k_render<kI16, SHADE>), dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
-  default: hipLaunchKernelGGL((k_render<kF32, SHADE>), dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
+  case kU16: hipLaunchKernelGGL((k_render<kU16, SHADE, F>), dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
+  case kI16: hipLaunchKernelGGL((k_render<kI16, SHADE, F>), dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
+  default: hipLaunchKernelGGL((k_render<kF32, SHADE, F>), dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
   }
   return hipGetLastError();
 }
@@ -135,7 +135,8 @@ hipError_t launch_render(const RenderArgs &a0, hipStream_t s) {
   a.use_box = with_box <= max_lds_per_workgroup() ? 1 : 0;
   if (a.use_box) lds = with_box;
   if (a.vol.dtype != kU16 && a.vol.dtype != kI16 && a.vol.dtype != kF32) return hipErrorInvalidValue;
-  return a.shaded ? launch_render_as<true>(a, grid, lds, s) : launch_render_as<false>(a, grid, lds, s);
+  if (a.shaded) return launch_render_as<true, 0>(a, grid, lds, s);
+  return a.filter == 1 ? launch_render_as<false, 1>(a, grid, lds, s) : launch_render_as<false, 0>(a, grid, lds, s);
 }
 
 // Serving: one workgroup per work item, a 16x16 super-tile of one admitted

@@ -401,7 +401,7 @@ vr_status vr_serve_add_volume(vr_server *s, const vr_volume *vol, int32_t block_
     return st;
   }
   std::lock_guard<std::mutex> lk(s->mu);
-  size_t bb = (size_t)vc.nbx * vc.nby * vc.nbz * sizeof(float2);
+  size_t bb = 2 * (size_t)vc.nbx * vc.nby * vc.nbz * sizeof(float2);  // plain and widened ranges
   if (s->hbm_used + bb > s->cfg.hbm_budget_bytes) {
     vr_blocks_free(blocks);
     return fail(VR_E_BUDGET, "blocks of %zu bytes exceed the HBM budget", bb);

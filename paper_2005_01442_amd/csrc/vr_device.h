@@ -399,6 +399,33 @@ __device__ inline Stencil make_stencil(float px, float py, float pz) {
   return s;
 }
 
+// Catmull-Rom weights of the same four taps (interpolating; two negative).
+__device__ inline void catmull_rom_weights(float t, float w[4]) {
+  const float t2 = t * t, t3 = t2 * t;
+  w[0] = 0.5f * (2.0f * t2 - t3 - t);
+  w[1] = 0.5f * fmaf(3.0f, t3, fmaf(-5.0f, t2, 2.0f));
+  w[2] = 0.5f * fmaf(-3.0f, t3, fmaf(4.0f, t2, t));
+  w[3] = 0.5f * (t3 - t2);
+}
+
+// Stencil with the filter's weights: F = 0 cubic B-spline, 1 Catmull-Rom.
+template <int F>
+__device__ inline Stencil make_stencil_f(float px, float py, float pz) {
+  if constexpr (F == 0) {
+    return make_stencil(px, py, pz);
+  } else {
+    Stencil s;
+    float fx = floorf(px), fy = floorf(py), fz = floorf(pz);
+    s.ix = (int)fx;
+    s.iy = (int)fy;
+    s.iz = (int)fz;
+    catmull_rom_weights(px - fx, s.wx);
+    catmull_rom_weights(py - fy, s.wy);
+    catmull_rom_weights(pz - fz, s.wz);
+    return s;
+  }
+}
+
 // Visit the 16 x-rows of a stencil's taps, row(c, b, t) with t[a] =
 // V[iz-1+c][iy-1+b][ix-1+a] under clamp-to-edge addressing, in the order
 // c = 0..3, b = 0..3.  Interior stencils take the packed-row loads.

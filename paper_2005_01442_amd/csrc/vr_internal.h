@@ -21,6 +21,8 @@ struct RenderArgs {
   int32_t W, H, n_views, chunk_edge;
   int32_t use_box;                 // stage volume boxes in LDS (set at launch)
   int32_t shaded;                  // nonzero: local lighting with `shade`
+  int32_t filter;                  // VR_FILTER_*
+  int32_t pad3;
   ShadeConst shade;
   CamConst cams[kMaxCamsPerLaunch];
 };
@@ -67,6 +69,9 @@ hipError_t launch_render_backward(const BackwardArgs &a, hipStream_t s);
 hipError_t launch_block_minmax(const VolConst &v, float2 *out, hipStream_t s);
 hipError_t launch_block_occupancy(const VolConst &v, const TfConst &tf, uint8_t *occ, hipStream_t s);
 hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s);
+// Catmull-Rom samples leave their taps' range by at most this fraction of it.
+constexpr float kCatmullRomWiden = 0.4765625f;  // ((1 + 2/8)^3 - 1) / 2
+hipError_t launch_widen_minmax(const float2 *in, float2 *out, int64_t n, float w, hipStream_t s);
 // coef: per axis (x, y, z) 2 n floats: 1 / pivot[i], then the eliminated
 // super-diagonal sup[i] of the prefilter's tridiagonal system.
 hipError_t launch_prefilter(const VolConst &v, float *out, const float *coef, hipStream_t s);
