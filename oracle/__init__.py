@@ -195,7 +195,8 @@ def render(vol, cameras, tf, step, ert=0.0, occ=None, edge=16, pixels=None, shad
     """FP64 render.  Returns dict(rgba, flags, counts); rgba is (views, H, W, 4)
     for a full render or (n, 4) for a pixel list.  ``shading`` (see
     ``shade_params``) switches on local lighting; ``filter`` 1 reconstructs
-    with Catmull-Rom instead of the cubic B-spline (unlit only)."""
+    with Catmull-Rom instead of the cubic B-spline, 2 pre-classifies
+    (opacity-weighted B-spline of the classified taps); both unlit only."""
     vol, dt, nx, ny, nz = _vol(vol)
     cams = pack_cameras(cameras)
     W, H = int(cameras[0].width), int(cameras[0].height)

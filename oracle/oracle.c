@@ -393,6 +393,38 @@ static void or_classify(const float *tf, int K, double v0, double v1, double v, 
     or_tf_at(tf, K, u, out, j_out, w_out);
 }
 
+/* Pre-classification (the alternative the paper weighs against interpolating */
+/* first, Section 2, Fig. 4 discussion): every tap is classified, then the   */
+/* B-spline interpolates the opacity-weighted channels (sigma r, sigma g,    */
+/* sigma b, sigma); the sample's colour is the weighted colour over its      */
+/* extinction (0 where the extinction is 0).                                 */
+static void or_preclassify(const or_vol *vol, const float *tf, int K, double v0, double v1, const double p[3],
+                           double out[4])
+{
+    long ix = (long)floor(p[0]), iy = (long)floor(p[1]), iz = (long)floor(p[2]);
+    double wx[4], wy[4], wz[4];
+    or_bspline(p[0] - (double)ix, wx);
+    or_bspline(p[1] - (double)iy, wy);
+    or_bspline(p[2] - (double)iz, wz);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < 4; ++c)
+        for (int b = 0; b < 4; ++b)
+            for (int a = 0; a < 4; ++a) {
+                long x = or_clampl(ix - 1 + a, 0, vol->nx - 1);
+                long y = or_clampl(iy - 1 + b, 0, vol->ny - 1);
+                long z = or_clampl(iz - 1 + c, 0, vol->nz - 1);
+                double t[4], tw;
+                long tj;
+                int tc;
+                or_classify(tf, K, v0, v1, or_voxel(vol, x, y, z), t, &tj, &tw, &tc);
+                double wt = wx[a] * wy[b] * wz[c];
+                for (int q = 0; q < 3; ++q) acc[q] += wt * t[3] * t[q];
+                acc[3] += wt * t[3];
+            }
+    for (int q = 0; q < 3; ++q) out[q] = acc[3] > 0.0 ? acc[q] / acc[3] : 0.0;
+    out[3] = acc[3];
+}
+
 typedef struct {
     const or_vol *vol;
     const double *cams;
@@ -461,11 +493,15 @@ static void or_trace(const or_ctx *cx, long view, long row, long col, double rgb
         double p[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
         if (cx->occ && !or_block_occupied(cx, p)) continue;
         counts[1]++;
-        or_reconstruct_f(cx->vol, p, &s, cx->filter);
         double val[4], w;
         long j;
         int cl;
-        or_classify(cx->tf, cx->K, cx->v0, cx->v1, s.v, val, &j, &w, &cl);
+        if (cx->filter == 2) {
+            or_preclassify(cx->vol, cx->tf, cx->K, cx->v0, cx->v1, p, val);
+        } else {
+            or_reconstruct_f(cx->vol, p, &s, cx->filter);
+            or_classify(cx->tf, cx->K, cx->v0, cx->v1, s.v, val, &j, &w, &cl);
+        }
         if (cx->shade) {
             double g[3];
             or_gradient(cx->vol, p, g);
@@ -504,7 +540,7 @@ static int or_render(const void *data, int dtype, long nx, long ny, long nz, con
         return 1;
     if (shade && !(shade[8] > 0.0 && shade[3] >= 1.0)) return 1;
     or_vol vol = {data, dtype, nx, ny, nz};
-    if (filter != 0 && filter != 1) return 1;
+    if (filter < 0 || filter > 2) return 1;
     or_ctx cx = {&vol, cams, W, H, tf, K, v0, v1, step, ert, occ, edge, shade, filter};
     long total = pix ? n_pix : (long)n_cams * W * H;
 #pragma omp parallel for schedule(dynamic, 16)

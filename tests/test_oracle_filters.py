@@ -1,6 +1,6 @@
 """Pins of the oracle's filter variants (the paper's filter comparison,
-Fig. 4 discussion): the interpolating (prefiltered) cubic B-spline and the
-Catmull-Rom cubic with its widened skip test."""
+Fig. 4 discussion): the interpolating (prefiltered) cubic B-spline, the
+Catmull-Rom cubic with its widened skip test, and pre-classification."""
 
 import numpy as np
 import pytest
@@ -115,3 +115,89 @@ def test_catmull_rom_skip_is_lossless_with_widened_ranges(oracle_lib):
     np.testing.assert_array_equal(skip["rgba"], full["rgba"])
     # the B-spline never undershoots: same volume, nothing visible
     assert oracle.render(vol, cams, tf, 0.5)["rgba"].max() == 0.0
+
+
+# ----------------------------------------------------- pre-classification --
+
+def _ramp_tf(K=9, v0=0.0, v1=4096.0):
+    """Extinction linear in the value, constant colour (fp32-exact nodes)."""
+    sig = np.arange(K) / 256.0
+    table = np.column_stack([np.full(K, 0.75), np.full(K, 0.5), np.full(K, 0.25), sig]).astype(np.float32)
+    return synth.TransferFunction(table, v0, v1)
+
+
+def test_preclassification_equals_post_for_linear_tfs(oracle_lib):
+    """A TF linear over the values commutes with the (non-negative, unit-sum)
+    B-spline weights: classifying taps then interpolating equals interpolating
+    then classifying."""
+    vol = synth.ellipsoid_phantom_u16(16, seed=507)
+    cams = synth.orbit_cameras((16, 16, 16), 2, 508, 50.0, 12, 12)
+    for tf in (_ramp_tf(), synth.TransferFunction(np.tile(np.float32([0.2, 0.6, 0.9, 0.07]), (8, 1)), 0.0, 4095.0)):
+        pre = oracle.render(vol, cams, tf, 0.625, filter=2)["rgba"]
+        post = oracle.render(vol, cams, tf, 0.625)["rgba"]
+        np.testing.assert_allclose(pre, post, rtol=0, atol=1e-12)
+
+
+def test_preclassification_matches_brute_force(oracle_lib):
+    rng = np.random.default_rng(509)
+    vol = rng.integers(0, 48, (5, 6, 7)).astype(np.uint16)
+    lists = vol.tolist()
+    K = 7
+    table = rng.uniform(0, 1, (K, 4)).astype(np.float32)
+    table[:, 3] *= 0.6
+    tf = synth.TransferFunction(table, 0.0, 48.0)
+    tt = table.astype(np.float64).tolist()
+    cam = synth.orbit_camera((7, 6, 5), np.array([0.5, 0.35, -0.79]), 45.0, 10, 10)
+    out = oracle.render(vol, [cam], tf, 0.4375, filter=2)
+    import math
+
+    def classified_sample(p):
+        fx, fy, fz = (math.floor(c) for c in p)
+        acc = [Fraction(0)] * 4
+        for z in range(fz - 1, fz + 3):
+            for y in range(fy - 1, fy + 3):
+                for x in range(fx - 1, fx + 3):
+                    v = vol[min(max(z, 0), 4)][min(max(y, 0), 5)][min(max(x, 0), 6)]
+                    r, g, b, sg = brute.tf_table_lookup(tt, 0.0, 48.0, float(v))
+                    w = (brute.bspline_kernel(Fraction(p[0]) - x) * brute.bspline_kernel(Fraction(p[1]) - y)
+                         * brute.bspline_kernel(Fraction(p[2]) - z))
+                    acc = [acc[0] + w * Fraction(sg * r), acc[1] + w * Fraction(sg * g), acc[2] + w * Fraction(sg * b),
+                           acc[3] + w * Fraction(sg)]
+        s = float(acc[3])
+        return [float(acc[q]) / s if s > 0 else 0.0 for q in range(3)] + [s]
+
+    checked = 0
+    for row in range(2, 8):
+        for col in range(2, 8):
+            o, d = brute.camera_ray(cam, row, col)
+            want, n = brute.composite_ray(lists, o, d, 0.4375, lambda v: (0, 0, 0, 0))
+            if n == 0:
+                continue
+            hit = brute.clip_planes(o, d, (7, 6, 5))
+            tin, tout = hit
+            k = 0
+            while (k + 0.5) * 0.4375 <= tin:
+                k += 1
+            C, T = [0.0, 0.0, 0.0], 1.0
+            while (k + 0.5) * 0.4375 < tout:
+                t = (k + 0.5) * 0.4375
+                r, g, b, sg = classified_sample([o[c] + t * d[c] for c in range(3)])
+                a = 1.0 - math.exp(-sg * 0.4375)
+                C = [C[0] + T * a * r, C[1] + T * a * g, C[2] + T * a * b]
+                T *= 1.0 - a
+                k += 1
+            np.testing.assert_allclose(out["rgba"][0, row, col], C + [1.0 - T], rtol=0, atol=1e-11)
+            checked += 1
+    assert checked >= 16
+
+
+def test_preclassification_skip_is_lossless_and_differs_from_post(oracle_lib):
+    vol = synth.ct_phantom_i16(40, 36, 32, seed=510, n_soft=4, n_bone=3)
+    tf = synth.tf1()
+    cams = synth.orbit_cameras((40, 36, 32), 2, 511, 55.0, 24, 20)
+    mm = oracle.blocks(vol, 8)
+    a = oracle.render(vol, cams, tf, 0.5, ert=0.99, filter=2, occ=oracle.occupancy(mm, tf), edge=8)
+    b = oracle.render(vol, cams, tf, 0.5, ert=0.99, filter=2)
+    np.testing.assert_array_equal(a["rgba"], b["rgba"])
+    post = oracle.render(vol, cams, tf, 0.5, ert=0.99)["rgba"]
+    assert np.abs(post - b["rgba"]).max() > 1e-3

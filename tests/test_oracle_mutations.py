@@ -62,6 +62,10 @@ MUTANTS = {
                              "w[1] = (3.0 * f * f * f - 4.0 * f * f + 2.0) / 2.0;"),
     "catmull_rom_range_not_widened": ("if (widen > 0.0f) {", "if (widen > 1e30f) {"),
     "catmull_rom_widened_low_end_wrong_way": ("float wlo = fmaf(-widen, d, lo)", "float wlo = fmaf(widen, d, lo)"),
+    "preclass_colour_not_opacity_weighted": ("for (int q = 0; q < 3; ++q) acc[q] += wt * t[3] * t[q];",
+                                             "for (int q = 0; q < 3; ++q) acc[q] += wt * t[q];"),
+    "preclass_colour_not_normalised": ("for (int q = 0; q < 3; ++q) out[q] = acc[3] > 0.0 ? acc[q] / acc[3] : 0.0;",
+                                       "for (int q = 0; q < 3; ++q) out[q] = acc[q];"),
 }
 
 
@@ -98,6 +102,8 @@ PINS = [
     filters.test_catmull_rom_weights_match_the_kernel,
     filters.test_catmull_rom_interpolates_and_reproduces_quadratics,
     filters.test_catmull_rom_skip_is_lossless_with_widened_ranges,
+    filters.test_preclassification_equals_post_for_linear_tfs,
+    filters.test_preclassification_matches_brute_force,
 ]
 
 
