@@ -506,15 +506,23 @@ def main():
             vr.vr_render(coef, cblocks, cams, tf, c["step"], c["ert"], True, out=out)
 
         wall_ip, ev_ip = time_steps(fwd_interp, args.steps, args.warmup, torch)
+
+        def fwd_pre():
+            vr.vr_render(vol, blocks, cams, tf, c["step"], c["ert"], True, out=out,
+                         filter=vr.VR_FILTER_BSPLINE_PRECLASSIFIED)
+
+        wall_pc, ev_pc = time_steps(fwd_pre, args.steps, args.warmup, torch)
         result["c1_filters"] = {
             "catmull_rom_ms": wall_cr / args.steps * 1e3,
             "interpolating_bspline_ms": wall_ip / args.steps * 1e3,
             "prefilter_ms": pre_ms,
+            "preclassified_ms": wall_pc / args.steps * 1e3,
             "note": "same frame; Catmull-Rom with widened block ranges; interpolating cubic B-spline = prefiltered "
                     "fp32 coefficient volume (256 B of taps per sample) rendered with the default filter",
         }
         log(f"filters: Catmull-Rom {wall_cr / args.steps * 1e3:.3f} ms, interpolating B-spline "
-            f"{wall_ip / args.steps * 1e3:.3f} ms (+ prefilter {pre_ms:.2f} ms once)")
+            f"{wall_ip / args.steps * 1e3:.3f} ms (+ prefilter {pre_ms:.2f} ms once), pre-classified "
+            f"{wall_pc / args.steps * 1e3:.3f} ms")
         del coef, cblocks
 
     if not args.no_bricked:

@@ -127,9 +127,16 @@ typedef struct {
  *   w = ((1 + 2/8)^3 - 1)/2 = 0.4765625 of it, so its block test widens every
  *   block's range to [lo - w (hi - lo), hi + w (hi - lo)] (fp32 fused
  *   multiply-adds) and skipping stays exact.
- * (The interpolating cubic B-spline is vr_prefilter_bspline + this default.) */
+ * VR_FILTER_BSPLINE_PRECLASSIFIED: pre-classification with the cubic
+ *   B-spline: every tap is classified first and the weights interpolate the
+ *   opacity-weighted channels (sigma r, sigma g, sigma b, sigma); the sample's
+ *   colour is the weighted colour over its extinction (0 where that is 0).
+ *   Its extinction is zero exactly where every tap's is, so the plain block
+ *   test stays exact.
+ * (The interpolating cubic B-spline is vr_prefilter_bspline + the default.) */
 #define VR_FILTER_BSPLINE 0
 #define VR_FILTER_CATMULL_ROM 1
+#define VR_FILTER_BSPLINE_PRECLASSIFIED 2
 
 /* ---------------------------------------------------------------------- */
 /* Blocks: the auxiliary structure for empty-space leaping (Section 2,     */

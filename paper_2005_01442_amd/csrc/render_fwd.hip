@@ -41,6 +41,16 @@ __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfCon
       }
       q = classify(s, tf.K, tf.v0, tf.scale, vg.x);
       light_colour(sc, rl, vg, q.c);
+    } else if constexpr (F == 2) {
+      Stencil st = make_stencil(px, py, pz);
+      float t[4][4][4];
+      if (box.valid) {
+        load_taps_box(box, st, t);
+      } else {
+        load_taps<DT>(rs, v, st, t);
+        ++unstaged;
+      }
+      q = preclassify(s, tf.K, tf.v0, tf.scale, st, t);
     } else {
       Stencil st = make_stencil_f<F>(px, py, pz);
       float val;
@@ -136,7 +146,9 @@ hipError_t launch_render(const RenderArgs &a0, hipStream_t s) {
   if (a.use_box) lds = with_box;
   if (a.vol.dtype != kU16 && a.vol.dtype != kI16 && a.vol.dtype != kF32) return hipErrorInvalidValue;
   if (a.shaded) return launch_render_as<true, 0>(a, grid, lds, s);
-  return a.filter == 1 ? launch_render_as<false, 1>(a, grid, lds, s) : launch_render_as<false, 0>(a, grid, lds, s);
+  if (a.filter == 1) return launch_render_as<false, 1>(a, grid, lds, s);
+  if (a.filter == 2) return launch_render_as<false, 2>(a, grid, lds, s);
+  return launch_render_as<false, 0>(a, grid, lds, s);
 }
 
 // Serving: one workgroup per work item, a 16x16 super-tile of one admitted

@@ -523,6 +523,21 @@ __device__ inline float combine(const Stencil &s, const float t[4][4][4]) {
   return acc;
 }
 
+// The 64 taps as values: row visitor that stores each row.
+struct TapRows {
+  float (*t)[4][4];
+  __device__ inline void operator()(int c, int b, const float r[4]) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a) t[c][b][a] = r[a];
+  }
+};
+
+template <int DT>
+__device__ inline void load_taps(__amdgpu_buffer_rsrc_t rs, const VolConst &v, const Stencil &s, float t[4][4][4]) {
+  TapRows f{t};
+  for_rows<DT>(rs, v, s, f);
+}
+
 // Derivatives of the B-spline weights with respect to the offset t.
 __device__ inline void bspline_dweights(float t, float d[4]) {
   const float s = 1.0f - t;
@@ -788,6 +803,47 @@ __device__ inline Classified classify(const TfShared &s, int K, float v0, float 
   q.j = j;
   q.w = w;
   return q;
+}
+
+// Pre-classification: every tap classified, the opacity-weighted channels
+// (sigma r, sigma g, sigma b, sigma) interpolated with the stencil's weights
+// (separable, x rows then y then z); the colour is the weighted colour over
+// the extinction, 0 where that is 0.
+__device__ inline Classified preclassify(const TfShared &s, int K, float v0, float scale, const Stencil &st,
+                                         const float t[4][4][4]) {
+  float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    float4 accy = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      float4 r = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const Classified q = classify(s, K, v0, scale, t[c][b][a]);
+        const float ws = st.wx[a] * q.c.w;
+        r.x = fmaf(ws, q.c.x, r.x);
+        r.y = fmaf(ws, q.c.y, r.y);
+        r.z = fmaf(ws, q.c.z, r.z);
+        r.w = fmaf(st.wx[a], q.c.w, r.w);
+      }
+      accy.x = fmaf(st.wy[b], r.x, accy.x);
+      accy.y = fmaf(st.wy[b], r.y, accy.y);
+      accy.z = fmaf(st.wy[b], r.z, accy.z);
+      accy.w = fmaf(st.wy[b], r.w, accy.w);
+    }
+    acc.x = fmaf(st.wz[c], accy.x, acc.x);
+    acc.y = fmaf(st.wz[c], accy.y, acc.y);
+    acc.z = fmaf(st.wz[c], accy.z, acc.z);
+    acc.w = fmaf(st.wz[c], accy.w, acc.w);
+  }
+  Classified out;
+  const float inv = acc.w > 0.0f ? 1.0f / acc.w : 0.0f;
+  out.c = make_float4(acc.x * inv, acc.y * inv, acc.z * inv, acc.w);
+  out.j = 0;
+  out.w = 0.0f;
+  out.clamped = false;
+  return out;
 }
 
 // exp(-x) for x >= 0 via the hardware exp2 (1 ulp); x = sigma * step.

@@ -123,3 +123,44 @@ def test_catmull_rom_is_rejected_where_unsupported():
         vr.vr_render(vol, None, cams, t, 0.5, shading=vr.Shading(), filter=CR)
     with pytest.raises(vr.VrError, match="unknown filter"):
         vr.vr_render(vol, None, cams, t, 0.5, filter=7)
+
+
+PRE = vr.VR_FILTER_BSPLINE_PRECLASSIFIED
+
+
+def _pre(vol_np, cams, tf, step, ert=0.0, use_skip=False, vol=None, counters=False):
+    v = vol if vol is not None else upload_volume(vol_np)
+    t = upload_tf(tf)
+    b = vr.vr_build_blocks(v, 16) if use_skip else None
+    ctr = torch.zeros(4, dtype=torch.int64, device=DEV) if counters else None
+    out = vr.vr_render(v, b, cams, t, step, ert, use_skip, counters=ctr, filter=PRE)
+    torch.cuda.synchronize()
+    img = out.cpu().numpy().astype(np.float64)
+    return (img, ctr.cpu().numpy()) if counters else img
+
+
+def test_preclassified_ct_skip_and_ert():
+    vol = _small_ct()
+    dims = (96, 80, 72)
+    cams = synth.orbit_cameras(dims, 2, 80, 60.0, 120, 104)
+    tf = synth.tf1()
+    v = upload_volume(vol)
+    a, ca = _pre(vol, cams, tf, 0.5, 0.99, True, vol=v, counters=True)
+    b = _pre(vol, cams, tf, 0.5, 0.99, False, vol=v)
+    assert np.array_equal(a, b)
+    ref = oracle.render(vol, cams, tf, 0.5, ert=0.99, filter=2)
+    un, nflag = compare_with_flags(a, ref["rgba"], ref["flags"], 0.99)
+    log(f"pre-classified ct: max unflagged |dRGBA| = {un:.3e}, flagged {nflag}")
+    assert nflag <= 1e-3 * a[..., 0].size + 2
+
+
+def test_preclassified_global_path_and_dtypes():
+    for vol, tf, dims in [(synth.density_grid_f32(48, seed=81), synth.tf3(), (48, 48, 48)),
+                          (synth.ellipsoid_phantom_u16(48, seed=82)[:, :47, :45].copy(), synth.tf0(), (45, 47, 48))]:
+        cams = synth.orbit_cameras(dims, 2, 83, 50.0, 12, 10)
+        img, ctr = _pre(vol, cams, tf, 0.5, counters=True)
+        ref = oracle.render(vol, cams, tf, 0.5, filter=2)
+        d = np.abs(img - ref["rgba"]).max()
+        log(f"pre-classified {vol.dtype}: max |dRGBA| = {d:.3e}, global-path samples {ctr[3]}")
+        assert d <= TOL
+        assert ctr[3] > 0
