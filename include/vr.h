@@ -133,10 +133,13 @@ typedef struct {
  *   colour is the weighted colour over its extinction (0 where that is 0).
  *   Its extinction is zero exactly where every tap's is, so the plain block
  *   test stays exact.
+ * VR_FILTER_TRILINEAR: the paper's baseline filter, weights (0, 1-t, t, 0)
+ *   on the same stencil (exact skipping with the plain block test).
  * (The interpolating cubic B-spline is vr_prefilter_bspline + the default.) */
 #define VR_FILTER_BSPLINE 0
 #define VR_FILTER_CATMULL_ROM 1
 #define VR_FILTER_BSPLINE_PRECLASSIFIED 2
+#define VR_FILTER_TRILINEAR 3
 
 /* ---------------------------------------------------------------------- */
 /* Blocks: the auxiliary structure for empty-space leaping (Section 2,     */

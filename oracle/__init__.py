@@ -196,7 +196,8 @@ def render(vol, cameras, tf, step, ert=0.0, occ=None, edge=16, pixels=None, shad
     for a full render or (n, 4) for a pixel list.  ``shading`` (see
     ``shade_params``) switches on local lighting; ``filter`` 1 reconstructs
     with Catmull-Rom instead of the cubic B-spline, 2 pre-classifies
-    (opacity-weighted B-spline of the classified taps); both unlit only."""
+    (opacity-weighted B-spline of the classified taps), 3 reconstructs
+    trilinearly; all unlit only."""
     vol, dt, nx, ny, nz = _vol(vol)
     cams = pack_cameras(cameras)
     W, H = int(cameras[0].width), int(cameras[0].height)
@@ -278,8 +279,8 @@ def ray(camera, row, col, dims_xyz, step):
 
 
 def sample(vol, p, filter=0) -> float:
-    """Tricubic value of ``vol`` at point p = (x, y, z): cubic B-spline
-    (filter 0) or Catmull-Rom (filter 1)."""
+    """Value of ``vol`` at point p = (x, y, z): cubic B-spline (filter 0),
+    Catmull-Rom (1) or trilinear (3)."""
     vol, dt, nx, ny, nz = _vol(vol)
     if filter == 0:
         return float(lib().oracle_sample(_ptr(vol), dt, nx, ny, nz, float(p[0]), float(p[1]), float(p[2])))

@@ -250,6 +250,16 @@ static void or_catmull_rom(double f, double w[4])
     w[3] = (f * f * f - f * f) / 2.0;
 }
 
+/* Trilinear weights on the same four taps (the paper's baseline filter): the */
+/* two nearest taps only.                                                    */
+static void or_trilinear(double f, double w[4])
+{
+    w[0] = 0.0;
+    w[1] = 1.0 - f;
+    w[2] = f;
+    w[3] = 0.0;
+}
+
 /* One reconstructed sample: the 64 taps, their weights and the value.      */
 typedef struct {
     long tap[64];
@@ -259,12 +269,12 @@ typedef struct {
 
 /* Tricubic reconstruction at p: the explicit 64-term sum over the 4x4x4     */
 /* stencil, clamp-to-edge addressing.                                        */
-/* filter: 0 cubic B-spline, 1 Catmull-Rom.                                 */
+/* filter: 0 cubic B-spline, 1 Catmull-Rom, 3 trilinear.                    */
 static void or_reconstruct_f(const or_vol *vol, const double p[3], or_sample *s, int filter)
 {
     long ix = (long)floor(p[0]), iy = (long)floor(p[1]), iz = (long)floor(p[2]);
     double wx[4], wy[4], wz[4];
-    void (*weights)(double, double *) = filter == 1 ? or_catmull_rom : or_bspline;
+    void (*weights)(double, double *) = filter == 1 ? or_catmull_rom : (filter == 3 ? or_trilinear : or_bspline);
     weights(p[0] - (double)ix, wx);
     weights(p[1] - (double)iy, wy);
     weights(p[2] - (double)iz, wz);
@@ -540,7 +550,7 @@ static int or_render(const void *data, int dtype, long nx, long ny, long nz, con
         return 1;
     if (shade && !(shade[8] > 0.0 && shade[3] >= 1.0)) return 1;
     or_vol vol = {data, dtype, nx, ny, nz};
-    if (filter < 0 || filter > 2) return 1;
+    if (filter < 0 || filter > 3) return 1;
     or_ctx cx = {&vol, cams, W, H, tf, K, v0, v1, step, ert, occ, edge, shade, filter};
     long total = pix ? n_pix : (long)n_cams * W * H;
 #pragma omp parallel for schedule(dynamic, 16)

@@ -19,7 +19,7 @@ import torch
 
 from . import _abi
 from ._abi import (VrError, VR_F32, VR_FILTER_BSPLINE, VR_FILTER_BSPLINE_PRECLASSIFIED, VR_FILTER_CATMULL_ROM,  # noqa: F401
-                   VR_I16, VR_U16, check, lib)
+                   VR_FILTER_TRILINEAR, VR_I16, VR_U16, check, lib)
 
 __all__ = [
     "VrError",

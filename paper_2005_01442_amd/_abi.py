@@ -27,7 +27,7 @@ STATUS_NAMES = {
     9: "VR_E_SHUTDOWN",
 }
 VR_U16, VR_I16, VR_F32 = 0, 1, 2
-VR_FILTER_BSPLINE, VR_FILTER_CATMULL_ROM, VR_FILTER_BSPLINE_PRECLASSIFIED = 0, 1, 2
+VR_FILTER_BSPLINE, VR_FILTER_CATMULL_ROM, VR_FILTER_BSPLINE_PRECLASSIFIED, VR_FILTER_TRILINEAR = 0, 1, 2, 3
 VR_MAX_TF_NODES = 1024
 
 

@@ -221,7 +221,8 @@ static vr_status prepare(const vr_volume *vol, const vr_blocks *blocks, const vr
     if (cams[i].width != cams[0].width || cams[i].height != cams[0].height)
       return fail(VR_E_INVALID_ARG, "all cameras must share one image size");
   }
-  if (p->filter != VR_FILTER_BSPLINE && p->filter != VR_FILTER_CATMULL_ROM && p->filter != VR_FILTER_BSPLINE_PRECLASSIFIED)
+  if (p->filter != VR_FILTER_BSPLINE && p->filter != VR_FILTER_CATMULL_ROM &&
+      p->filter != VR_FILTER_BSPLINE_PRECLASSIFIED && p->filter != VR_FILTER_TRILINEAR)
     return fail(VR_E_INVALID_ARG, "unknown filter %d", p->filter);
   if (p->use_skip && (s = attach_blocks(blocks, vol, &a->vol))) return s;
   a->filter = p->filter;

@@ -148,6 +148,7 @@ hipError_t launch_render(const RenderArgs &a0, hipStream_t s) {
   if (a.shaded) return launch_render_as<true, 0>(a, grid, lds, s);
   if (a.filter == 1) return launch_render_as<false, 1>(a, grid, lds, s);
   if (a.filter == 2) return launch_render_as<false, 2>(a, grid, lds, s);
+  if (a.filter == 3) return launch_render_as<false, 3>(a, grid, lds, s);
   return launch_render_as<false, 0>(a, grid, lds, s);
 }
 

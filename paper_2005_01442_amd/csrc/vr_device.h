@@ -408,7 +408,16 @@ __device__ inline void catmull_rom_weights(float t, float w[4]) {
   w[3] = 0.5f * (t3 - t2);
 }
 
-// Stencil with the filter's weights: F = 0 cubic B-spline, 1 Catmull-Rom.
+// Trilinear weights on the same four taps: the two nearest only.
+__device__ inline void trilinear_weights(float t, float w[4]) {
+  w[0] = 0.0f;
+  w[1] = 1.0f - t;
+  w[2] = t;
+  w[3] = 0.0f;
+}
+
+// Stencil with the filter's weights: F = 0 cubic B-spline, 1 Catmull-Rom,
+// 3 trilinear.
 template <int F>
 __device__ inline Stencil make_stencil_f(float px, float py, float pz) {
   if constexpr (F == 0) {
@@ -419,9 +428,15 @@ __device__ inline Stencil make_stencil_f(float px, float py, float pz) {
     s.ix = (int)fx;
     s.iy = (int)fy;
     s.iz = (int)fz;
-    catmull_rom_weights(px - fx, s.wx);
-    catmull_rom_weights(py - fy, s.wy);
-    catmull_rom_weights(pz - fz, s.wz);
+    if constexpr (F == 3) {
+      trilinear_weights(px - fx, s.wx);
+      trilinear_weights(py - fy, s.wy);
+      trilinear_weights(pz - fz, s.wz);
+    } else {
+      catmull_rom_weights(px - fx, s.wx);
+      catmull_rom_weights(py - fy, s.wy);
+      catmull_rom_weights(pz - fz, s.wz);
+    }
     return s;
   }
 }

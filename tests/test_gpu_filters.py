@@ -164,3 +164,21 @@ def test_preclassified_global_path_and_dtypes():
         log(f"pre-classified {vol.dtype}: max |dRGBA| = {d:.3e}, global-path samples {ctr[3]}")
         assert d <= TOL
         assert ctr[3] > 0
+
+
+
+def test_trilinear_ct_skip_and_ert():
+    vol = _small_ct()
+    dims = (96, 80, 72)
+    cams = synth.orbit_cameras(dims, 2, 84, 60.0, 120, 104)
+    tf = synth.tf1()
+    v = upload_volume(vol)
+    t = upload_tf(tf)
+    b = vr.vr_build_blocks(v, 16)
+    a = vr.vr_render(v, b, cams, t, 0.5, 0.99, True, filter=vr.VR_FILTER_TRILINEAR).cpu().numpy().astype(np.float64)
+    n = vr.vr_render(v, None, cams, t, 0.5, 0.99, False, filter=vr.VR_FILTER_TRILINEAR).cpu().numpy().astype(np.float64)
+    assert np.array_equal(a, n)
+    ref = oracle.render(vol, cams, tf, 0.5, ert=0.99, filter=3)
+    un, nflag = compare_with_flags(a, ref["rgba"], ref["flags"], 0.99)
+    log(f"trilinear ct: max unflagged |dRGBA| = {un:.3e}, flagged {nflag}")
+    assert nflag <= 1e-3 * a[..., 0].size + 2

@@ -201,3 +201,29 @@ def test_preclassification_skip_is_lossless_and_differs_from_post(oracle_lib):
     np.testing.assert_array_equal(a["rgba"], b["rgba"])
     post = oracle.render(vol, cams, tf, 0.5, ert=0.99)["rgba"]
     assert np.abs(post - b["rgba"]).max() > 1e-3
+
+
+# -------------------------------------------------------------- trilinear --
+
+def test_trilinear_is_the_eight_tap_formula(oracle_lib):
+    rng = np.random.default_rng(512)
+    vol = rng.normal(0, 10, (5, 6, 7))
+    for _ in range(50):
+        p = rng.uniform(-0.5, [6.5, 5.5, 4.5])
+        q = [min(max(c, 0.0), n - 1.0) for c, n in zip(p, (7, 6, 5))]
+        i = [min(int(np.floor(c)), n - 2) for c, n in zip(q, (7, 6, 5))]
+        f = [q[a] - i[a] if q[a] < (7, 6, 5)[a] - 1 else 1.0 for a in range(3)]
+        # clamp-to-edge: below the first centre the value is the edge value
+        f = [0.0 if p[a] < 0 else f[a] for a in range(3)]
+        want = 0.0
+        for dz in (0, 1):
+            for dy in (0, 1):
+                for dx in (0, 1):
+                    w = (f[0] if dx else 1 - f[0]) * (f[1] if dy else 1 - f[1]) * (f[2] if dz else 1 - f[2])
+                    want += w * vol[min(i[2] + dz, 4), min(i[1] + dy, 5), min(i[0] + dx, 6)]
+        assert abs(oracle.sample(vol, p, filter=3) - want) < 1e-11, p
+    z_, y_, x_ = np.meshgrid(np.arange(8.0), np.arange(8.0), np.arange(8.0), indexing="ij")
+    lin = 2 * x_ - y_ + 0.5 * z_
+    for _ in range(20):
+        p = rng.uniform(0.0, 6.99, 3)
+        assert abs(oracle.sample(lin, p, filter=3) - (2 * p[0] - p[1] + 0.5 * p[2])) < 1e-11

@@ -66,6 +66,7 @@ MUTANTS = {
                                              "for (int q = 0; q < 3; ++q) acc[q] += wt * t[q];"),
     "preclass_colour_not_normalised": ("for (int q = 0; q < 3; ++q) out[q] = acc[3] > 0.0 ? acc[q] / acc[3] : 0.0;",
                                        "for (int q = 0; q < 3; ++q) out[q] = acc[q];"),
+    "trilinear_weights_swapped": ("    w[1] = 1.0 - f;\n    w[2] = f;", "    w[1] = f;\n    w[2] = 1.0 - f;"),
 }
 
 
@@ -104,6 +105,7 @@ PINS = [
     filters.test_catmull_rom_skip_is_lossless_with_widened_ranges,
     filters.test_preclassification_equals_post_for_linear_tfs,
     filters.test_preclassification_matches_brute_force,
+    filters.test_trilinear_is_the_eight_tap_formula,
 ]
 
 
