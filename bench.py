@@ -67,17 +67,20 @@ def parse():
     return ap.parse_args()
 
 
+KERNEL_SOURCES = ("render_fwd.hip", "vr_device.h", "vr_internal.h")
+
+
 def kernel_source_hash():
-    """sha256 over the HIP sources; stored PMC traffic is valid only for them."""
+    """sha256 over the sources of the forward kernel (k_render) and its
+    headers; stored PMC traffic is valid only for them."""
     import hashlib
 
     d = os.path.join(ROOT, "paper_2005_01442_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h", ".cpp")):
-            h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+    for f in KERNEL_SOURCES:
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 

@@ -341,7 +341,10 @@ static vr_status render_views(RenderArgs &a, const vr_camera *cams, int32_t n_ca
     for (int32_t i = 0; i < n; ++i) check_camera(&cams[v0 + i], &a.cams[i]);
     a.n_views = n;
     a.out = out_rgba + (size_t)v0 * view_floats;
+    a.order = make_tile_order(a, (hipStream_t)stream);
     hipError_t e = preint ? launch_render_preint(a, preint, (hipStream_t)stream) : launch_render(a, (hipStream_t)stream);
+    if (a.order) (void)hipFreeAsync(const_cast<int32_t *>(a.order), (hipStream_t)stream);
+    a.order = nullptr;
     if (e != hipSuccess) return hip_fail(e, "render launch");
   }
   return VR_OK;
@@ -494,7 +497,10 @@ vr_status vr_render_backward(const vr_volume *vol, const vr_blocks *blocks, cons
     b.grad_tf = grad_tf;
     b.use_box = 0;
     b.pad = 0;
+    b.r.order = make_tile_order(b.r, st);
     e = launch_render_backward(b, st);
+    if (b.r.order) (void)hipFreeAsync(const_cast<int32_t *>(b.r.order), st);
+    b.r.order = nullptr;
     if (e != hipSuccess) return hip_fail(e, "backward launch");
   }
   return VR_OK;

@@ -281,7 +281,7 @@ __global__ __launch_bounds__(kWgSize) void k_render_bwd(const BackwardArgs args)
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const BackwardArgs &a = kernarg<BackwardArgs>();
   const RenderArgs &ra = a.r;
-  SuperTile st = map_workgroup(blockIdx.x, ra.W, ra.H, ra.n_views, ra.chunk_edge);
+  SuperTile st = tile_of(ra.order, blockIdx.x, ra.W, ra.H, ra.n_views, ra.chunk_edge);
   if (!st.valid) return;  // uniform over the workgroup
   const int K = ra.tf.K;
   const uint32_t tf_bytes = tf_lds_bytes(K);
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(kWgSize) void k_render_bwd(const BackwardArgs args)
 hipError_t launch_render_backward(const BackwardArgs &a0, hipStream_t s) {
   BackwardArgs a = a0;
   const RenderArgs &ra = a.r;
-  int64_t grid = grid_size_for(ra.W, ra.H, ra.n_views, ra.chunk_edge);
+  int64_t grid = render_grid(ra);
   uint32_t lds = tf_lds_bytes(ra.tf.K) + (a.grad_tf ? (uint32_t)ra.tf.K * 16u : 0u);
   const uint32_t box_bytes = (uint32_t)(kWgSize / kWaveSize) * (kBoxCells + kWaveSize * kRec) * 4u;
   const uint32_t with_box = box_lds_offset(ra.tf.K, a.grad_tf != nullptr) + box_bytes;

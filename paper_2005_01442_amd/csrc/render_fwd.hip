@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(SHADE ?
 void k_render(const RenderArgs args) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const RenderArgs &a = kernarg<RenderArgs>();
-  SuperTile st = map_workgroup(blockIdx.x, a.W, a.H, a.n_views, a.chunk_edge);
+  SuperTile st = tile_of(a.order, blockIdx.x, a.W, a.H, a.n_views, a.chunk_edge);
   if (!st.valid) return;  // uniform over the workgroup
   TfShared s = carve_tf(lds, a.tf.K);
   load_tf(s, a.tf);
@@ -137,9 +137,94 @@ static hipError_t launch_render_as(const RenderArgs &a, int64_t grid, uint32_t l
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Centre-out workgroup order: a bucket sort (quarter-tile buckets of the
+// distance to the projected volume centre) in one workgroup.  Items of one
+// bucket come in any order; the image does not depend on the order.
+// ---------------------------------------------------------------------------
+constexpr int kOrderBuckets = 1024;
+constexpr int kOrderThreads = 1024;
+
+struct OrderArgs {
+  float cx[kMaxCamsPerLaunch], cy[kMaxCamsPerLaunch];  // centre, in super-tile units
+  int32_t tx, ty, n_views;
+};
+
+__device__ inline int order_bucket(const OrderArgs &o, int q) {
+  const int per = o.tx * o.ty, v = q / per, t = q % per;
+  const float dx = (float)(t % o.tx) - o.cx[v], dy = (float)(t / o.tx) - o.cy[v];
+  const float d = sqrtf(fmaf(dx, dx, dy * dy)) * 4.0f;
+  return d < (float)(kOrderBuckets - 1) ? (int)d : kOrderBuckets - 1;
+}
+
+__global__ __launch_bounds__(kOrderThreads) void k_tile_order(const OrderArgs o, int32_t *order) {
+  __shared__ int cnt[kOrderBuckets];
+  const int n = o.n_views * o.tx * o.ty;
+  for (int i = threadIdx.x; i < kOrderBuckets; i += kOrderThreads) cnt[i] = 0;
+  __syncthreads();
+  for (int q = threadIdx.x; q < n; q += kOrderThreads) atomicAdd(&cnt[order_bucket(o, q)], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int b = 0; b < kOrderBuckets; ++b) {
+      const int c = cnt[b];
+      cnt[b] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < n; q += kOrderThreads) order[atomicAdd(&cnt[order_bucket(o, q)], 1)] = q;
+}
+
+int64_t render_grid(const RenderArgs &a) {
+  if (a.order)
+    return (int64_t)a.n_views * ((a.W + kSuperEdge - 1) / kSuperEdge) * ((a.H + kSuperEdge - 1) / kSuperEdge);
+  return grid_size_for(a.W, a.H, a.n_views, a.chunk_edge);
+}
+
+int32_t *make_tile_order(const RenderArgs &a, hipStream_t s) {
+  OrderArgs o;
+  o.tx = (a.W + kSuperEdge - 1) / kSuperEdge;
+  o.ty = (a.H + kSuperEdge - 1) / kSuperEdge;
+  o.n_views = a.n_views;
+  const double p[3] = {0.5 * (a.vol.nx - 1), 0.5 * (a.vol.ny - 1), 0.5 * (a.vol.nz - 1)};
+  for (int v = 0; v < a.n_views; ++v) {
+    const CamConst &c = a.cams[v];
+    double d[3], z = 0.0, x = 0.0, y = 0.0;
+    for (int k = 0; k < 3; ++k) d[k] = p[k] - c.eye[k];
+    for (int k = 0; k < 3; ++k) {
+      z += d[k] * c.fwd[k];
+      x += d[k] * c.right[k];
+      y += d[k] * c.up[k];
+    }
+    double sx = 0.0, sy = 0.0;  // image centre when the volume centre does not project
+    if (c.proj != 0) {
+      if (z > 0.0) {
+        sx = x / (z * c.th * ((double)c.W / (double)c.H));
+        sy = y / (z * c.th);
+      }
+    } else {
+      sx = c.hw > 0.0 ? x / c.hw : 0.0;
+      sy = c.hh > 0.0 ? y / c.hh : 0.0;
+    }
+    const double col = (sx + 1.0) * 0.5 * c.W - 0.5, row = (1.0 - sy) * 0.5 * c.H - 0.5;
+    o.cx[v] = (float)fmin(fmax((col + 0.5) / kSuperEdge - 0.5, -1e6), 1e6);
+    o.cy[v] = (float)fmin(fmax((row + 0.5) / kSuperEdge - 0.5, -1e6), 1e6);
+  }
+  const int64_t n = (int64_t)a.n_views * o.tx * o.ty;
+  int32_t *order = nullptr;
+  if (hipMallocAsync((void **)&order, (size_t)n * sizeof(int32_t), s) != hipSuccess) return nullptr;
+  hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, s, o, order);
+  if (hipGetLastError() != hipSuccess) {
+    (void)hipFreeAsync(order, s);
+    return nullptr;
+  }
+  return order;
+}
+
 hipError_t launch_render(const RenderArgs &a0, hipStream_t s) {
   RenderArgs a = a0;
-  int64_t grid = grid_size_for(a.W, a.H, a.n_views, a.chunk_edge);
+  int64_t grid = render_grid(a);
   uint32_t lds = tf_lds_bytes(a.tf.K);
   const uint32_t with_box = vbox_lds_offset(a.tf.K) + vbox_lds_bytes();
   a.use_box = with_box <= max_lds_per_workgroup() ? 1 : 0;

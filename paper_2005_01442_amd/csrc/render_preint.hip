@@ -194,7 +194,7 @@ template <int DT>
 __global__ __launch_bounds__(kWgSize) void k_render_preint(const RenderArgs args, const float4 *tab) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const RenderArgs &a = kernarg<RenderArgs>();
-  SuperTile st = map_workgroup(blockIdx.x, a.W, a.H, a.n_views, a.chunk_edge);
+  SuperTile st = tile_of(a.order, blockIdx.x, a.W, a.H, a.n_views, a.chunk_edge);
   if (!st.valid) return;  // uniform over the workgroup
   TfShared s = carve_tf(lds, a.tf.K);
   load_tf(s, a.tf);
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(kWgSize) void k_render_preint(const RenderArgs args
 
 hipError_t launch_render_preint(const RenderArgs &a0, const float4 *tab, hipStream_t s) {
   RenderArgs a = a0;
-  const int64_t grid = grid_size_for(a.W, a.H, a.n_views, a.chunk_edge);
+  const int64_t grid = render_grid(a);
   uint32_t lds = tf_lds_bytes(a.tf.K);
   const uint32_t with_box = vbox_lds_offset(a.tf.K) + vbox_lds_bytes();
   a.use_box = with_box <= max_lds_per_workgroup() ? 1 : 0;

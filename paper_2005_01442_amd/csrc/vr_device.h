@@ -1042,6 +1042,20 @@ __device__ inline SuperTile map_workgroup(int64_t wg, int W, int H, int views, i
   return st;
 }
 
+// Workgroup -> super-tile through a precomputed order (item q = view * tiles
+// + sy * tiles_x + sx), or the Morton chunk mapping when there is none.
+__device__ inline SuperTile tile_of(const int32_t *order, int64_t wg, int W, int H, int views, int ce) {
+  if (!order) return map_workgroup(wg, W, H, views, ce);
+  const int tx = (W + kSuperEdge - 1) / kSuperEdge, ty = (H + kSuperEdge - 1) / kSuperEdge;
+  const int q = order[wg], per = tx * ty;
+  SuperTile st;
+  st.view = q / per;
+  st.sx = (q % per) % tx;
+  st.sy = (q % per) / tx;
+  st.valid = true;
+  return st;
+}
+
 __device__ inline void pixel_of(int sx, int sy, int &col, int &row) {
   int wave = threadIdx.x / kWaveSize, lane = threadIdx.x % kWaveSize;
   col = sx * kSuperEdge + (wave & 1) * kTileEdge + (lane & 7);

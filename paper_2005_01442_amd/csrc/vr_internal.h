@@ -18,6 +18,7 @@ struct RenderArgs {
   MarchConst mc;
   float *out;                      // RGBA of the first view of this launch
   unsigned long long *counters;    // optional [evaluated, lattice, hit, -]
+  const int32_t *order;            // workgroup -> super-tile order, or nullptr
   int32_t W, H, n_views, chunk_edge;
   int32_t use_box;                 // stage volume boxes in LDS (set at launch)
   int32_t shaded;                  // nonzero: local lighting with `shade`
@@ -65,6 +66,16 @@ uint32_t max_lds_per_workgroup();
 int32_t chunk_edge_setting();
 
 hipError_t launch_render(const RenderArgs &a, hipStream_t s);
+// Number of workgroups of a render launch of `a` (one per super-tile with an
+// order, else the padded Morton grid).
+int64_t render_grid(const RenderArgs &a);
+// Centre-out workgroup order for the views of `a`: super-tiles sorted by
+// their distance to the projection of the volume's centre (the tiles whose
+// rays cross the most volume go first, so the longest tiles do not start
+// last).  Allocated on `s` (stream-ordered); the caller frees it with
+// hipFreeAsync after its launches.  nullptr when it cannot be allocated (the
+// Morton mapping is used then).
+int32_t *make_tile_order(const RenderArgs &a, hipStream_t s);
 hipError_t launch_render_backward(const BackwardArgs &a, hipStream_t s);
 hipError_t launch_block_minmax(const VolConst &v, float2 *out, hipStream_t s);
 hipError_t launch_block_occupancy(const VolConst &v, const TfConst &tf, uint8_t *occ, hipStream_t s);
