@@ -57,6 +57,7 @@ struct Request {
   size_t image_bytes = 0;
   int64_t items_total = 0, items_issued = 0, items_done = 0;
   int32_t stx = 0, sty = 0;  // super-tile grid
+  std::vector<int32_t> order;  // super-tiles, nearest to the projected volume centre first
   bool released = false;
 };
 
@@ -263,6 +264,8 @@ bool issue(vr_server *s, Batch &b) {
   int32_t max_k = 2;
   b.per_request.clear();
   b.pixels = 0;
+  std::vector<std::pair<float, ServeItem>> keyed;
+  keyed.reserve((size_t)n_items_total);
   for (size_t i = 0; i < n; ++i) {
     if (take[i] == 0) continue;
     Request &r = *s->requests[live[i]];
@@ -280,10 +283,14 @@ bool issue(vr_server *s, Batch &b) {
     sl.tf.table = reinterpret_cast<const float *>(b.dev + tf_cursor);
     tf_cursor += align16((size_t)r.K * 16);
     for (int64_t q = 0; q < take[i]; ++q) {
-      int64_t id = r.items_issued + q;
-      items[item].slot = slot;
-      items[item].sx = (int16_t)(id % r.stx);
-      items[item].sy = (int16_t)(id / r.stx);
+      const int64_t rank = r.items_issued + q;
+      const int32_t id = r.order[(size_t)rank];
+      ServeItem it;
+      it.slot = slot;
+      it.sx = (int16_t)(id % r.stx);
+      it.sy = (int16_t)(id / r.stx);
+      // heavy (central) tiles of every request first: merge by relative rank
+      keyed.emplace_back((float)rank / (float)r.items_total, it);
       ++item;
     }
     r.items_issued += take[i];
@@ -291,6 +298,9 @@ bool issue(vr_server *s, Batch &b) {
     b.pixels += take[i] * kSuperEdge * kSuperEdge;
     ++slot;
   }
+  std::stable_sort(keyed.begin(), keyed.end(),
+                   [](const std::pair<float, ServeItem> &a, const std::pair<float, ServeItem> &c) { return a.first < c.first; });
+  for (size_t q = 0; q < keyed.size(); ++q) items[q] = keyed[q].second;
   hipError_t e = hipMemcpyAsync(b.dev, b.host, total, hipMemcpyHostToDevice, b.stream);
   if (e == hipSuccess)
     e = launch_serve_batch(reinterpret_cast<const ServeSlot *>(b.dev + off_slots),
@@ -454,6 +464,45 @@ vr_status vr_serve_submit(vr_server *s, const vr_request *req, uint64_t *ticket)
   r->sty = (req->cam.height + kSuperEdge - 1) / kSuperEdge;
   if (r->stx > 32767 || r->sty > 32767) return fail(VR_E_UNSUPPORTED, "image too large for serving");
   r->items_total = (int64_t)r->stx * r->sty;
+  // centre-out tile order (the volume's projected centre; image centre if it does not project)
+  double centre[3] = {0.0, 0.0, 0.0};
+  {
+    std::lock_guard<std::mutex> lk0(s->mu);
+    auto vit0 = s->volumes.find(req->volume_id);
+    if (vit0 != s->volumes.end()) {
+      centre[0] = 0.5 * (double)(vit0->second.desc.nx - 1);
+      centre[1] = 0.5 * (double)(vit0->second.desc.ny - 1);
+      centre[2] = 0.5 * (double)(vit0->second.desc.nz - 1);
+    }
+  }
+  {
+    const CamConst &c = r->cam;
+    double d[3], x = 0.0, y = 0.0, z = 0.0;
+    for (int k = 0; k < 3; ++k) d[k] = centre[k] - c.eye[k];
+    for (int k = 0; k < 3; ++k) {
+      z += d[k] * c.fwd[k];
+      x += d[k] * c.right[k];
+      y += d[k] * c.up[k];
+    }
+    double sx = 0.0, sy = 0.0;
+    if (c.proj != 0) {
+      if (z > 0.0) {
+        sx = x / (z * c.th * ((double)c.W / (double)c.H));
+        sy = y / (z * c.th);
+      }
+    } else {
+      sx = c.hw > 0.0 ? x / c.hw : 0.0;
+      sy = c.hh > 0.0 ? y / c.hh : 0.0;
+    }
+    const double cx = std::fmin(std::fmax(((sx + 1.0) * 0.5 * c.W) / kSuperEdge - 0.5, -1e6), 1e6);
+    const double cy = std::fmin(std::fmax(((1.0 - sy) * 0.5 * c.H) / kSuperEdge - 0.5, -1e6), 1e6);
+    std::vector<std::pair<float, int32_t>> kd((size_t)r->items_total);
+    for (int32_t t = 0; t < (int32_t)r->items_total; ++t)
+      kd[(size_t)t] = {(float)std::hypot((double)(t % r->stx) - cx, (double)(t / r->stx) - cy), t};
+    std::sort(kd.begin(), kd.end());
+    r->order.resize(kd.size());
+    for (size_t q = 0; q < kd.size(); ++q) r->order[q] = kd[q].second;
+  }
   std::lock_guard<std::mutex> lk(s->mu);
   if (s->stop) return fail(VR_E_SHUTDOWN, "server is shutting down");
   if (s->dead) return fail(s->dead_status, "server failed earlier");
