@@ -358,7 +358,7 @@ def bricked_measurements(vr, torch, np, c, cams, tf, out, args):
         log(f"out of core {label}: {ms:.2f} ms/frame, {res[label]['passes_per_frame']:.1f} passes, "
             f"{up / 2**20:.1f} MiB uploaded per frame")
         del bv
-    res["note"] = ("bricks = 64^3 blocks with their cubic-stencil apron (67^3 voxels); image bit-identical to the "
+    res["note"] = ("bricks = 64^3 blocks with their cubic-stencil apron (stored as 68^3 voxels); image bit-identical to the "
                    "in-core render with 64^3 skip blocks; frame time includes the occupancy readback, the host's "
                    "pass planning and the host-to-device brick copies")
     return res

@@ -298,8 +298,9 @@ vr_status vr_render_preint(const vr_volume *vol, const vr_blocks *blocks, const 
 /* ---------------------------------------------------------------------- */
 
 /* Opaque, library-owned: a volume kept in pinned host memory as bricks (the
- * footprint [bE-1, bE+E+1] per axis of every E^3 block, edge-clamped, (E+3)^3
- * voxels each) plus a device pool of whole bricks with a page table. */
+ * footprint [bE-1, bE+E+1] per axis of every E^3 block, edge-clamped, stored
+ * with one more plane per axis as (E+4)^3 voxels) plus a device pool of whole
+ * bricks with a page table. */
 typedef struct vr_bricked vr_bricked;
 
 typedef struct {

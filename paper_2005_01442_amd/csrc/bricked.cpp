@@ -55,8 +55,9 @@ namespace vr {
 
 static inline int64_t clampl(int64_t a, int64_t lo, int64_t hi) { return a < lo ? lo : (a > hi ? hi : a); }
 
-// Copy brick (bx, by, bz)'s footprint into dst (S^3 elements, x fastest) and
-// return its (min, max).
+// Copy brick (bx, by, bz)'s footprint into dst (S^3 elements from bE - 1 on
+// each axis, x fastest, edge-clamped) and return the (min, max) of the
+// footprint proper, [bE-1, bE+E+1] (the extra last plane does not count).
 template <class T>
 static float2 gather_brick(const T *src, int64_t nx, int64_t ny, int64_t nz, int E, int S, int64_t bx, int64_t by,
                            int64_t bz, T *dst) {
@@ -71,9 +72,11 @@ static float2 gather_brick(const T *src, int64_t nx, int64_t ny, int64_t nz, int
       for (int xl = 0; xl < S; ++xl) {
         const T v = row[clampl(ox + xl, 0, nx - 1)];
         out[xl] = v;
-        const float f = (float)v;
-        mn = f < mn ? f : mn;
-        mx = f > mx ? f : mx;
+        if (xl <= E + 2 && yl <= E + 2 && zl <= E + 2) {
+          const float f = (float)v;
+          mn = f < mn ? f : mn;
+          mx = f > mx ? f : mx;
+        }
       }
     }
   }
@@ -149,7 +152,7 @@ vr_status vr_bricked_create(const vr_volume *host_vol, int32_t brick_edge, uint6
   v->ny = host_vol->ny;
   v->nz = host_vol->nz;
   v->E = brick_edge;
-  v->S = brick_edge + 3;
+  v->S = brick_edge + 4;  // the footprint E + 3 plus one plane: an even row length
   v->nbx = (int32_t)((v->nx + brick_edge - 1) / brick_edge);
   v->nby = (int32_t)((v->ny + brick_edge - 1) / brick_edge);
   v->nbz = (int32_t)((v->nz + brick_edge - 1) / brick_edge);

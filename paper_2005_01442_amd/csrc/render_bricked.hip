@@ -6,7 +6,8 @@
 // decomposition, the overlap of three voxels for cubic sampling, Fig. 3, and
 // the analysis of its pros and cons).  Here a brick is one block's footprint
 // [bE-1, bE+E+1] per axis (the voxels any sample whose cell lies in the block
-// reads, edge-clamped), resident in a pool slot of (E+3)^3 voxels.  A pass
+// reads, edge-clamped; one more plane per axis makes the slot edge E+4 even),
+// resident in a pool slot of (E+4)^3 voxels.  A pass
 // renders, for every ray, its samples in the resident bricks, continuing from
 // the ray's state (next lattice index, C, T) that earlier passes left; passes
 // follow a front-to-back brick order, so every ray's samples are composited
@@ -23,23 +24,21 @@ template <int DT>
 __device__ inline float reconstruct_slot(const char *slot, int S, int ox, int oy, int oz, int nx, int ny, int nz,
                                          const Stencil &s) {
   float t[4][4][4];
-  const bool xrow = DT != kF32 && s.ix >= 1 && s.ix + 2 <= nx - 1;  // the 4 x taps are one contiguous run
-  int xs[4];
+  const bool inner = (s.ix >= 1) & (s.ix + 2 <= nx - 1) & (s.iy >= 1) & (s.iy + 2 <= ny - 1) & (s.iz >= 1) &
+                     (s.iz + 2 <= nz - 1);
+  if (DT != kF32 && inner) {
+    // 16-bit taps, no clamping: every x-run of 4 taps lies in the dword window
+    // w0 + (c S + b) S / 2 .. + 2 (S is even, so all runs share e's parity;
+    // the slot padding keeps the last window inside)
+    const uint32_t e = ((uint32_t)(s.iz - 1 - oz) * (uint32_t)S + (uint32_t)(s.iy - 1 - oy)) * (uint32_t)S +
+                       (uint32_t)(s.ix - 1 - ox);
+    const uint32_t *w0 = reinterpret_cast<const uint32_t *>(slot) + (e >> 1);
+    const uint32_t sh = (e & 1u) * 16u, half = (uint32_t)S >> 1;
 #pragma unroll
-  for (int a = 0; a < 4; ++a) xs[a] = min(max(s.ix - 1 + a, 0), nx - 1) - ox;
+    for (int c = 0; c < 4; ++c)
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const int z = min(max(s.iz - 1 + c, 0), nz - 1) - oz;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int y = min(max(s.iy - 1 + b, 0), ny - 1) - oy;
-      const size_t row = ((size_t)z * S + y) * S;
-      if (xrow) {
-        // 16-bit taps: the dword-aligned 12-byte window holding them, shifted
-        // by the run's parity (the slot padding keeps the window inside)
-        const size_t e = row + xs[0];
-        const uint32_t *w = reinterpret_cast<const uint32_t *>(slot + (e & ~(size_t)1) * 2);
-        const uint32_t sh = (uint32_t)(e & 1) * 16u;
+      for (int b = 0; b < 4; ++b) {
+        const uint32_t *w = w0 + ((uint32_t)c * (uint32_t)S + (uint32_t)b) * half;
         const uint32_t lo = __builtin_amdgcn_alignbit(w[1], w[0], sh), hi = __builtin_amdgcn_alignbit(w[2], w[1], sh);
         if (DT == kI16) {
           t[c][b][0] = (float)(int16_t)(lo & 0xffffu);
@@ -52,11 +51,22 @@ __device__ inline float reconstruct_slot(const char *slot, int S, int ox, int oy
           t[c][b][2] = (float)(hi & 0xffffu);
           t[c][b][3] = (float)(hi >> 16);
         }
-        continue;
       }
+    return combine(s, t);
+  }
+  int xs[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) xs[a] = min(max(s.ix - 1 + a, 0), nx - 1) - ox;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int z = min(max(s.iz - 1 + c, 0), nz - 1) - oz;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int y = min(max(s.iy - 1 + b, 0), ny - 1) - oy;
+      const uint32_t row = ((uint32_t)z * (uint32_t)S + (uint32_t)y) * (uint32_t)S;
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
-        const size_t e = row + xs[a];
+        const uint32_t e = row + (uint32_t)xs[a];
         if (DT == kF32)
           t[c][b][a] = reinterpret_cast<const float *>(slot)[e];
         else if (DT == kI16)
@@ -69,10 +79,13 @@ __device__ inline float reconstruct_slot(const char *slot, int S, int ox, int oy
   return combine(s, t);
 }
 
-// One pass over one view.  One lane per pixel (16x16 pixels per workgroup,
-// row-major over the image).  state: per pixel (C_r, C_g, C_b, T); next: the
-// next lattice index, or -1 once the ray is finished.  first: initialise the
-// state instead of reading it.
+// One pass over one view.  Workgroups of 16x16 pixels in raster order,
+// wavefronts of 8x8 that march their rays in step (the walk of the in-core
+// kernel, started at each ray's saved index): samples in empty bricks are
+// leapt over, samples in resident bricks evaluated from their slot, and a
+// ray parks at its first sample in an occupied brick of a later pass.
+// state: per pixel (C_r, C_g, C_b, T); next: the next lattice index, or -1
+// once the ray is finished.  first: initialise the state instead of reading it.
 template <int DT>
 __global__ __launch_bounds__(kWgSize) void k_bricked_pass(const BrickedArgs args) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
@@ -80,44 +93,41 @@ __global__ __launch_bounds__(kWgSize) void k_bricked_pass(const BrickedArgs args
   TfShared s = carve_tf(lds, a.tf.K);
   load_tf(s, a.tf);
   const int tiles_x = (a.W + kSuperEdge - 1) / kSuperEdge;
-  const int col = (int)(blockIdx.x % tiles_x) * kSuperEdge + (int)(threadIdx.x % kSuperEdge);
-  const int row = (int)(blockIdx.x / tiles_x) * kSuperEdge + (int)(threadIdx.x / kSuperEdge);
-  if (col >= a.W || row >= a.H) return;
-  const size_t pix = (size_t)row * a.W + col;
-  int k;
-  float4 st;
-  if (a.first) {
-    k = 0;
-    st = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
-  } else {
-    k = a.next[pix];
-    if (k < 0) return;
-    st = a.state[pix];
+  int col, row;
+  pixel_of((int)(blockIdx.x % tiles_x), (int)(blockIdx.x / tiles_x), col, row);
+  const bool inside = col < a.W && row < a.H;
+  const size_t pix = inside ? (size_t)row * a.W + col : 0;
+  int kstart = 0;
+  float4 st = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+  bool active = inside;
+  if (inside && !a.first) {
+    kstart = a.next[pix];
+    active = kstart >= 0;
+    if (active) st = a.state[pix];
   }
-  const Ray r = setup_ray(a.cam, col, row, a.vol.nx, a.vol.ny, a.vol.nz, a.mc.step);
-  if (a.first) k = r.k0;
-  const int kend = r.hit ? r.k0 + r.ns : 0;
+  // every lane takes part in the walk; finished or outside lanes carry no ray
+  Ray r;
+  r.hit = false;
+  r.ns = 0;
+  r.k0 = 0;
+  r.s0 = 0.0f;
+  if (active) r = setup_ray(a.cam, col, row, a.vol.nx, a.vol.ny, a.vol.nz, a.mc.step);
+  if (a.first) kstart = r.k0;
   const float sl2 = a.mc.step * 1.4426950408889634f;
   const bool ert_on = a.mc.ert > 0.0f && a.mc.ert < 1.0f;
-  const int S = a.slot_edge;
-  bool done = !r.hit;
-  int bc[3];
-  while (!done && k < kend) {
-    float px, py, pz;
-    lattice_point(r, a.mc.step, k, px, py, pz);
+  const int S = a.slot_edge, E = a.vol.edge;
+  int parked = -1;
+  auto visit = [&](int k, float px, float py, float pz) -> bool {
+    int bc[3];
     const int b = block_of(a.vol, px, py, pz, bc);
-    if (!a.occ[b]) {  // empty brick: its samples add exactly zero
-      const int t = leap_target(a.vol, r, bc, a.mc.step, k);
-      k = t > k + 1 ? t : k + 1;
-      continue;
-    }
     const int slot = a.page[b];
-    if (slot < 0) break;  // a later pass holds this brick
+    if (slot < 0) {  // a later pass holds this brick
+      parked = k;
+      return false;
+    }
     const Stencil sten = make_stencil(px, py, pz);
-    const char *base = a.pool + (size_t)slot * a.slot_bytes;
-    const int E = a.vol.edge;
-    const float val = reconstruct_slot<DT>(base, S, bc[0] * E - 1, bc[1] * E - 1, bc[2] * E - 1, a.vol.nx, a.vol.ny,
-                                           a.vol.nz, sten);
+    const float val = reconstruct_slot<DT>(a.pool + (size_t)slot * a.slot_bytes, S, bc[0] * E - 1, bc[1] * E - 1,
+                                           bc[2] * E - 1, a.vol.nx, a.vol.ny, a.vol.nz, sten);
     const Classified q = classify(s, a.tf.K, a.tf.v0, a.tf.scale, val);
     const float e = transmit(q.c.w, sl2);
     const float ta = st.w * (1.0f - e);
@@ -125,12 +135,15 @@ __global__ __launch_bounds__(kWgSize) void k_bricked_pass(const BrickedArgs args
     st.y = fmaf(ta, q.c.y, st.y);
     st.z = fmaf(ta, q.c.z, st.z);
     st.w = st.w * e;
-    ++k;
-    if (ert_on && (1.0f - st.w) >= a.mc.ert) done = true;
+    return !(ert_on && (1.0f - st.w) >= a.mc.ert);
+  };
+  NoPrep prep;
+  NoPost post;
+  walk<decltype(visit), NoPrep, NoPost, true>(a.vol, s, a.tf, a.mc, r, visit, prep, post, kstart);
+  if (active) {
+    a.state[pix] = st;
+    a.next[pix] = parked;
   }
-  if (k >= kend) done = true;
-  a.state[pix] = st;
-  a.next[pix] = done ? -1 : k;
 }
 
 // Premultiplied RGBA from the pass state: (C, 1 - T).

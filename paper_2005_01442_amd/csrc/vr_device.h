@@ -935,10 +935,12 @@ struct NoPost {
   __device__ inline void operator()() const {}
 };
 
-template <class Visit, class Prep, class Post>
+// FROM: start at lattice index kstart (>= r.k0) instead of r.k0 -- a ray
+// resumed where an earlier pass left it; positions still follow r.
+template <class Visit, class Prep, class Post, bool FROM = false>
 __device__ inline void walk(const VolConst &v, const TfShared &s, const TfConst &tf, const MarchConst &mc,
-                            const Ray &r, Visit &visit, Prep &prep, Post &post) {
-  const int kb = r.hit ? r.k0 : 0x7fffffff;
+                            const Ray &r, Visit &visit, Prep &prep, Post &post, int kstart = 0) {
+  const int kb = r.hit ? (FROM ? max(r.k0, kstart) : r.k0) : 0x7fffffff;
   const int ke = r.hit ? r.k0 + r.ns : 0;
   bool alive = r.hit;
   int k = wave_min_i32(kb);

@@ -41,7 +41,8 @@ struct BackwardArgs {
 
 
 // Out-of-core pass over one view: bricks of edge E (the blocks' footprints,
-// (E+3)^3 voxels each) resident in pool slots listed by the page table.
+// (E+4)^3 voxels each: the footprint plus one plane) resident in pool slots
+// listed by the page table.
 struct BrickedArgs {
   VolConst vol;            // dims, block grid, edge, edge_shift (no data)
   TfConst tf;
@@ -53,7 +54,7 @@ struct BrickedArgs {
   float4 *state;           // per pixel: (C_r, C_g, C_b, T)
   int32_t *next;           // per pixel: next lattice index, -1 when finished
   int64_t slot_bytes;
-  int32_t slot_edge;       // E + 3
+  int32_t slot_edge;       // E + 4 (even)
   int32_t W, H;
   int32_t first;           // initialise the ray state
 };

@@ -32,7 +32,7 @@ def _incore(vol_np, cams, tf, step, ert, edge):
 
 
 def _bricked(vol_np, cams, tf, step, ert, edge, pool_bricks):
-    slot = (((edge + 3) ** 3 * vol_np.dtype.itemsize + 16 + 255) // 256) * 256
+    slot = (((edge + 4) ** 3 * vol_np.dtype.itemsize + 16 + 255) // 256) * 256
     bv = vr.BrickedVolume(vol_np, edge, pool_bricks * slot)
     t = upload_tf(tf)
     out = bv.render(cams, t, step, ert)
@@ -105,7 +105,7 @@ def test_bricked_c1_full_size_bit_identical():
     c = synth.config_c1()
     log("bricked c1 512x512x400 edge 64, pool 64 MiB")
     want = _incore(c["volume"], c["cameras"], c["tf"], c["step"], c["ert"], 64)
-    slot = ((67 ** 3 * 2 + 16 + 255) // 256) * 256
+    slot = ((68 ** 3 * 2 + 16 + 255) // 256) * 256
     got, bv = _bricked(c["volume"], c["cameras"], c["tf"], c["step"], c["ert"], 64, (64 << 20) // slot)
     st = bv.stats()
     log(f"c1 bricked: passes {st['passes']}, occupied {st['bricks_occupied']}/{st['bricks_total']}, "
