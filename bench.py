@@ -64,6 +64,7 @@ def parse():
                     help="skip the pre-integrated forward and the step-artefact measurement")
     ap.add_argument("--no-bricked", action="store_true", help="skip the out-of-core (brick pool) measurement")
     ap.add_argument("--no-filters", action="store_true", help="skip the Catmull-Rom / interpolating-spline frames")
+    ap.add_argument("--no-c2", action="store_true", help="skip the large 1024^3 -> 2048^2 forward measurement")
     return ap.parse_args()
 
 
@@ -364,6 +365,47 @@ def bricked_measurements(vr, torch, np, c, cams, tf, out, args):
     return res
 
 
+def large_forward(vr, torch, np, synth, args):
+    """The large forward: 1024^3 int16 (2 GiB, larger than the 256 MB MALL)
+    to 2048^2, step 0.25, skip + ERT; effective gather and HBM-side bytes."""
+    log("building the 1024^3 int16 phantom")
+    c2 = synth.config_c2()
+    vol2 = vr.Volume(torch.from_numpy(c2["volume"]).cuda())
+    del c2["volume"]
+    tf2 = vr.TF(torch.from_numpy(c2["tf"].table).cuda(), c2["tf"].v0, c2["tf"].v1)
+    b2 = vr.vr_build_blocks(vol2, 16)
+    cams2 = c2["cameras"]
+    W2, H2 = cams2[0].width, cams2[0].height
+    out2 = torch.empty((1, H2, W2, 4), dtype=torch.float32, device="cuda")
+    ctr = torch.zeros(4, dtype=torch.int64, device="cuda")
+    vr.vr_render(vol2, b2, cams2, tf2, c2["step"], c2["ert"], True, out=out2, counters=ctr)
+    torch.cuda.synchronize()
+    ev2 = int(ctr[0].item())
+
+    def fwd2():
+        vr.vr_render(vol2, b2, cams2, tf2, c2["step"], c2["ert"], True, out=out2)
+
+    steps = max(3, args.steps // 4)
+    wall, ev = time_steps(fwd2, steps, max(1, args.warmup // 2), torch)
+    ms = wall / steps * 1e3
+    gbs = ev2 * TAPS_BYTES_I16 / (float(np.mean(ev)) * 1e-3) / 1e9
+    log(f"c2: {ms:.2f} ms/frame, {ev2 / (wall / steps):.4g} samples/s, {gbs:.0f} GB/s effective")
+    res = {
+        "workload": "c2_ct1024cube_i16_to_2048x2048_persp60_step0.25_skip16_ert0.99",
+        "ms_per_step": ms,
+        "kernel_ms": float(np.mean(ev)),
+        "samples_per_s": ev2 / (wall / steps),
+        "rays_per_s": W2 * H2 / (wall / steps),
+        "evaluated_samples_per_frame": ev2,
+        "lattice_samples_per_frame": int(ctr[1].item()),
+        "effective_gather_gb_per_s": gbs,
+        "roofline_frac": gbs / HBM_PEAK_GBS,
+    }
+    del vol2, b2, out2
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -530,6 +572,9 @@ def main():
 
     if not args.no_bricked:
         result["c1_out_of_core"] = bricked_measurements(vr, torch, np, c, cams, tf, out, args)
+
+    if not args.no_c2:
+        result["c2_large"] = large_forward(vr, torch, np, synth, args)
 
     if not args.no_bwd:
         gv_holder = {}
