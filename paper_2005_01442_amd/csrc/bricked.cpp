@@ -39,8 +39,11 @@ struct vr_bricked {
   float2 *minmax_dev;      // nbricks
   uint8_t *occ_dev;
   uint8_t *occ_host;       // pinned
-  int32_t *page_dev;
-  int32_t *page_host;      // pinned
+  int32_t *page_dev[2];    // per pool half (streaming) or [0] (all resident)
+  int32_t *page_host[2];   // pinned
+  hipStream_t copy_stream; // brick copies while the render stream renders
+  hipEvent_t copied[2], rendered[2];
+  bool copied_rec[2], rendered_rec[2];
   char *pool;
   int64_t nslots;
   std::vector<int64_t> slot_brick;  // slot -> brick or -1
@@ -118,10 +121,15 @@ static void destroy(vr_bricked *v) {
   if (!v) return;
   if (v->host_bricks) (void)hipHostFree(v->host_bricks);
   if (v->occ_host) (void)hipHostFree(v->occ_host);
-  if (v->page_host) (void)hipHostFree(v->page_host);
+  for (int h = 0; h < 2; ++h) {
+    if (v->page_host[h]) (void)hipHostFree(v->page_host[h]);
+    (void)hipFree(v->page_dev[h]);
+    if (v->copied[h]) (void)hipEventDestroy(v->copied[h]);
+    if (v->rendered[h]) (void)hipEventDestroy(v->rendered[h]);
+  }
+  if (v->copy_stream) (void)hipStreamDestroy(v->copy_stream);
   (void)hipFree(v->minmax_dev);
   (void)hipFree(v->occ_dev);
-  (void)hipFree(v->page_dev);
   (void)hipFree(v->pool);
   (void)hipFree(v->state);
   (void)hipFree(v->next);
@@ -196,15 +204,26 @@ vr_status vr_bricked_create(const vr_volume *host_vol, int32_t brick_edge, uint6
   for (auto &th : pool) th.join();
   const size_t nb = (size_t)v->nbricks;
   if ((e = hipMalloc(&v->minmax_dev, nb * sizeof(float2))) != hipSuccess ||
-      (e = hipMalloc(&v->occ_dev, nb)) != hipSuccess || (e = hipMalloc(&v->page_dev, nb * sizeof(int32_t))) != hipSuccess ||
+      (e = hipMalloc(&v->occ_dev, nb)) != hipSuccess ||
+      (e = hipMalloc(&v->page_dev[0], nb * sizeof(int32_t))) != hipSuccess ||
+      (e = hipMalloc(&v->page_dev[1], nb * sizeof(int32_t))) != hipSuccess ||
       (e = hipMalloc(&v->pool, (size_t)(v->nslots * v->slot_bytes))) != hipSuccess) {
     destroy(v);
     return fail(VR_E_OOM, "device allocation for the brick pool: %s", hipGetErrorString(e));
   }
   if ((e = hipHostMalloc((void **)&v->occ_host, nb, hipHostMallocDefault)) != hipSuccess ||
-      (e = hipHostMalloc((void **)&v->page_host, nb * sizeof(int32_t), hipHostMallocDefault)) != hipSuccess) {
+      (e = hipHostMalloc((void **)&v->page_host[0], nb * sizeof(int32_t), hipHostMallocDefault)) != hipSuccess ||
+      (e = hipHostMalloc((void **)&v->page_host[1], nb * sizeof(int32_t), hipHostMallocDefault)) != hipSuccess) {
     destroy(v);
     return fail(VR_E_OOM, "pinned host allocation: %s", hipGetErrorString(e));
+  }
+  if ((e = hipStreamCreateWithFlags(&v->copy_stream, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&v->copied[0], hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&v->copied[1], hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&v->rendered[0], hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&v->rendered[1], hipEventDisableTiming)) != hipSuccess) {
+    destroy(v);
+    return hip_fail(e, "copy stream and events");
   }
   if ((e = hipMemcpy(v->minmax_dev, mm.data(), nb * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess) {
     destroy(v);
@@ -287,7 +306,7 @@ vr_status vr_bricked_render(vr_bricked *v, const vr_camera *cams, int32_t n_cams
       (e = hipStreamSynchronize(st)) != hipSuccess)
     return hip_fail(e, "occupancy readback");
   a.pool = v->pool;
-  a.page = v->page_dev;
+  a.page = v->page_dev[0];
   a.occ = v->occ_dev;
   a.state = v->state;
   a.next = v->next;
@@ -303,48 +322,100 @@ vr_status vr_bricked_render(vr_bricked *v, const vr_camera *cams, int32_t n_cams
     order_bricks(a.cam, v->E, v->nbx, v->nby, v->nbz, v->occ_host, order);
     // 3. passes
     const int64_t nocc = (int64_t)order.size();
-    int64_t pos = 0;
-    a.first = 1;
-    do {
-      const int64_t end = std::min(nocc, pos + v->nslots);
-      for (int64_t q = pos; q < end; ++q) in_pass[(size_t)order[q]] = 1;
-      // free the slots of resident bricks outside this pass
-      std::vector<int64_t> free_slots;
-      for (int64_t sl = 0; sl < v->nslots; ++sl) {
-        const int64_t b = v->slot_brick[(size_t)sl];
-        if (b >= 0 && !in_pass[(size_t)b]) {
-          v->brick_slot[(size_t)b] = -1;
-          v->slot_brick[(size_t)sl] = -1;
-        }
-        if (v->slot_brick[(size_t)sl] < 0) free_slots.push_back(sl);
-      }
-      // the previous pass's page-table copy has been consumed once the stream is idle
-      if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "pass synchronisation");
-      for (int64_t b = 0; b < v->nbricks; ++b) v->page_host[b] = -1;
-      size_t fi = 0;
-      for (int64_t q = pos; q < end; ++q) {
-        const int64_t b = order[q];
-        int64_t sl = v->brick_slot[(size_t)b];
-        if (sl < 0) {
-          sl = free_slots[fi++];
+    if (nocc > v->nslots && v->nslots >= 2) {
+      // streaming: passes of half a pool each, alternating halves; the copies
+      // of a pass (on the copy stream) overlap the previous pass's rendering
+      const int64_t half = v->nslots / 2;
+      int64_t pos = 0;
+      a.first = 1;
+      for (int pass = 0; pos < nocc; ++pass) {
+        const int h = pass & 1;
+        const int64_t end = std::min(nocc, pos + half);
+        // the page table of this half is free once its last copy has run
+        if (v->copied_rec[h] && (e = hipEventSynchronize(v->copied[h])) != hipSuccess)
+          return hip_fail(e, "page table reuse");
+        // the slots of this half are free once the pass that read them has run
+        if (v->rendered_rec[h] && (e = hipStreamWaitEvent(v->copy_stream, v->rendered[h], 0)) != hipSuccess)
+          return hip_fail(e, "copy stream wait");
+        int32_t *page = v->page_host[h];
+        for (int64_t b = 0; b < v->nbricks; ++b) page[b] = -1;
+        for (int64_t q = pos; q < end; ++q) {
+          const int64_t b = order[q], sl = h * half + (q - pos);
+          const int64_t old = v->slot_brick[(size_t)sl];
+          if (old >= 0) v->brick_slot[(size_t)old] = -1;
+          const int64_t had = v->brick_slot[(size_t)b];
+          if (had >= 0) v->slot_brick[(size_t)had] = -1;
           e = hipMemcpyAsync(v->pool + sl * v->slot_bytes, v->host_bricks + b * v->slot_bytes, (size_t)v->slot_bytes,
-                             hipMemcpyHostToDevice, st);
+                             hipMemcpyHostToDevice, v->copy_stream);
           if (e != hipSuccess) return hip_fail(e, "brick upload");
           v->brick_slot[(size_t)b] = sl;
           v->slot_brick[(size_t)sl] = b;
           v->stats.bricks_uploaded++;
           v->stats.bytes_uploaded += (uint64_t)v->slot_bytes;
+          page[b] = (int32_t)sl;
         }
-        v->page_host[b] = (int32_t)sl;
+        e = hipMemcpyAsync(v->page_dev[h], page, (size_t)v->nbricks * sizeof(int32_t), hipMemcpyHostToDevice,
+                           v->copy_stream);
+        if (e != hipSuccess || (e = hipEventRecord(v->copied[h], v->copy_stream)) != hipSuccess)
+          return hip_fail(e, "page table upload");
+        v->copied_rec[h] = true;
+        if ((e = hipStreamWaitEvent(st, v->copied[h], 0)) != hipSuccess) return hip_fail(e, "render stream wait");
+        a.page = v->page_dev[h];
+        if ((e = launch_bricked_pass(a, st)) != hipSuccess) return hip_fail(e, "pass launch");
+        if ((e = hipEventRecord(v->rendered[h], st)) != hipSuccess) return hip_fail(e, "pass event");
+        v->rendered_rec[h] = true;
+        v->stats.passes++;
+        a.first = 0;
+        pos = end;
       }
-      e = hipMemcpyAsync(v->page_dev, v->page_host, (size_t)v->nbricks * sizeof(int32_t), hipMemcpyHostToDevice, st);
-      if (e != hipSuccess) return hip_fail(e, "page table upload");
-      if ((e = launch_bricked_pass(a, st)) != hipSuccess) return hip_fail(e, "pass launch");
-      v->stats.passes++;
-      a.first = 0;
-      for (int64_t q = pos; q < end; ++q) in_pass[(size_t)order[q]] = 0;
-      pos = end;
-    } while (pos < nocc);
+    } else {
+      // every occupied brick fits (or the pool holds a single brick): passes
+      // over the whole pool on the render stream, resident bricks reused
+      int64_t pos = 0;
+      a.first = 1;
+      a.page = v->page_dev[0];
+      do {
+        const int64_t end = std::min(nocc, pos + v->nslots);
+        for (int64_t q = pos; q < end; ++q) in_pass[(size_t)order[q]] = 1;
+        // free the slots of resident bricks outside this pass
+        std::vector<int64_t> free_slots;
+        for (int64_t sl = 0; sl < v->nslots; ++sl) {
+          const int64_t b = v->slot_brick[(size_t)sl];
+          if (b >= 0 && !in_pass[(size_t)b]) {
+            v->brick_slot[(size_t)b] = -1;
+            v->slot_brick[(size_t)sl] = -1;
+          }
+          if (v->slot_brick[(size_t)sl] < 0) free_slots.push_back(sl);
+        }
+        // the previous page-table copy has been consumed once the stream is idle
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "pass synchronisation");
+        int32_t *page = v->page_host[0];
+        for (int64_t b = 0; b < v->nbricks; ++b) page[b] = -1;
+        size_t fi = 0;
+        for (int64_t q = pos; q < end; ++q) {
+          const int64_t b = order[q];
+          int64_t sl = v->brick_slot[(size_t)b];
+          if (sl < 0) {
+            sl = free_slots[fi++];
+            e = hipMemcpyAsync(v->pool + sl * v->slot_bytes, v->host_bricks + b * v->slot_bytes,
+                               (size_t)v->slot_bytes, hipMemcpyHostToDevice, st);
+            if (e != hipSuccess) return hip_fail(e, "brick upload");
+            v->brick_slot[(size_t)b] = sl;
+            v->slot_brick[(size_t)sl] = b;
+            v->stats.bricks_uploaded++;
+            v->stats.bytes_uploaded += (uint64_t)v->slot_bytes;
+          }
+          page[b] = (int32_t)sl;
+        }
+        e = hipMemcpyAsync(v->page_dev[0], page, (size_t)v->nbricks * sizeof(int32_t), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "page table upload");
+        if ((e = launch_bricked_pass(a, st)) != hipSuccess) return hip_fail(e, "pass launch");
+        v->stats.passes++;
+        a.first = 0;
+        for (int64_t q = pos; q < end; ++q) in_pass[(size_t)order[q]] = 0;
+        pos = end;
+      } while (pos < nocc);
+    }
     v->stats.bricks_occupied = (uint64_t)nocc;
     // 4. image
     float4 *dst = reinterpret_cast<float4 *>(out_rgba) + (size_t)view * (size_t)npix;
