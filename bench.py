@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--no-bricked", action="store_true", help="skip the out-of-core (brick pool) measurement")
     ap.add_argument("--no-filters", action="store_true", help="skip the Catmull-Rom / interpolating-spline frames")
     ap.add_argument("--no-c2", action="store_true", help="skip the large 1024^3 -> 2048^2 forward measurement")
+    ap.add_argument("--gigavoxel", action="store_true",
+                    help="also render a 512x512x5382 int16 volume (the paper's largest CT) out of core through a "
+                         "1 GiB pool (about a minute of host-side set-up)")
     return ap.parse_args()
 
 
@@ -406,6 +409,44 @@ def large_forward(vr, torch, np, synth, args):
     return res
 
 
+def gigavoxel(vr, torch, synth, c, args):
+    """A 512x512x5382 int16 CT phantom (1.41e9 voxels, 2.8 GB) rendered out of
+    core to 1024^2 (TF1, step 0.5, ERT 0.99) through a 1 GiB brick pool."""
+    dims = (512, 512, 5382)
+    log("building the 512x512x5382 int16 phantom")
+    t0 = time.perf_counter()
+    vol = synth.ct_phantom_i16(*dims, seed=12)
+    gen_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    bv = vr.BrickedVolume(vol, 64, 1 << 30)
+    create_s = time.perf_counter() - t0
+    del vol
+    tf = vr.TF(torch.from_numpy(c["tf"].table).cuda(), c["tf"].v0, c["tf"].v1)
+    cams = synth.orbit_cameras(dims, 1, 13, 60.0, 1024, 1024)
+    out = torch.empty((1, 1024, 1024, 4), dtype=torch.float32, device="cuda")
+    bv.render(cams, tf, 0.5, 0.99, out=out)
+    torch.cuda.synchronize()
+    s0 = bv.stats()
+    steps = 3
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        bv.render(cams, tf, 0.5, 0.99, out=out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    s1 = bv.stats()
+    up = (s1["bytes_uploaded"] - s0["bytes_uploaded"]) / steps
+    log(f"gigavoxel out of core: {ms:.1f} ms/frame, {(s1['passes'] - s0['passes']) / steps:.0f} passes, "
+        f"{up / 2**30:.2f} GiB uploaded per frame, {s1['bricks_occupied']}/{s1['bricks_total']} bricks occupied")
+    res = {
+        "volume": list(dims), "volume_bytes": 2 * dims[0] * dims[1] * dims[2], "pool_bytes": 1 << 30,
+        "ms_per_frame": ms, "passes_per_frame": (s1["passes"] - s0["passes"]) / steps,
+        "bytes_uploaded_per_frame": up, "bricks_occupied": s1["bricks_occupied"], "bricks_total": s1["bricks_total"],
+        "phantom_s": gen_s, "create_s": create_s,
+    }
+    del bv
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -575,6 +616,9 @@ def main():
 
     if not args.no_c2:
         result["c2_large"] = large_forward(vr, torch, np, synth, args)
+
+    if args.gigavoxel:
+        result["gigavoxel_out_of_core"] = gigavoxel(vr, torch, synth, c, args)
 
     if not args.no_bwd:
         gv_holder = {}
