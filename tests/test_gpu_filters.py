@@ -182,3 +182,26 @@ def test_trilinear_ct_skip_and_ert():
     un, nflag = compare_with_flags(a, ref["rgba"], ref["flags"], 0.99)
     log(f"trilinear ct: max unflagged |dRGBA| = {un:.3e}, flagged {nflag}")
     assert nflag <= 1e-3 * a[..., 0].size + 2
+
+
+@pytest.mark.parametrize("mode", ["catmull_rom", "preclassified", "trilinear", "interpolating"])
+def test_filters_c1_full_size_sampled_pixels(mode):
+    """The 512x512x400 frame in the bench's launch configuration for every
+    filter variant; 512 sampled pixels checked against the oracle."""
+    c = synth.config_c1()
+    v = upload_volume(c["volume"])
+    t = upload_tf(c["tf"])
+    pix = synth.sample_pixels(1, 1024, 1024, 512, seed=85)
+    if mode == "interpolating":
+        coef = vr.vr_prefilter_bspline(v)
+        img = vr.vr_render(coef, vr.vr_build_blocks(coef, 16), c["cameras"], t, c["step"], c["ert"], True)
+        ref = oracle.render(oracle.prefilter(c["volume"]), c["cameras"], c["tf"], c["step"], ert=c["ert"], pixels=pix)
+    else:
+        f = {"catmull_rom": (CR, 1), "preclassified": (PRE, 2), "trilinear": (vr.VR_FILTER_TRILINEAR, 3)}[mode]
+        img = vr.vr_render(v, vr.vr_build_blocks(v, 16), c["cameras"], t, c["step"], c["ert"], True, filter=f[0])
+        ref = oracle.render(c["volume"], c["cameras"], c["tf"], c["step"], ert=c["ert"], pixels=pix, filter=f[1])
+    torch.cuda.synchronize()
+    got = img.cpu().numpy().astype(np.float64)[pix[:, 0], pix[:, 1], pix[:, 2]]
+    un, nflag = compare_with_flags(got, ref["rgba"], ref["flags"], c["ert"])
+    log(f"c1 {mode}: max unflagged |dRGBA| = {un:.3e}, flagged {nflag}")
+    assert nflag <= 4
