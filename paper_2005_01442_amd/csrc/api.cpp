@@ -336,6 +336,21 @@ void vr_blocks_free(vr_blocks *b) {
 static vr_status render_views(RenderArgs &a, const vr_camera *cams, int32_t n_cams, float *out_rgba, void *stream,
                               const float4 *preint = nullptr) {
   const size_t view_floats = (size_t)a.W * a.H * 4;
+  // the blocks' occupancy under this TF, once for all views (without it the
+  // kernels decide from min/max and the TF on every block change)
+  uint32_t *bits = nullptr;
+  if (!preint && a.mc.skip && a.vol.minmax) {
+    const int64_t words = ((int64_t)a.vol.nbx * a.vol.nby * a.vol.nbz + 31) / 32;
+    if (hipMallocAsync(reinterpret_cast<void **>(&bits), (size_t)words * 4, (hipStream_t)stream) != hipSuccess) {
+      (void)hipGetLastError();
+      bits = nullptr;
+    } else if (launch_occupancy_bits(a.vol, a.tf, bits, (hipStream_t)stream) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipFreeAsync(bits, (hipStream_t)stream);
+      bits = nullptr;
+    }
+  }
+  a.vol.occ = bits;
   for (int32_t v0 = 0; v0 < n_cams; v0 += kMaxCamsPerLaunch) {
     const int32_t n = std::min(kMaxCamsPerLaunch, n_cams - v0);
     for (int32_t i = 0; i < n; ++i) check_camera(&cams[v0 + i], &a.cams[i]);
@@ -345,8 +360,13 @@ static vr_status render_views(RenderArgs &a, const vr_camera *cams, int32_t n_ca
     hipError_t e = preint ? launch_render_preint(a, preint, (hipStream_t)stream) : launch_render(a, (hipStream_t)stream);
     if (a.order) (void)hipFreeAsync(const_cast<int32_t *>(a.order), (hipStream_t)stream);
     a.order = nullptr;
-    if (e != hipSuccess) return hip_fail(e, "render launch");
+    if (e != hipSuccess) {
+      if (bits) (void)hipFreeAsync(bits, (hipStream_t)stream);
+      return hip_fail(e, "render launch");
+    }
   }
+  if (bits) (void)hipFreeAsync(bits, (hipStream_t)stream);
+  a.vol.occ = nullptr;
   return VR_OK;
 }
 

@@ -84,6 +84,28 @@ hipError_t launch_block_occupancy(const VolConst &v, const TfConst &tf, uint8_t 
   return hipGetLastError();
 }
 
+// One thread per block, one ballot per 64 blocks; bits past the last block
+// are zero.
+__global__ __launch_bounds__(kWgSize) void k_occupancy_bits(const VolConst v, const TfConst tf, uint32_t *bits) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  TfShared s = carve_tf(lds, tf.K);
+  load_tf(s, tf);
+  const int64_t nb = (int64_t)v.nbx * v.nby * v.nbz;
+  const int64_t b = (int64_t)blockIdx.x * kWgSize + threadIdx.x;
+  const unsigned long long m = __ballot(b < nb && block_occupied(v, s, tf, (int)b));
+  const int lane = threadIdx.x % kWaveSize;
+  if ((lane == 0 || lane == 32) && b < nb) bits[b >> 5] = lane == 0 ? (uint32_t)m : (uint32_t)(m >> 32);
+}
+
+hipError_t launch_occupancy_bits(const VolConst &v, const TfConst &tf, uint32_t *bits, hipStream_t s) {
+  VolConst vm = v;
+  vm.occ = nullptr;  // decide from minmax
+  const int64_t nb = (int64_t)v.nbx * v.nby * v.nbz;
+  const unsigned grid = (unsigned)((nb + kWgSize - 1) / kWgSize);
+  hipLaunchKernelGGL(k_occupancy_bits, dim3(grid), dim3(kWgSize), tf_lds_bytes(tf.K), s, vm, tf, bits);
+  return hipGetLastError();
+}
+
 // Widened block ranges [lo - w (hi - lo), hi + w (hi - lo)] (fused, fp32).
 __global__ __launch_bounds__(kWgSize) void k_widen_minmax(const float2 *in, float2 *out, int64_t n, float w) {
   const int64_t i = (int64_t)blockIdx.x * kWgSize + threadIdx.x;

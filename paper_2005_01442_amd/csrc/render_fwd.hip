@@ -23,8 +23,11 @@ __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfCon
   const bool ert_on = mc.ert > 0.0f && mc.ert < 1.0f;
   RayLight rl;
   if constexpr (SHADE) rl = ray_light(sc, r.d);
+  // lighting and pre-classification hold more registers: two box rows in
+  // flight per lane
+  constexpr int kFillBatch = SHADE || F == 2 ? 2 : 4;
   auto prep = [&](bool want, float px, float py, float pz) {
-    if (box.cells) vbox_prepare<DT>(box, rs, v, r, want, px, py, pz);
+    if (box.cells) vbox_prepare<DT, kFillBatch>(box, rs, v, r, want, px, py, pz);
   };
   auto visit = [&](int, float px, float py, float pz) -> bool {
     Classified q;
@@ -81,6 +84,11 @@ __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfCon
 #ifndef VR_FWD_MAX_WAVES
 #define VR_FWD_MAX_WAVES 3
 #endif
+#ifndef VR_OCC_LDS
+#define VR_OCC_LDS 1
+#endif
+constexpr uint32_t kLdsPerCu = 160u * 1024u;  // gfx950
+constexpr uint32_t kFwdWgPerCu = 3;
 template <int DT, bool SHADE, int F>
 __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(SHADE ? VR_FWD_MAX_WAVES : 1, VR_FWD_MAX_WAVES)))
 void k_render(const RenderArgs args) {
@@ -89,6 +97,8 @@ void k_render(const RenderArgs args) {
   SuperTile st = tile_of(a.order, blockIdx.x, a.W, a.H, a.n_views, a.chunk_edge);
   if (!st.valid) return;  // uniform over the workgroup
   TfShared s = carve_tf(lds, a.tf.K);
+  if (a.occ_lds_words > 0)
+    stage_occupancy(s, a.vol, lds + vbox_lds_offset(a.tf.K) + vbox_lds_bytes(), a.occ_lds_words);
   load_tf(s, a.tf);
   int col, row;
   pixel_of(st.sx, st.sy, col, row);
@@ -229,6 +239,16 @@ hipError_t launch_render(const RenderArgs &a0, hipStream_t s) {
   const uint32_t with_box = vbox_lds_offset(a.tf.K) + vbox_lds_bytes();
   a.use_box = with_box <= max_lds_per_workgroup() ? 1 : 0;
   if (a.use_box) lds = with_box;
+  // the occupancy bits join the LDS state when three workgroups still fit
+  // on a compute unit
+  a.occ_lds_words = 0;
+  if (VR_OCC_LDS && a.use_box && a.vol.occ) {
+    const int64_t words = ((int64_t)a.vol.nbx * a.vol.nby * a.vol.nbz + 31) / 32;
+    if ((int64_t)lds + words * 4 <= (int64_t)(kLdsPerCu / kFwdWgPerCu)) {
+      a.occ_lds_words = (int32_t)words;
+      lds += (uint32_t)words * 4u;
+    }
+  }
   if (a.vol.dtype != kU16 && a.vol.dtype != kI16 && a.vol.dtype != kF32) return hipErrorInvalidValue;
   if (a.shaded) return launch_render_as<true, 0>(a, grid, lds, s);
   if (a.filter == 1) return launch_render_as<false, 1>(a, grid, lds, s);

@@ -30,15 +30,29 @@ constexpr int kDefaultChunkEdge = 4;  // super-tiles per chunk edge (XCD mapping
 
 enum Dtype : int32_t { kU16 = 0, kI16 = 1, kF32 = 2 };
 
-// Wavefront-wide min / max, returned as a uniform (scalar) value.
+// Wavefront-wide min / max over all 64 lanes (every lane active), returned as
+// a uniform (scalar) value: a butterfly inside each row of 16 lanes through
+// DPP lane permutations (quad_perm [1,0,3,2], quad_perm [2,3,0,1],
+// row_half_mirror, row_mirror: VALU only, no LDS round trips), then the four
+// row results combined on the scalar unit.
+constexpr int kDppQuadSwap1 = 0xB1, kDppQuadSwap2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+
 __device__ inline int wave_min_i32(int x) {
-  for (int off = 32; off > 0; off >>= 1) x = min(x, __shfl_xor(x, off, kWaveSize));
-  return __builtin_amdgcn_readfirstlane(x);
+  x = min(x, __builtin_amdgcn_mov_dpp(x, kDppQuadSwap1, 0xF, 0xF, false));
+  x = min(x, __builtin_amdgcn_mov_dpp(x, kDppQuadSwap2, 0xF, 0xF, false));
+  x = min(x, __builtin_amdgcn_mov_dpp(x, kDppHalfMirror, 0xF, 0xF, false));
+  x = min(x, __builtin_amdgcn_mov_dpp(x, kDppMirror, 0xF, 0xF, false));
+  return min(min(__builtin_amdgcn_readlane(x, 0), __builtin_amdgcn_readlane(x, 16)),
+             min(__builtin_amdgcn_readlane(x, 32), __builtin_amdgcn_readlane(x, 48)));
 }
 
 __device__ inline int wave_max_i32(int x) {
-  for (int off = 32; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off, kWaveSize));
-  return __builtin_amdgcn_readfirstlane(x);
+  x = max(x, __builtin_amdgcn_mov_dpp(x, kDppQuadSwap1, 0xF, 0xF, false));
+  x = max(x, __builtin_amdgcn_mov_dpp(x, kDppQuadSwap2, 0xF, 0xF, false));
+  x = max(x, __builtin_amdgcn_mov_dpp(x, kDppHalfMirror, 0xF, 0xF, false));
+  x = max(x, __builtin_amdgcn_mov_dpp(x, kDppMirror, 0xF, 0xF, false));
+  return max(max(__builtin_amdgcn_readlane(x, 0), __builtin_amdgcn_readlane(x, 16)),
+             max(__builtin_amdgcn_readlane(x, 32), __builtin_amdgcn_readlane(x, 48)));
 }
 
 
@@ -59,6 +73,9 @@ struct VolConst {
   int32_t nbx, nby, nbz, edge;
   int32_t edge_shift;       // log2(edge)
   int32_t row_even;         // nx even: every x-row starts at an even element
+  // per-launch block occupancy under the TF, bit b % 32 of word b / 32
+  // (nullptr: decided from minmax and the TF on the fly)
+  const uint32_t *occ = nullptr;
 };
 
 struct TfConst {
@@ -79,10 +96,14 @@ struct MarchConst {
 // extinction nodes (block occupancy in O(1)).  Carved out of dynamic LDS,
 // sized by K.
 // ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
 struct TfShared {
   float4 *node;                // K nodes (r, g, b, sigma)
   int32_t *pref;               // K + 1: pref[j] = #{i < j : sigma_i != 0}
   unsigned long long *mask;    // ceil(K / 64) ballot words
+  lds_u32 *occ;                // LDS copy of VolConst::occ when occ_lds
+  bool occ_lds;
 };
 
 __host__ __device__ inline uint32_t tf_lds_bytes(int K) {
@@ -98,6 +119,8 @@ __device__ inline TfShared carve_tf(char *base, int K) {
   s.pref = reinterpret_cast<int32_t *>(base + (uint32_t)K * 16u);
   s.mask = reinterpret_cast<unsigned long long *>(base + (uint32_t)K * 16u +
                                                   ((((uint32_t)K + 1u) * 4u + 7u) & ~7u));
+  s.occ = nullptr;
+  s.occ_lds = false;
   return s;
 }
 
@@ -287,19 +310,27 @@ template <> struct Vox<kI16> {
   }
   // the dwordx3 window of the row starting at e lies inside the buffer
   __device__ static inline bool window_ok(uint32_t e, uint32_t nvox) { return (e & ~1u) + 6u <= nvox; }
-  // 16 consecutive voxels from element e (9-dword window from e & ~1)
+  // 16 consecutive voxels from element e: the 9-dword window from e & ~1,
+  // loaded by row16_load and converted by row16_unpack (so that a caller can
+  // keep several rows in flight)
   __device__ static inline bool row16_ok(uint32_t e, uint32_t nvox) { return (e & ~1u) + 18u <= nvox; }
-  __device__ static inline void row16(__amdgpu_buffer_rsrc_t r, uint32_t e, float t[16]) {
-    const uint32_t b = (e & ~1u) * 2u, sh = (e & 1u) * 16u;
-    const u32x4 p = __builtin_amdgcn_raw_buffer_load_b128(r, b, 0, 0);
-    const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(r, b + 16u, 0, 0);
-    const uint32_t z = __builtin_amdgcn_raw_buffer_load_b32(r, b + 32u, 0, 0);
-    const uint32_t d[9] = {p.x, p.y, p.z, p.w, q.x, q.y, q.z, q.w, z};
+  struct Raw {
+    u32x4 p, q;
+    uint32_t z;
+  };
+  __device__ static inline Raw row16_load(__amdgpu_buffer_rsrc_t r, uint32_t e) {
+    const uint32_t b = (e & ~1u) * 2u;
+    return Raw{__builtin_amdgcn_raw_buffer_load_b128(r, b, 0, 0), __builtin_amdgcn_raw_buffer_load_b128(r, b + 16u, 0, 0),
+               __builtin_amdgcn_raw_buffer_load_b32(r, b + 32u, 0, 0)};
+  }
+  __device__ static inline void row16_unpack(const Raw &w, uint32_t e, float t[16]) {
+    const uint32_t sh = (e & 1u) * 16u;
+    const uint32_t d[9] = {w.p.x, w.p.y, w.p.z, w.p.w, w.q.x, w.q.y, w.q.z, w.q.w, w.z};
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      uint32_t w = __builtin_amdgcn_alignbit(d[j + 1], d[j], sh);
-      t[2 * j] = (float)(int16_t)(w & 0xffffu);
-      t[2 * j + 1] = (float)((int32_t)w >> 16);
+      uint32_t x = __builtin_amdgcn_alignbit(d[j + 1], d[j], sh);
+      t[2 * j] = (float)(int16_t)(x & 0xffffu);
+      t[2 * j + 1] = (float)((int32_t)x >> 16);
     }
   }
 };
@@ -332,17 +363,16 @@ template <> struct Vox<kU16> {
   }
   __device__ static inline bool window_ok(uint32_t e, uint32_t nvox) { return (e & ~1u) + 6u <= nvox; }
   __device__ static inline bool row16_ok(uint32_t e, uint32_t nvox) { return (e & ~1u) + 18u <= nvox; }
-  __device__ static inline void row16(__amdgpu_buffer_rsrc_t r, uint32_t e, float t[16]) {
-    const uint32_t b = (e & ~1u) * 2u, sh = (e & 1u) * 16u;
-    const u32x4 p = __builtin_amdgcn_raw_buffer_load_b128(r, b, 0, 0);
-    const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(r, b + 16u, 0, 0);
-    const uint32_t z = __builtin_amdgcn_raw_buffer_load_b32(r, b + 32u, 0, 0);
-    const uint32_t d[9] = {p.x, p.y, p.z, p.w, q.x, q.y, q.z, q.w, z};
+  using Raw = Vox<kI16>::Raw;
+  __device__ static inline Raw row16_load(__amdgpu_buffer_rsrc_t r, uint32_t e) { return Vox<kI16>::row16_load(r, e); }
+  __device__ static inline void row16_unpack(const Raw &w, uint32_t e, float t[16]) {
+    const uint32_t sh = (e & 1u) * 16u;
+    const uint32_t d[9] = {w.p.x, w.p.y, w.p.z, w.p.w, w.q.x, w.q.y, w.q.z, w.q.w, w.z};
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      uint32_t w = __builtin_amdgcn_alignbit(d[j + 1], d[j], sh);
-      t[2 * j] = (float)(w & 0xffffu);
-      t[2 * j + 1] = (float)(w >> 16);
+      uint32_t x = __builtin_amdgcn_alignbit(d[j + 1], d[j], sh);
+      t[2 * j] = (float)(x & 0xffffu);
+      t[2 * j + 1] = (float)(x >> 16);
     }
   }
 };
@@ -369,10 +399,19 @@ template <> struct Vox<kF32> {
   }
   __device__ static inline bool window_ok(uint32_t, uint32_t) { return true; }
   __device__ static inline bool row16_ok(uint32_t, uint32_t) { return true; }
-  __device__ static inline void row16(__amdgpu_buffer_rsrc_t r, uint32_t e, float t[16]) {
+  struct Raw {
+    u32x4 a[4];
+  };
+  __device__ static inline Raw row16_load(__amdgpu_buffer_rsrc_t r, uint32_t e) {
+    Raw w;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w.a[j] = __builtin_amdgcn_raw_buffer_load_b128(r, (e + 4u * j) * 4u, 0, 0);
+    return w;
+  }
+  __device__ static inline void row16_unpack(const Raw &w, uint32_t, float t[16]) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, (e + 4u * j) * 4u, 0, 0));
+      const f32x4 v = __builtin_bit_cast(f32x4, w.a[j]);
       t[4 * j] = v.x;
       t[4 * j + 1] = v.y;
       t[4 * j + 2] = v.z;
@@ -642,33 +681,60 @@ struct ValBox {
   bool valid;
 };
 
-template <int DT>
+// kBatch rows per lane are loaded before any is stored (all of them by
+// default; kernels short of registers take fewer).
+template <int DT, int kBatch = (kVBox * kVBox + kWaveSize - 1) / kWaveSize>
 __device__ inline void vbox_fill(ValBox &b, __amdgpu_buffer_rsrc_t rs, const VolConst &v) {
+  constexpr int kRows = kVBox * kVBox;
+  constexpr int kPer = (kRows + kWaveSize - 1) / kWaveSize;  // rows per lane
   const int lane = threadIdx.x % kWaveSize;
   const uint32_t nvox = (uint32_t)v.nx * (uint32_t)v.ny * (uint32_t)v.nz;
-#pragma unroll 1
-  for (int row = lane; row < kVBox * kVBox; row += kWaveSize) {
-    const int cy = row % kVBox, cz = row / kVBox;
-    const uint32_t y = (uint32_t)min(max(b.oy + cy, 0), v.ny - 1);
-    const uint32_t z = (uint32_t)min(max(b.oz + cz, 0), v.nz - 1);
-    const uint32_t rowbase = (z * (uint32_t)v.ny + y) * (uint32_t)v.nx;
-    float t[16];  // a 16-voxel window; the first kVBox are stored
-    if (b.ox >= 0 && b.ox + 15 <= v.nx - 1 && Vox<DT>::row16_ok(rowbase + (uint32_t)b.ox, nvox)) {
-      Vox<DT>::row16(rs, rowbase + (uint32_t)b.ox, t);
-    } else {
+  const bool x_in = b.ox >= 0 && b.ox + 15 <= v.nx - 1;
+  auto batch = [&](int j0) {
+    // first the 16-voxel windows of the batch's rows, so that their loads
+    // are in flight together (every load is bounds-checked by the hardware,
+    // so the windows of rows that take the clamped path below are harmless)
+    uint32_t base[kBatch];
+    typename Vox<DT>::Raw raw[kBatch];
 #pragma unroll
-      for (int i = 0; i < kVBox; ++i) t[i] = Vox<DT>::one(rs, rowbase + (uint32_t)min(max(b.ox + i, 0), v.nx - 1));
+    for (int j = 0; j < kBatch; ++j) {
+      const int row = min(lane + (j0 + j) * kWaveSize, kRows - 1);
+      const uint32_t y = (uint32_t)min(max(b.oy + row % kVBox, 0), v.ny - 1);
+      const uint32_t z = (uint32_t)min(max(b.oz + row / kVBox, 0), v.nz - 1);
+      base[j] = (z * (uint32_t)v.ny + y) * (uint32_t)v.nx;
+      raw[j] = Vox<DT>::row16_load(rs, base[j] + (uint32_t)max(b.ox, 0));
     }
-    float2 *dst = reinterpret_cast<float2 *>(b.cells + cz * kVBoxZ + cy * kVBox);
 #pragma unroll
-    for (int j = 0; j < kVBox / 2; ++j) dst[j] = make_float2(t[2 * j], t[2 * j + 1]);
+    for (int j = 0; j < kBatch; ++j) {
+      const int row = lane + (j0 + j) * kWaveSize;
+      if (j0 + j < kPer && row < kRows) {
+        const uint32_t rowbase = base[j];
+        float t[16];  // a 16-voxel window; the first kVBox are stored
+        if (x_in && Vox<DT>::row16_ok(rowbase + (uint32_t)b.ox, nvox)) {
+          Vox<DT>::row16_unpack(raw[j], rowbase + (uint32_t)b.ox, t);
+        } else {
+#pragma unroll
+          for (int i = 0; i < kVBox; ++i)
+            t[i] = Vox<DT>::one(rs, rowbase + (uint32_t)min(max(b.ox + i, 0), v.nx - 1));
+        }
+        float2 *dst = reinterpret_cast<float2 *>(b.cells + (row / kVBox) * kVBoxZ + (row % kVBox) * kVBox);
+#pragma unroll
+        for (int i = 0; i < kVBox / 2; ++i) dst[i] = make_float2(t[2 * i], t[2 * i + 1]);
+      }
+    }
+  };
+  if constexpr (kBatch >= kPer) {
+    batch(0);
+  } else {
+#pragma unroll 1
+    for (int j0 = 0; j0 < kPer; j0 += kBatch) batch(j0);
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
 }
 
 // Wavefront-wide, before the samples of a step.
-template <int DT>
+template <int DT, int kBatch = (kVBox * kVBox + kWaveSize - 1) / kWaveSize>
 __device__ inline void vbox_prepare(ValBox &b, __amdgpu_buffer_rsrc_t rs, const VolConst &v, const Ray &r,
                                     bool want, float px, float py, float pz) {
   int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
@@ -711,7 +777,7 @@ __device__ inline void vbox_prepare(ValBox &b, __amdgpu_buffer_rsrc_t rs, const 
   b.ox = __builtin_amdgcn_readfirstlane(org[0]);
   b.oy = __builtin_amdgcn_readfirstlane(org[1]);
   b.oz = __builtin_amdgcn_readfirstlane(org[2]);
-  vbox_fill<DT>(b, rs, v);
+  vbox_fill<DT, kBatch>(b, rs, v);
   b.valid = true;
 }
 
@@ -880,10 +946,21 @@ __device__ inline int block_of(const VolConst &v, float px, float py, float pz, 
   return bc[0] + v.nbx * (bc[1] + v.nby * bc[2]);
 }
 
+// 1 / x in FP64: the hardware reciprocal refined by two Newton steps (a few
+// ulp of error, far inside the margins of leap_target).
+__device__ inline double recip64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
 // Every lattice index k' with k <= k' < result samples strictly inside the
 // current block: positions fl(fma(s, d, p0)) are monotone in s per axis, and
 // the bound is pulled in by 2^-9 voxel (more than the fp32 rounding of any
-// position below 8192) and by one more full step.  Computed in FP64.
+// position below 8192) and by one more full step.  Computed in FP64 (the
+// quotients through recip64: errors of order 1e-16 relative).
 __device__ inline int leap_target(const VolConst &v, const Ray &r, const int bc[3], float step, int k) {
   const int nb[3] = {v.nbx, v.nby, v.nbz};
   double smin = INFINITY;
@@ -893,15 +970,15 @@ __device__ inline int leap_target(const VolConst &v, const Ray &r, const int bc[
     double pa = (double)r.p0[a];
     if (da > 0.0 && bc[a] < nb[a] - 1) {
       double bound = (double)((bc[a] + 1) << v.edge_shift) - 0x1p-9;
-      smin = fmin(smin, (bound - pa) / da);
+      smin = fmin(smin, (bound - pa) * recip64(da));
     } else if (da < 0.0 && bc[a] > 0) {
       double bound = (double)(bc[a] << v.edge_shift) + 0x1p-9;
-      smin = fmin(smin, (bound - pa) / da);
+      smin = fmin(smin, (bound - pa) * recip64(da));
     }
   }
   if (!(smin < 1e30)) return 0x7fffffff;
   // first j with s0 + j step >= smin, minus one step of margin
-  double jf = ceil((smin - (double)r.s0) / (double)step) - 1.0;
+  double jf = ceil((smin - (double)r.s0) * recip64((double)step)) - 1.0;
   if (jf > 2.0e9) return 0x7fffffff;
   int kt = r.k0 + (int)fmax(jf, 0.0);
   return max(kt, k + 1);
@@ -981,8 +1058,18 @@ __device__ inline void walk(const VolConst &v, const TfShared &s, const TfConst 
 }
 
 __device__ inline bool block_occupied(const VolConst &v, const TfShared &s, const TfConst &tf, int b) {
+  if (s.occ_lds) return (s.occ[b >> 5] >> (b & 31)) & 1u;
+  if (v.occ) return (v.occ[b >> 5] >> (b & 31)) & 1u;
   float2 mm = v.minmax[b];
   return range_occupied(s, tf.K, tf.v0, tf.scale, mm.x, mm.y);
+}
+
+// Copy the occupancy bits of a launch into LDS at `dst` (all threads of the
+// workgroup; visible after the next barrier).
+__device__ inline void stage_occupancy(TfShared &s, const VolConst &v, char *dst, int words) {
+  s.occ = (lds_u32 *)dst;
+  s.occ_lds = true;
+  for (int j = threadIdx.x; j < words; j += kWgSize) s.occ[j] = v.occ[j];
 }
 
 // ---------------------------------------------------------------------------

@@ -23,7 +23,7 @@ struct RenderArgs {
   int32_t use_box;                 // stage volume boxes in LDS (set at launch)
   int32_t shaded;                  // nonzero: local lighting with `shade`
   int32_t filter;                  // VR_FILTER_*
-  int32_t pad3;
+  int32_t occ_lds_words;           // > 0: stage vol.occ in LDS (set at launch)
   ShadeConst shade;
   CamConst cams[kMaxCamsPerLaunch];
 };
@@ -80,6 +80,8 @@ int32_t *make_tile_order(const RenderArgs &a, hipStream_t s);
 hipError_t launch_render_backward(const BackwardArgs &a, hipStream_t s);
 hipError_t launch_block_minmax(const VolConst &v, float2 *out, hipStream_t s);
 hipError_t launch_block_occupancy(const VolConst &v, const TfConst &tf, uint8_t *occ, hipStream_t s);
+// The same decisions packed 32 blocks to a word (ceil(nb / 32) words).
+hipError_t launch_occupancy_bits(const VolConst &v, const TfConst &tf, uint32_t *bits, hipStream_t s);
 hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s);
 // Catmull-Rom samples leave their taps' range by at most this fraction of it.
 constexpr float kCatmullRomWiden = 0.4765625f;  // ((1 + 2/8)^3 - 1) / 2
