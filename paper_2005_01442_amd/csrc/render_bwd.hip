@@ -122,7 +122,7 @@ __device__ inline void box_prepare(GradBox &b, float *grad, const VolConst &v, c
   int org[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    float da = __shfl(r.d[a], first, kWaveSize);
+    const float da = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, r.d[a]), first));
     int oa = da >= 0.0f ? mn[a] : mx[a] - kBox + 1;
     org[a] = max(oa, 0);
   }

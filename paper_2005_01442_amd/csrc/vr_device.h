@@ -768,7 +768,7 @@ __device__ inline void vbox_prepare(ValBox &b, __amdgpu_buffer_rsrc_t rs, const 
   int org[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    float da = __shfl(r.d[a], first, kWaveSize);
+    const float da = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, r.d[a]), first));
     org[a] = da >= 0.0f ? mn[a] : mx[a] - kVBox + 1;
   }
   // the lanes may still read the previous contents: order the refill after them
@@ -1001,7 +1001,8 @@ __device__ inline bool block_occupied(const VolConst &v, const TfShared &s, cons
 // block that is empty under the TF (such a sample would add exactly zero).
 // When no lane has a sample to evaluate, the wavefront leaps to the smallest
 // index any lane may need: its next lattice start, or the first index that
-// may leave its empty block.  prep(want, px, py, pz) runs on every lane of the
+// may leave its empty block (the lane sits out until then, without looking
+// at its samples).  prep(want, px, py, pz) runs on every lane of the
 // wavefront before the samples of a step (for wavefront-wide staging);
 // visit(k, px, py, pz) evaluates one sample and returns false to stop the ray.
 // post() runs on every lane after the samples of a step.
@@ -1022,11 +1023,12 @@ __device__ inline void walk(const VolConst &v, const TfShared &s, const TfConst 
   bool alive = r.hit;
   int k = wave_min_i32(kb);
   const int kend = wave_max_i32(ke);
+  int kfree = kb;  // indices below kfree: before the ray, or left in an empty block
   int cur_block = -1;
   bool cur_occ = false;
   int bc[3] = {0, 0, 0};
   while (k < kend) {
-    const bool in = alive && k >= kb && k < ke;
+    const bool in = alive && k >= kfree && k < ke;
     bool want = in;
     float px = 0.0f, py = 0.0f, pz = 0.0f;
     if (in) {
@@ -1041,11 +1043,8 @@ __device__ inline void walk(const VolConst &v, const TfShared &s, const TfConst 
       }
     }
     if (__ballot(want) == 0ull) {
-      int prop = 0x7fffffff;
-      if (in)
-        prop = leap_target(v, r, bc, mc.step, k);
-      else if (alive && k < kb)
-        prop = kb;
+      if (in) kfree = leap_target(v, r, bc, mc.step, k);
+      const int prop = alive && k < ke ? kfree : 0x7fffffff;
       const int m = wave_min_i32(prop);
       k = m > k + 1 ? m : k + 1;
       continue;
