@@ -12,6 +12,10 @@
 #include "vr.h"
 #include "vr_internal.h"
 
+#ifndef VR_EMPTY_RADIUS
+#define VR_EMPTY_RADIUS 2
+#endif
+
 struct vr_blocks {
   const void *data;
   int32_t dtype;
@@ -339,18 +343,23 @@ static vr_status render_views(RenderArgs &a, const vr_camera *cams, int32_t n_ca
   // the blocks' occupancy under this TF, once for all views (without it the
   // kernels decide from min/max and the TF on every block change)
   uint32_t *bits = nullptr;
+  bool radius = false;
   if (!preint && a.mc.skip && a.vol.minmax) {
     const int64_t words = ((int64_t)a.vol.nbx * a.vol.nby * a.vol.nbz + 31) / 32;
-    if (hipMallocAsync(reinterpret_cast<void **>(&bits), (size_t)words * 4, (hipStream_t)stream) != hipSuccess) {
+    if (hipMallocAsync(reinterpret_cast<void **>(&bits), (size_t)words * 12, (hipStream_t)stream) != hipSuccess) {
       (void)hipGetLastError();
       bits = nullptr;
     } else if (launch_occupancy_bits(a.vol, a.tf, bits, (hipStream_t)stream) != hipSuccess) {
       (void)hipGetLastError();
       (void)hipFreeAsync(bits, (hipStream_t)stream);
       bits = nullptr;
+    } else {
+      radius = launch_empty_radius_bits(a.vol, bits, (hipStream_t)stream) == hipSuccess;
+      if (!radius) (void)hipGetLastError();
     }
   }
   a.vol.occ = bits;
+  a.vol.occ_radius = radius ? VR_EMPTY_RADIUS : 0;
   for (int32_t v0 = 0; v0 < n_cams; v0 += kMaxCamsPerLaunch) {
     const int32_t n = std::min(kMaxCamsPerLaunch, n_cams - v0);
     for (int32_t i = 0; i < n; ++i) check_camera(&cams[v0 + i], &a.cams[i]);
@@ -367,6 +376,7 @@ static vr_status render_views(RenderArgs &a, const vr_camera *cams, int32_t n_ca
   }
   if (bits) (void)hipFreeAsync(bits, (hipStream_t)stream);
   a.vol.occ = nullptr;
+  a.vol.occ_radius = 0;
   return VR_OK;
 }
 

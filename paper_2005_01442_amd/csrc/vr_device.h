@@ -76,6 +76,10 @@ struct VolConst {
   // per-launch block occupancy under the TF, bit b % 32 of word b / 32
   // (nullptr: decided from minmax and the TF on the fly)
   const uint32_t *occ = nullptr;
+  // nonzero: occ holds three planes of ceil(nb / 32) words -- occupancy,
+  // then "every block within Chebyshev distance 1 is empty", then distance 2;
+  // leaps use cubes of blocks up to this radius
+  int32_t occ_radius = 0;
 };
 
 struct TfConst {
@@ -961,18 +965,23 @@ __device__ inline double recip64(double x) {
 // the bound is pulled in by 2^-9 voxel (more than the fp32 rounding of any
 // position below 8192) and by one more full step.  Computed in FP64 (the
 // quotients through recip64: errors of order 1e-16 relative).
-__device__ inline int leap_target(const VolConst &v, const Ray &r, const int bc[3], float step, int k) {
+//
+// With rad > 0 every block within Chebyshev distance rad of the current one
+// is empty too, and the bound is the exit from that cube of blocks (on a
+// side where the cube reaches the edge of the grid the ray leaves the volume
+// first).
+__device__ inline int leap_target(const VolConst &v, const Ray &r, const int bc[3], float step, int k, int rad = 0) {
   const int nb[3] = {v.nbx, v.nby, v.nbz};
   double smin = INFINITY;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     double da = (double)r.d[a];
     double pa = (double)r.p0[a];
-    if (da > 0.0 && bc[a] < nb[a] - 1) {
-      double bound = (double)((bc[a] + 1) << v.edge_shift) - 0x1p-9;
+    if (da > 0.0 && bc[a] + rad < nb[a] - 1) {
+      double bound = (double)((bc[a] + rad + 1) << v.edge_shift) - 0x1p-9;
       smin = fmin(smin, (bound - pa) * recip64(da));
-    } else if (da < 0.0 && bc[a] > 0) {
-      double bound = (double)(bc[a] << v.edge_shift) + 0x1p-9;
+    } else if (da < 0.0 && bc[a] - rad > 0) {
+      double bound = (double)((bc[a] - rad) << v.edge_shift) + 0x1p-9;
       smin = fmin(smin, (bound - pa) * recip64(da));
     }
   }
@@ -994,6 +1003,7 @@ __device__ inline void lattice_point(const Ray &r, float step, int k, float &px,
 
 // Blocks' minmax and TF decide occupancy.
 __device__ inline bool block_occupied(const VolConst &v, const TfShared &s, const TfConst &tf, int b);
+__device__ inline int empty_radius(const VolConst &v, int b);
 
 // Walk one ray's lattice with the whole wavefront in step: all lanes look at
 // the same index k (a thin slab of the tile's rays).  A lane sits out when k
@@ -1043,7 +1053,7 @@ __device__ inline void walk(const VolConst &v, const TfShared &s, const TfConst 
       }
     }
     if (__ballot(want) == 0ull) {
-      if (in) kfree = leap_target(v, r, bc, mc.step, k);
+      if (in) kfree = leap_target(v, r, bc, mc.step, k, empty_radius(v, cur_block));
       const int prop = alive && k < ke ? kfree : 0x7fffffff;
       const int m = wave_min_i32(prop);
       k = m > k + 1 ? m : k + 1;
@@ -1061,6 +1071,17 @@ __device__ inline bool block_occupied(const VolConst &v, const TfShared &s, cons
   if (v.occ) return (v.occ[b >> 5] >> (b & 31)) & 1u;
   float2 mm = v.minmax[b];
   return range_occupied(s, tf.K, tf.v0, tf.scale, mm.x, mm.y);
+}
+
+// Chebyshev radius (0, 1 or 2 blocks) around the empty block b within which
+// every block is empty: two more bit planes after the occupancy bits, when
+// the launch has them (else 0).
+__device__ inline int empty_radius(const VolConst &v, int b) {
+  if (!v.occ || !v.occ_radius) return 0;
+  const int64_t words = ((int64_t)v.nbx * v.nby * v.nbz + 31) / 32;
+  const uint32_t w1 = v.occ[words + (b >> 5)], w2 = v.occ[2 * words + (b >> 5)];
+  const uint32_t m = 1u << (b & 31);
+  return (v.occ_radius >= 2 && (w2 & m)) ? 2 : ((w1 & m) ? 1 : 0);
 }
 
 // Copy the occupancy bits of a launch into LDS at `dst` (all threads of the

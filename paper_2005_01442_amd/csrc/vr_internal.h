@@ -82,6 +82,8 @@ hipError_t launch_block_minmax(const VolConst &v, float2 *out, hipStream_t s);
 hipError_t launch_block_occupancy(const VolConst &v, const TfConst &tf, uint8_t *occ, hipStream_t s);
 // The same decisions packed 32 blocks to a word (ceil(nb / 32) words).
 hipError_t launch_occupancy_bits(const VolConst &v, const TfConst &tf, uint32_t *bits, hipStream_t s);
+// Planes 1 and 2 (empty within Chebyshev distance 1 and 2) after plane 0.
+hipError_t launch_empty_radius_bits(const VolConst &v, uint32_t *bits, hipStream_t s);
 hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s);
 // Catmull-Rom samples leave their taps' range by at most this fraction of it.
 constexpr float kCatmullRomWiden = 0.4765625f;  // ((1 + 2/8)^3 - 1) / 2

@@ -266,3 +266,42 @@ def test_empty_view_list_is_rejected():
     t = upload_tf(synth.tf1())
     with pytest.raises((vr.VrError, IndexError)):
         vr.vr_render(vol, None, [], t, 0.5)
+
+
+def _islands(dims_xyz, seed, n=7, edge_hugging=True):
+    """Zero volume with a few small dense cubes (values 1000-3000), some touching
+    the volume's faces: long runs of empty blocks between them, so leaps cross
+    cubes of empty blocks (and reach the edge of the block grid)."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = dims_xyz
+    vol = np.zeros((nz, ny, nx), np.uint16)
+    for i in range(n):
+        s = int(rng.integers(3, 9))
+        lo = [int(rng.integers(0, d - s)) for d in (nx, ny, nz)]
+        if edge_hugging and i < 2:
+            lo[i] = 0 if i == 0 else dims_xyz[i] - s
+        x, y, z = lo
+        vol[z:z + s, y:y + s, x:x + s] = rng.integers(1000, 3000, size=(s, s, s))
+    return vol
+
+
+@pytest.mark.parametrize("edge", [4, 8, 16])
+def test_sparse_islands_skip_is_bit_identical(edge):
+    """Sparse occupancy: skipping (per-render occupancy bits, leaps across
+    cubes of empty blocks) must give exactly the no-skip image."""
+    dims = (150, 136, 120)
+    vol = _islands(dims, 90 + edge)
+    cams = (synth.orbit_cameras(dims, 5, 91, 50.0, 80, 72) + [synth.ortho_axis_camera(150, 80, 72)])
+    c = synth.orbit_camera(dims, np.array([0.6, -0.5, 0.62]), 70.0, 80, 72)
+    c.eye = np.array([70.2, 60.9, 55.3])  # inside the volume
+    cams.append(c)
+    tf = synth.tf_from_points([(0, (0, 0, 0, 0)), (600, (0, 0, 0, 0)), (800, (1.0, 0.5, 0.2, 0.05)),
+                               (3000, (1, 1, 1, 0.2))], 256, 0.0, 4080.0)
+    v = upload_volume(vol)
+    log(f"islands {dims} edge {edge}, {len(cams)} views")
+    for ert in (0.0, 0.99):
+        a, ca = gpu_render(vol, cams, tf, 0.5, ert=ert, use_skip=False, counters=True, vol=v)
+        b, cb = gpu_render(vol, cams, tf, 0.5, ert=ert, use_skip=True, counters=True, vol=v, block_edge=edge)
+        assert np.array_equal(a, b), f"ert {ert}: max diff {np.abs(a - b).max():.3e}"
+        assert cb[0] < ca[0] / 4  # most samples lie in empty blocks
+        log(f"ert {ert}: evaluated {cb[0]} of {ca[0]}")
