@@ -13,7 +13,7 @@
 #include "vr_internal.h"
 
 #ifndef VR_EMPTY_RADIUS
-#define VR_EMPTY_RADIUS 2
+#define VR_EMPTY_RADIUS 3
 #endif
 
 struct vr_blocks {
@@ -344,17 +344,19 @@ static vr_status render_views(RenderArgs &a, const vr_camera *cams, int32_t n_ca
   // kernels decide from min/max and the TF on every block change)
   uint32_t *bits = nullptr;
   bool radius = false;
-  if (!preint && a.mc.skip && a.vol.minmax) {
+  if (a.mc.skip && a.vol.minmax) {
     const int64_t words = ((int64_t)a.vol.nbx * a.vol.nby * a.vol.nbz + 31) / 32;
-    if (hipMallocAsync(reinterpret_cast<void **>(&bits), (size_t)words * 12, (hipStream_t)stream) != hipSuccess) {
+    const int64_t rwords = ((int64_t)a.vol.nbx * a.vol.nby * a.vol.nbz + 15) / 16;
+    if (hipMallocAsync(reinterpret_cast<void **>(&bits), (size_t)(words + rwords) * 4, (hipStream_t)stream) !=
+        hipSuccess) {
       (void)hipGetLastError();
       bits = nullptr;
     } else if (launch_occupancy_bits(a.vol, a.tf, bits, (hipStream_t)stream) != hipSuccess) {
       (void)hipGetLastError();
       (void)hipFreeAsync(bits, (hipStream_t)stream);
       bits = nullptr;
-    } else {
-      radius = launch_empty_radius_bits(a.vol, bits, (hipStream_t)stream) == hipSuccess;
+    } else if (!preint) {  // (pre-integration leaps block by block: its cells span two blocks)
+      radius = launch_empty_radius(a.vol, bits, (hipStream_t)stream) == hipSuccess;
       if (!radius) (void)hipGetLastError();
     }
   }

@@ -106,19 +106,31 @@ hipError_t launch_occupancy_bits(const VolConst &v, const TfConst &tf, uint32_t 
   return hipGetLastError();
 }
 
-// Planes 1 and 2 of the occupancy bits: bit b set when every block within
-// Chebyshev distance 1 (2) of b is empty (tested on plane 0; outside the grid
-// counts as empty).  The blocks around a workgroup's 256 consecutive blocks
-// lie within kEmptyReach = 2 (1 + nbx + nbx nby) bit positions of them, so
-// the workgroup stages that window of plane 0 in LDS first.
+// The radius plane after the occupancy bits: 2 bits per block (16 blocks a
+// word), for an empty block b the largest r <= kEmptyRadiusMax such that
+// every block within Chebyshev distance r of b is empty (tested on the
+// occupancy bits; outside the grid counts as empty), 0 for occupied blocks.
+// The blocks around a workgroup's 256 consecutive blocks lie within
+// empty_reach bit positions of them, so the workgroup stages that window of
+// the occupancy bits in LDS first.
 __host__ __device__ inline int64_t empty_reach(const VolConst &v) {
-  return 2 * (1 + (int64_t)v.nbx + (int64_t)v.nbx * v.nby);
+  return kEmptyRadiusMax * (1 + (int64_t)v.nbx + (int64_t)v.nbx * v.nby);
 }
 __host__ __device__ inline int64_t empty_window_words(const VolConst &v) {
   return (kWgSize + 2 * empty_reach(v)) / 32 + 2;
 }
 
-__global__ __launch_bounds__(kWgSize) void k_empty_radius_bits(const VolConst v, uint32_t *bits) {
+// Bits 0..15 of x moved to the even positions 0, 2, .., 30.
+__device__ inline uint32_t spread16(uint32_t x) {
+  x &= 0xffffu;
+  x = (x | (x << 8)) & 0x00ff00ffu;
+  x = (x | (x << 4)) & 0x0f0f0f0fu;
+  x = (x | (x << 2)) & 0x33333333u;
+  x = (x | (x << 1)) & 0x55555555u;
+  return x;
+}
+
+__global__ __launch_bounds__(kWgSize) void k_empty_radius(const VolConst v, uint32_t *bits) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   uint32_t *win = reinterpret_cast<uint32_t *>(lds);
   const int64_t nb = (int64_t)v.nbx * v.nby * v.nbz;
@@ -129,42 +141,42 @@ __global__ __launch_bounds__(kWgSize) void k_empty_radius_bits(const VolConst v,
   for (int64_t j = threadIdx.x; j < nw; j += kWgSize) win[j] = w0 + j < words ? bits[w0 + j] : 0u;
   __syncthreads();
   const int64_t b = b0 + threadIdx.x;
-  bool e1 = false, e2 = false;
+  int rad = 0;
   if (b < nb) {
     const int bx = (int)(b % v.nbx), by = (int)((b / v.nbx) % v.nby), bz = (int)(b / ((int64_t)v.nbx * v.nby));
-    int near = 3;  // smallest Chebyshev distance of an occupied block, capped at 3
+    constexpr int R = kEmptyRadiusMax;
+    int near = R + 1;  // smallest Chebyshev distance of an occupied block, capped at R + 1
+    for (int dz = -R; dz <= R; ++dz)
+      for (int dy = -R; dy <= R; ++dy) {
+        const int y = by + dy, z = bz + dz;
+        if (y < 0 || z < 0 || y >= v.nby || z >= v.nbz) continue;
+        const int dyz = max(abs(dy), abs(dz));
 #pragma unroll
-    for (int dz = -2; dz <= 2; ++dz)
-#pragma unroll
-      for (int dy = -2; dy <= 2; ++dy)
-#pragma unroll
-        for (int dx = -2; dx <= 2; ++dx) {
-          const int x = bx + dx, y = by + dy, z = bz + dz;
-          if (x < 0 || y < 0 || z < 0 || x >= v.nbx || y >= v.nby || z >= v.nbz) continue;
+        for (int dx = -R; dx <= R; ++dx) {
+          const int x = bx + dx;
+          if (x < 0 || x >= v.nbx) continue;
           const int64_t q = x + (int64_t)v.nbx * (y + (int64_t)v.nby * z);
-          const int dist = max(max(abs(dx), abs(dy)), abs(dz));
-          if ((win[(q >> 5) - w0] >> (q & 31)) & 1u) near = min(near, dist);
+          if ((win[(q >> 5) - w0] >> (q & 31)) & 1u) near = min(near, max(dyz, abs(dx)));
         }
-    e1 = near > 1;
-    e2 = near > 2;
+      }
+    rad = near - 1 < 0 ? 0 : near - 1;
   }
-  const unsigned long long m1 = __ballot(e1), m2 = __ballot(e2);
+  const unsigned long long lo = __ballot(rad & 1), hi = __ballot(rad & 2);
   const int lane = threadIdx.x % kWaveSize;
-  if ((lane == 0 || lane == 32) && b < nb) {
-    bits[words + (b >> 5)] = lane == 0 ? (uint32_t)m1 : (uint32_t)(m1 >> 32);
-    bits[2 * words + (b >> 5)] = lane == 0 ? (uint32_t)m2 : (uint32_t)(m2 >> 32);
-  }
+  const int64_t rw = words + (b >> 4);
+  if ((lane & 15) == 0 && b < nb)
+    bits[rw] = spread16((uint32_t)(lo >> lane)) | (spread16((uint32_t)(hi >> lane)) << 1);
 }
 
-hipError_t launch_empty_radius_bits(const VolConst &v, uint32_t *bits, hipStream_t s) {
+hipError_t launch_empty_radius(const VolConst &v, uint32_t *bits, hipStream_t s) {
   const int64_t nb = (int64_t)v.nbx * v.nby * v.nbz;
   const int64_t lds = empty_window_words(v) * 4;
   if (lds > (int64_t)max_lds_per_workgroup()) return hipErrorInvalidValue;  // the caller leaps block by block
   const unsigned grid = (unsigned)((nb + kWgSize - 1) / kWgSize);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_empty_radius_bits),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_empty_radius),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_empty_radius_bits, dim3(grid), dim3(kWgSize), (uint32_t)lds, s, v, bits);
+  hipLaunchKernelGGL(k_empty_radius, dim3(grid), dim3(kWgSize), (uint32_t)lds, s, v, bits);
   return hipGetLastError();
 }
 

@@ -84,11 +84,17 @@ __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfCon
 #ifndef VR_FWD_MAX_WAVES
 #define VR_FWD_MAX_WAVES 3
 #endif
-#ifndef VR_OCC_LDS
-#define VR_OCC_LDS 1
-#endif
 constexpr uint32_t kLdsPerCu = 160u * 1024u;  // gfx950
 constexpr uint32_t kFwdWgPerCu = 3;
+
+// The occupancy bits join the LDS state (after the boxes) when three
+// workgroups still fit on a compute unit; else the kernels read them from
+// global memory.
+int32_t occupancy_lds_words(const RenderArgs &a, uint32_t lds) {
+  if (!a.use_box || !a.vol.occ) return 0;
+  const int64_t words = ((int64_t)a.vol.nbx * a.vol.nby * a.vol.nbz + 31) / 32;
+  return (int64_t)lds + words * 4 <= (int64_t)(kLdsPerCu / kFwdWgPerCu) ? (int32_t)words : 0;
+}
 template <int DT, bool SHADE, int F>
 __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(SHADE ? VR_FWD_MAX_WAVES : 1, VR_FWD_MAX_WAVES)))
 void k_render(const RenderArgs args) {
@@ -239,16 +245,8 @@ hipError_t launch_render(const RenderArgs &a0, hipStream_t s) {
   const uint32_t with_box = vbox_lds_offset(a.tf.K) + vbox_lds_bytes();
   a.use_box = with_box <= max_lds_per_workgroup() ? 1 : 0;
   if (a.use_box) lds = with_box;
-  // the occupancy bits join the LDS state when three workgroups still fit
-  // on a compute unit
-  a.occ_lds_words = 0;
-  if (VR_OCC_LDS && a.use_box && a.vol.occ) {
-    const int64_t words = ((int64_t)a.vol.nbx * a.vol.nby * a.vol.nbz + 31) / 32;
-    if ((int64_t)lds + words * 4 <= (int64_t)(kLdsPerCu / kFwdWgPerCu)) {
-      a.occ_lds_words = (int32_t)words;
-      lds += (uint32_t)words * 4u;
-    }
-  }
+  a.occ_lds_words = occupancy_lds_words(a, lds);
+  lds += (uint32_t)a.occ_lds_words * 4u;
   if (a.vol.dtype != kU16 && a.vol.dtype != kI16 && a.vol.dtype != kF32) return hipErrorInvalidValue;
   if (a.shaded) return launch_render_as<true, 0>(a, grid, lds, s);
   if (a.filter == 1) return launch_render_as<false, 1>(a, grid, lds, s);

@@ -119,8 +119,8 @@ __device__ inline float4 march_preint(const VolConst &v, const TfShared &s, cons
   bool alive = r.hit;
   int k = wave_min_i32(kb);
   const int kend = wave_max_i32(ke);
+  int kfree = kb;  // points below kfree: before the ray, or left in an empty block
   int cb = -1;
-  float2 cmm = make_float2(0.0f, 0.0f);
   bool cocc = false;
   int bc[3] = {0, 0, 0};
   int kprev = -0x7fffffff;
@@ -133,7 +133,7 @@ __device__ inline float4 march_preint(const VolConst &v, const TfShared &s, cons
     return reconstruct<DT>(rs, v, st);
   };
   while (k < kend) {
-    const bool in = alive && k >= kb && k < ke;
+    const bool in = alive && k >= kfree && k < ke;
     bool want = false;
     float px = 0.0f, py = 0.0f, pz = 0.0f;
     if (in) {
@@ -142,13 +142,15 @@ __device__ inline float4 march_preint(const VolConst &v, const TfShared &s, cons
         const int b = block_of(v, px, py, pz, bc);
         bool pair = cocc;
         if (b != cb) {
-          const float2 pmm = cmm;
-          const bool pocc = cocc, had = cb >= 0;
+          const int pb = cb;
+          const bool pocc = cocc;
           cb = b;
-          cmm = v.minmax[b];
-          cocc = range_occupied(s, tf.K, tf.v0, tf.scale, cmm.x, cmm.y);
-          pair = cocc || (had && (pocc || range_occupied(s, tf.K, tf.v0, tf.scale, fminf(pmm.x, cmm.x),
-                                                         fmaxf(pmm.y, cmm.y))));
+          cocc = block_occupied(v, s, tf, b);
+          // two empty blocks: the cell between them is empty only if the
+          // union of their ranges is
+          pair = cocc || pocc ||
+                 (pb >= 0 && range_occupied(s, tf.K, tf.v0, tf.scale, fminf(v.minmax[pb].x, v.minmax[b].x),
+                                            fmaxf(v.minmax[pb].y, v.minmax[b].y)));
         }
         want = k > kb && pair;
       } else {
@@ -157,10 +159,16 @@ __device__ inline float4 march_preint(const VolConst &v, const TfShared &s, cons
     }
     if (__ballot(want) == 0ull) {
       int prop = 0x7fffffff;
-      if (in)
-        prop = (mc.skip && !cocc) ? leap_target(v, r, bc, mc.step, k) : k + 1;
-      else if (alive && k < kb)
-        prop = kb;
+      if (in) {
+        if (mc.skip && !cocc) {
+          kfree = leap_target(v, r, bc, mc.step, k);
+          prop = kfree;
+        } else {
+          prop = k + 1;
+        }
+      } else if (alive && k < ke) {
+        prop = kfree;
+      }
       const int m = wave_min_i32(prop);
       k = m > k + 1 ? m : k + 1;
       continue;
@@ -197,6 +205,8 @@ __global__ __launch_bounds__(kWgSize) void k_render_preint(const RenderArgs args
   SuperTile st = tile_of(a.order, blockIdx.x, a.W, a.H, a.n_views, a.chunk_edge);
   if (!st.valid) return;  // uniform over the workgroup
   TfShared s = carve_tf(lds, a.tf.K);
+  if (a.occ_lds_words > 0)
+    stage_occupancy(s, a.vol, lds + vbox_lds_offset(a.tf.K) + vbox_lds_bytes(), a.occ_lds_words);
   load_tf(s, a.tf);
   int col, row;
   pixel_of(st.sx, st.sy, col, row);
@@ -232,6 +242,8 @@ hipError_t launch_render_preint(const RenderArgs &a0, const float4 *tab, hipStre
   const uint32_t with_box = vbox_lds_offset(a.tf.K) + vbox_lds_bytes();
   a.use_box = with_box <= max_lds_per_workgroup() ? 1 : 0;
   if (a.use_box) lds = with_box;
+  a.occ_lds_words = occupancy_lds_words(a, lds);
+  lds += (uint32_t)a.occ_lds_words * 4u;
   const void *fn = a.vol.dtype == kU16   ? reinterpret_cast<const void *>(&k_render_preint<kU16>)
                    : a.vol.dtype == kI16 ? reinterpret_cast<const void *>(&k_render_preint<kI16>)
                                          : reinterpret_cast<const void *>(&k_render_preint<kF32>);

@@ -27,6 +27,7 @@ constexpr int kMaxTf = 1024;          // max TF nodes (LDS: 16 KiB table)
 constexpr int kMaxCamsPerLaunch = 16; // cameras carried in kernel arguments
 constexpr int kXcds = 8;              // MI355X: 8 accelerator complex dies
 constexpr int kDefaultChunkEdge = 4;  // super-tiles per chunk edge (XCD mapping)
+constexpr int kEmptyRadiusMax = 3;    // largest cube of empty blocks a leap crosses
 
 enum Dtype : int32_t { kU16 = 0, kI16 = 1, kF32 = 2 };
 
@@ -76,9 +77,9 @@ struct VolConst {
   // per-launch block occupancy under the TF, bit b % 32 of word b / 32
   // (nullptr: decided from minmax and the TF on the fly)
   const uint32_t *occ = nullptr;
-  // nonzero: occ holds three planes of ceil(nb / 32) words -- occupancy,
-  // then "every block within Chebyshev distance 1 is empty", then distance 2;
-  // leaps use cubes of blocks up to this radius
+  // nonzero: after the occupancy bits, occ holds the 2-bit radius plane
+  // (ceil(nb / 16) words; see empty_radius); leaps use cubes of empty blocks
+  // up to this radius
   int32_t occ_radius = 0;
 };
 
@@ -1073,15 +1074,13 @@ __device__ inline bool block_occupied(const VolConst &v, const TfShared &s, cons
   return range_occupied(s, tf.K, tf.v0, tf.scale, mm.x, mm.y);
 }
 
-// Chebyshev radius (0, 1 or 2 blocks) around the empty block b within which
-// every block is empty: two more bit planes after the occupancy bits, when
-// the launch has them (else 0).
+// Chebyshev radius (in blocks, at most kEmptyRadiusMax) around the empty
+// block b within which every block is empty: the 2-bit radius plane after the
+// occupancy bits, when the launch has it (else 0).
 __device__ inline int empty_radius(const VolConst &v, int b) {
   if (!v.occ || !v.occ_radius) return 0;
   const int64_t words = ((int64_t)v.nbx * v.nby * v.nbz + 31) / 32;
-  const uint32_t w1 = v.occ[words + (b >> 5)], w2 = v.occ[2 * words + (b >> 5)];
-  const uint32_t m = 1u << (b & 31);
-  return (v.occ_radius >= 2 && (w2 & m)) ? 2 : ((w1 & m) ? 1 : 0);
+  return min((int)(v.occ[words + (b >> 4)] >> (2 * (b & 15))) & 3, v.occ_radius);
 }
 
 // Copy the occupancy bits of a launch into LDS at `dst` (all threads of the

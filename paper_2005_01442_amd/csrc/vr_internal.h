@@ -67,6 +67,9 @@ uint32_t max_lds_per_workgroup();
 int32_t chunk_edge_setting();
 
 hipError_t launch_render(const RenderArgs &a, hipStream_t s);
+// Words of a.vol.occ a render launch stages in LDS after `lds` bytes of
+// other state (0: read from global memory).
+int32_t occupancy_lds_words(const RenderArgs &a, uint32_t lds);
 // Number of workgroups of a render launch of `a` (one per super-tile with an
 // order, else the padded Morton grid).
 int64_t render_grid(const RenderArgs &a);
@@ -82,8 +85,8 @@ hipError_t launch_block_minmax(const VolConst &v, float2 *out, hipStream_t s);
 hipError_t launch_block_occupancy(const VolConst &v, const TfConst &tf, uint8_t *occ, hipStream_t s);
 // The same decisions packed 32 blocks to a word (ceil(nb / 32) words).
 hipError_t launch_occupancy_bits(const VolConst &v, const TfConst &tf, uint32_t *bits, hipStream_t s);
-// Planes 1 and 2 (empty within Chebyshev distance 1 and 2) after plane 0.
-hipError_t launch_empty_radius_bits(const VolConst &v, uint32_t *bits, hipStream_t s);
+// The 2-bit radius plane (ceil(nb / 16) words) after the occupancy bits.
+hipError_t launch_empty_radius(const VolConst &v, uint32_t *bits, hipStream_t s);
 hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s);
 // Catmull-Rom samples leave their taps' range by at most this fraction of it.
 constexpr float kCatmullRomWiden = 0.4765625f;  // ((1 + 2/8)^3 - 1) / 2
