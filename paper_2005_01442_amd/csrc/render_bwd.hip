@@ -181,13 +181,27 @@ __device__ inline void box_apply(GradBox &b, unsigned long long staged) {
   const int l = threadIdx.x % kWaveSize;
   const int ta = l & 3, tb = (l >> 2) & 3, tc = l >> 4;
   const int off = tc * kBoxZ + tb * kBoxY + ta;
+  // the records of up to kApplyBatch samples are read before their cells are
+  // updated (records are not written here), the cells in record order
+  constexpr int kApplyBatch = 8;
   while (staged) {
-    const int sl = __ffsll((long long)staged) - 1;
-    staged &= staged - 1ull;
-    const float *rec = b.recs + sl * kRec;
-    const float w = rec[ta] * rec[4 + tb] * rec[8 + tc];
-    const int cell = reinterpret_cast<const int *>(rec)[12] + off;
-    b.cells[cell] += w;
+    float w[kApplyBatch];
+    int cell[kApplyBatch];
+    int n = 0;
+#pragma unroll
+    for (int i = 0; i < kApplyBatch; ++i) {
+      if (staged) {
+        const int sl = __ffsll((long long)staged) - 1;
+        staged &= staged - 1ull;
+        const float *rec = b.recs + sl * kRec;
+        w[i] = rec[ta] * rec[4 + tb] * rec[8 + tc];
+        cell[i] = reinterpret_cast<const int *>(rec)[12] + off;
+        n = i + 1;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < kApplyBatch; ++i)
+      if (i < n) b.cells[cell[i]] += w[i];
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -221,9 +235,18 @@ __device__ inline void march_backward(const VolConst &v, const TfShared &s, floa
     if (grad_vol && box.cells) box_apply(box, __ballot(staged));
     staged = false;
   };
-  auto visit = [&](int, float px, float py, float pz) -> bool {
+  // the taps of the next lattice point are loaded while this one is
+  // processed (in the adjoint every lattice point of a ray is usually visited)
+  TapPrefetch<DT> pf;
+  pf.ix = INT_MIN;
+  auto visit = [&](int k, float px, float py, float pz) -> bool {
     Stencil st = make_stencil(px, py, pz);
-    float val = reconstruct<DT>(rs, v, st);
+    float val = reconstruct_prefetched<DT>(pf, rs, v, st);
+    if (k + 1 < r.k0 + r.ns) {
+      float qx, qy, qz;
+      lattice_point(r, mc.step, k + 1, qx, qy, qz);
+      prefetch_taps<DT>(pf, rs, v, (int)floorf(qx), (int)floorf(qy), (int)floorf(qz));
+    }
     Classified q = classify(s, tf.K, tf.v0, tf.scale, val);
     float e = transmit(q.c.w, sl2);
     float ta = T * (1.0f - e);  // T_k a_k
@@ -276,8 +299,10 @@ __device__ inline void march_backward(const VolConst &v, const TfShared &s, floa
   if (grad_vol) box_flush(box, grad_vol, v);
 }
 
+// LDS holds two workgroups per CU (two wavefronts per SIMD): 256 registers.
 template <int DT>
-__global__ __launch_bounds__(kWgSize) void k_render_bwd(const BackwardArgs args) {
+__global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_render_bwd(
+    const BackwardArgs args) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const BackwardArgs &a = kernarg<BackwardArgs>();
   const RenderArgs &ra = a.r;

@@ -287,7 +287,20 @@ template <int DT> struct Vox;
 template <> struct Vox<kI16> {
   static constexpr int kBytes = 2;
   // even-length rows: byte offset of the pair-aligned window `voff` (per
-  // lane), row offset `soff` (uniform, in the SGPR soffset), shift `sh`
+  // lane), row offset `soff` (uniform, in the SGPR soffset), shift `sh`;
+  // row_s_load + row_unpack are the same in two parts (loads ahead of use)
+  using RawRow = u32x3;
+  __device__ static inline RawRow row_s_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_amdgcn_raw_buffer_load_b96(r, voff, soff, 0);
+  }
+  __device__ static inline void row_unpack(const RawRow &v, uint32_t sh, float t[4]) {
+    uint32_t lo = __builtin_amdgcn_alignbit(v.y, v.x, sh);
+    uint32_t hi = __builtin_amdgcn_alignbit(v.z, v.y, sh);
+    t[0] = (float)(int16_t)(lo & 0xffffu);
+    t[1] = (float)((int32_t)lo >> 16);
+    t[2] = (float)(int16_t)(hi & 0xffffu);
+    t[3] = (float)((int32_t)hi >> 16);
+  }
   __device__ static inline void row_s(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t sh,
                                       float t[4]) {
     u32x3 v = __builtin_amdgcn_raw_buffer_load_b96(r, voff, soff, 0);
@@ -342,6 +355,18 @@ template <> struct Vox<kI16> {
 
 template <> struct Vox<kU16> {
   static constexpr int kBytes = 2;
+  using RawRow = u32x3;
+  __device__ static inline RawRow row_s_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_amdgcn_raw_buffer_load_b96(r, voff, soff, 0);
+  }
+  __device__ static inline void row_unpack(const RawRow &v, uint32_t sh, float t[4]) {
+    uint32_t lo = __builtin_amdgcn_alignbit(v.y, v.x, sh);
+    uint32_t hi = __builtin_amdgcn_alignbit(v.z, v.y, sh);
+    t[0] = (float)(lo & 0xffffu);
+    t[1] = (float)(lo >> 16);
+    t[2] = (float)(hi & 0xffffu);
+    t[3] = (float)(hi >> 16);
+  }
   __device__ static inline void row_s(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t sh,
                                       float t[4]) {
     u32x3 v = __builtin_amdgcn_raw_buffer_load_b96(r, voff, soff, 0);
@@ -384,6 +409,17 @@ template <> struct Vox<kU16> {
 
 template <> struct Vox<kF32> {
   static constexpr int kBytes = 4;
+  using RawRow = u32x4;
+  __device__ static inline RawRow row_s_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+  }
+  __device__ static inline void row_unpack(const RawRow &w, uint32_t, float t[4]) {
+    const f32x4 v = __builtin_bit_cast(f32x4, w);
+    t[0] = v.x;
+    t[1] = v.y;
+    t[2] = v.z;
+    t[3] = v.w;
+  }
   __device__ static inline void row_s(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t,
                                       float t[4]) {
     f32x4 v = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
@@ -567,6 +603,55 @@ template <int DT>
 __device__ inline float reconstruct(__amdgpu_buffer_rsrc_t rs, const VolConst &v, const Stencil &s) {
   ValueRows f{s, 0.0f, 0.0f};
   for_rows<DT>(rs, v, s, f);
+  return f.acc;
+}
+
+// The 16 x-rows of the stencil at cell (ix, iy, iz), loaded ahead of the
+// sample that needs them (for_rows' interior fast path only; else empty).
+template <int DT> struct TapPrefetch {
+  typename Vox<DT>::RawRow raw[16];
+  int ix, iy, iz;  // ix == INT_MIN: empty
+  uint32_t sh;
+};
+
+template <int DT>
+__device__ inline void prefetch_taps(TapPrefetch<DT> &p, __amdgpu_buffer_rsrc_t rs, const VolConst &v, int ix, int iy,
+                                     int iz) {
+  p.ix = INT_MIN;
+  const int nx = v.nx, ny = v.ny, nz = v.nz;
+  const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
+  const bool inner = (ix >= 1) & (ix + 2 <= nx - 1) & (iy >= 1) & (iy + 2 <= ny - 1) & (iz >= 1) & (iz + 2 <= nz - 1);
+  if (!inner || !(DT == kF32 || v.row_even)) return;
+  const uint32_t e0 = ((uint32_t)(iz - 1) * (uint32_t)ny + (uint32_t)(iy - 1)) * (uint32_t)nx + (uint32_t)(ix - 1);
+  if (!Vox<DT>::window_ok(e0 + 3u * nxy + 3u * (uint32_t)nx, nxy * (uint32_t)nz)) return;
+  const uint32_t kb = (uint32_t)Vox<DT>::kBytes;
+  const uint32_t voff = (DT == kF32) ? e0 * 4u : (e0 & ~1u) * 2u;
+  const uint32_t rs_x = (uint32_t)nx * kb, rs_xy = nxy * kb;
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) p.raw[4 * c + b] = Vox<DT>::row_s_load(rs, voff, (uint32_t)c * rs_xy + (uint32_t)b * rs_x);
+  p.sh = (e0 & 1u) * 16u;
+  p.ix = ix;
+  p.iy = iy;
+  p.iz = iz;
+}
+
+// reconstruct() from the prefetched rows when they are this stencil's (the
+// same taps in the same order: bit-identical), else from memory.
+template <int DT>
+__device__ inline float reconstruct_prefetched(const TapPrefetch<DT> &p, __amdgpu_buffer_rsrc_t rs, const VolConst &v,
+                                               const Stencil &s) {
+  if (p.ix != s.ix || p.iy != s.iy || p.iz != s.iz) return reconstruct<DT>(rs, v, s);
+  ValueRows f{s, 0.0f, 0.0f};
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      float t[4];
+      Vox<DT>::row_unpack(p.raw[4 * c + b], p.sh, t);
+      f(c, b, t);
+    }
   return f.acc;
 }
 
