@@ -1026,14 +1026,15 @@ __device__ inline float transmit(float sigma, float step_log2e) {
 // Empty-space leaping.  Block of the (clamped) cell of p, and the first
 // lattice index that may leave it.
 // ---------------------------------------------------------------------------
-__device__ inline int block_of(const VolConst &v, float px, float py, float pz, int bc[3]) {
-  int cx = min(max((int)floorf(px), 0), v.nx - 1);
-  int cy = min(max((int)floorf(py), 0), v.ny - 1);
-  int cz = min(max((int)floorf(pz), 0), v.nz - 1);
-  bc[0] = cx >> v.edge_shift;
-  bc[1] = cy >> v.edge_shift;
-  bc[2] = cz >> v.edge_shift;
+__device__ inline int block_of_cell(const VolConst &v, int ix, int iy, int iz, int bc[3]) {
+  bc[0] = min(max(ix, 0), v.nx - 1) >> v.edge_shift;
+  bc[1] = min(max(iy, 0), v.ny - 1) >> v.edge_shift;
+  bc[2] = min(max(iz, 0), v.nz - 1) >> v.edge_shift;
   return bc[0] + v.nbx * (bc[1] + v.nby * bc[2]);
+}
+
+__device__ inline int block_of(const VolConst &v, float px, float py, float pz, int bc[3]) {
+  return block_of_cell(v, (int)floorf(px), (int)floorf(py), (int)floorf(pz), bc);
 }
 
 // 1 / x in FP64: the hardware reciprocal refined by two Newton steps (a few
@@ -1126,17 +1127,18 @@ __device__ inline void walk(const VolConst &v, const TfShared &s, const TfConst 
   while (k < kend) {
     const bool in = alive && k >= kfree && k < ke;
     bool want = in;
-    float px = 0.0f, py = 0.0f, pz = 0.0f;
-    if (in) {
-      lattice_point(r, mc.step, k, px, py, pz);
-      if (mc.skip) {
-        const int b = block_of(v, px, py, pz, bc);
-        if (b != cur_block) {
-          cur_block = b;
-          cur_occ = block_occupied(v, s, tf, b);
-        }
-        want = cur_occ;
+    // every lane computes its position and cell (used by in-lanes only), so the
+    // floors dominate, and are shared with, the box test and the stencil
+    float px, py, pz;
+    lattice_point(r, mc.step, k, px, py, pz);
+    const int ix = (int)floorf(px), iy = (int)floorf(py), iz = (int)floorf(pz);
+    if (in && mc.skip) {
+      const int b = block_of_cell(v, ix, iy, iz, bc);
+      if (b != cur_block) {
+        cur_block = b;
+        cur_occ = block_occupied(v, s, tf, b);
       }
+      want = cur_occ;
     }
     if (__ballot(want) == 0ull) {
       if (in) kfree = leap_target(v, r, bc, mc.step, k, empty_radius(v, cur_block));
