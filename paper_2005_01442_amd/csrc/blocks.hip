@@ -168,10 +168,12 @@ __global__ __launch_bounds__(kWgSize) void k_empty_radius(const VolConst v, uint
     bits[rw] = spread16((uint32_t)(lo >> lane)) | (spread16((uint32_t)(hi >> lane)) << 1);
 }
 
+bool empty_radius_fits(const VolConst &v) { return empty_window_words(v) * 4 <= (int64_t)max_lds_per_workgroup(); }
+
 hipError_t launch_empty_radius(const VolConst &v, uint32_t *bits, hipStream_t s) {
   const int64_t nb = (int64_t)v.nbx * v.nby * v.nbz;
   const int64_t lds = empty_window_words(v) * 4;
-  if (lds > (int64_t)max_lds_per_workgroup()) return hipErrorInvalidValue;  // the caller leaps block by block
+  if (!empty_radius_fits(v)) return hipErrorInvalidValue;  // the caller leaps block by block
   const unsigned grid = (unsigned)((nb + kWgSize - 1) / kWgSize);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_empty_radius),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -59,11 +59,19 @@ struct Request {
   int32_t stx = 0, sty = 0;  // super-tile grid
   std::vector<int32_t> order;  // super-tiles, nearest to the projected volume centre first
   bool released = false;
+  // block occupancy under this request's TF and the radius plane (the
+  // kernels' cheap leaps), computed by the first batch that carries it
+  uint32_t *occ = nullptr;
+  size_t occ_bytes = 0;
+  int32_t occ_radius = 0;
+  int occ_batch = -1;      // batch that computed it
+  uint64_t occ_gen = 0;    // that batch's issue generation
 };
 
 struct Volume {
   vr_volume desc{};
   VolConst vc{};
+  bool radius_fits = false;  // the radius plane can be built for its block grid
   vr_blocks *blocks = nullptr;
   size_t block_bytes = 0;
   int64_t users = 0;  // queued + admitted requests
@@ -74,6 +82,8 @@ struct Volume {
 struct Batch {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
+  hipEvent_t occ_done = nullptr;  // after the occupancy launches of this batch
+  uint64_t gen = 0;               // issue generation
   char *host = nullptr;  // pinned staging
   char *dev = nullptr;
   size_t cap = 0;
@@ -108,6 +118,8 @@ struct vr_server {
   // HBM accounting (result images + blocks)
   uint64_t hbm_used = 0, hbm_peak = 0;
   std::multimap<size_t, float *> image_pool;  // free images by size
+  std::multimap<size_t, uint32_t *> occ_pool;  // free occupancy buffers by size
+  std::vector<uint32_t *> occ_retired;         // of requests that did not finish (freed at destroy)
 
   Batch batches[2];
   int next_batch = 0;
@@ -204,6 +216,10 @@ void retire(vr_server *s, Batch &b) {
       s->pixels_done += (uint64_t)r.cam.W * r.cam.H;
       s->admitted.erase(std::find(s->admitted.begin(), s->admitted.end(), r.ticket));
       s->volumes[r.volume_id].users--;
+      if (r.occ) {  // every batch that read it has finished
+        s->occ_pool.emplace(r.occ_bytes, r.occ);
+        r.occ = nullptr;
+      }
     }
   }
   b.per_request.clear();
@@ -264,6 +280,11 @@ bool issue(vr_server *s, Batch &b) {
   int32_t max_k = 2;
   b.per_request.clear();
   b.pixels = 0;
+  const int bi = (int)(&b - s->batches);
+  Batch &other = s->batches[bi ^ 1];
+  b.gen++;
+  std::vector<std::pair<Request *, size_t>> occ_new;  // requests whose occupancy this batch computes, TF offset
+  bool wait_other = false;
   std::vector<std::pair<float, ServeItem>> keyed;
   keyed.reserve((size_t)n_items_total);
   for (size_t i = 0; i < n; ++i) {
@@ -281,6 +302,30 @@ bool issue(vr_server *s, Batch &b) {
     sl.tf.scale = (float)(r.K - 1) / (r.v1 - r.v0);
     memcpy(b.host + tf_cursor, r.tf.data(), (size_t)r.K * 16);
     sl.tf.table = reinterpret_cast<const float *>(b.dev + tf_cursor);
+    if (!r.occ && r.mc.skip && v.vc.minmax) {
+      const size_t need = occupancy_bytes(v.vc);
+      auto it = s->occ_pool.find(need);
+      uint32_t *p = nullptr;
+      if (it != s->occ_pool.end()) {
+        p = it->second;
+        s->occ_pool.erase(it);
+      } else if (hipMalloc(reinterpret_cast<void **>(&p), need) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+      }
+      if (p) {
+        r.occ = p;
+        r.occ_bytes = need;
+        r.occ_radius = v.radius_fits ? kEmptyRadiusMax : 0;
+        r.occ_batch = bi;
+        r.occ_gen = b.gen;
+        occ_new.emplace_back(&r, tf_cursor);
+      }
+    } else if (r.occ && r.occ_batch == (bi ^ 1) && other.busy && other.gen == r.occ_gen) {
+      wait_other = true;  // computed by the other batch, which may still run
+    }
+    sl.vol.occ = r.occ;
+    sl.vol.occ_radius = r.occ ? r.occ_radius : 0;
     tf_cursor += align16((size_t)r.K * 16);
     for (int64_t q = 0; q < take[i]; ++q) {
       const int64_t rank = r.items_issued + q;
@@ -302,6 +347,20 @@ bool issue(vr_server *s, Batch &b) {
                    [](const std::pair<float, ServeItem> &a, const std::pair<float, ServeItem> &c) { return a.first < c.first; });
   for (size_t q = 0; q < keyed.size(); ++q) items[q] = keyed[q].second;
   hipError_t e = hipMemcpyAsync(b.dev, b.host, total, hipMemcpyHostToDevice, b.stream);
+  for (auto &rn : occ_new) {  // from the TF tables just copied
+    if (e != hipSuccess) break;
+    Request &r = *rn.first;
+    const Volume &v = s->volumes[r.volume_id];
+    TfConst tc;
+    tc.table = reinterpret_cast<const float *>(b.dev + rn.second);
+    tc.K = r.K;
+    tc.v0 = r.v0;
+    tc.scale = (float)(r.K - 1) / (r.v1 - r.v0);
+    e = launch_occupancy_bits(v.vc, tc, r.occ, b.stream);
+    if (e == hipSuccess && r.occ_radius > 0) e = launch_empty_radius(v.vc, r.occ, b.stream);
+  }
+  if (e == hipSuccess) e = hipEventRecord(b.occ_done, b.stream);
+  if (e == hipSuccess && wait_other) e = hipStreamWaitEvent(b.stream, other.occ_done, 0);
   if (e == hipSuccess)
     e = launch_serve_batch(reinterpret_cast<const ServeSlot *>(b.dev + off_slots),
                            reinterpret_cast<const ServeItem *>(b.dev + off_items), (int32_t)item, max_k,
@@ -380,6 +439,7 @@ vr_status vr_serve_create(const vr_serve_config *cfg, vr_server **out) {
     b.cap = cap;
     if ((e = hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
     if ((e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
+    if ((e = hipEventCreateWithFlags(&b.occ_done, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
     if ((e = hipHostMalloc((void **)&b.host, cap, hipHostMallocDefault)) != hipSuccess) return hip_fail(e, "pinned staging");
     if ((e = hipMalloc((void **)&b.dev, cap)) != hipSuccess) return fail(VR_E_OOM, "device staging: %s", hipGetErrorString(e));
   }
@@ -421,6 +481,7 @@ vr_status vr_serve_add_volume(vr_server *s, const vr_volume *vol, int32_t block_
   Volume &v = s->volumes[id];
   v.desc = *vol;
   v.vc = vc;
+  v.radius_fits = empty_radius_fits(vc);
   v.blocks = blocks;
   v.block_bytes = bb;
   *volume_id = id;
@@ -559,6 +620,7 @@ vr_status vr_serve_release(vr_server *s, uint64_t ticket) {
   if (r.state == RState::Queued || r.state == RState::Admitted)
     return fail(VR_E_BUSY, "ticket %llu is not complete", (unsigned long long)ticket);
   release_image(s, r.image, r.image_bytes);
+  if (r.occ) s->occ_retired.push_back(r.occ);  // a cancelled request's batches may still read it
   s->requests.erase(it);
   s->cv_work.notify_one();
   return VR_OK;
@@ -647,13 +709,18 @@ vr_status vr_serve_destroy(vr_server *s) {
   }
   for (Batch &b : s->batches) {
     if (b.done) (void)hipEventDestroy(b.done);
+    if (b.occ_done) (void)hipEventDestroy(b.occ_done);
     if (b.stream) (void)hipStreamDestroy(b.stream);
     if (b.host) (void)hipHostFree(b.host);
     if (b.dev) (void)hipFree(b.dev);
   }
-  for (auto &kv : s->requests)
+  for (auto &kv : s->requests) {
     if (kv.second->image) (void)hipFree(kv.second->image);
+    if (kv.second->occ) (void)hipFree(kv.second->occ);
+  }
   for (auto &kv : s->image_pool) (void)hipFree(kv.second);
+  for (auto &kv : s->occ_pool) (void)hipFree(kv.second);
+  for (uint32_t *p : s->occ_retired) (void)hipFree(p);
   for (auto &kv : s->volumes) vr_blocks_free(kv.second.blocks);
   delete s;
   return VR_OK;

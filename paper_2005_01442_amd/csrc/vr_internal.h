@@ -87,6 +87,13 @@ hipError_t launch_block_occupancy(const VolConst &v, const TfConst &tf, uint8_t 
 hipError_t launch_occupancy_bits(const VolConst &v, const TfConst &tf, uint32_t *bits, hipStream_t s);
 // The 2-bit radius plane (ceil(nb / 16) words) after the occupancy bits.
 hipError_t launch_empty_radius(const VolConst &v, uint32_t *bits, hipStream_t s);
+// Whether launch_empty_radius can run for this block grid (its LDS window fits).
+bool empty_radius_fits(const VolConst &v);
+// Bytes of the occupancy bits plus the radius plane of a block grid.
+inline size_t occupancy_bytes(const VolConst &v) {
+  const int64_t nb = (int64_t)v.nbx * v.nby * v.nbz;
+  return (size_t)(((nb + 31) / 32 + (nb + 15) / 16) * 4);
+}
 hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t s);
 // Catmull-Rom samples leave their taps' range by at most this fraction of it.
 constexpr float kCatmullRomWiden = 0.4765625f;  // ((1 + 2/8)^3 - 1) / 2
