@@ -37,6 +37,12 @@ struct vr_bricked {
   int64_t slot_bytes;
   char *host_bricks;       // pinned, nbricks * slot_bytes
   float2 *minmax_dev;      // nbricks
+  int32_t F;               // skip-block edge (min(E, 16)): blocks of F^3 inside each brick
+  int32_t fnbx, fnby, fnbz;
+  int64_t nfine;
+  float2 *fine_minmax_dev; // nfine
+  uint32_t *fine_bits_dev; // occupancy bits + radius plane, rebuilt per render
+  bool fine_radius;        // the radius plane can be built for the fine grid
   uint8_t *occ_dev;
   uint8_t *occ_host;       // pinned
   int32_t *page_dev[2];    // per pool half (streaming) or [0] (all resident)
@@ -86,6 +92,33 @@ static float2 gather_brick(const T *src, int64_t nx, int64_t ny, int64_t nz, int
   return make_float2(mn, mx);
 }
 
+// (min, max) of every skip block of edge F inside brick (bx, by, bz), over
+// its footprint [fF-1, fF+F+1] per axis, read from the brick's gathered
+// (edge-clamped) footprint; out[] is indexed like the fine grid.
+template <class T>
+static void fine_minmax(const T *slot, int E, int S, int F, int64_t bx, int64_t by, int64_t bz, int32_t fnbx,
+                        int32_t fnby, int32_t fnbz, float2 *out) {
+  const int per = E / F;
+  for (int fk = 0; fk < per; ++fk)
+    for (int fj = 0; fj < per; ++fj)
+      for (int fi = 0; fi < per; ++fi) {
+        const int64_t gx = bx * per + fi, gy = by * per + fj, gz = bz * per + fk;
+        if (gx >= fnbx || gy >= fnby || gz >= fnbz) continue;
+        float mn = INFINITY, mx = -INFINITY;
+        // slot-local footprint: [fi F, fi F + F + 2] (the slot starts at bE - 1)
+        for (int z = fk * F; z <= fk * F + F + 2; ++z)
+          for (int y = fj * F; y <= fj * F + F + 2; ++y) {
+            const T *row = slot + ((int64_t)z * S + y) * S;
+            for (int x = fi * F; x <= fi * F + F + 2; ++x) {
+              const float f = (float)row[x];
+              mn = f < mn ? f : mn;
+              mx = f > mx ? f : mx;
+            }
+          }
+        out[gx + (int64_t)fnbx * (gy + (int64_t)fnby * gz)] = make_float2(mn, mx);
+      }
+}
+
 // Front-to-back rank of brick (i, j, k) for a camera (see the file comment).
 static int64_t brick_rank(const CamConst &c, int E, int64_t i, int64_t j, int64_t k) {
   const int64_t idx[3] = {i, j, k};
@@ -117,6 +150,26 @@ static void order_bricks(const CamConst &c, int E, int32_t nbx, int32_t nby, int
   for (auto &kv : keyed) out.push_back(kv.second);
 }
 
+// The walk's grid: the volume's skip blocks of edge F (no data; occupancy
+// bits attached per render).
+static VolConst fine_grid(const vr_bricked *v) {
+  VolConst f;
+  f.data = nullptr;
+  f.dtype = v->dtype;
+  f.nx = (int32_t)v->nx;
+  f.ny = (int32_t)v->ny;
+  f.nz = (int32_t)v->nz;
+  f.bytes = 0;
+  f.minmax = v->fine_minmax_dev;
+  f.nbx = v->fnbx;
+  f.nby = v->fnby;
+  f.nbz = v->fnbz;
+  f.edge = v->F;
+  f.edge_shift = __builtin_ctz((unsigned)v->F);
+  f.row_even = (v->nx % 2) == 0 ? 1 : 0;
+  return f;
+}
+
 static void destroy(vr_bricked *v) {
   if (!v) return;
   if (v->host_bricks) (void)hipHostFree(v->host_bricks);
@@ -129,6 +182,8 @@ static void destroy(vr_bricked *v) {
   }
   if (v->copy_stream) (void)hipStreamDestroy(v->copy_stream);
   (void)hipFree(v->minmax_dev);
+  (void)hipFree(v->fine_minmax_dev);
+  (void)hipFree(v->fine_bits_dev);
   (void)hipFree(v->occ_dev);
   (void)hipFree(v->pool);
   (void)hipFree(v->state);
@@ -165,6 +220,11 @@ vr_status vr_bricked_create(const vr_volume *host_vol, int32_t brick_edge, uint6
   v->nby = (int32_t)((v->ny + brick_edge - 1) / brick_edge);
   v->nbz = (int32_t)((v->nz + brick_edge - 1) / brick_edge);
   v->nbricks = (int64_t)v->nbx * v->nby * v->nbz;
+  v->F = std::min<int32_t>(brick_edge, 16);
+  v->fnbx = (int32_t)((v->nx + v->F - 1) / v->F);
+  v->fnby = (int32_t)((v->ny + v->F - 1) / v->F);
+  v->fnbz = (int32_t)((v->nz + v->F - 1) / v->F);
+  v->nfine = (int64_t)v->fnbx * v->fnby * v->fnbz;
   v->esz = v->dtype == VR_F32 ? 4 : 2;
   // 16 bytes of padding keep the kernel's 12-byte row windows inside the slot
   v->slot_bytes = (((int64_t)v->S * v->S * v->S * v->esz) + 16 + 255) & ~(int64_t)255;
@@ -182,8 +242,10 @@ vr_status vr_bricked_create(const vr_volume *host_vol, int32_t brick_edge, uint6
     return fail(VR_E_OOM, "pinned host allocation of %lld brick bytes: %s", (long long)(v->nbricks * v->slot_bytes),
                 hipGetErrorString(e));
   }
-  // gather every footprint (and its min/max) with the host's threads
+  // gather every footprint (and its min/max, and its skip blocks' min/max)
+  // with the host's threads
   std::vector<float2> mm((size_t)v->nbricks);
+  std::vector<float2> fmm((size_t)v->nfine);
   const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   std::vector<std::thread> pool;
   for (unsigned t = 0; t < nt; ++t)
@@ -191,19 +253,27 @@ vr_status vr_bricked_create(const vr_volume *host_vol, int32_t brick_edge, uint6
       for (int64_t b = t; b < v->nbricks; b += nt) {
         const int64_t i = b % v->nbx, j = (b / v->nbx) % v->nby, k = b / ((int64_t)v->nbx * v->nby);
         char *dst = v->host_bricks + b * v->slot_bytes;
-        if (v->dtype == VR_F32)
+        if (v->dtype == VR_F32) {
           mm[b] = gather_brick((const float *)host_vol->data, v->nx, v->ny, v->nz, v->E, v->S, i, j, k, (float *)dst);
-        else if (v->dtype == VR_I16)
+          fine_minmax((const float *)dst, v->E, v->S, v->F, i, j, k, v->fnbx, v->fnby, v->fnbz, fmm.data());
+        } else if (v->dtype == VR_I16) {
           mm[b] = gather_brick((const int16_t *)host_vol->data, v->nx, v->ny, v->nz, v->E, v->S, i, j, k,
                                (int16_t *)dst);
-        else
+          fine_minmax((const int16_t *)dst, v->E, v->S, v->F, i, j, k, v->fnbx, v->fnby, v->fnbz, fmm.data());
+        } else {
           mm[b] = gather_brick((const uint16_t *)host_vol->data, v->nx, v->ny, v->nz, v->E, v->S, i, j, k,
                                (uint16_t *)dst);
+          fine_minmax((const uint16_t *)dst, v->E, v->S, v->F, i, j, k, v->fnbx, v->fnby, v->fnbz, fmm.data());
+        }
       }
     });
   for (auto &th : pool) th.join();
   const size_t nb = (size_t)v->nbricks;
+  VolConst fvc = fine_grid(v);
+  v->fine_radius = empty_radius_fits(fvc);
   if ((e = hipMalloc(&v->minmax_dev, nb * sizeof(float2))) != hipSuccess ||
+      (e = hipMalloc(&v->fine_minmax_dev, (size_t)v->nfine * sizeof(float2))) != hipSuccess ||
+      (e = hipMalloc(&v->fine_bits_dev, occupancy_bytes(fvc))) != hipSuccess ||
       (e = hipMalloc(&v->occ_dev, nb)) != hipSuccess ||
       (e = hipMalloc(&v->page_dev[0], nb * sizeof(int32_t))) != hipSuccess ||
       (e = hipMalloc(&v->page_dev[1], nb * sizeof(int32_t))) != hipSuccess ||
@@ -225,7 +295,9 @@ vr_status vr_bricked_create(const vr_volume *host_vol, int32_t brick_edge, uint6
     destroy(v);
     return hip_fail(e, "copy stream and events");
   }
-  if ((e = hipMemcpy(v->minmax_dev, mm.data(), nb * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess) {
+  if ((e = hipMemcpy(v->minmax_dev, mm.data(), nb * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(v->fine_minmax_dev, fmm.data(), (size_t)v->nfine * sizeof(float2), hipMemcpyHostToDevice)) !=
+          hipSuccess) {
     destroy(v);
     return hip_fail(e, "copy brick min/max");
   }
@@ -300,8 +372,18 @@ vr_status vr_bricked_render(vr_bricked *v, const vr_camera *cams, int32_t n_cams
   vc.nbz = v->nbz;
   vc.edge = v->E;
   vc.edge_shift = __builtin_ctz((unsigned)v->E);
-  // 1. occupancy under this TF
+  // 1. occupancy under this TF: of the bricks (their order and residency) and
+  // of the skip blocks (the walk's leaps)
   if ((e = launch_block_occupancy(vc, a.tf, v->occ_dev, st)) != hipSuccess) return hip_fail(e, "occupancy launch");
+  a.fine = fine_grid(v);
+  if ((e = launch_occupancy_bits(a.fine, a.tf, v->fine_bits_dev, st)) != hipSuccess)
+    return hip_fail(e, "occupancy bits launch");
+  a.fine.occ = v->fine_bits_dev;
+  a.fine.occ_radius = 0;
+  if (v->fine_radius) {
+    if ((e = launch_empty_radius(a.fine, v->fine_bits_dev, st)) != hipSuccess) return hip_fail(e, "radius launch");
+    a.fine.occ_radius = kEmptyRadiusMax;
+  }
   if ((e = hipMemcpyAsync(v->occ_host, v->occ_dev, (size_t)v->nbricks, hipMemcpyDeviceToHost, st)) != hipSuccess ||
       (e = hipStreamSynchronize(st)) != hipSuccess)
     return hip_fail(e, "occupancy readback");

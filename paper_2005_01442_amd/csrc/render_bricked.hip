@@ -139,7 +139,9 @@ __global__ __launch_bounds__(kWgSize) void k_bricked_pass(const BrickedArgs args
   };
   NoPrep prep;
   NoPost post;
-  walk<decltype(visit), NoPrep, NoPost, true>(a.vol, s, a.tf, a.mc, r, visit, prep, post, kstart);
+  // skipping on the fine blocks; the brick of a sample to evaluate decides
+  // whether this pass has it
+  walk<decltype(visit), NoPrep, NoPost, true>(a.fine, s, a.tf, a.mc, r, visit, prep, post, kstart);
   if (active) {
     a.state[pix] = st;
     a.next[pix] = parked;

@@ -44,7 +44,8 @@ struct BackwardArgs {
 // (E+4)^3 voxels each: the footprint plus one plane) resident in pool slots
 // listed by the page table.
 struct BrickedArgs {
-  VolConst vol;            // dims, block grid, edge, edge_shift (no data)
+  VolConst vol;            // dims, brick grid, edge, edge_shift (no data)
+  VolConst fine;           // the same volume's skip blocks (edge <= 16) with occupancy bits: the walk's grid
   TfConst tf;
   MarchConst mc;
   CamConst cam;
