@@ -86,8 +86,10 @@ __device__ inline float reconstruct_slot(const char *slot, int S, int ox, int oy
 // ray parks at its first sample in an occupied brick of a later pass.
 // state: per pixel (C_r, C_g, C_b, T); next: the next lattice index, or -1
 // once the ray is finished.  first: initialise the state instead of reading it.
+// The LDS boxes allow three workgroups per CU; the register budget matches.
 template <int DT>
-__global__ __launch_bounds__(kWgSize) void k_bricked_pass(const BrickedArgs args) {
+__global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_bricked_pass(
+    const BrickedArgs args) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const BrickedArgs &a = kernarg<BrickedArgs>();
   TfShared s = carve_tf(lds, a.tf.K);
@@ -117,17 +119,64 @@ __global__ __launch_bounds__(kWgSize) void k_bricked_pass(const BrickedArgs args
   const bool ert_on = a.mc.ert > 0.0f && a.mc.ert < 1.0f;
   const int S = a.slot_edge, E = a.vol.edge;
   int parked = -1;
+  // LDS value box of the wavefront, filled from one slot: the slot holds its
+  // footprint edge-clamped, so within the slot's extent no further clamping
+  // is needed and the box sees exactly the taps reconstruct_slot reads.
+  ValBox box;
+  box.valid = false;
+  box.ox = box.oy = box.oz = 0;
+  box.cells = a.use_box ? reinterpret_cast<float *>(lds + vbox_lds_offset(a.tf.K)) + (threadIdx.x / kWaveSize) * kVBoxCells
+                        : nullptr;
+  int box_slot = -1;  // uniform: the slot the box holds
+  int step_brick = -1, step_slot = -1;  // this lane's brick and slot at the current step (prep -> visit)
+  auto prep = [&](bool want, float px, float py, float pz) {
+    step_brick = -1;
+    step_slot = -1;
+    if (want) {
+      int bc[3];
+      step_brick = block_of(a.vol, px, py, pz, bc);
+      step_slot = a.page[step_brick];
+    }
+    if (!box.cells) return;
+    const unsigned long long wm = __ballot(want);
+    const int first = __ffsll((long long)wm) - 1;
+    const int s0 = __builtin_amdgcn_readlane(step_slot, first);
+    const int b0 = __builtin_amdgcn_readlane(step_brick, first);
+    if (s0 < 0 || __ballot(want && step_slot != s0) != 0ull) {  // not one resident brick
+      box.valid = false;
+      return;
+    }
+    if (s0 != box_slot) box.valid = false;
+    box_slot = s0;
+    const int bx = b0 % a.vol.nbx, by = (b0 / a.vol.nbx) % a.vol.nby, bz = b0 / (a.vol.nbx * a.vol.nby);
+    VolConst sv = a.vol;  // the slot as a small volume of S^3 voxels
+    sv.nx = sv.ny = sv.nz = S;
+    sv.bytes = (uint32_t)a.slot_bytes;
+    const __amdgpu_buffer_rsrc_t srs = make_rsrc(a.pool + (size_t)s0 * a.slot_bytes, (uint32_t)a.slot_bytes);
+    vbox_prepare<DT>(box, srs, sv, r, want, px - (float)(bx * E - 1), py - (float)(by * E - 1),
+                     pz - (float)(bz * E - 1));
+  };
   auto visit = [&](int k, float px, float py, float pz) -> bool {
     int bc[3];
     const int b = block_of(a.vol, px, py, pz, bc);
-    const int slot = a.page[b];
+    const int slot = step_slot;
     if (slot < 0) {  // a later pass holds this brick
       parked = k;
       return false;
     }
-    const Stencil sten = make_stencil(px, py, pz);
-    const float val = reconstruct_slot<DT>(a.pool + (size_t)slot * a.slot_bytes, S, bc[0] * E - 1, bc[1] * E - 1,
-                                           bc[2] * E - 1, a.vol.nx, a.vol.ny, a.vol.nz, sten);
+    Stencil sten = make_stencil(px, py, pz);
+    const int ox = bc[0] * E - 1, oy = bc[1] * E - 1, oz = bc[2] * E - 1;
+    float val;
+    if (box.valid) {  // every sampling lane is in the box's slot
+      sten.ix -= ox;
+      sten.iy -= oy;
+      sten.iz -= oz;
+      val = reconstruct_box(box, sten);
+    } else {
+      val = reconstruct_slot<DT>(a.pool + (size_t)slot * a.slot_bytes, S, ox, oy, oz, a.vol.nx, a.vol.ny, a.vol.nz,
+                                 sten);
+    }
+    (void)b;
     const Classified q = classify(s, a.tf.K, a.tf.v0, a.tf.scale, val);
     const float e = transmit(q.c.w, sl2);
     const float ta = st.w * (1.0f - e);
@@ -137,11 +186,10 @@ __global__ __launch_bounds__(kWgSize) void k_bricked_pass(const BrickedArgs args
     st.w = st.w * e;
     return !(ert_on && (1.0f - st.w) >= a.mc.ert);
   };
-  NoPrep prep;
   NoPost post;
   // skipping on the fine blocks; the brick of a sample to evaluate decides
   // whether this pass has it
-  walk<decltype(visit), NoPrep, NoPost, true>(a.fine, s, a.tf, a.mc, r, visit, prep, post, kstart);
+  walk<decltype(visit), decltype(prep), NoPost, true>(a.fine, s, a.tf, a.mc, r, visit, prep, post, kstart);
   if (active) {
     a.state[pix] = st;
     a.next[pix] = parked;
@@ -157,9 +205,18 @@ __global__ __launch_bounds__(kWgSize) void k_bricked_finish(const float4 *state,
   }
 }
 
-hipError_t launch_bricked_pass(const BrickedArgs &a, hipStream_t s) {
+hipError_t launch_bricked_pass(const BrickedArgs &a0, hipStream_t s) {
+  BrickedArgs a = a0;
   const int tiles = ((a.W + kSuperEdge - 1) / kSuperEdge) * ((a.H + kSuperEdge - 1) / kSuperEdge);
-  const uint32_t lds = tf_lds_bytes(a.tf.K);
+  uint32_t lds = tf_lds_bytes(a.tf.K);
+  const uint32_t with_box = vbox_lds_offset(a.tf.K) + vbox_lds_bytes();
+  a.use_box = with_box <= max_lds_per_workgroup() ? 1 : 0;
+  if (a.use_box) lds = with_box;
+  const void *fn = a.vol.dtype == kU16   ? reinterpret_cast<const void *>(&k_bricked_pass<kU16>)
+                   : a.vol.dtype == kI16 ? reinterpret_cast<const void *>(&k_bricked_pass<kI16>)
+                                         : reinterpret_cast<const void *>(&k_bricked_pass<kF32>);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
   switch (a.vol.dtype) {
   case kU16: hipLaunchKernelGGL(k_bricked_pass<kU16>, dim3((unsigned)tiles), dim3(kWgSize), lds, s, a); break;
   case kI16: hipLaunchKernelGGL(k_bricked_pass<kI16>, dim3((unsigned)tiles), dim3(kWgSize), lds, s, a); break;

@@ -58,6 +58,7 @@ struct BrickedArgs {
   int32_t slot_edge;       // E + 4 (even)
   int32_t W, H;
   int32_t first;           // initialise the ray state
+  int32_t use_box;         // stage LDS value boxes from the slots (set at launch)
 };
 
 // Largest dynamic LDS a workgroup may allocate on the current device.
