@@ -135,11 +135,14 @@ __device__ inline float4 march_preint(const VolConst &v, const TfShared &s, cons
   while (k < kend) {
     const bool in = alive && k >= kfree && k < ke;
     bool want = false;
-    float px = 0.0f, py = 0.0f, pz = 0.0f;
+    // every lane computes its point and cell (as walk does), shared with the
+    // box test and the stencil
+    float px, py, pz;
+    lattice_point(r, mc.step, k, px, py, pz);
+    const int ix = (int)floorf(px), iy = (int)floorf(py), iz = (int)floorf(pz);
     if (in) {
-      lattice_point(r, mc.step, k, px, py, pz);
       if (mc.skip) {
-        const int b = block_of(v, px, py, pz, bc);
+        const int b = block_of_cell(v, ix, iy, iz, bc);
         bool pair = cocc;
         if (b != cb) {
           const int pb = cb;
