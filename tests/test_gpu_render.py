@@ -305,3 +305,25 @@ def test_sparse_islands_skip_is_bit_identical(edge):
         assert np.array_equal(a, b), f"ert {ert}: max diff {np.abs(a - b).max():.3e}"
         assert cb[0] < ca[0] / 4  # most samples lie in empty blocks
         log(f"ert {ert}: evaluated {cb[0]} of {ca[0]}")
+
+
+def test_wide_block_grid_falls_back_and_stays_exact():
+    """A block grid too wide for the radius kernel's LDS window (and for LDS
+    staging of the occupancy bits): leaps fall back to single blocks with the
+    bits read from global memory; the image is still exactly the no-skip one."""
+    rng = np.random.default_rng(95)
+    nx, ny, nz = 8192, 8192, 4
+    vol = np.zeros((nz, ny, nx), np.int16)
+    for _ in range(40):
+        x, y = int(rng.integers(0, nx - 40)), int(rng.integers(0, ny - 40))
+        vol[:, y:y + 40, x:x + 40] = rng.integers(200, 1500, size=(nz, 40, 40))
+    v = upload_volume(vol)
+    cams = [synth.ortho_axis_camera(8192, 96, 96)]
+    c = synth.orbit_camera((nx, ny, nz), np.array([0.3, 0.2, 0.93]), 40.0, 96, 96)
+    cams.append(c)
+    tf = synth.tf1()
+    log("wide grid 8192x8192x4 int16, 16^3 blocks (512 x 512 x 1)")
+    a, ca = gpu_render(vol, cams, tf, 0.5, ert=0.99, use_skip=False, counters=True, vol=v)
+    b, cb = gpu_render(vol, cams, tf, 0.5, ert=0.99, use_skip=True, counters=True, vol=v)
+    assert np.array_equal(a, b)
+    assert cb[0] <= ca[0]
