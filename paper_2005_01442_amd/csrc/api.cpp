@@ -351,13 +351,17 @@ static vr_status render_views(RenderArgs &a, const vr_camera *cams, int32_t n_ca
         hipSuccess) {
       (void)hipGetLastError();
       bits = nullptr;
-    } else if (launch_occupancy_bits(a.vol, a.tf, bits, (hipStream_t)stream) != hipSuccess) {
-      (void)hipGetLastError();
-      (void)hipFreeAsync(bits, (hipStream_t)stream);
-      bits = nullptr;
-    } else if (!preint) {  // (pre-integration leaps block by block: its cells span two blocks)
-      radius = launch_empty_radius(a.vol, bits, (hipStream_t)stream) == hipSuccess;
-      if (!radius) (void)hipGetLastError();
+    } else {
+      // (pre-integration leaps block by block: its cells span two blocks)
+      if (!preint && occupancy_planes_fit(a.vol, a.tf.K)) {
+        radius = launch_occupancy_planes(a.vol, a.tf, bits, (hipStream_t)stream) == hipSuccess;
+        if (!radius) (void)hipGetLastError();
+      }
+      if (!radius && launch_occupancy_bits(a.vol, a.tf, bits, (hipStream_t)stream) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFreeAsync(bits, (hipStream_t)stream);
+        bits = nullptr;
+      }
     }
   }
   a.vol.occ = bits;

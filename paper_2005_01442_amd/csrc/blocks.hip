@@ -106,18 +106,23 @@ hipError_t launch_occupancy_bits(const VolConst &v, const TfConst &tf, uint32_t 
   return hipGetLastError();
 }
 
-// The radius plane after the occupancy bits: 2 bits per block (16 blocks a
-// word), for an empty block b the largest r <= kEmptyRadiusMax such that
-// every block within Chebyshev distance r of b is empty (tested on the
-// occupancy bits; outside the grid counts as empty), 0 for occupied blocks.
-// The blocks around a workgroup's 256 consecutive blocks lie within
-// empty_reach bit positions of them, so the workgroup stages that window of
-// the occupancy bits in LDS first.
+// Both planes in one launch: the occupancy bits (plane 0, as k_occupancy_bits)
+// and the radius plane after them: 2 bits per block (16 blocks a word), for
+// an empty block b the largest r <= kEmptyRadiusMax such that every block
+// within Chebyshev distance r of b is empty (outside the grid counts as
+// empty), 0 for occupied blocks.  The blocks around a workgroup's 256
+// consecutive blocks lie within empty_reach bit positions of them: the
+// workgroup decides the occupancy of that window itself (from min/max and the
+// TF in LDS), writes plane 0 for its own blocks, and reads each x-row of a
+// neighbourhood as one bit field of at most 2R + 1 bits.
 __host__ __device__ inline int64_t empty_reach(const VolConst &v) {
   return kEmptyRadiusMax * (1 + (int64_t)v.nbx + (int64_t)v.nbx * v.nby);
 }
 __host__ __device__ inline int64_t empty_window_words(const VolConst &v) {
   return (kWgSize + 2 * empty_reach(v)) / 32 + 2;
+}
+__host__ __device__ inline uint32_t planes_lds_bytes(const VolConst &v, int K) {
+  return ((tf_lds_bytes(K) + 15u) & ~15u) + (uint32_t)empty_window_words(v) * 4u;
 }
 
 // Bits 0..15 of x moved to the even positions 0, 2, .., 30.
@@ -130,55 +135,78 @@ __device__ inline uint32_t spread16(uint32_t x) {
   return x;
 }
 
-__global__ __launch_bounds__(kWgSize) void k_empty_radius(const VolConst v, uint32_t *bits) {
+__global__ __launch_bounds__(kWgSize) void k_occupancy_planes(const VolConst v, const TfConst tf, uint32_t *bits) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
-  uint32_t *win = reinterpret_cast<uint32_t *>(lds);
+  TfShared s = carve_tf(lds, tf.K);
+  uint32_t *win = reinterpret_cast<uint32_t *>(lds + ((tf_lds_bytes(tf.K) + 15u) & ~15u));
+  load_tf(s, tf);  // ends with a barrier
   const int64_t nb = (int64_t)v.nbx * v.nby * v.nbz;
   const int64_t words = (nb + 31) / 32;
   const int64_t b0 = (int64_t)blockIdx.x * kWgSize;
   const int64_t w0 = max(b0 - empty_reach(v), (int64_t)0) >> 5;
   const int64_t nw = empty_window_words(v);
-  for (int64_t j = threadIdx.x; j < nw; j += kWgSize) win[j] = w0 + j < words ? bits[w0 + j] : 0u;
+  // window occupancy: each wavefront decides 64 blocks (two words) at a time
+  const int lane = threadIdx.x % kWaveSize, wave = threadIdx.x / kWaveSize;
+  for (int64_t j = 2 * wave; j < nw; j += 2 * (kWgSize / kWaveSize)) {
+    const int64_t q = 32 * (w0 + j) + lane;
+    const unsigned long long m = __ballot(q < nb && block_occupied(v, s, tf, (int)q));
+    if (lane == 0) win[j] = (uint32_t)m;
+    if (lane == 32 && j + 1 < nw) win[j + 1] = (uint32_t)(m >> 32);
+  }
   __syncthreads();
+  if (threadIdx.x < kWgSize / 32) {  // plane 0 of this workgroup's blocks
+    const int64_t w = (b0 >> 5) + threadIdx.x;
+    if (w < words) bits[w] = win[w - w0];
+  }
   const int64_t b = b0 + threadIdx.x;
   int rad = 0;
   if (b < nb) {
     const int bx = (int)(b % v.nbx), by = (int)((b / v.nbx) % v.nby), bz = (int)(b / ((int64_t)v.nbx * v.nby));
     constexpr int R = kEmptyRadiusMax;
+    const int lx = max(bx - R, 0), hx = min(bx + R, v.nbx - 1), c = bx - lx, n = hx - lx + 1;
     int near = R + 1;  // smallest Chebyshev distance of an occupied block, capped at R + 1
     for (int dz = -R; dz <= R; ++dz)
       for (int dy = -R; dy <= R; ++dy) {
         const int y = by + dy, z = bz + dz;
         if (y < 0 || z < 0 || y >= v.nby || z >= v.nbz) continue;
-        const int dyz = max(abs(dy), abs(dz));
-#pragma unroll
-        for (int dx = -R; dx <= R; ++dx) {
-          const int x = bx + dx;
-          if (x < 0 || x >= v.nbx) continue;
-          const int64_t q = x + (int64_t)v.nbx * (y + (int64_t)v.nby * z);
-          if ((win[(q >> 5) - w0] >> (q & 31)) & 1u) near = min(near, max(dyz, abs(dx)));
+        // bits lx .. hx of row (y, z)
+        const int64_t q = lx + (int64_t)v.nbx * (y + (int64_t)v.nby * z) - 32 * w0;
+        const int64_t w = q >> 5;
+        const int off = (int)(q & 31);
+        const uint64_t pair = (uint64_t)win[w] | (w + 1 < nw ? (uint64_t)win[w + 1] << 32 : 0ull);
+        const uint32_t field = (uint32_t)(pair >> off) & ((1u << n) - 1u);
+        if (!field) continue;
+        int dx = R;
+        for (int t = 0; t < R; ++t) {  // nearest set bit to position c
+          const int lo = max(c - t, 0), hi = min(c + t, n - 1);
+          if (field & (((1u << (hi - lo + 1)) - 1u) << lo)) {
+            dx = t;
+            break;
+          }
         }
+        near = min(near, max(max(abs(dy), abs(dz)), dx));
       }
     rad = near - 1 < 0 ? 0 : near - 1;
   }
   const unsigned long long lo = __ballot(rad & 1), hi = __ballot(rad & 2);
-  const int lane = threadIdx.x % kWaveSize;
   const int64_t rw = words + (b >> 4);
   if ((lane & 15) == 0 && b < nb)
     bits[rw] = spread16((uint32_t)(lo >> lane)) | (spread16((uint32_t)(hi >> lane)) << 1);
 }
 
-bool empty_radius_fits(const VolConst &v) { return empty_window_words(v) * 4 <= (int64_t)max_lds_per_workgroup(); }
+bool occupancy_planes_fit(const VolConst &v, int K) { return planes_lds_bytes(v, K) <= max_lds_per_workgroup(); }
 
-hipError_t launch_empty_radius(const VolConst &v, uint32_t *bits, hipStream_t s) {
+hipError_t launch_occupancy_planes(const VolConst &v, const TfConst &tf, uint32_t *bits, hipStream_t s) {
+  if (!occupancy_planes_fit(v, tf.K)) return hipErrorInvalidValue;  // the caller leaps block by block
+  VolConst vm = v;
+  vm.occ = nullptr;  // decide from min/max
   const int64_t nb = (int64_t)v.nbx * v.nby * v.nbz;
-  const int64_t lds = empty_window_words(v) * 4;
-  if (!empty_radius_fits(v)) return hipErrorInvalidValue;  // the caller leaps block by block
+  const uint32_t lds = planes_lds_bytes(v, tf.K);
   const unsigned grid = (unsigned)((nb + kWgSize - 1) / kWgSize);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_empty_radius),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_occupancy_planes),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_empty_radius, dim3(grid), dim3(kWgSize), (uint32_t)lds, s, v, bits);
+  hipLaunchKernelGGL(k_occupancy_planes, dim3(grid), dim3(kWgSize), lds, s, vm, tf, bits);
   return hipGetLastError();
 }
 

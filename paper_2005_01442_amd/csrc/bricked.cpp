@@ -270,7 +270,7 @@ vr_status vr_bricked_create(const vr_volume *host_vol, int32_t brick_edge, uint6
   for (auto &th : pool) th.join();
   const size_t nb = (size_t)v->nbricks;
   VolConst fvc = fine_grid(v);
-  v->fine_radius = empty_radius_fits(fvc);
+  v->fine_radius = occupancy_planes_fit(fvc, VR_MAX_TF_NODES);
   if ((e = hipMalloc(&v->minmax_dev, nb * sizeof(float2))) != hipSuccess ||
       (e = hipMalloc(&v->fine_minmax_dev, (size_t)v->nfine * sizeof(float2))) != hipSuccess ||
       (e = hipMalloc(&v->fine_bits_dev, occupancy_bytes(fvc))) != hipSuccess ||
@@ -376,14 +376,11 @@ vr_status vr_bricked_render(vr_bricked *v, const vr_camera *cams, int32_t n_cams
   // of the skip blocks (the walk's leaps)
   if ((e = launch_block_occupancy(vc, a.tf, v->occ_dev, st)) != hipSuccess) return hip_fail(e, "occupancy launch");
   a.fine = fine_grid(v);
-  if ((e = launch_occupancy_bits(a.fine, a.tf, v->fine_bits_dev, st)) != hipSuccess)
-    return hip_fail(e, "occupancy bits launch");
+  e = v->fine_radius ? launch_occupancy_planes(a.fine, a.tf, v->fine_bits_dev, st)
+                     : launch_occupancy_bits(a.fine, a.tf, v->fine_bits_dev, st);
+  if (e != hipSuccess) return hip_fail(e, "occupancy bits launch");
   a.fine.occ = v->fine_bits_dev;
-  a.fine.occ_radius = 0;
-  if (v->fine_radius) {
-    if ((e = launch_empty_radius(a.fine, v->fine_bits_dev, st)) != hipSuccess) return hip_fail(e, "radius launch");
-    a.fine.occ_radius = kEmptyRadiusMax;
-  }
+  a.fine.occ_radius = v->fine_radius ? kEmptyRadiusMax : 0;
   if ((e = hipMemcpyAsync(v->occ_host, v->occ_dev, (size_t)v->nbricks, hipMemcpyDeviceToHost, st)) != hipSuccess ||
       (e = hipStreamSynchronize(st)) != hipSuccess)
     return hip_fail(e, "occupancy readback");

@@ -356,8 +356,8 @@ bool issue(vr_server *s, Batch &b) {
     tc.K = r.K;
     tc.v0 = r.v0;
     tc.scale = (float)(r.K - 1) / (r.v1 - r.v0);
-    e = launch_occupancy_bits(v.vc, tc, r.occ, b.stream);
-    if (e == hipSuccess && r.occ_radius > 0) e = launch_empty_radius(v.vc, r.occ, b.stream);
+    e = r.occ_radius > 0 ? launch_occupancy_planes(v.vc, tc, r.occ, b.stream)
+                         : launch_occupancy_bits(v.vc, tc, r.occ, b.stream);
   }
   if (e == hipSuccess) e = hipEventRecord(b.occ_done, b.stream);
   if (e == hipSuccess && wait_other) e = hipStreamWaitEvent(b.stream, other.occ_done, 0);
@@ -481,7 +481,7 @@ vr_status vr_serve_add_volume(vr_server *s, const vr_volume *vol, int32_t block_
   Volume &v = s->volumes[id];
   v.desc = *vol;
   v.vc = vc;
-  v.radius_fits = empty_radius_fits(vc);
+  v.radius_fits = occupancy_planes_fit(vc, VR_MAX_TF_NODES);
   v.blocks = blocks;
   v.block_bytes = bb;
   *volume_id = id;

@@ -87,10 +87,11 @@ hipError_t launch_block_minmax(const VolConst &v, float2 *out, hipStream_t s);
 hipError_t launch_block_occupancy(const VolConst &v, const TfConst &tf, uint8_t *occ, hipStream_t s);
 // The same decisions packed 32 blocks to a word (ceil(nb / 32) words).
 hipError_t launch_occupancy_bits(const VolConst &v, const TfConst &tf, uint32_t *bits, hipStream_t s);
-// The 2-bit radius plane (ceil(nb / 16) words) after the occupancy bits.
-hipError_t launch_empty_radius(const VolConst &v, uint32_t *bits, hipStream_t s);
-// Whether launch_empty_radius can run for this block grid (its LDS window fits).
-bool empty_radius_fits(const VolConst &v);
+// The occupancy bits and, after them, the 2-bit radius plane (ceil(nb / 16)
+// words) in one launch; hipErrorInvalidValue when its LDS window does not fit
+// (see occupancy_planes_fit; then only launch_occupancy_bits applies).
+hipError_t launch_occupancy_planes(const VolConst &v, const TfConst &tf, uint32_t *bits, hipStream_t s);
+bool occupancy_planes_fit(const VolConst &v, int K);
 // Bytes of the occupancy bits plus the radius plane of a block grid.
 inline size_t occupancy_bytes(const VolConst &v) {
   const int64_t nb = (int64_t)v.nbx * v.nby * v.nbz;
