@@ -180,14 +180,23 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const OrderArgs o,
   __syncthreads();
   for (int q = threadIdx.x; q < n; q += kOrderThreads) atomicAdd(&cnt[order_bucket(o, q)], 1);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int run = 0;
-    for (int b = 0; b < kOrderBuckets; ++b) {
-      const int c = cnt[b];
-      cnt[b] = run;
-      run += c;
-    }
+  // exclusive prefix sum of the counts, one bucket per thread: an inclusive
+  // scan inside each wavefront, then the wavefront totals
+  static_assert(kOrderBuckets == kOrderThreads, "one bucket per thread");
+  __shared__ int wsum[kOrderThreads / kWaveSize];
+  const int lane = threadIdx.x % kWaveSize, wave = threadIdx.x / kWaveSize;
+  const int c = cnt[threadIdx.x];
+  int x = c;
+#pragma unroll
+  for (int off = 1; off < kWaveSize; off <<= 1) {
+    const int y = __shfl_up(x, off, kWaveSize);
+    if (lane >= off) x += y;
   }
+  if (lane == kWaveSize - 1) wsum[wave] = x;
+  __syncthreads();
+  int before = 0;
+  for (int w = 0; w < wave; ++w) before += wsum[w];
+  cnt[threadIdx.x] = before + x - c;
   __syncthreads();
   for (int q = threadIdx.x; q < n; q += kOrderThreads) order[atomicAdd(&cnt[order_bucket(o, q)], 1)] = q;
 }
