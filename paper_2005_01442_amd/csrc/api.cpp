@@ -12,10 +12,6 @@
 #include "vr.h"
 #include "vr_internal.h"
 
-#ifndef VR_EMPTY_RADIUS
-#define VR_EMPTY_RADIUS 3
-#endif
-
 struct vr_blocks {
   const void *data;
   int32_t dtype;
@@ -365,7 +361,7 @@ static vr_status render_views(RenderArgs &a, const vr_camera *cams, int32_t n_ca
     }
   }
   a.vol.occ = bits;
-  a.vol.occ_radius = radius ? VR_EMPTY_RADIUS : 0;
+  a.vol.occ_radius = radius ? kEmptyRadiusMax : 0;
   for (int32_t v0 = 0; v0 < n_cams; v0 += kMaxCamsPerLaunch) {
     const int32_t n = std::min(kMaxCamsPerLaunch, n_cams - v0);
     for (int32_t i = 0; i < n; ++i) check_camera(&cams[v0 + i], &a.cams[i]);
