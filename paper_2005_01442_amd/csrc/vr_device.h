@@ -1098,8 +1098,9 @@ __device__ inline int empty_radius(const VolConst &v, int b);
 // block that is empty under the TF (such a sample would add exactly zero).
 // When no lane has a sample to evaluate, the wavefront leaps to the smallest
 // index any lane may need: its next lattice start, or the first index that
-// may leave its empty block (the lane sits out until then, without looking
-// at its samples).  prep(want, px, py, pz) runs on every lane of the
+// may leave its empty block -- or the cube of empty blocks around it, when
+// the launch carries the radius plane (the lane sits out until then, without
+// looking at its samples).  prep(want, px, py, pz) runs on every lane of the
 // wavefront before the samples of a step (for wavefront-wide staging);
 // visit(k, px, py, pz) evaluates one sample and returns false to stop the ray.
 // post() runs on every lane after the samples of a step.
