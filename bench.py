@@ -451,8 +451,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(
-            f"bench.py measures one GPU: --gpus {args.gpus} is not supported (this build runs on a single "
-            "MI355X; the multi-GPU sharding is design only)",
+            f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the renderer runs on a single "
+            "MI355X; sharding across GPUs is not implemented)",
             file=sys.stderr,
         )
         sys.exit(2)
