@@ -20,6 +20,8 @@ __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfCon
                                uint32_t &evaluated, uint32_t &unstaged) {
   float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, T = 1.0f;
   const float sl2 = mc.step * 1.4426950408889634f;
+  float tf_v0 = tf.v0, tf_scale = tf.scale;  // held in registers (as the walk's grid constants)
+  asm volatile("" : "+v"(tf_v0), "+v"(tf_scale));
   const bool ert_on = mc.ert > 0.0f && mc.ert < 1.0f;
   RayLight rl;
   if constexpr (SHADE) rl = ray_light(sc, r.d);
@@ -63,7 +65,7 @@ __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfCon
         val = reconstruct<DT>(rs, v, st);
         ++unstaged;
       }
-      q = classify(s, tf.K, tf.v0, tf.scale, val);
+      q = classify(s, tf.K, tf_v0, tf_scale, val);
     }
     float e = transmit(q.c.w, sl2);
     float ta = T * (1.0f - e);

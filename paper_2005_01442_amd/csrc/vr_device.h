@@ -1122,6 +1122,11 @@ __device__ inline void walk(const VolConst &v, const TfShared &s, const TfConst 
   int k = wave_min_i32(kb);
   const int kend = wave_max_i32(ke);
   int kfree = kb;  // indices below kfree: before the ray, or left in an empty block
+  // the grid constants of the per-step block lookup and leap held in
+  // registers, so the loop does not re-read them from the kernel arguments
+  // (a scalar load whose wait also drains the wavefront's LDS reads)
+  VolConst vg = v;
+  asm volatile("" : "+v"(vg.nx), "+v"(vg.ny), "+v"(vg.nz), "+v"(vg.edge_shift), "+v"(vg.nbx), "+v"(vg.nby));
   int cur_block = -1;
   bool cur_occ = false;
   int bc[3] = {0, 0, 0};
@@ -1134,7 +1139,7 @@ __device__ inline void walk(const VolConst &v, const TfShared &s, const TfConst 
     lattice_point(r, mc.step, k, px, py, pz);
     const int ix = (int)floorf(px), iy = (int)floorf(py), iz = (int)floorf(pz);
     if (in && mc.skip) {
-      const int b = block_of_cell(v, ix, iy, iz, bc);
+      const int b = block_of_cell(vg, ix, iy, iz, bc);
       if (b != cur_block) {
         cur_block = b;
         cur_occ = block_occupied(v, s, tf, b);
@@ -1142,7 +1147,7 @@ __device__ inline void walk(const VolConst &v, const TfShared &s, const TfConst 
       want = cur_occ;
     }
     if (__ballot(want) == 0ull) {
-      if (in) kfree = leap_target(v, r, bc, mc.step, k, empty_radius(v, cur_block));
+      if (in) kfree = leap_target(vg, r, bc, mc.step, k, empty_radius(v, cur_block));
       const int prop = alive && k < ke ? kfree : 0x7fffffff;
       const int m = wave_min_i32(prop);
       k = m > k + 1 ? m : k + 1;
