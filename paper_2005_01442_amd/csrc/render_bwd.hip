@@ -133,10 +133,10 @@ __device__ inline void box_prepare(GradBox &b, float *grad, const VolConst &v, c
 }
 
 // A lane whose stencil is interior stages its scatter record (x, y, z weights
-// with dv folded into the z weights, and the box cell of tap (0, 0, 0)); the
-// wavefront then applies the staged records one sample at a time with the
-// lanes transposed onto the 64 taps (box_apply).  Clamped stencils, whose taps
-// can coincide, add their taps with LDS atomics right away.
+// with dv folded into the z weights, the box cell of tap (0, 0, 0) and its
+// coordinates); the wavefront then applies the staged records with the lanes
+// transposed onto the 64 taps (box_apply).  Clamped stencils, whose taps can
+// coincide, add their taps with LDS atomics right away.
 __device__ inline bool box_stage(GradBox &b, const VolConst &v, const Stencil &st, float dv) {
   const bool inner = (st.ix >= 1) & (st.ix + 2 <= v.nx - 1) & (st.iy >= 1) & (st.iy + 2 <= v.ny - 1) &
                      (st.iz >= 1) & (st.iz + 2 <= v.nz - 1);
@@ -148,7 +148,15 @@ __device__ inline bool box_stage(GradBox &b, const VolConst &v, const Stencil &s
     *reinterpret_cast<f32x4 *>(rec + 0) = wx;
     *reinterpret_cast<f32x4 *>(rec + 4) = wy;
     *reinterpret_cast<f32x4 *>(rec + 8) = wz;
-    reinterpret_cast<int *>(rec)[12] = (st.iz - 1 - b.oz) * kBoxZ + (st.iy - 1 - b.oy) * kBoxY + (st.ix - 1 - b.ox);
+    // box coordinates of tap (0, 0, 0): its cell, and two packings used to
+    // find where two records' stencils overlap
+    const int x = st.ix - 1 - b.ox, y = st.iy - 1 - b.oy, z = st.iz - 1 - b.oz;
+    int4 m;
+    m.x = z * kBoxZ + y * kBoxY + x;
+    m.y = x + 16 * y + 256 * z;
+    m.z = 4 * (x + 4 * y + 16 * z);
+    m.w = 0;
+    *reinterpret_cast<int4 *>(rec + 12) = m;
     return true;
   }
   int xs[4];
@@ -167,13 +175,19 @@ __device__ inline bool box_stage(GradBox &b, const VolConst &v, const Stencil &s
   return false;
 }
 
-// Wavefront-wide: apply the records of the lanes in `staged`, one record at a
-// time.  For one record the 64 lanes update 64 distinct cells in 64 distinct
-// banks, so a plain read-add-write is exact and conflict-free; records are
-// applied in order (the wavefront's LDS operations execute in issue order),
-// which keeps cells shared between records exact.  (LDS float atomics measure
-// far slower here, also without conflicts; batching the record reads of
-// several records measured slower too.)
+// Wavefront-wide: apply the records of the lanes in `staged`.  For one record
+// the 64 lanes update 64 distinct cells in 64 distinct banks, so a plain
+// read-add-write is exact.  Records are applied two at a time with one LDS
+// round trip: both cells are read before either is written, and where the
+// second record's tap lands on a cell of the first record's stencil, the lane
+// adds the first record's weight for that cell, fetched from the lane that owns
+// it with a cross-lane permute; the writes go out in record order, so a cell
+// shared by the two ends up with both contributions.  The next pair's record
+// words are read before this pair's cells are written (records never alias
+// cells).  An odd record is paired with a zero-weight copy of itself.  (LDS
+// float atomics measure about three times slower here, also without bank
+// conflicts; groups of three or four records, or record words read eight
+// records at a time, measured slower than pairs.)
 __device__ inline void box_apply(GradBox &b, unsigned long long staged) {
   if (staged == 0ull) return;
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -181,27 +195,57 @@ __device__ inline void box_apply(GradBox &b, unsigned long long staged) {
   const int l = threadIdx.x % kWaveSize;
   const int ta = l & 3, tb = (l >> 2) & 3, tc = l >> 4;
   const int off = tc * kBoxZ + tb * kBoxY + ta;
-  // the records of up to kApplyBatch samples are read before their cells are
-  // updated (records are not written here), the cells in record order
-  constexpr int kApplyBatch = 8;
-  while (staged) {
-    float w[kApplyBatch];
-    int cell[kApplyBatch];
-    int n = 0;
-#pragma unroll
-    for (int i = 0; i < kApplyBatch; ++i) {
-      if (staged) {
-        const int sl = __ffsll((long long)staged) - 1;
-        staged &= staged - 1ull;
-        const float *rec = b.recs + sl * kRec;
-        w[i] = rec[ta] * rec[4 + tb] * rec[8 + tc];
-        cell[i] = reinterpret_cast<const int *>(rec)[12] + off;
-        n = i + 1;
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < kApplyBatch; ++i)
-      if (i < n) b.cells[cell[i]] += w[i];
+  // tap coordinates biased by 4 in 4-bit fields: adding another record's
+  // offset (x + 16 y + 256 z) leaves every field in [4, 7] exactly when the
+  // shifted tap is inside that record's stencil
+  const int tp = (ta + 4) + 16 * (tb + 4) + 256 * (tc + 4);
+  const int l4 = 4 * l;
+  struct Pair {
+    float x[2], y[2], z[2];  // this lane's tap weights, not yet multiplied
+    int cell[2], P[2], Q4[2];
+    bool has1;
+  };
+  auto load_pair = [&](Pair &q) {
+    const int sl0 = __ffsll((long long)staged) - 1;
+    staged &= staged - 1ull;
+    q.has1 = staged != 0ull;
+    const int sl1 = q.has1 ? __ffsll((long long)staged) - 1 : sl0;
+    staged &= staged - 1ull;
+    const float *r0 = b.recs + sl0 * kRec, *r1 = b.recs + sl1 * kRec;
+    const int4 m0 = *reinterpret_cast<const int4 *>(r0 + 12);
+    const int4 m1 = *reinterpret_cast<const int4 *>(r1 + 12);
+    q.x[0] = r0[ta];
+    q.y[0] = r0[4 + tb];
+    q.z[0] = r0[8 + tc];
+    q.x[1] = r1[ta];
+    q.y[1] = r1[4 + tb];
+    q.z[1] = r1[8 + tc];
+    q.cell[0] = m0.x + off;
+    q.P[0] = m0.y;
+    q.Q4[0] = m0.z;
+    q.cell[1] = m1.x + off;
+    q.P[1] = m1.y;
+    q.Q4[1] = m1.z;
+  };
+  Pair cur;
+  load_pair(cur);
+  for (;;) {
+    const float w0 = cur.x[0] * cur.y[0] * cur.z[0];
+    const float w1 = cur.has1 ? cur.x[1] * cur.y[1] * cur.z[1] : 0.0f;
+    // the first record's weight at this lane's tap of the second record
+    const float c = __builtin_bit_cast(
+        float, __builtin_amdgcn_ds_bpermute(l4 + cur.Q4[1] - cur.Q4[0], __builtin_bit_cast(int, w0)));
+    float v0 = b.cells[cur.cell[0]];
+    float v1 = b.cells[cur.cell[1]];
+    const bool more = staged != 0ull;
+    Pair nxt;
+    if (more) load_pair(nxt);
+    const int t = tp + cur.P[1] - cur.P[0];
+    v1 += (t & 0xCCC) == 0x444 ? c : 0.0f;
+    b.cells[cur.cell[0]] = v0 + w0;
+    b.cells[cur.cell[1]] = v1 + w1;
+    if (!more) break;
+    cur = nxt;
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
