@@ -74,6 +74,26 @@ def test_grad_volume_only_with_skipping_matches_oracle():
     assert max(e) <= REL
 
 
+@pytest.mark.parametrize("W", [8, 11])
+def test_grad_narrow_ray_bundle_matches_oracle(W):
+    """All rays of a tile inside about one voxel (1 degree field of view): the
+    stencils of one wavefront step coincide or overlap, so nearly every pair
+    of scatter records applied together shares cells, and the number of
+    records per step varies (odd counts included; W = 11 leaves ragged
+    tiles)."""
+    import dataclasses
+
+    grid, tf, cams, _ = _case(n=16, views=2, W=W, seed=57)
+    cams = [dataclasses.replace(c, fov_y=float(np.deg2rad(1.0))) for c in cams]
+    g = np.random.default_rng(58).standard_normal((2, W, W, 4))
+    gv, gtf, _ = _gpu_grad(grid, tf, cams, g, 0.25)
+    rv, rt = oracle.grad(grid, cams, tf, 0.25, g)
+    ev, et = _rel(gv, rv), _rel(gtf, rt)
+    log(f"narrow bundle W={W}: grid rel {ev[0]:.2e}/{ev[1]:.2e}  tf rel {et[0]:.2e}/{et[1]:.2e}")
+    assert np.abs(rv).max() > 0.0
+    assert max(ev) <= REL and max(et) <= REL
+
+
 def test_grad_against_fp64_central_differences():
     """GPU analytic gradient on 32 seeded voxels of the non-zero region
     against central differences of the FP64 oracle render."""
