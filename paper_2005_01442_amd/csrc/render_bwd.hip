@@ -59,7 +59,7 @@ __host__ __device__ inline uint32_t box_lds_offset(int K, bool with_tf_grad) {
 
 struct GradBox {
   float *cells;  // this wavefront's LDS cells, [z][y][x], zero outside use
-  float *recs;   // this wavefront's staged scatter records, kRec dwords per lane
+  float *recs;   // this wavefront's staged scatter records, kRec dwords per slot
   int ox, oy, oz;
   bool valid;
 };
@@ -141,7 +141,11 @@ __device__ inline bool box_stage(GradBox &b, const VolConst &v, const Stencil &s
   const bool inner = (st.ix >= 1) & (st.ix + 2 <= v.nx - 1) & (st.iy >= 1) & (st.iy + 2 <= v.ny - 1) &
                      (st.iz >= 1) & (st.iz + 2 <= v.nz - 1);
   if (inner) {
-    float *rec = b.recs + (threadIdx.x % kWaveSize) * kRec;
+    // records are packed in lane order: this lane's slot is its rank among
+    // the staging lanes (all of which are active here together)
+    const unsigned long long act = __ballot(1);
+    const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
+    float *rec = b.recs + rank * kRec;
     f32x4 wx = {st.wx[0], st.wx[1], st.wx[2], st.wx[3]};
     f32x4 wy = {st.wy[0], st.wy[1], st.wy[2], st.wy[3]};
     f32x4 wz = {dv * st.wz[0], dv * st.wz[1], dv * st.wz[2], dv * st.wz[3]};
@@ -175,16 +179,17 @@ __device__ inline bool box_stage(GradBox &b, const VolConst &v, const Stencil &s
   return false;
 }
 
-// Wavefront-wide: apply the records of the lanes in `staged`.  For one record
-// the 64 lanes update 64 distinct cells in 64 distinct banks, so a plain
-// read-add-write is exact.  Records are applied two at a time with one LDS
+// Wavefront-wide: apply the records of the lanes in `staged` (packed in slots
+// 0 .. n-1 by box_stage).  For one record the 64 lanes update 64 distinct
+// cells in 64 distinct banks, so a plain read-add-write is exact.  Records are
+// applied two at a time with one LDS
 // round trip: both cells are read before either is written, and where the
 // second record's tap lands on a cell of the first record's stencil, the lane
 // adds the first record's weight for that cell, fetched from the lane that owns
 // it with a cross-lane permute; the writes go out in record order, so a cell
 // shared by the two ends up with both contributions.  The next pair's record
 // words are read before this pair's cells are written (records never alias
-// cells).  An odd record is paired with a zero-weight copy of itself.  (LDS
+// cells).  An odd last record is applied on its own.  (LDS
 // float atomics measure about three times slower here, also without bank
 // conflicts; groups of three or four records, or record words read eight
 // records at a time, measured slower than pairs.)
@@ -200,18 +205,14 @@ __device__ inline void box_apply(GradBox &b, unsigned long long staged) {
   // shifted tap is inside that record's stencil
   const int tp = (ta + 4) + 16 * (tb + 4) + 256 * (tc + 4);
   const int l4 = 4 * l;
+  const int n = __popcll(staged);
   struct Pair {
     float x[2], y[2], z[2];  // this lane's tap weights, not yet multiplied
     int cell[2], P[2], Q4[2];
-    bool has1;
   };
-  auto load_pair = [&](Pair &q) {
-    const int sl0 = __ffsll((long long)staged) - 1;
-    staged &= staged - 1ull;
-    q.has1 = staged != 0ull;
-    const int sl1 = q.has1 ? __ffsll((long long)staged) - 1 : sl0;
-    staged &= staged - 1ull;
-    const float *r0 = b.recs + sl0 * kRec, *r1 = b.recs + sl1 * kRec;
+  // records i and i + 1 (adjacent slots)
+  auto load_pair = [&](int i, Pair &q) {
+    const float *r0 = b.recs + i * kRec, *r1 = r0 + kRec;
     const int4 m0 = *reinterpret_cast<const int4 *>(r0 + 12);
     const int4 m1 = *reinterpret_cast<const int4 *>(r1 + 12);
     q.x[0] = r0[ta];
@@ -227,25 +228,35 @@ __device__ inline void box_apply(GradBox &b, unsigned long long staged) {
     q.P[1] = m1.y;
     q.Q4[1] = m1.z;
   };
-  Pair cur;
-  load_pair(cur);
-  for (;;) {
-    const float w0 = cur.x[0] * cur.y[0] * cur.z[0];
-    const float w1 = cur.has1 ? cur.x[1] * cur.y[1] * cur.z[1] : 0.0f;
-    // the first record's weight at this lane's tap of the second record
-    const float c = __builtin_bit_cast(
-        float, __builtin_amdgcn_ds_bpermute(l4 + cur.Q4[1] - cur.Q4[0], __builtin_bit_cast(int, w0)));
-    float v0 = b.cells[cur.cell[0]];
-    float v1 = b.cells[cur.cell[1]];
-    const bool more = staged != 0ull;
-    Pair nxt;
-    if (more) load_pair(nxt);
-    const int t = tp + cur.P[1] - cur.P[0];
-    v1 += (t & 0xCCC) == 0x444 ? c : 0.0f;
-    b.cells[cur.cell[0]] = v0 + w0;
-    b.cells[cur.cell[1]] = v1 + w1;
-    if (!more) break;
-    cur = nxt;
+  int i = 0;
+  if (n >= 2) {
+    Pair cur;
+    load_pair(0, cur);
+    for (;;) {
+      const float w0 = cur.x[0] * cur.y[0] * cur.z[0];
+      const float w1 = cur.x[1] * cur.y[1] * cur.z[1];
+      // the first record's weight at this lane's tap of the second record
+      const float c = __builtin_bit_cast(
+          float, __builtin_amdgcn_ds_bpermute(l4 + cur.Q4[1] - cur.Q4[0], __builtin_bit_cast(int, w0)));
+      float v0 = b.cells[cur.cell[0]];
+      float v1 = b.cells[cur.cell[1]];
+      const bool more = i + 3 < n;
+      Pair nxt;
+      if (more) load_pair(i + 2, nxt);
+      const int t = tp + cur.P[1] - cur.P[0];
+      v1 += (t & 0xCCC) == 0x444 ? c : 0.0f;
+      b.cells[cur.cell[0]] = v0 + w0;
+      b.cells[cur.cell[1]] = v1 + w1;
+      i += 2;
+      if (!more) break;
+      cur = nxt;
+    }
+  }
+  if (i < n) {  // an odd last record
+    const float *r = b.recs + i * kRec;
+    const float w = r[ta] * r[4 + tb] * r[8 + tc];
+    const int cell = reinterpret_cast<const int *>(r)[12] + off;
+    b.cells[cell] += w;
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
