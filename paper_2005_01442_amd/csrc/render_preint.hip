@@ -120,6 +120,22 @@ __device__ inline float4 march_preint(const VolConst &v, const TfShared &s, cons
   int k = wave_min_i32(kb);
   const int kend = wave_max_i32(ke);
   int kfree = kb;  // points below kfree: before the ray, or left in an empty block
+  // the grid constants of the block lookup and leap pinned in scalar
+  // registers, so the loop does not re-read them from the kernel arguments
+  // (vector registers would exceed this kernel's budget)
+  VolConst vg = v;
+  {
+    int a0 = __builtin_amdgcn_readfirstlane(vg.nx), a1 = __builtin_amdgcn_readfirstlane(vg.ny),
+        a2 = __builtin_amdgcn_readfirstlane(vg.nz), a3 = __builtin_amdgcn_readfirstlane(vg.edge_shift),
+        a4 = __builtin_amdgcn_readfirstlane(vg.nbx), a5 = __builtin_amdgcn_readfirstlane(vg.nby);
+    asm volatile("" : "+s"(a0), "+s"(a1), "+s"(a2), "+s"(a3), "+s"(a4), "+s"(a5));
+    vg.nx = a0;
+    vg.ny = a1;
+    vg.nz = a2;
+    vg.edge_shift = a3;
+    vg.nbx = a4;
+    vg.nby = a5;
+  }
   int cb = -1;
   bool cocc = false;
   int bc[3] = {0, 0, 0};
@@ -142,7 +158,7 @@ __device__ inline float4 march_preint(const VolConst &v, const TfShared &s, cons
     const int ix = (int)floorf(px), iy = (int)floorf(py), iz = (int)floorf(pz);
     if (in) {
       if (mc.skip) {
-        const int b = block_of_cell(v, ix, iy, iz, bc);
+        const int b = block_of_cell(vg, ix, iy, iz, bc);
         bool pair = cocc;
         if (b != cb) {
           const int pb = cb;
@@ -164,7 +180,7 @@ __device__ inline float4 march_preint(const VolConst &v, const TfShared &s, cons
       int prop = 0x7fffffff;
       if (in) {
         if (mc.skip && !cocc) {
-          kfree = leap_target(v, r, bc, mc.step, k);
+          kfree = leap_target(vg, r, bc, mc.step, k);
           prop = kfree;
         } else {
           prop = k + 1;
