@@ -170,6 +170,16 @@ static VolConst fine_grid(const vr_bricked *v) {
   return f;
 }
 
+// A device buffer released on its stream when it goes out of scope (after the
+// work queued with it).
+struct StreamBuffer {
+  int32_t *p;
+  hipStream_t s;
+  ~StreamBuffer() {
+    if (p) (void)hipFreeAsync(p, s);
+  }
+};
+
 static void destroy(vr_bricked *v) {
   if (!v) return;
   if (v->host_bricks) (void)hipHostFree(v->host_bricks);
@@ -397,6 +407,16 @@ vr_status vr_bricked_render(vr_bricked *v, const vr_camera *cams, int32_t n_cams
   std::vector<char> in_pass((size_t)v->nbricks, 0);
   for (int32_t view = 0; view < n_cams; ++view) {
     check_camera(&cams[view], &a.cam);
+    // the in-core kernel's centre-out order of the super-tiles, shared by the
+    // passes of this view (raster order if it cannot be allocated)
+    RenderArgs ra{};
+    ra.vol = vc;
+    ra.W = a.W;
+    ra.H = a.H;
+    ra.n_views = 1;
+    ra.cams[0] = a.cam;
+    const StreamBuffer tile_order{make_tile_order(ra, st), st};
+    a.order = tile_order.p;
     // 2. front-to-back order of the occupied bricks
     order_bricks(a.cam, v->E, v->nbx, v->nby, v->nbz, v->occ_host, order);
     // 3. passes

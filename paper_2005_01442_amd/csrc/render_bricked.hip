@@ -79,8 +79,10 @@ __device__ inline float reconstruct_slot(const char *slot, int S, int ox, int oy
   return combine(s, t);
 }
 
-// One pass over one view.  Workgroups of 16x16 pixels in raster order,
-// wavefronts of 8x8 that march their rays in step (the walk of the in-core
+// One pass over one view.  Workgroups of 16x16 pixels, taken centre-out when
+// the launch carries the in-core kernel's super-tile order (the tiles whose
+// rays cross the most volume first), else in raster order; wavefronts of 8x8
+// that march their rays in step (the walk of the in-core
 // kernel, started at each ray's saved index): samples in empty bricks are
 // leapt over, samples in resident bricks evaluated from their slot, and a
 // ray parks at its first sample in an occupied brick of a later pass.
@@ -95,8 +97,9 @@ __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(3, 3)))
   TfShared s = carve_tf(lds, a.tf.K);
   load_tf(s, a.tf);
   const int tiles_x = (a.W + kSuperEdge - 1) / kSuperEdge;
+  const int q = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
   int col, row;
-  pixel_of((int)(blockIdx.x % tiles_x), (int)(blockIdx.x / tiles_x), col, row);
+  pixel_of(q % tiles_x, q / tiles_x, col, row);
   const bool inside = col < a.W && row < a.H;
   const size_t pix = inside ? (size_t)row * a.W + col : 0;
   int kstart = 0;

@@ -59,6 +59,7 @@ struct BrickedArgs {
   int32_t W, H;
   int32_t first;           // initialise the ray state
   int32_t use_box;         // stage LDS value boxes from the slots (set at launch)
+  const int32_t *order;    // workgroup -> super-tile (centre-out, as in core), or nullptr: raster order
 };
 
 // Largest dynamic LDS a workgroup may allocate on the current device.
