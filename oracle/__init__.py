@@ -82,6 +82,8 @@ def _prototypes(L):
         f64 = ctypes.c_double
         f32 = ctypes.c_float
         L.oracle_num_threads.restype = i32
+        L.oracle_set_num_threads.argtypes = [i32]
+        L.oracle_set_num_threads.restype = None
         L.oracle_blocks.argtypes = [P, i32, i64, i64, i64, i32, P]
         L.oracle_blocks.restype = i32
         L.oracle_occupancy.argtypes = [P, i64, P, i32, f32, f32, f32, P]
@@ -90,7 +92,7 @@ def _prototypes(L):
                                     P, i32, i32, P, i64, P, P, P]
         L.oracle_render.restype = i32
         L.oracle_grad.argtypes = [P, i32, i64, i64, i64, P, i32, i32, i32, P, i32, f64, f64, f64, f64,
-                                  P, i32, P, P, P]
+                                  P, i32, P, P, P, P, P]
         L.oracle_grad.restype = i32
         L.oracle_ray.argtypes = [P, i32, i32, i64, i64, i64, i64, i64, f64, P, P]
         L.oracle_ray.restype = i32
@@ -151,6 +153,11 @@ def pack_cameras(cameras) -> np.ndarray:
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads the following oracle calls use (n >= 1)."""
+    lib().oracle_set_num_threads(int(n))
 
 
 def blocks(vol, edge: int = 16) -> np.ndarray:
@@ -234,10 +241,13 @@ def render(vol, cameras, tf, step, ert=0.0, occ=None, edge=16, pixels=None, shad
     return dict(rgba=rgba, flags=flags, counts=counts)
 
 
-def grad(vol, cameras, tf, step, grad_rgba, ert=0.0, occ=None, edge=16, want_volume=True, want_tf=True):
+def grad(vol, cameras, tf, step, grad_rgba, ert=0.0, occ=None, edge=16, want_volume=True, want_tf=True,
+         magnitudes=False):
     """Gradient of sum(grad_rgba * RGBA) w.r.t. the voxel values and the TF
     table, in FP64.  Returns (grad_volume shaped like vol or None, grad_tf (K, 4)
-    or None)."""
+    or None); with ``magnitudes`` also the same sums taken over the terms'
+    magnitudes (the scale of any evaluation's rounding error), as a 4-tuple
+    (grad_volume, grad_tf, mag_volume, mag_tf)."""
     vol, dt, nx, ny, nz = _vol(vol)
     cams = pack_cameras(cameras)
     W, H = int(cameras[0].width), int(cameras[0].height)
@@ -245,14 +255,17 @@ def grad(vol, cameras, tf, step, grad_rgba, ert=0.0, occ=None, edge=16, want_vol
     g = np.ascontiguousarray(grad_rgba, dtype=np.float64).reshape(len(cameras), H, W, 4)
     gv = np.zeros(vol.shape, dtype=np.float64) if want_volume else None
     gt = np.zeros(table.shape, dtype=np.float64) if want_tf else None
+    mv = np.zeros(vol.shape, dtype=np.float64) if (want_volume and magnitudes) else None
+    mt = np.zeros(table.shape, dtype=np.float64) if (want_tf and magnitudes) else None
     occ_a = None if occ is None else np.ascontiguousarray(occ, dtype=np.uint8)
     rc = lib().oracle_grad(
         _ptr(vol), dt, nx, ny, nz, _ptr(cams), len(cameras), W, H, _ptr(table), table.shape[0],
         f32(tf.v0), f32(tf.v1), f32(step), f32(ert), _ptr(occ_a), int(edge), _ptr(g), _ptr(gv), _ptr(gt),
+        _ptr(mv), _ptr(mt),
     )
     if rc:
         raise ValueError("oracle_grad rejected its arguments")
-    return gv, gt
+    return (gv, gt, mv, mt) if magnitudes else (gv, gt)
 
 
 def lattice(cameras, dims_xyz, step) -> np.ndarray:

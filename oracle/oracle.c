@@ -75,6 +75,16 @@ int oracle_num_threads(void)
 #endif
 }
 
+/* Threads of the following calls (the CPU baseline times one core too). */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Block min/max (the auxiliary structure for empty-space leaping).          */
 /*                                                                           */
@@ -616,6 +626,10 @@ int oracle_render_shaded(const void *data, int dtype, long nx, long ny, long nz,
 /* samples are stored and the suffix sums S_k formed explicitly.             */
 /* grad_rgba: 4 doubles per pixel of the full image set.                     */
 /* grad_vol (nx*ny*nz) and grad_tf (K*4) are accumulated into (+=).          */
+/* mag_vol / mag_tf (optional, same shapes, +=) receive the same sums with  */
+/* every term replaced by its magnitude, the suffix-sum difference included */
+/* (|T_{k+1} c_k| + |S_k|): the scale of the rounding error of any          */
+/* evaluation of these sums, for element-wise error bounds.                 */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     or_sample s;
@@ -628,7 +642,8 @@ typedef struct {
 
 int oracle_grad(const void *data, int dtype, long nx, long ny, long nz, const double *cams, int n_cams, int W,
                 int H, const float *tf, int K, double v0, double v1, double step, double ert, const uint8_t *occ,
-                int edge, const double *grad_rgba, double *grad_vol, double *grad_tf)
+                int edge, const double *grad_rgba, double *grad_vol, double *grad_tf, double *mag_vol,
+                double *mag_tf)
 {
     if (!data || !cams || !tf || !grad_rgba || n_cams <= 0 || W <= 0 || H <= 0 || K < 2 || !(v1 > v0) ||
         !(step > 0.0))
@@ -678,14 +693,18 @@ int oracle_grad(const void *data, int dtype, long nx, long ny, long nz, const do
             for (long m = n - 1; m >= 0; --m) {
                 or_rec *r = &rec[m];
                 double Tnext = r->Tk * exp(-r->val[3] * step);
-                double dval[4];
-                double ds = 0.0;
+                double dval[4], dmag[4];
+                double ds = 0.0, dsmag = 0.0;
                 for (int c = 0; c < 3; ++c) {
                     dval[c] = g[c] * r->Tk * r->alpha;
                     ds += g[c] * (Tnext * r->val[c] - S[c]);
+                    dmag[c] = fabs(dval[c]);
+                    dsmag += fabs(g[c]) * (Tnext * fabs(r->val[c]) + fabs(S[c]));
                 }
                 ds += g[3] * Tend;
+                dsmag += fabs(g[3]) * Tend;
                 dval[3] = step * ds;
+                dmag[3] = step * dsmag;
                 for (int c = 0; c < 3; ++c) S[c] += r->Tk * r->alpha * r->val[c];
                 if (grad_tf) {
                     for (int c = 0; c < 4; ++c) {
@@ -693,15 +712,29 @@ int oracle_grad(const void *data, int dtype, long nx, long ny, long nz, const do
                         grad_tf[4 * r->j + c] += (1.0 - r->w) * dval[c];
 #pragma omp atomic
                         grad_tf[4 * (r->j + 1) + c] += r->w * dval[c];
+                        if (mag_tf) {
+#pragma omp atomic
+                            mag_tf[4 * r->j + c] += (1.0 - r->w) * dmag[c];
+#pragma omp atomic
+                            mag_tf[4 * (r->j + 1) + c] += r->w * dmag[c];
+                        }
                     }
                 }
                 if (grad_vol && !r->clamped) {
-                    double dv = 0.0;
-                    for (int c = 0; c < 4; ++c)
-                        dv += dval[c] * ((double)tf[4 * (r->j + 1) + c] - (double)tf[4 * r->j + c]) * slope_scale;
+                    double dv = 0.0, dvmag = 0.0;
+                    for (int c = 0; c < 4; ++c) {
+                        const double slope =
+                            ((double)tf[4 * (r->j + 1) + c] - (double)tf[4 * r->j + c]) * slope_scale;
+                        dv += dval[c] * slope;
+                        dvmag += dmag[c] * fabs(slope);
+                    }
                     for (int t = 0; t < 64; ++t) {
 #pragma omp atomic
                         grad_vol[r->s.tap[t]] += dv * r->s.wt[t];
+                        if (mag_vol) {
+#pragma omp atomic
+                            mag_vol[r->s.tap[t]] += dvmag * fabs(r->s.wt[t]);
+                        }
                     }
                 }
             }

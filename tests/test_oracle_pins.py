@@ -437,3 +437,27 @@ def test_grad_with_ert_matches_fd_with_fixed_stop(oracle_lib):
         if checked == 12:
             break
     assert checked >= 8
+
+
+def test_grad_magnitudes_bound_the_gradient(oracle_lib):
+    """The magnitude sums (every term of the adjoint sums by its absolute
+    value, the suffix-sum difference |T_{k+1} c_k| + |S_k| included) bound the
+    gradient element-wise (triangle inequality), equal it where no term can
+    cancel (dC/dc of a homogeneous medium: every term positive), do not depend
+    on the sign of dL/dRGBA and scale with its magnitude."""
+    vol, tf, cams, g = _grad_case()
+    step = 0.4375
+    gv, gt, mv, mt = oracle.grad(vol, cams, tf, step, g, magnitudes=True)
+    assert np.all(mv >= np.abs(gv) * (1 - 1e-12)) and np.all(mt >= np.abs(gt) * (1 - 1e-12))
+    assert (mv > np.abs(gv) * (1 + 1e-6)).any()  # cancellation happens somewhere
+    gv2, gt2, mv2, mt2 = oracle.grad(vol, cams, tf, step, -2.0 * g, magnitudes=True)
+    assert np.allclose(gv2, -2.0 * gv, rtol=1e-12, atol=1e-15) and np.allclose(mv2, 2.0 * mv, rtol=1e-12, atol=1e-15)
+    assert np.allclose(mt2, 2.0 * mt, rtol=1e-12, atol=1e-15)
+    n = 16
+    hv = np.full((n, n, n), 3, dtype=np.uint16)
+    htf = _constant_tf((0.25, 0.5, 1.0), 1.0 / 16.0)
+    cam = synth.ortho_axis_camera(n, 4, 4)
+    gg = np.zeros((1, 4, 4, 4))
+    gg[0, 1, 2, 0] = 1.0
+    _, ht, _, hm = oracle.grad(hv, [cam], htf, 0.5, gg, magnitudes=True)
+    assert abs(hm[3, 0] - ht[3, 0]) <= 1e-12 * abs(ht[3, 0])
