@@ -16,11 +16,19 @@ Printed as one JSON line:
   serve          the serving mix: 8 resident volumes, Poisson arrivals at
                  200 req/s, random poses, 256^2 / 512^2 / 1024^2 images;
                  p50/p99 latency (submit -> completion) and rays/s
-  roofline       effective gather bytes (evaluated samples x 64 taps x 2 B)
-                 per forward launch / that launch's average duration (HIP
-                 events on the launch stream) against the 8 TB/s HBM peak
-  cpu_baseline   the FP64 oracle on a bounded seeded sample of the same frame
-                 on this host's cores
+  roofline       compulsory HBM bytes of one forward launch (the int16 volume
+                 read once + the fp32 RGBA image written once) / that launch's
+                 median duration (HIP events on the launch stream), against
+                 the 8 TB/s HBM peak and against the achievable bandwidth a
+                 streaming-read probe measures on this GPU; the HBM-side
+                 traffic the PMC counters saw (stored, with its ratio to the
+                 compulsory bytes) and the VALU-issue ceiling beside it
+  effective_gather  evaluated samples x 64 taps x 2 B per launch / time: the
+                 gather rate the taps are served at (LDS boxes and caches
+                 serve most of them, so it is not an HBM figure)
+  cpu_baseline   the FP64 oracle on the same frame (same skipping and early
+                 termination, rays counted over all pixels as on the GPU) on
+                 this host's cores, and on one core for a seeded sample
 """
 
 from __future__ import annotations
@@ -38,6 +46,10 @@ sys.path.insert(0, ROOT)
 METRIC = "samples/s and rays/s (fwd, fwd+bwd) on 512x512x400 at 1024^2; HBM roofline %; p99"
 HBM_PEAK_GBS = 8000.0
 TAPS_BYTES_I16 = 64 * 2
+# MI355X: 256 CUs x 4 SIMDs at 2.4 GHz; one wave64 VALU instruction takes a
+# SIMD 4 cycles without packed-FP32 (disabled in this build), so the chip
+# issues 256 x 4 x 2.4e9 / 4 wave64 VALU instructions per second
+VALU_WAVE_INSTS_PER_S = 256 * 4 * 2.4e9 / 4
 
 
 def log(msg):
@@ -56,7 +68,10 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-bwd", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="all-core oracle budget (the whole frame if it fits)")
+    ap.add_argument("--cpu-single-seconds", type=float, default=8.0, help="single-core oracle budget")
+    ap.add_argument("--no-probe", action="store_true", help="skip the achievable-HBM streaming-read probe")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "render_fwd_c1_traffic.json"))
     ap.add_argument("--no-c3", action="store_true", help="skip the differentiable 256^3 x 64-view measurement")
     ap.add_argument("--no-lit", action="store_true", help="skip the lit (local lighting) forward measurement")
@@ -88,6 +103,37 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
+def stats_ms(ev_ms):
+    """Median and p99 (nearest rank) of per-step event times."""
+    import numpy as np
+
+    a = np.sort(np.asarray(ev_ms, dtype=np.float64))
+    return float(np.median(a)), float(a[min(len(a) - 1, int(np.ceil(0.99 * len(a))) - 1)])
+
+
+def hbm_probe(vr, torch, gib=8, repeats=10):
+    """Achievable HBM read bandwidth: a streaming 16-byte-load read of a
+    ``gib`` GiB buffer, best of ``repeats`` (HIP events)."""
+    nbytes = gib << 30
+    buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    buf.fill_(1)
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    vr.vr_probe_stream_read(buf, sink)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(repeats):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        vr.vr_probe_stream_read(buf, sink)
+        b.record()
+        torch.cuda.synchronize()
+        best = min(best, a.elapsed_time(b))
+    del buf
+    torch.cuda.empty_cache()
+    return {"bytes": nbytes, "best_ms": best, "gb_per_s": nbytes / (best * 1e-3) / 1e9, "repeats": repeats,
+            "kernel": "k_stream_read (16-byte nontemporal loads, 4 in flight per lane, 8 workgroups per CU)"}
+
+
 def time_steps(fn, steps, warmup, torch):
     """W untimed steps, then exactly K steps bracketed by device syncs; per
     step HIP events on the current (launch) stream."""
@@ -107,34 +153,75 @@ def time_steps(fn, steps, warmup, torch):
     return wall, ev_ms
 
 
-def cpu_baseline(c, lattice, seconds):
-    """Time the FP64 oracle on seeded hit pixels of the frame."""
+def cpu_baseline(c, seconds, single_seconds):
+    """The FP64 oracle on the C1 frame as the GPU renders it: the same block
+    skipping (occupancy from the oracle's own block min/max) and early
+    termination; pixels drawn from the whole frame (misses included), so
+    rays/s counts all pixels like the GPU figure.  All host cores on the whole
+    frame when it fits ``seconds`` (else a seeded sample of that size), then
+    one core on a seeded sample of about ``single_seconds``."""
     import numpy as np
 
     import oracle
-    import synth
 
-    hits = np.argwhere(lattice[0] > 0)
-    rng = np.random.default_rng(80)
-    order = rng.permutation(len(hits))
-    def run(n):
-        pix = np.concatenate([np.zeros((n, 1), np.int64), hits[order[:n]]], axis=1)
-        t = time.perf_counter()
-        r = oracle.render(c["volume"], c["cameras"], c["tf"], c["step"], ert=c["ert"], pixels=pix)
-        return time.perf_counter() - t, int(r["counts"][:, 1].sum())
-    dt, _ = run(256)
-    n = int(min(len(hits), max(256, 256 * seconds / max(dt, 1e-3))))
-    dt, evaluated = run(n)
-    # whole-frame rays/s: hit fraction of the frame scaled in
+    W, H = c["cameras"][0].width, c["cameras"][0].height
+    occ = oracle.occupancy(oracle.blocks(c["volume"], 16), c["tf"])
+    order = np.random.default_rng(80).permutation(W * H)
+    all_threads = oracle.num_threads()
+
+    def run(n, threads):
+        q = np.sort(order[:n])
+        pix = np.stack([np.zeros(n, np.int64), q // W, q % W], axis=1)
+        oracle.set_num_threads(threads)
+        try:
+            t = time.perf_counter()
+            r = oracle.render(c["volume"], c["cameras"], c["tf"], c["step"], ert=c["ert"], occ=occ, pixels=pix)
+            return time.perf_counter() - t, int(r["counts"][:, 1].sum())
+        finally:
+            oracle.set_num_threads(all_threads)
+
+    def measure(threads, budget):
+        dt, _ = run(4096, threads)
+        n = int(min(W * H, max(4096, 4096 * budget / max(dt, 1e-3))))
+        dt, ev = run(n, threads)
+        return n, dt, ev
+
+    n, dt, ev = measure(all_threads, seconds)
+    n1, dt1, ev1 = measure(1, single_seconds)
+    what = "the whole 1024^2 frame" if n == W * H else f"{n} seeded pixels of the 1024^2 frame"
     return dict(
-        value=evaluated / dt,
+        value=ev / dt,
         unit="samples/s",
         rays_per_s=n / dt,
         seconds=dt,
-        cores=oracle.num_threads(),
+        cores=all_threads,
         kind="oracle",
-        sample=f"{n} seeded hit pixels of the 1024^2 frame (skip + ERT 0.99), FP64, OpenMP over pixels",
+        sample=f"{what} (misses included), FP64, the GPU's 16^3 block skipping and early termination at 0.99, "
+               f"OpenMP over pixels; {ev} evaluated samples",
+        single_core={"value": ev1 / dt1, "unit": "samples/s", "rays_per_s": n1 / dt1, "seconds": dt1, "cores": 1,
+                     "sample": f"{n1} seeded pixels of the same frame, one thread; {ev1} evaluated samples"},
     )
+
+
+def c0_plain(vr, torch, np, synth, args):
+    """The plain forward (64^3 uint16, 256^2 orthographic along +z, step 0.5,
+    no skipping, no early termination): launch-overhead-sized."""
+    c0 = synth.config_c0()
+    vol = vr.Volume(torch.from_numpy(c0["volume"].view(np.int16)).cuda(), dtype=vr.VR_U16)
+    tf = vr.TF(torch.from_numpy(c0["tf"].table).cuda(), c0["tf"].v0, c0["tf"].v1)
+    cams = c0["cameras"]
+    out = torch.empty((1, cams[0].height, cams[0].width, 4), dtype=torch.float32, device="cuda")
+
+    def fwd():
+        vr.vr_render(vol, None, cams, tf, c0["step"], 0.0, False, out=out)
+
+    wall, ev = time_steps(fwd, args.steps, args.warmup, torch)
+    med, p99 = stats_ms(ev)
+    samples = 65536 * 128
+    return {"workload": "c0_ellipsoids64cube_u16_to_256x256_ortho_step0.5_noskip_noert",
+            "ms_per_step": wall / args.steps * 1e3, "kernel_ms_median": med, "kernel_ms_p99": p99,
+            "samples_per_s": samples / (wall / args.steps), "rays_per_s": 65536 / (wall / args.steps),
+            "evaluated_samples_per_frame": samples}
 
 
 def differentiable_c3(vr, torch, steps=3):
@@ -199,6 +286,12 @@ def serve_mix(vr, torch, n_req, n_warm, rate):
     ready = [threading.Event() for _ in range(total)]
     finished = [threading.Event() for _ in range(total)]
     phase_start = {}
+    # 50 seeded requests of the measured phase keep their images for the
+    # alone-vs-mix check
+    check_idx = set(int(i) for i in np.random.default_rng(81).choice(np.arange(n_warm, total), 50, replace=False))
+    kept = {}
+    depth = []  # (t, queued, inflight) every 5 ms of the measured phase
+    stop_sampling = threading.Event()
 
     def producer():
         t_base = time.perf_counter()
@@ -220,21 +313,54 @@ def serve_mix(vr, torch, n_req, n_warm, rate):
     def consumer():
         for i in range(total):
             ready[i].wait()
-            srv.wait(tickets[i])
-            srv.release(tickets[i])
+            if i in check_idx:
+                s = reqs[i]["size"]
+                kept[i] = srv.result(tickets[i], s, s)
+            else:
+                srv.wait(tickets[i])
+                srv.release(tickets[i])
             finished[i].set()
         done_at["t"] = time.perf_counter()
 
+    def sampler():
+        while not stop_sampling.is_set():
+            if "t" in phase_start:
+                st_ = srv.stats()
+                depth.append((time.perf_counter() - phase_start["t"], int(st_["queued"]), int(st_["inflight"])))
+            time.sleep(0.005)
+
     th_p = threading.Thread(target=producer)
     th_c = threading.Thread(target=consumer)
+    th_s = threading.Thread(target=sampler)
     th_p.start()
     th_c.start()
+    th_s.start()
     th_p.join()
     th_c.join()
+    stop_sampling.set()
+    th_s.join()
     st = srv.stats()
     wall = done_at["t"] - phase_start["t"]
     pixels = sum(r["size"] ** 2 for r in reqs[n_warm:])
     srv.close()
+    # the kept requests re-rendered alone through vr_render
+    blocks = {}
+    tf_dev = vr.TF(torch.from_numpy(tf.table).cuda(), tf.v0, tf.v1)
+    max_diff, identical = 0.0, 0
+    for i, img in kept.items():
+        r = reqs[i]
+        vi = r["volume"]
+        if vi not in blocks:
+            blocks[vi] = vr.vr_build_blocks(vols[vi], 16)
+        alone = vr.vr_render(vols[vi], blocks[vi], [r["camera"]], tf_dev, 0.5, 0.99, True)[0]
+        d = float((alone - img).abs().max().item())
+        max_diff = max(max_diff, d)
+        identical += int(torch.equal(alone, img))
+    q = np.array([d[1] for d in depth]) if depth else np.zeros(1)
+    series = []
+    for t0 in np.arange(0.0, wall, 0.1):
+        w = [d[1] for d in depth if t0 <= d[0] < t0 + 0.1]
+        series.append(int(max(w)) if w else 0)
     return dict(
         requests=n_req,
         offered_req_per_s=rate,
@@ -245,8 +371,18 @@ def serve_mix(vr, torch, n_req, n_warm, rate):
         max_ms=st["max_ms"],
         rays_per_s=pixels / wall,
         rays_per_busy_s=st["rays_per_s"],
+        samples_per_s=st["samples"] / wall,
+        samples_per_busy_s=st["samples_per_s"],
+        evaluated_samples=st["samples"],
         launches=st["launches"],
         hbm_peak_bytes=st["hbm_peak"],
+        resident_bytes=st["resident_bytes"],
+        queue_depth={"time_mean": st["queued_mean"], "max": st["queued_max"], "p50_sampled": float(np.median(q)),
+                     "p99_sampled": float(np.percentile(q, 99)), "max_per_100ms": series,
+                     "note": "queued (not yet admitted) requests; time_mean/max from the server, the rest sampled "
+                             "every 5 ms"},
+        alone_check={"requests": len(kept), "bit_identical": identical, "max_abs_diff": max_diff,
+                     "note": "50 seeded requests of the measured phase re-rendered alone with vr_render"},
     )
 
 
@@ -492,11 +628,16 @@ def main():
     wall, ev_ms = time_steps(fwd, args.steps, args.warmup, torch)
     ms_per_step = wall / args.steps * 1e3
     kern_ms = float(np.mean(ev_ms))
+    kern_med, kern_p99 = stats_ms(ev_ms)
     value = evaluated / (wall / args.steps)
     rays = W * H / (wall / args.steps)
-    achieved_gbs = evaluated * TAPS_BYTES_I16 / (kern_ms * 1e-3) / 1e9
-    log(f"fwd: {ms_per_step:.3f} ms/frame wall, {kern_ms:.3f} ms/launch events, {value:.4g} samples/s, "
-        f"{achieved_gbs:.1f} GB/s effective")
+    gather_gbs = evaluated * TAPS_BYTES_I16 / (kern_med * 1e-3) / 1e9
+    vol_bytes = 512 * 512 * 400 * 2
+    img_bytes = W * H * 16
+    compulsory = vol_bytes + img_bytes
+    achieved_gbs = compulsory / (kern_med * 1e-3) / 1e9
+    log(f"fwd: {ms_per_step:.3f} ms/frame wall, {kern_med:.3f} ms/launch median ({kern_p99:.3f} p99), "
+        f"{value:.4g} samples/s, {gather_gbs:.1f} GB/s effective gather")
 
     result = {
         "metric": METRIC,
@@ -528,16 +669,24 @@ def main():
         "hit_rays_per_frame": hit,
         "unstaged_sample_fraction": unstaged / max(evaluated, 1),
         "kernel_ms": kern_ms,
+        "kernel_ms_median": kern_med,
+        "kernel_ms_p99": kern_p99,
         "block_build_ms": float(np.mean(ev_b)),
     }
-    traffic = None
+    probe = None if args.no_probe else hbm_probe(vr, torch)
+    if probe:
+        log(f"hbm probe: {probe['gb_per_s']:.0f} GB/s streaming read of {probe['bytes'] >> 30} GiB (best of "
+            f"{probe['repeats']})")
+    stored, traffic, valu_insts = None, None, None
     if os.path.exists(args.traffic_json):
         try:
             tj = json.load(open(args.traffic_json))
             if tj.get("kernel_source_sha256") == kernel_source_hash():
+                stored = tj
                 traffic = tj.get("bytes_per_launch")
+                valu_insts = tj.get("sq_insts_valu_per_launch")
         except Exception:
-            traffic = None
+            stored = None
     result["roofline"] = {
         "bound": "hbm",
         "achieved": achieved_gbs,
@@ -545,9 +694,38 @@ def main():
         "unit": "GB/s",
         "frac": achieved_gbs / HBM_PEAK_GBS,
         "traffic": traffic,
-        "kernel": "k_render<kI16, unlit, B-spline>",
-        "bytes_per_launch": evaluated * TAPS_BYTES_I16,
+        "kernel": "k_render<kI16, unlit, B-spline> (+ k_tile_order, k_occupancy_planes: one vr_render)",
+        "bytes_per_launch": compulsory,
+        "bytes_definition": f"compulsory: the int16 volume read once ({vol_bytes} B) + the fp32 RGBA image "
+                            f"written once ({img_bytes} B); time = median of the {args.steps} timed launches",
+        "achievable_gb_per_s": probe["gb_per_s"] if probe else None,
+        "frac_of_achievable": achieved_gbs / probe["gb_per_s"] if probe else None,
+        "traffic_source": (f"stored: {os.path.relpath(args.traffic_json, ROOT)} (rocprofv3 --pmc FETCH_SIZE, "
+                           "WRITE_SIZE per dispatch, scaled by a 1 GiB copy's readings), valid for the hashed "
+                           "forward-kernel sources") if traffic else "none stored for the current kernel sources",
+        "traffic_over_compulsory": traffic / compulsory if traffic else None,
+        "traffic_gb_per_s": traffic / (kern_med * 1e-3) / 1e9 if traffic else None,
     }
+    result["effective_gather"] = {
+        "bytes_per_launch": evaluated * TAPS_BYTES_I16,
+        "gb_per_s": gather_gbs,
+        "over_achievable_hbm": gather_gbs / probe["gb_per_s"] if probe else None,
+        "over_hbm_peak": gather_gbs / HBM_PEAK_GBS,
+        "note": "evaluated samples x 64 taps x 2 B per launch / median launch time: the rate taps are "
+                "gathered at; LDS value boxes, L1 and L2 serve most taps, so this is not HBM traffic",
+    }
+    if valu_insts:
+        t_valu = valu_insts / VALU_WAVE_INSTS_PER_S * 1e3
+        result["valu_ceiling"] = {
+            "sq_insts_valu_per_launch": valu_insts,
+            "min_ms_at_full_issue": t_valu,
+            "frac": t_valu / kern_med,
+            "derivation": "256 CUs x 4 SIMDs x 2.4 GHz / 4 cycles per wave64 VALU instruction (no packed FP32) "
+                          "= 6.144e11 wave instructions/s; SQ_INSTS_VALU of one launch (stored with the traffic)",
+        }
+
+    result["c0"] = c0_plain(vr, torch, np, synth, args)
+    log(f"c0: {result['c0']['kernel_ms_median'] * 1e3:.1f} us/frame median")
 
     if not args.no_lit:
         shade = vr.Shading(**synth.SHADE_CT)
@@ -629,8 +807,11 @@ def main():
 
         wall_fb, ev_fb = time_steps(fwd_bwd, args.bwd_steps, 1, torch)
         ms_fb = wall_fb / args.bwd_steps * 1e3
+        med_fb, p99_fb = stats_ms(ev_fb)
         result["fwd_bwd"] = {
             "ms_per_step": ms_fb,
+            "ms_median": med_fb,
+            "ms_p99": p99_fb,
             "samples_per_s": lattice_total / (ms_fb * 1e-3),
             "rays_per_s": W * H / (ms_fb * 1e-3),
             "note": "forward (skip+ERT) + adjoint to grid (fp32) and TF; samples counted as lattice samples "
@@ -654,8 +835,7 @@ def main():
         import oracle
 
         log("cpu baseline (oracle)")
-        lat = oracle.lattice(cams, (512, 512, 400), c["step"])
-        result["cpu_baseline"] = cpu_baseline(c, lat, args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(c, args.cpu_seconds, args.cpu_single_seconds)
 
     print(json.dumps(result), flush=True)
 

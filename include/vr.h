@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define VR_ABI_VERSION 1
+#define VR_ABI_VERSION 2
 
 typedef enum {
     VR_OK = 0,
@@ -65,8 +65,9 @@ typedef struct {
     int64_t nx, ny, nz;
 } vr_volume;
 
-/* A camera ("the position of the observer and the direction of the ray",
- * Section 2).  All vectors in index space; right/up/forward orthonormal.
+/* A camera: where the observer stands and, for every pixel, the direction
+ * its ray leaves in (the ray-casting paragraph of Section 2).  All vectors
+ * in index space; right/up/forward orthonormal.
  * Pixel (i, j), i the column and j the row, has centre (i+1/2, j+1/2) and
  *   sx = 2 (i + 1/2) / width - 1,   sy = 1 - 2 (j + 1/2) / height.
  * Perspective (projection 1): origin = eye,
@@ -89,7 +90,12 @@ typedef struct {
  * between nodes, the end nodes beyond [v0, v1].  r, g, b are emission colours;
  * sigma >= 0 is the extinction per voxel length, so a sample's opacity is
  * 1 - exp(-sigma step) (0 fully transparent, 1 opaque).
- * table: DEVICE, K*4 floats.  2 <= K <= VR_MAX_TF_NODES, v1 > v0. */
+ * table: DEVICE, K*4 floats.  2 <= K <= VR_MAX_TF_NODES, v1 > v0.
+ * Every entry must be finite and every sigma >= 0.  The host cannot read a
+ * device table without waiting for the device, so the kernels check it as
+ * they stage it: a call that meets an invalid table writes NaN to all of its
+ * results (pixels, gradients, occupancy counts every block occupied) and
+ * records the fault on the device; vr_device_status reports it. */
 #define VR_MAX_TF_NODES 1024
 typedef struct {
     const float *table;
@@ -98,8 +104,13 @@ typedef struct {
 } vr_tf;
 
 /* Marching parameters.
- *   step           in [1/1024, 1024] voxels.  Samples sit at the midpoints
- *                  t_in + (k + 1/2) step of every full step inside the box.
+ *   step           in [1/1024, 1024] voxels.  The ray moves from its origin
+ *                  with this step: samples sit at distances
+ *                  t_k = (k + 1/2) step from the origin, for every integer
+ *                  k >= 0 with t_in < t_k < t_out, where [t_in, t_out] is
+ *                  the ray's intersection with the box (t_in clamped to 0).
+ *                  Positions are computed from k, never accumulated; rays of
+ *                  neighbouring pixels share sample distances.
  *   ert_threshold  early ray termination: a ray stops after the sample whose
  *                  accumulated opacity reaches the threshold; values outside
  *                  (0, 1) disable it.
@@ -257,7 +268,7 @@ vr_status vr_render_shaded(const vr_volume *vol, const vr_blocks *blocks, const 
  * pair, integrated in FP64 (pieces between node crossings, Gauss-Legendre on
  * sub-intervals of optical depth <= 1/32) and stored as fp32.
  * Opaque, library-owned; it remembers the TF (pointer, K, v0, v1) and step it
- * was built for.  Negative or NaN extinction reads as zero. */
+ * was built for.  A table built from an invalid TF is all NaN (see vr_tf). */
 typedef struct vr_preint vr_preint;
 
 /* Build the K x K table for `tf` (HOST struct; its DEVICE table is read by
@@ -371,7 +382,9 @@ vr_status vr_render_backward(const vr_volume *vol, const vr_blocks *blocks, cons
 typedef struct vr_server vr_server;
 
 typedef struct {
-    uint64_t hbm_budget_bytes; /* device bytes the server may hold for result images */
+    uint64_t hbm_budget_bytes; /* device bytes charged to the server: resident volumes
+                                  (their caller-owned memory), block structures, result
+                                  images and per-request occupancy buffers */
     int32_t max_inflight;      /* admitted requests at once (slots), >= 1             */
     int32_t max_batch_tiles;   /* 16x16-pixel work items per launch (0 = 2048)        */
     int32_t device;            /* HIP device ordinal                                  */
@@ -397,22 +410,32 @@ typedef struct {
     double p50_ms, p99_ms, mean_ms, max_ms; /* arrival (submit) -> completion */
     double rays_per_s;                      /* completed pixels / busy wall time */
     double busy_s;                          /* wall time with work in flight     */
+    uint64_t samples;                       /* evaluated samples of completed launches */
+    double samples_per_s;                   /* samples / busy wall time          */
+    uint64_t queued_max;                    /* longest queue since the reset     */
+    double queued_mean;                     /* time-averaged queue length        */
+    uint64_t resident_bytes;                /* volumes + blocks charged          */
 } vr_serve_stats;
 
 /* Create a server with its own scheduler thread and HIP streams. */
 vr_status vr_serve_create(const vr_serve_config *cfg, vr_server **out);
 
 /* Register a resident volume (caller keeps its memory alive until removal)
- * and build its blocks with edge `block_edge`.  Blocks count against the
- * budget.  *volume_id receives the id. */
+ * and build its blocks with edge `block_edge`.  The volume's bytes and its
+ * blocks count against the budget (pooled result images are freed to make
+ * room); VR_E_BUDGET when they do not fit.  *volume_id receives the id. */
 vr_status vr_serve_add_volume(vr_server *s, const vr_volume *vol, int32_t block_edge, int32_t *volume_id);
 
 /* Unregister; VR_E_BUSY while requests on it are queued or in flight. */
 vr_status vr_serve_remove_volume(vr_server *s, int32_t volume_id);
 
 /* Non-blocking submit; *ticket identifies the request.  VR_E_BUDGET if the
- * result image alone exceeds the whole budget, VR_E_NOT_FOUND for an unknown
- * volume, VR_E_INVALID_ARG for invalid fields, VR_E_SHUTDOWN after destroy. */
+ * request's device memory (result image + occupancy buffer) can never fit
+ * next to the resident volumes and blocks, VR_E_NOT_FOUND for an unknown
+ * volume, VR_E_INVALID_ARG for invalid fields (a non-finite TF entry or a
+ * negative extinction included), VR_E_SHUTDOWN after destroy.  Admission is
+ * FIFO; a queued request that can no longer fit (volumes were added since)
+ * completes with VR_E_BUDGET instead of blocking the queue. */
 vr_status vr_serve_submit(vr_server *s, const vr_request *req, uint64_t *ticket);
 
 /* Wait up to timeout_us (negative = forever) for `ticket`.  On VR_OK,
@@ -435,6 +458,12 @@ vr_status vr_serve_stats_reset(vr_server *s);
 vr_status vr_serve_destroy(vr_server *s);
 
 /* ---------------------------------------------------------------------- */
+
+/* Waits for `stream`, then reports whether a kernel on the current device
+ * has met an invalid transfer-function table since the last call
+ * (VR_E_INVALID_ARG, and the record is cleared) or not (VR_OK).
+ * Errors: VR_E_DEVICE. */
+vr_status vr_device_status(void *stream);
 
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char *vr_last_error(void);

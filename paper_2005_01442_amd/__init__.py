@@ -31,6 +31,7 @@ __all__ = [
     "vr_block_occupancy",
     "vr_render",
     "vr_render_backward",
+    "device_status",
     "Shading",
     "PreintTable",
     "vr_prefilter_bspline",
@@ -121,10 +122,19 @@ def camera_struct(cam) -> _abi.vr_camera:
 
 
 def _cameras(cams):
+    """ctypes array of the cameras; None for an empty list (the library then
+    rejects the call with VR_E_INVALID_ARG)."""
+    if len(cams) == 0:
+        return None
     arr = (_abi.vr_camera * len(cams))()
     for i, cam in enumerate(cams):
         arr[i] = camera_struct(cam)
     return arr
+
+
+def _image_size(cams):
+    """(W, H) of the views; (0, 0) for an empty list."""
+    return (int(cams[0].width), int(cams[0].height)) if len(cams) else (0, 0)
 
 
 class Blocks:
@@ -208,6 +218,24 @@ class Shading:
         return c
 
 
+def device_status(stream=None):
+    """Wait for ``stream`` and raise VrError (VR_E_INVALID_ARG) if a kernel on
+    the current device has met an invalid TF table since the last check
+    (``vr_device_status``; the calls that read it wrote NaN results)."""
+    check(lib().vr_device_status(_stream_ptr(stream)))
+
+
+def vr_probe_stream_read(buf: torch.Tensor, sink: torch.Tensor, stream=None):
+    """Stream-read the whole of the contiguous CUDA tensor ``buf`` once with
+    16-byte loads, folding it into ``sink`` (an int32 CUDA tensor of one
+    element): the achievable-HBM-bandwidth probe (time it with events)."""
+    if not buf.is_cuda or not buf.is_contiguous() or not sink.is_cuda or sink.dtype != torch.int32:
+        raise ValueError("buf must be a contiguous CUDA tensor and sink an int32 CUDA tensor")
+    nbytes = buf.numel() * buf.element_size()
+    check(lib().vr_probe_stream_read(ctypes.c_void_p(buf.data_ptr()), nbytes, ctypes.c_void_p(sink.data_ptr()),
+                                     _stream_ptr(stream)))
+
+
 def vr_render(volume: Volume, blocks, cameras, tf: TF, step: float, ert: float = 0.0, use_skip: bool = False,
               out: torch.Tensor | None = None, counters: torch.Tensor | None = None, stream=None,
               shading: Shading | None = None, filter: int = 0) -> torch.Tensor:
@@ -217,7 +245,7 @@ def vr_render(volume: Volume, blocks, cameras, tf: TF, step: float, ert: float =
     global memory instead of an LDS box] to.  ``shading`` switches on local
     lighting (``vr_render_shaded``); ``filter`` selects the reconstruction
     (VR_FILTER_BSPLINE, VR_FILTER_CATMULL_ROM)."""
-    W, H = int(cameras[0].width), int(cameras[0].height)
+    W, H = _image_size(cameras)
     if out is None:
         out = torch.empty((len(cameras), H, W, 4), dtype=torch.float32, device=volume.tensor.device)
     if counters is not None and (counters.dtype != torch.int64 or counters.numel() < 4 or not counters.is_cuda):
@@ -280,7 +308,7 @@ def vr_render_preint(volume: Volume, blocks, cameras, tf: TF, table: PreintTable
                      stream=None) -> torch.Tensor:
     """Pre-integrated render of len(cameras) views; (views, H, W, 4) fp32
     premultiplied RGBA.  ``counters`` as vr_render, counting lattice cells."""
-    W, H = int(cameras[0].width), int(cameras[0].height)
+    W, H = _image_size(cameras)
     if out is None:
         out = torch.empty((len(cameras), H, W, 4), dtype=torch.float32, device=volume.tensor.device)
     if counters is not None and (counters.dtype != torch.int64 or counters.numel() < 4 or not counters.is_cuda):
@@ -318,7 +346,7 @@ class BrickedVolume:
 
     def render(self, cameras, tf: TF, step: float, ert: float = 0.0, out: torch.Tensor | None = None,
                stream=None) -> torch.Tensor:
-        W, H = int(cameras[0].width), int(cameras[0].height)
+        W, H = _image_size(cameras)
         if out is None:
             out = torch.empty((len(cameras), H, W, 4), dtype=torch.float32, device=tf.table.device)
         cams = _cameras(cameras)

@@ -29,6 +29,7 @@ STATUS_NAMES = {
 VR_U16, VR_I16, VR_F32 = 0, 1, 2
 VR_FILTER_BSPLINE, VR_FILTER_CATMULL_ROM, VR_FILTER_BSPLINE_PRECLASSIFIED, VR_FILTER_TRILINEAR = 0, 1, 2, 3
 VR_MAX_TF_NODES = 1024
+VR_ABI_VERSION = 2
 
 
 class VrError(RuntimeError):
@@ -84,7 +85,9 @@ class vr_serve_stats(ctypes.Structure):
     _fields_ = [("submitted", c_uint64), ("admitted", c_uint64), ("completed", c_uint64), ("rejected", c_uint64),
                 ("queued", c_uint64), ("inflight", c_uint64), ("hbm_used", c_uint64), ("hbm_peak", c_uint64),
                 ("launches", c_uint64), ("tiles", c_uint64), ("p50_ms", c_double), ("p99_ms", c_double),
-                ("mean_ms", c_double), ("max_ms", c_double), ("rays_per_s", c_double), ("busy_s", c_double)]
+                ("mean_ms", c_double), ("max_ms", c_double), ("rays_per_s", c_double), ("busy_s", c_double),
+                ("samples", c_uint64), ("samples_per_s", c_double), ("queued_max", c_uint64),
+                ("queued_mean", c_double), ("resident_bytes", c_uint64)]
 
 
 # exported function -> (argtypes, restype)
@@ -123,6 +126,8 @@ PROTOTYPES = {
     "vr_serve_stats_get": ([c_void_p, POINTER(vr_serve_stats)], c_int32),
     "vr_serve_stats_reset": ([c_void_p], c_int32),
     "vr_serve_destroy": ([c_void_p], c_int32),
+    "vr_device_status": ([c_void_p], c_int32),
+    "vr_probe_stream_read": ([c_void_p, c_uint64, c_void_p, c_void_p], c_int32),
 }
 
 _lib = None
@@ -142,7 +147,7 @@ def lib():
             fn = getattr(L, name)
             fn.argtypes = args
             fn.restype = res
-        if L.vr_abi_version() != 1:
+        if L.vr_abi_version() != VR_ABI_VERSION:
             raise RuntimeError("libvr.so ABI version mismatch")
         _lib = L
     return _lib

@@ -32,6 +32,10 @@ COMMON = [
     "-Wall",
     "-Wno-unused-result",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit FMA contraction: every fused multiply-add is written out, so
+    # kernels that share device functions (the whole-image render, the
+    # serving kernel, the out-of-core pass) compute bit-identical samples
+    "-ffp-contract=off",
     "-munsafe-fp-atomics",
 ]
 

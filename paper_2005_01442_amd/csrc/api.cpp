@@ -91,6 +91,7 @@ vr_status check_tf_fields(const void *table, int32_t K, float v0, float v1, TfCo
     out->K = K;
     out->v0 = v0;
     out->scale = (float)(K - 1) / (v1 - v0);
+    out->status = tf_status_word();
   }
   return VR_OK;
 }
@@ -426,7 +427,7 @@ vr_status vr_preint_build(const vr_tf *tf, float step, void *stream, vr_preint *
     delete t;
     return fail(VR_E_OOM, "hipMalloc of %zu table bytes: %s", bytes, hipGetErrorString(e));
   }
-  e = launch_preint_table(tf->table, tf->K, step, t->table, (hipStream_t)stream);
+  e = launch_preint_table(tf->table, tf->K, step, t->table, tc.status, (hipStream_t)stream);
   if (e != hipSuccess) {
     (void)hipFree(t->table);
     delete t;

@@ -95,13 +95,20 @@ __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(3, 3)))
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const BrickedArgs &a = kernarg<BrickedArgs>();
   TfShared s = carve_tf(lds, a.tf.K);
-  load_tf(s, a.tf);
+  const bool tf_ok = load_tf(s, a.tf);
   const int tiles_x = (a.W + kSuperEdge - 1) / kSuperEdge;
   const int q = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
   int col, row;
   pixel_of(q % tiles_x, q / tiles_x, col, row);
   const bool inside = col < a.W && row < a.H;
   const size_t pix = inside ? (size_t)row * a.W + col : 0;
+  if (!tf_ok) {  // uniform: an invalid TF finishes every ray with NaN
+    if (inside) {
+      a.state[pix] = nan_rgba();
+      a.next[pix] = -1;
+    }
+    return;
+  }
   int kstart = 0;
   float4 st = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
   bool active = inside;

@@ -362,7 +362,6 @@ __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(2, 2)))
   const BackwardArgs &a = kernarg<BackwardArgs>();
   const RenderArgs &ra = a.r;
   SuperTile st = tile_of(ra.order, blockIdx.x, ra.W, ra.H, ra.n_views, ra.chunk_edge);
-  if (!st.valid) return;  // uniform over the workgroup
   const int K = ra.tf.K;
   const uint32_t tf_bytes = tf_lds_bytes(K);
   float *sgtf = a.grad_tf ? reinterpret_cast<float *>(lds + tf_bytes) : nullptr;
@@ -380,7 +379,20 @@ __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(2, 2)))
     for (int i = threadIdx.x % kWaveSize; i < kBoxCells; i += kWaveSize) box.cells[i] = 0.0f;
   }
   TfShared s = carve_tf(lds, K);
-  load_tf(s, ra.tf);  // ends with a barrier, which also orders the zeroing
+  const bool tf_ok = load_tf(s, ra.tf);  // ends with a barrier, which also orders the zeroing
+  if (!tf_ok) {
+    // uniform over the launch: every workgroup (tile or padding) fills its
+    // share of the gradients with NaN and nothing is accumulated
+    const float q = __builtin_nanf("");
+    const int64_t nvox = (int64_t)ra.vol.nx * ra.vol.ny * ra.vol.nz;
+    if (a.grad_vol)
+      for (int64_t i = (int64_t)blockIdx.x * kWgSize + threadIdx.x; i < nvox; i += (int64_t)gridDim.x * kWgSize)
+        a.grad_vol[i] = q;
+    if (a.grad_tf && blockIdx.x == 0)
+      for (int j = threadIdx.x; j < 4 * K; j += kWgSize) a.grad_tf[j] = q;
+    return;
+  }
+  if (!st.valid) return;  // uniform over the workgroup
   int col, row;
   pixel_of(st.sx, st.sy, col, row);
   // every lane enters the march (it steps the wavefront in unison); lanes

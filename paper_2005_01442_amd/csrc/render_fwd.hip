@@ -107,10 +107,14 @@ void k_render(const RenderArgs args) {
   TfShared s = carve_tf(lds, a.tf.K);
   if (a.occ_lds_words > 0)
     stage_occupancy(s, a.vol, lds + vbox_lds_offset(a.tf.K) + vbox_lds_bytes(), a.occ_lds_words);
-  load_tf(s, a.tf);
+  const bool tf_ok = load_tf(s, a.tf);
   int col, row;
   pixel_of(st.sx, st.sy, col, row);
   const bool inside = col < a.W && row < a.H;
+  if (!tf_ok) {  // uniform: an invalid TF gives NaN pixels
+    if (inside) reinterpret_cast<float4 *>(a.out)[((size_t)st.view * a.H + row) * a.W + col] = nan_rgba();
+    return;
+  }
   const CamConst &cam = a.cams[st.view];
   uint32_t evaluated = 0, unstaged = 0;
   // every lane enters the march (it steps the wavefront in unison); pixels
@@ -271,15 +275,19 @@ hipError_t launch_render(const RenderArgs &a0, hipStream_t s) {
 // volumes, sizes and TFs.  The per-ray arithmetic is the whole-image
 // kernel's, so a request's pixels do not depend on what it is batched with.
 __global__ __launch_bounds__(kWgSize) void k_serve(const ServeSlot *slots, const ServeItem *items, int lds_k,
-                                                   int use_box) {
+                                                   int use_box, unsigned long long *samples) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const ServeItem it = items[blockIdx.x];
   const ServeSlot &sl = slots[it.slot];
   TfShared s = carve_tf(lds, sl.tf.K);
-  load_tf(s, sl.tf);
+  const bool tf_ok = load_tf(s, sl.tf);
   int col, row;
   pixel_of(it.sx, it.sy, col, row);
   const bool inside = col < sl.cam.W && row < sl.cam.H;
+  if (!tf_ok) {  // (the server validates every table at submit)
+    if (inside) reinterpret_cast<float4 *>(sl.out)[(size_t)row * sl.cam.W + col] = nan_rgba();
+    return;
+  }
   Ray r;
   r.hit = false;
   r.ns = 0;
@@ -299,10 +307,11 @@ __global__ __launch_bounds__(kWgSize) void k_serve(const ServeSlot *slots, const
   default: rgba = march<kF32, false>(sl.vol, s, sl.tf, sl.mc, ShadeConst{}, r, rs, box, evaluated, unstaged); break;
   }
   if (inside) reinterpret_cast<float4 *>(sl.out)[(size_t)row * sl.cam.W + col] = rgba;
+  wave_count(samples, evaluated);
 }
 
 hipError_t launch_serve_batch(const ServeSlot *slots_dev, const ServeItem *items_dev, int32_t n_items,
-                              int32_t max_tf_k, hipStream_t s) {
+                              int32_t max_tf_k, unsigned long long *samples, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   uint32_t lds = tf_lds_bytes(max_tf_k);
   const uint32_t with_box = vbox_lds_offset(max_tf_k) + vbox_lds_bytes();
@@ -312,7 +321,7 @@ hipError_t launch_serve_batch(const ServeSlot *slots_dev, const ServeItem *items
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_serve, dim3((unsigned)n_items), dim3(kWgSize), lds, s, slots_dev, items_dev, max_tf_k,
-                     use_box);
+                     use_box, samples);
   return hipGetLastError();
 }
 

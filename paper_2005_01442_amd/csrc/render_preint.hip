@@ -28,11 +28,21 @@ __device__ inline void tf_node(const float *tf, int K, int j, double out[4]) {
   out[0] = n.x;
   out[1] = n.y;
   out[2] = n.z;
-  out[3] = fmax((double)n.w, 0.0);  // negative or NaN extinction reads as zero
+  out[3] = n.w;  // the table kernel has checked every node
 }
 
-__global__ __launch_bounds__(256) void k_preint_table(const float *tf, int K, double step, float4 *out) {
+__global__ __launch_bounds__(256) void k_preint_table(const float *tf, int K, double step, float4 *out,
+                                                     uint32_t *status) {
+  // an invalid node anywhere makes the whole table NaN (and is recorded)
+  int bad = 0;
+  for (int j = threadIdx.x; j < K; j += 256) bad |= tf_node_valid(reinterpret_cast<const float4 *>(tf)[j]) ? 0 : 1;
+  bad = __syncthreads_or(bad);
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (bad) {
+    if (threadIdx.x == 0 && status) __hip_atomic_store(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (e < (int64_t)K * K) out[e] = nan_rgba();
+    return;
+  }
   if (e >= (int64_t)K * K) return;
   const int i = (int)(e / K), j = (int)(e % K);
   double C[3] = {0.0, 0.0, 0.0}, tau = 0.0;
@@ -73,9 +83,10 @@ __global__ __launch_bounds__(256) void k_preint_table(const float *tf, int K, do
   out[e] = make_float4((float)C[0], (float)C[1], (float)C[2], (float)(-expm1(-tau)));
 }
 
-hipError_t launch_preint_table(const float *tf, int K, float step, float4 *out, hipStream_t s) {
+hipError_t launch_preint_table(const float *tf, int K, float step, float4 *out, uint32_t *status, hipStream_t s) {
   const int64_t n = (int64_t)K * K;
-  hipLaunchKernelGGL(k_preint_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tf, K, (double)step, out);
+  hipLaunchKernelGGL(k_preint_table, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, tf, K, (double)step, out,
+                     status);
   return hipGetLastError();
 }
 
@@ -226,10 +237,14 @@ __global__ __launch_bounds__(kWgSize) void k_render_preint(const RenderArgs args
   TfShared s = carve_tf(lds, a.tf.K);
   if (a.occ_lds_words > 0)
     stage_occupancy(s, a.vol, lds + vbox_lds_offset(a.tf.K) + vbox_lds_bytes(), a.occ_lds_words);
-  load_tf(s, a.tf);
+  const bool tf_ok = load_tf(s, a.tf);
   int col, row;
   pixel_of(st.sx, st.sy, col, row);
   const bool inside = col < a.W && row < a.H;
+  if (!tf_ok) {
+    if (inside) reinterpret_cast<float4 *>(a.out)[((size_t)st.view * a.H + row) * a.W + col] = nan_rgba();
+    return;
+  }
   const CamConst &cam = a.cams[st.view];
   uint32_t evaluated = 0, unstaged = 0;
   Ray r;

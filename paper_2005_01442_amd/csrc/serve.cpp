@@ -6,7 +6,8 @@
 // volumes and their block structures stay resident in HBM; clients submit
 // requests (volume, camera, TF, step) from any thread; a scheduler thread
 //   1. admits queued requests in FIFO order while a slot is free and the
-//      result image fits the HBM budget,
+//      request's device memory (result image, occupancy buffer) fits the HBM
+//      budget next to the resident volumes and their blocks,
 //   2. cuts every admitted request into 16x16-pixel work items and fills each
 //      launch round-robin from all admitted requests (so requests of
 //      different volumes, image sizes and TFs share launches, and a request
@@ -73,7 +74,7 @@ struct Volume {
   VolConst vc{};
   bool radius_fits = false;  // the radius plane can be built for its block grid
   vr_blocks *blocks = nullptr;
-  size_t block_bytes = 0;
+  size_t resident_bytes = 0;  // the volume's memory + its blocks (charged)
   int64_t users = 0;  // queued + admitted requests
 };
 
@@ -90,6 +91,7 @@ struct Batch {
   bool busy = false;
   std::vector<std::pair<uint64_t, int32_t>> per_request;  // ticket, items in this batch
   int64_t pixels = 0;
+  unsigned long long *samples_host = nullptr;  // pinned: the launch's evaluated samples, copied after it
 };
 
 size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
@@ -115,8 +117,10 @@ struct vr_server {
   uint64_t next_ticket = 1;
   size_t rr = 0;                      // round-robin cursor over admitted
 
-  // HBM accounting (result images + blocks)
+  // HBM accounting: resident volumes and blocks, result images, occupancy
+  // buffers (pooled ones included until they are evicted)
   uint64_t hbm_used = 0, hbm_peak = 0;
+  uint64_t resident_bytes = 0;  // volumes + blocks
   std::multimap<size_t, float *> image_pool;  // free images by size
   std::multimap<size_t, uint32_t *> occ_pool;  // free occupancy buffers by size
   std::vector<uint32_t *> occ_retired;         // of requests that did not finish (freed at destroy)
@@ -128,7 +132,10 @@ struct vr_server {
   uint64_t n_submitted = 0, n_admitted = 0, n_completed = 0, n_rejected = 0, n_launches = 0, n_items = 0;
   std::vector<double> latencies_ms;
   double busy_s = 0, busy_since = -1;
-  uint64_t pixels_done = 0;
+  uint64_t pixels_done = 0, samples_done = 0;
+  // queue length over time (since the last reset)
+  double q_area = 0, q_since = 0, q_last = 0;
+  uint64_t q_max = 0;
 };
 
 namespace {
@@ -138,25 +145,62 @@ void charge(vr_server *s, size_t bytes) {
   s->hbm_peak = std::max(s->hbm_peak, s->hbm_used);
 }
 
-// Get a result image of exactly `bytes`: from the pool, else a new
-// allocation if the budget allows (evicting pooled images of other sizes).
-// Called with the lock held.  Returns nullptr when the budget is full.
-float *acquire_image(vr_server *s, size_t bytes) {
-  auto it = s->image_pool.find(bytes);
-  if (it != s->image_pool.end()) {
-    float *p = it->second;
-    s->image_pool.erase(it);
+// Account the queue length up to now (call before the queue changes and
+// after, lock held).
+void note_queue(vr_server *s) {
+  const double t = now_s();
+  s->q_area += (double)s->queue.size() * (t - s->q_last);
+  s->q_last = t;
+  s->q_max = std::max<uint64_t>(s->q_max, s->queue.size());
+}
+
+// Free pooled buffers (largest first) until `bytes` more fit the budget.
+// Lock held.  Returns whether they fit.
+bool make_room(vr_server *s, size_t bytes) {
+  while (s->hbm_used + bytes > s->cfg.hbm_budget_bytes && (!s->image_pool.empty() || !s->occ_pool.empty())) {
+    const bool img = !s->image_pool.empty() &&
+                     (s->occ_pool.empty() || std::prev(s->image_pool.end())->first >= std::prev(s->occ_pool.end())->first);
+    if (img) {
+      auto big = std::prev(s->image_pool.end());
+      (void)hipFree(big->second);
+      s->hbm_used -= big->first;
+      s->image_pool.erase(big);
+    } else {
+      auto big = std::prev(s->occ_pool.end());
+      (void)hipFree(big->second);
+      s->hbm_used -= big->first;
+      s->occ_pool.erase(big);
+    }
+  }
+  return s->hbm_used + bytes <= s->cfg.hbm_budget_bytes;
+}
+
+// Device bytes a request holds while admitted: its result image and, when it
+// skips, the occupancy buffer of its volume's block grid.
+size_t request_bytes(const vr_server *s, int32_t volume_id, size_t image_bytes, bool skip) {
+  auto it = s->volumes.find(volume_id);
+  size_t b = image_bytes;
+  if (skip && it != s->volumes.end() && it->second.vc.minmax) b += occupancy_bytes(it->second.vc);
+  return b;
+}
+
+// Get a buffer of exactly `bytes` from `pool`, else a new allocation if the
+// budget allows (evicting pooled buffers of other sizes).  Lock held.
+// Returns nullptr when the budget is full.
+template <class T>
+T *acquire(vr_server *s, std::multimap<size_t, T *> &pool, size_t bytes) {
+  auto it = pool.find(bytes);
+  if (it != pool.end()) {
+    T *p = it->second;
+    pool.erase(it);
     return p;
   }
-  while (s->hbm_used + bytes > s->cfg.hbm_budget_bytes && !s->image_pool.empty()) {
-    auto big = std::prev(s->image_pool.end());
-    (void)hipFree(big->second);
-    s->hbm_used -= big->first;
-    s->image_pool.erase(big);
+  if (!make_room(s, bytes)) return nullptr;
+  T *p = nullptr;
+  if (hipMalloc(reinterpret_cast<void **>(&p), bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
   }
-  if (s->hbm_used + bytes > s->cfg.hbm_budget_bytes) return nullptr;
-  float *p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
   charge(s, bytes);
   return p;
 }
@@ -167,7 +211,7 @@ void release_image(vr_server *s, float *p, size_t bytes) {
 
 size_t batch_capacity(const vr_serve_config &c) {
   return (size_t)c.max_inflight * (align16(sizeof(ServeSlot)) + (size_t)VR_MAX_TF_NODES * 16) +
-         (size_t)c.max_batch_tiles * sizeof(ServeItem) + 64;
+         (size_t)c.max_batch_tiles * sizeof(ServeItem) + 64 + 16;
 }
 
 void fail_all(vr_server *s, vr_status st) {
@@ -181,20 +225,52 @@ void fail_all(vr_server *s, vr_status st) {
       s->volumes[r.volume_id].users--;
     }
   }
+  note_queue(s);
   s->queue.clear();
+  note_queue(s);
   s->admitted.clear();
   s->cv_done.notify_all();
 }
 
-// FIFO admission; lock held.
+// FIFO admission; lock held.  A head request that can never fit next to the
+// resident volumes (volumes were added after it was queued) fails with
+// VR_E_BUDGET instead of blocking the queue.
 void admit(vr_server *s) {
   while (!s->queue.empty() && (int32_t)s->admitted.size() < s->cfg.max_inflight) {
     Request &r = *s->requests[s->queue.front()];
-    float *img = acquire_image(s, r.image_bytes);
+    const bool skip = r.mc.skip && s->volumes[r.volume_id].vc.minmax;
+    const size_t need = request_bytes(s, r.volume_id, r.image_bytes, r.mc.skip != 0);
+    if (s->resident_bytes + need > s->cfg.hbm_budget_bytes) {
+      note_queue(s);
+      s->queue.pop_front();
+      note_queue(s);
+      r.state = RState::Failed;
+      r.error = VR_E_BUDGET;
+      s->volumes[r.volume_id].users--;
+      s->n_rejected++;
+      s->cv_done.notify_all();
+      continue;
+    }
+    float *img = acquire(s, s->image_pool, r.image_bytes);
     if (!img) break;  // head of line waits for memory
+    uint32_t *occ = nullptr;
+    if (skip) {
+      const size_t ob = occupancy_bytes(s->volumes[r.volume_id].vc);
+      occ = acquire(s, s->occ_pool, ob);
+      if (!occ) {
+        release_image(s, img, r.image_bytes);
+        break;  // waits for memory
+      }
+      r.occ = occ;
+      r.occ_bytes = ob;
+      r.occ_radius = s->volumes[r.volume_id].radius_fits ? kEmptyRadiusMax : 0;
+      r.occ_batch = -1;  // computed by the first batch that carries the request
+    }
     r.image = img;
     r.state = RState::Admitted;
+    note_queue(s);
     s->queue.pop_front();
+    note_queue(s);
     s->admitted.push_back(r.ticket);
     s->n_admitted++;
   }
@@ -203,6 +279,7 @@ void admit(vr_server *s) {
 // Retire a finished batch; lock held.
 void retire(vr_server *s, Batch &b) {
   double t = now_s();
+  s->samples_done += *b.samples_host;
   for (auto &pr : b.per_request) {
     auto it = s->requests.find(pr.first);
     if (it == s->requests.end()) continue;
@@ -270,7 +347,8 @@ bool issue(vr_server *s, Batch &b) {
     if (take[i] > 0) tf_bytes += align16((size_t)s->requests[live[i]]->K * 16);
   size_t off_items = off_tf + tf_bytes;
   int64_t n_items_total = cap_items - left;
-  size_t total = off_items + (size_t)n_items_total * sizeof(ServeItem);
+  size_t off_count = align16(off_items + (size_t)n_items_total * sizeof(ServeItem));
+  size_t total = off_count + sizeof(unsigned long long);
   if (total > b.cap) return false;  // cannot happen: capacity covers the worst case
   ServeSlot *slots = reinterpret_cast<ServeSlot *>(b.host + off_slots);
   ServeItem *items = reinterpret_cast<ServeItem *>(b.host + off_items);
@@ -300,27 +378,13 @@ bool issue(vr_server *s, Batch &b) {
     max_k = std::max(max_k, r.K);
     sl.tf.v0 = r.v0;
     sl.tf.scale = (float)(r.K - 1) / (r.v1 - r.v0);
+    sl.tf.status = nullptr;  // validated at submit
     memcpy(b.host + tf_cursor, r.tf.data(), (size_t)r.K * 16);
     sl.tf.table = reinterpret_cast<const float *>(b.dev + tf_cursor);
-    if (!r.occ && r.mc.skip && v.vc.minmax) {
-      const size_t need = occupancy_bytes(v.vc);
-      auto it = s->occ_pool.find(need);
-      uint32_t *p = nullptr;
-      if (it != s->occ_pool.end()) {
-        p = it->second;
-        s->occ_pool.erase(it);
-      } else if (hipMalloc(reinterpret_cast<void **>(&p), need) != hipSuccess) {
-        (void)hipGetLastError();
-        p = nullptr;
-      }
-      if (p) {
-        r.occ = p;
-        r.occ_bytes = need;
-        r.occ_radius = v.radius_fits ? kEmptyRadiusMax : 0;
-        r.occ_batch = bi;
-        r.occ_gen = b.gen;
-        occ_new.emplace_back(&r, tf_cursor);
-      }
+    if (r.occ && r.occ_batch < 0) {
+      r.occ_batch = bi;
+      r.occ_gen = b.gen;
+      occ_new.emplace_back(&r, tf_cursor);
     } else if (r.occ && r.occ_batch == (bi ^ 1) && other.busy && other.gen == r.occ_gen) {
       wait_other = true;  // computed by the other batch, which may still run
     }
@@ -346,6 +410,7 @@ bool issue(vr_server *s, Batch &b) {
   std::stable_sort(keyed.begin(), keyed.end(),
                    [](const std::pair<float, ServeItem> &a, const std::pair<float, ServeItem> &c) { return a.first < c.first; });
   for (size_t q = 0; q < keyed.size(); ++q) items[q] = keyed[q].second;
+  *reinterpret_cast<unsigned long long *>(b.host + off_count) = 0;  // the launch's sample counter
   hipError_t e = hipMemcpyAsync(b.dev, b.host, total, hipMemcpyHostToDevice, b.stream);
   for (auto &rn : occ_new) {  // from the TF tables just copied
     if (e != hipSuccess) break;
@@ -356,6 +421,7 @@ bool issue(vr_server *s, Batch &b) {
     tc.K = r.K;
     tc.v0 = r.v0;
     tc.scale = (float)(r.K - 1) / (r.v1 - r.v0);
+    tc.status = nullptr;
     e = r.occ_radius > 0 ? launch_occupancy_planes(v.vc, tc, r.occ, b.stream)
                          : launch_occupancy_bits(v.vc, tc, r.occ, b.stream);
   }
@@ -364,7 +430,9 @@ bool issue(vr_server *s, Batch &b) {
   if (e == hipSuccess)
     e = launch_serve_batch(reinterpret_cast<const ServeSlot *>(b.dev + off_slots),
                            reinterpret_cast<const ServeItem *>(b.dev + off_items), (int32_t)item, max_k,
-                           b.stream);
+                           reinterpret_cast<unsigned long long *>(b.dev + off_count), b.stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b.samples_host, b.dev + off_count, sizeof(unsigned long long), hipMemcpyDeviceToHost, b.stream);
   if (e == hipSuccess) e = hipEventRecord(b.done, b.stream);
   if (e != hipSuccess) {
     fail(VR_E_DEVICE, "serve launch: %s", hipGetErrorString(e));
@@ -441,8 +509,12 @@ vr_status vr_serve_create(const vr_serve_config *cfg, vr_server **out) {
     if ((e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
     if ((e = hipEventCreateWithFlags(&b.occ_done, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
     if ((e = hipHostMalloc((void **)&b.host, cap, hipHostMallocDefault)) != hipSuccess) return hip_fail(e, "pinned staging");
+    if ((e = hipHostMalloc((void **)&b.samples_host, sizeof(unsigned long long), hipHostMallocDefault)) != hipSuccess)
+      return hip_fail(e, "pinned counter");
+    *b.samples_host = 0;
     if ((e = hipMalloc((void **)&b.dev, cap)) != hipSuccess) return fail(VR_E_OOM, "device staging: %s", hipGetErrorString(e));
   }
+  s->q_since = s->q_last = now_s();
   vr_server *raw = s.release();
   raw->thread = std::thread(scheduler, raw);
   *out = raw;
@@ -471,19 +543,23 @@ vr_status vr_serve_add_volume(vr_server *s, const vr_volume *vol, int32_t block_
     return st;
   }
   std::lock_guard<std::mutex> lk(s->mu);
-  size_t bb = 2 * (size_t)vc.nbx * vc.nby * vc.nbz * sizeof(float2);  // plain and widened ranges
-  if (s->hbm_used + bb > s->cfg.hbm_budget_bytes) {
+  // the volume's own memory (caller-owned, resident) and its blocks (plain and widened ranges)
+  const size_t vb = (size_t)vc.bytes;
+  const size_t bb = 2 * (size_t)vc.nbx * vc.nby * vc.nbz * sizeof(float2);
+  if (!make_room(s, vb + bb)) {
     vr_blocks_free(blocks);
-    return fail(VR_E_BUDGET, "blocks of %zu bytes exceed the HBM budget", bb);
+    return fail(VR_E_BUDGET, "volume (%zu bytes) and blocks (%zu bytes) do not fit the HBM budget (%llu of %llu bytes held)",
+                vb, bb, (unsigned long long)s->hbm_used, (unsigned long long)s->cfg.hbm_budget_bytes);
   }
-  charge(s, bb);
+  charge(s, vb + bb);
+  s->resident_bytes += vb + bb;
   int32_t id = s->next_volume++;
   Volume &v = s->volumes[id];
   v.desc = *vol;
   v.vc = vc;
   v.radius_fits = occupancy_planes_fit(vc, VR_MAX_TF_NODES);
   v.blocks = blocks;
-  v.block_bytes = bb;
+  v.resident_bytes = vb + bb;
   *volume_id = id;
   return VR_OK;
 }
@@ -495,7 +571,8 @@ vr_status vr_serve_remove_volume(vr_server *s, int32_t volume_id) {
   if (it == s->volumes.end()) return fail(VR_E_NOT_FOUND, "unknown volume %d", volume_id);
   if (it->second.users > 0) return fail(VR_E_BUSY, "volume %d has %lld requests queued or in flight", volume_id, (long long)it->second.users);
   vr_blocks_free(it->second.blocks);
-  s->hbm_used -= it->second.block_bytes;
+  s->hbm_used -= it->second.resident_bytes;
+  s->resident_bytes -= it->second.resident_bytes;
   s->volumes.erase(it);
   return VR_OK;
 }
@@ -572,16 +649,22 @@ vr_status vr_serve_submit(vr_server *s, const vr_request *req, uint64_t *ticket)
     s->n_rejected++;
     return fail(VR_E_NOT_FOUND, "unknown volume %d", req->volume_id);
   }
-  if (r->image_bytes > s->cfg.hbm_budget_bytes) {
+  const size_t need = request_bytes(s, req->volume_id, r->image_bytes, r->mc.skip != 0);
+  if (s->resident_bytes + need > s->cfg.hbm_budget_bytes) {
     s->n_rejected++;
-    return fail(VR_E_BUDGET, "result image of %zu bytes exceeds the HBM budget", r->image_bytes);
+    return fail(VR_E_BUDGET,
+                "the request needs %zu device bytes (image and occupancy buffer); %llu of the %llu-byte budget are "
+                "held by resident volumes and blocks",
+                need, (unsigned long long)s->resident_bytes, (unsigned long long)s->cfg.hbm_budget_bytes);
   }
   Volume &v = vit->second;
   r->ticket = s->next_ticket++;
   r->t_submit = now_s();
   v.users++;
   *ticket = r->ticket;
+  note_queue(s);
   s->queue.push_back(r->ticket);
+  note_queue(s);
   s->requests.emplace(r->ticket, std::move(r));
   s->n_submitted++;
   s->cv_work.notify_one();
@@ -658,6 +741,12 @@ vr_status vr_serve_stats_get(vr_server *s, vr_serve_stats *o) {
   double busy = s->busy_s + (s->busy_since >= 0 ? now_s() - s->busy_since : 0.0);
   o->busy_s = busy;
   o->rays_per_s = busy > 0 ? (double)s->pixels_done / busy : 0.0;
+  o->samples = s->samples_done;
+  o->samples_per_s = busy > 0 ? (double)s->samples_done / busy : 0.0;
+  note_queue(s);
+  o->queued_max = s->q_max;
+  o->queued_mean = s->q_last > s->q_since ? s->q_area / (s->q_last - s->q_since) : 0.0;
+  o->resident_bytes = s->resident_bytes;
   return VR_OK;
 }
 
@@ -669,7 +758,11 @@ vr_status vr_serve_stats_reset(vr_server *s) {
   s->busy_s = 0;
   if (s->busy_since >= 0) s->busy_since = now_s();
   s->pixels_done = 0;
+  s->samples_done = 0;
   s->hbm_peak = s->hbm_used;
+  s->q_area = 0;
+  s->q_since = s->q_last = now_s();
+  s->q_max = s->queue.size();
   return VR_OK;
 }
 
@@ -683,6 +776,7 @@ vr_status vr_serve_destroy(vr_server *s) {
       r.state = RState::Cancelled;
       s->volumes[r.volume_id].users--;
     }
+    note_queue(s);
     s->queue.clear();
     s->cv_work.notify_all();
   }
@@ -712,6 +806,7 @@ vr_status vr_serve_destroy(vr_server *s) {
     if (b.occ_done) (void)hipEventDestroy(b.occ_done);
     if (b.stream) (void)hipStreamDestroy(b.stream);
     if (b.host) (void)hipHostFree(b.host);
+    if (b.samples_host) (void)hipHostFree(b.samples_host);
     if (b.dev) (void)hipFree(b.dev);
   }
   for (auto &kv : s->requests) {

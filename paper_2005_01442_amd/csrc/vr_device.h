@@ -87,6 +87,7 @@ struct TfConst {
   const float *table;  // K x 4 fp32
   int32_t K;
   float v0, scale;     // u = (v - v0) * scale, scale = (K-1)/(v1-v0) in fp32
+  uint32_t *status;    // device word set to 1 when the table holds an invalid node (nullptr: not reported)
 };
 
 struct MarchConst {
@@ -129,22 +130,39 @@ __device__ inline TfShared carve_tf(char *base, int K) {
   return s;
 }
 
+// A TF node is valid when all four channels are finite and the extinction is
+// not negative.
+__device__ inline bool tf_node_valid(float4 n) {
+  return __builtin_isfinite(n.x) && __builtin_isfinite(n.y) && __builtin_isfinite(n.z) && __builtin_isfinite(n.w) &&
+         n.w >= 0.0f;
+}
+
+__device__ inline float4 nan_rgba() {
+  const float q = __builtin_nanf("");
+  return make_float4(q, q, q, q);
+}
+
 // Load the TF into LDS and build the prefix counts.  All 256 threads call it.
-// Negative or NaN extinction is read as zero.
-__device__ inline void load_tf(TfShared &s, const TfConst &tf) {
+// Returns false (uniformly) when some node is invalid: the caller then writes
+// NaN results instead of rendering, the status word records it, and every
+// block counts as occupied (negative or NaN extinction is read as zero in the
+// LDS copy, so nothing downstream sees it).
+__device__ inline bool load_tf(TfShared &s, const TfConst &tf) {
   const int t = threadIdx.x;
   const float4 *src = reinterpret_cast<const float4 *>(tf.table);
+  int bad = 0;
   for (int j = t; j < tf.K; j += kWgSize) {
     float4 n = src[j];
+    bad |= tf_node_valid(n) ? 0 : 1;
     n.w = fmaxf(n.w, 0.0f);
     s.node[j] = n;
   }
-  __syncthreads();
+  bad = __syncthreads_or(bad);
   const int words = (tf.K + 63) / 64;
   const int wave = t / kWaveSize, lane = t % kWaveSize;
   for (int w = wave; w < words; w += kWgSize / kWaveSize) {
     int j = w * 64 + lane;
-    bool nz = (j < tf.K) && (s.node[j].w != 0.0f);
+    bool nz = (j < tf.K) && (bad || s.node[j].w != 0.0f);
     unsigned long long m = __ballot(nz);
     if (lane == 0) s.mask[w] = m;
   }
@@ -157,6 +175,8 @@ __device__ inline void load_tf(TfShared &s, const TfConst &tf) {
     s.pref[j] = c;
   }
   __syncthreads();
+  if (bad && t == 0 && tf.status) __hip_atomic_store(tf.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return !bad;
 }
 
 // Occupancy of a block with value range [mn, mx]: some node in

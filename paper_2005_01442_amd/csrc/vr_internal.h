@@ -107,7 +107,7 @@ hipError_t launch_widen_minmax(const float2 *in, float2 *out, int64_t n, float w
 hipError_t launch_prefilter(const VolConst &v, float *out, const float *coef, hipStream_t s);
 hipError_t launch_bricked_pass(const BrickedArgs &a, hipStream_t s);
 hipError_t launch_bricked_finish(const float4 *state, float4 *out, int64_t n, hipStream_t s);
-hipError_t launch_preint_table(const float *tf, int K, float step, float4 *out, hipStream_t s);
+hipError_t launch_preint_table(const float *tf, int K, float step, float4 *out, uint32_t *status, hipStream_t s);
 hipError_t launch_render_preint(const RenderArgs &a, const float4 *tab, hipStream_t s);
 
 // Serving: one work item is a 16x16 super-tile of one request slot.
@@ -124,6 +124,10 @@ struct ServeItem {
   int16_t sx, sy;
 };
 
+// Device address of the current device's TF status word (device_state.hip),
+// nullptr when it cannot be obtained.
+uint32_t *tf_status_word();
+
 // Validation helpers of the ABI layer (api.cpp); each fills the kernel-side
 // constants and records vr_last_error on failure.
 vr_status fail(vr_status s, const char *fmt, ...);
@@ -135,7 +139,8 @@ vr_status check_march(float step, float ert, int32_t use_skip, MarchConst *out);
 vr_status check_shading(const vr_shading *sh, ShadeConst *out);
 vr_status attach_blocks(const vr_blocks *b, const vr_volume *v, VolConst *vc);
 
+// `samples`: device counter the launch adds its evaluated samples to.
 hipError_t launch_serve_batch(const ServeSlot *slots_dev, const ServeItem *items_dev, int32_t n_items,
-                              int32_t max_tf_k, hipStream_t s);
+                              int32_t max_tf_k, unsigned long long *samples, hipStream_t s);
 
 }  // namespace vr

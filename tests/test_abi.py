@@ -10,12 +10,14 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = sorted(os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))
+                 if f.endswith(".h"))
 HEADER = os.path.join(ROOT, "include", "vr.h")
 LIB = os.path.join(ROOT, "paper_2005_01442_amd", "libvr.so")
 
 
 def _declared_functions():
-    text = open(HEADER).read()
+    text = "\n".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(vr_[a-z_]+)\s*\(", text)))
 
@@ -42,7 +44,7 @@ def test_every_declared_symbol_is_exported(abi):
 
 
 def test_abi_version(abi):
-    assert abi.lib().vr_abi_version() == 1
+    assert abi.lib().vr_abi_version() == abi.VR_ABI_VERSION == 2
 
 
 def test_struct_layout_matches_the_header(abi, tmp_path):
@@ -55,7 +57,8 @@ def test_struct_layout_matches_the_header(abi, tmp_path):
         "vr_shading": ["ambient", "shininess", "light", "headlight", "grad_min"],
         "vr_serve_config": ["hbm_budget_bytes", "max_inflight", "max_batch_tiles", "device"],
         "vr_request": ["volume_id", "K", "tf_table_host", "tf_v1", "cam", "step", "use_skip"],
-        "vr_serve_stats": ["submitted", "tiles", "p50_ms", "p99_ms", "busy_s"],
+        "vr_serve_stats": ["submitted", "tiles", "p50_ms", "p99_ms", "busy_s", "samples", "samples_per_s",
+                           "queued_max", "queued_mean", "resident_bytes"],
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "vr.h"', "int main(void){"]
     for s, fields in checks.items():

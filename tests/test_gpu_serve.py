@@ -14,9 +14,26 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
+import oracle  # noqa: E402
 import synth  # noqa: E402
 import paper_2005_01442_amd as vr  # noqa: E402
-from gpu_util import DEV, log, upload_tf, upload_volume  # noqa: E402
+from gpu_util import DEV, compare_with_flags, log, upload_tf, upload_volume  # noqa: E402
+
+
+def _resident_bytes(dims, edge=16, esize=2):
+    """Device bytes a served volume is charged: its voxels, its blocks (plain
+    and widened ranges, 16 B per block)."""
+    nb = 1
+    for d in dims:
+        nb *= -(-d // edge)
+    return dims[0] * dims[1] * dims[2] * esize + 16 * nb
+
+
+def _occupancy_bytes(dims, edge=16):
+    nb = 1
+    for d in dims:
+        nb *= -(-d // edge)
+    return ((nb + 31) // 32 + (nb + 15) // 16) * 4
 
 
 def _volumes():
@@ -63,8 +80,11 @@ def test_admission_errors_timeout_busy_and_shutdown():
     vols, dv = _volumes()
     tf = synth.tf1()
     img_bytes = 64 * 64 * 16
-    srv = vr.Server(hbm_budget_bytes=img_bytes + 64 * 1024, max_inflight=4)
+    # room for the volume, one 64^2 request and a little more
+    res = _resident_bytes(dv[0].dims) + _occupancy_bytes(dv[0].dims)
+    srv = vr.Server(hbm_budget_bytes=res + img_bytes + 8 * 1024, max_inflight=4)
     vid = srv.add_volume(dv[0])
+    assert srv.stats()["resident_bytes"] == _resident_bytes(dv[0].dims)
     cam = synth.orbit_camera(dv[0].dims, np.array([0.3, 0.4, 0.8]), 60.0, 64, 64)
     with pytest.raises(vr.VrError, match="VR_E_NOT_FOUND"):
         srv.submit(vid + 7, cam, tf.table, tf.v0, tf.v1, 0.5)
@@ -82,8 +102,8 @@ def test_admission_errors_timeout_busy_and_shutdown():
     srv.wait(b)
     srv.release(b)
     srv.remove_volume(vid)
-    vid = srv.add_volume(dv[1])
-    cam1 = synth.orbit_camera(dv[1].dims, np.array([0.3, 0.4, 0.8]), 60.0, 64, 64)
+    vid = srv.add_volume(dv[0])  # registered again after its removal
+    cam1 = synth.orbit_camera(dv[0].dims, np.array([0.3, 0.4, 0.8]), 60.0, 64, 64)
     c = srv.submit(vid, cam1, tf.table, tf.v0, tf.v1, 0.5)
     srv.wait(c)  # holds the budget
     d = srv.submit(vid, cam1, tf.table, tf.v0, tf.v1, 0.5)  # queued behind the budget
@@ -115,4 +135,103 @@ def test_request_validation():
         srv.submit(vid, cam, neg, tf.v0, tf.v1, 0.5)
     with pytest.raises(vr.VrError, match="step"):
         srv.submit(vid, cam, tf.table, tf.v0, tf.v1, -1.0)
+    nan = tf.table.copy()
+    nan[3, 1] = np.nan
+    with pytest.raises(vr.VrError, match="not finite"):
+        srv.submit(vid, cam, nan, tf.v0, tf.v1, 0.5)
+    srv.close()
+
+
+def test_budget_counts_volumes_and_never_blocks_the_queue():
+    """A 512x512x800 volume is charged to the budget with its blocks: a
+    budget of one 1024^2 image plus a margin cannot hold it (VR_E_BUDGET at
+    registration, not a time-out later); with room for the volume and one
+    request a second request waits for the first's release; a request that
+    can never fit next to the volume fails at submit; and a queued request
+    that stops fitting because another volume was registered meanwhile
+    completes with VR_E_BUDGET instead of blocking the requests behind it."""
+    dims = (512, 512, 800)
+    vol = synth.ct_phantom_i16(*dims, seed=64, n_soft=6, n_bone=4)
+    dvol = upload_volume(vol)
+    small = upload_volume(synth.ct_phantom_i16(48, 40, 32, seed=65, n_soft=3, n_bone=2))
+    tf = synth.tf1()
+    img = 1024 * 1024 * 16
+    srv = vr.Server(hbm_budget_bytes=img + (1 << 20), max_inflight=4)
+    with pytest.raises(vr.VrError, match="VR_E_BUDGET"):
+        srv.add_volume(dvol)
+    srv.close()
+    need = _resident_bytes(dims) + _occupancy_bytes(dims) + img
+    srv = vr.Server(hbm_budget_bytes=need + (64 << 10), max_inflight=4)
+    vid = srv.add_volume(dvol)
+    cam = synth.orbit_camera(dims, np.array([0.2, -0.5, 0.8]), 60.0, 1024, 1024)
+    a = srv.submit(vid, cam, tf.table, tf.v0, tf.v1, 0.5, 0.99, True)
+    srv.wait(a)
+    b = srv.submit(vid, cam, tf.table, tf.v0, tf.v1, 0.5, 0.99, True)
+    with pytest.raises(vr.VrError, match="VR_E_TIMEOUT"):
+        srv.wait(b, timeout_us=20000)
+    srv.release(a)
+    srv.wait(b)
+    srv.release(b)
+    big = synth.orbit_camera(dims, np.array([0.2, -0.5, 0.8]), 60.0, 1100, 1024)
+    with pytest.raises(vr.VrError, match="VR_E_BUDGET"):
+        srv.submit(vid, big, tf.table, tf.v0, tf.v1, 0.5, 0.99, True)
+    # c (256^2) holds image memory, so d (1024^2) queues; registering a small
+    # volume then leaves d no room at all (it needed the whole margin); e,
+    # queued behind d, must still complete
+    cam_c = synth.orbit_camera(dims, np.array([0.2, -0.5, 0.8]), 60.0, 256, 256)
+    c = srv.submit(vid, cam_c, tf.table, tf.v0, tf.v1, 0.5, 0.99, True)
+    srv.wait(c)
+    d = srv.submit(vid, cam, tf.table, tf.v0, tf.v1, 0.5, 0.99, True)
+    with pytest.raises(vr.VrError, match="VR_E_TIMEOUT"):
+        srv.wait(d, timeout_us=20000)
+    sid = srv.add_volume(small)
+    cam_s = synth.orbit_camera(small.dims, np.array([0.3, 0.4, 0.8]), 60.0, 16, 16)
+    e = srv.submit(sid, cam_s, tf.table, tf.v0, tf.v1, 0.5, 0.99, True)
+    with pytest.raises(vr.VrError, match="VR_E_BUDGET"):
+        srv.wait(d, timeout_us=30_000_000)
+    srv.release(d)
+    srv.wait(e, timeout_us=30_000_000)
+    srv.release(e)
+    srv.release(c)
+    st = srv.stats()
+    assert st["hbm_peak"] <= need + (64 << 10)
+    srv.close()
+
+
+def test_c4_mix_matches_alone_renders_and_the_oracle():
+    """The serving configuration's volumes (8 C4 phantoms, 128^3 up to
+    452x496x688 int16, all resident) with 24 requests of the C4 stream
+    (random volume, 256^2 / 512^2 / 1024^2, random orbit pose, TF1, step 0.5,
+    early termination at 0.99, skipping) submitted at once so that they share
+    launches: every served image equals vr_render of the same request alone
+    (bit-identical), and 300 sampled hit pixels of each equal the FP64 oracle
+    (2e-4; early-termination ties by the flag rule)."""
+    dims = synth.config_c4_volumes(seed=10, count=8)
+    host = [synth.ct_phantom_i16(*d, seed=sd) for d, sd in dims]
+    dev = [upload_volume(v) for v in host]
+    blocks = [vr.vr_build_blocks(v, 16) for v in dev]
+    tf = synth.tf1()
+    t_dev = upload_tf(tf)
+    srv = vr.Server(hbm_budget_bytes=4 << 30, max_inflight=32)
+    ids = [srv.add_volume(v) for v in dev]
+    reqs = synth.c4_arrivals(24, seed=11, n_volumes=8, dims_list=[d for d, _ in dims])
+    log(f"c4 mix: {len(reqs)} requests, sizes {sorted(set(r['size'] for r in reqs))}")
+    tickets = [srv.submit(ids[r["volume"]], r["camera"], tf.table, tf.v0, tf.v1, 0.5, 0.99, True) for r in reqs]
+    worst, flagged = 0.0, 0
+    for q, (t, r) in enumerate(zip(tickets, reqs)):
+        cam = r["camera"]
+        got = srv.result(t, cam.height, cam.width).cpu().numpy()
+        vi = r["volume"]
+        alone = vr.vr_render(dev[vi], blocks[vi], [cam], t_dev, 0.5, 0.99, True)[0].cpu().numpy()
+        assert np.array_equal(got, alone), (q, vi, cam.width)
+        lat = oracle.lattice([cam], dims[vi][0], 0.5)
+        pix = synth.sample_pixels(1, cam.width, cam.height, 3000, seed=200 + q)
+        pix = pix[lat[0, pix[:, 1], pix[:, 2]] > 0][:300]
+        ref = oracle.render(host[vi], [cam], tf, 0.5, ert=0.99, pixels=pix)
+        un, nf = compare_with_flags(got[pix[:, 1], pix[:, 2]].astype(np.float64), ref["rgba"], ref["flags"], 0.99)
+        worst, flagged = max(worst, un), flagged + nf
+    st = srv.stats()
+    log(f"c4 mix: max unflagged |dRGBA| vs oracle {worst:.3e}, flagged {flagged}; launches {st['launches']}, "
+        f"samples {st['samples']}")
+    assert st["completed"] == len(reqs) and st["launches"] >= 2 and st["samples"] > 0
     srv.close()
