@@ -211,6 +211,22 @@ void vr_blocks_free(vr_blocks *blocks);
 vr_status vr_render(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,
                     const vr_tf *tf, const vr_params *p, float *out_rgba, void *stream);
 
+/* vr_render for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.
+ * Arguments, results and errors as vr_render (the image is bit-identical);
+ * nothing is allocated: the per-launch workgroup order and the occupancy
+ * planes of the block grid live in a 2 MiB scratch array the library keeps
+ * in device memory on every GPU it runs on (until the process ends).
+ * Limits: a view of at most 262,144 16x16 tiles (8192 x 8192 pixels; views
+ * are launched as many at a time as the scratch orders), and with
+ * use_skip at most 2,796,192 blocks (1 MiB of occupancy planes); beyond them
+ * VR_E_INVALID_ARG, nothing enqueued.  Every call on one GPU uses that GPU's
+ * array: calls that overlap on one GPU (other streams, other threads) race,
+ * so serialise them.  Every scratch entry a launch reads is written by that
+ * launch first. */
+vr_status vr_render_noalloc(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,
+                            const vr_tf *tf, const vr_params *p, float *out_rgba, void *stream);
+
 /* Interpolating cubic B-spline.  The paper compares reconstruction filters
  * (Section 2, the filter comparison of Fig. 4); the plain cubic B-spline
  * smooths, its prefiltered form interpolates.  Writes to coeff_out (DEVICE,

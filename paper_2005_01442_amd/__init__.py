@@ -30,6 +30,7 @@ __all__ = [
     "vr_blocks_minmax",
     "vr_block_occupancy",
     "vr_render",
+    "vr_render_noalloc",
     "vr_render_backward",
     "device_status",
     "Shading",
@@ -261,6 +262,25 @@ def vr_render(volume: Volume, blocks, cameras, tf: TF, step: float, ert: float =
         check(lib().vr_render_shaded(ctypes.byref(volume.c), None if blocks is None else blocks.ptr, cams,
                                      len(cameras), ctypes.byref(tf.c), ctypes.byref(p), ctypes.byref(sh),
                                      ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
+    return out
+
+
+def vr_render_noalloc(volume: Volume, blocks, cameras, tf: TF, step: float, ert: float, use_skip: bool,
+                      out: torch.Tensor, counters: torch.Tensor | None = None, stream=None, filter: int = 0):
+    """vr_render into the caller's ``out`` ((views, H, W, 4) fp32 CUDA tensor)
+    without any device allocation (``vr_render_noalloc``: the library's
+    per-GPU scratch array holds the launch order and occupancy planes)."""
+    if counters is not None and (counters.dtype != torch.int64 or counters.numel() < 4 or not counters.is_cuda):
+        raise ValueError("counters must be an int64 CUDA tensor of at least 4 elements")
+    W, H = _image_size(cameras)
+    if (not out.is_cuda or out.dtype != torch.float32 or not out.is_contiguous()
+            or out.numel() < len(cameras) * H * W * 4):
+        raise ValueError("out must be a contiguous float32 CUDA tensor holding views x H x W x 4")
+    cams = _cameras(cameras)
+    p = _params(step, ert, use_skip, counters, filter)
+    check(lib().vr_render_noalloc(ctypes.byref(volume.c), None if blocks is None else blocks.ptr, cams, len(cameras),
+                                  ctypes.byref(tf.c), ctypes.byref(p), ctypes.c_void_p(out.data_ptr()),
+                                  _stream_ptr(stream)))
     return out
 
 

@@ -101,6 +101,8 @@ PROTOTYPES = {
     "vr_blocks_free": ([c_void_p], None),
     "vr_render": ([POINTER(vr_volume), c_void_p, POINTER(vr_camera), c_int32, POINTER(vr_tf), POINTER(vr_params),
                    c_void_p, c_void_p], c_int32),
+    "vr_render_noalloc": ([POINTER(vr_volume), c_void_p, POINTER(vr_camera), c_int32, POINTER(vr_tf),
+                           POINTER(vr_params), c_void_p, c_void_p], c_int32),
     "vr_render_shaded": ([POINTER(vr_volume), c_void_p, POINTER(vr_camera), c_int32, POINTER(vr_tf),
                           POINTER(vr_params), POINTER(vr_shading), c_void_p, c_void_p], c_int32),
     "vr_preint_build": ([POINTER(vr_tf), c_float, c_void_p, POINTER(c_void_p)], c_int32),

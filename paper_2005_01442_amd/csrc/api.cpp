@@ -207,7 +207,7 @@ int32_t chunk_edge_setting() {
 
 // Validate the common arguments of vr_render / vr_render_backward and fill
 // the launch arguments (cameras excluded).
-static vr_status prepare(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,
+vr_status prepare_render(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,
                          const vr_tf *tf, const vr_params *p, RenderArgs *a) {
   memset(a, 0, sizeof(*a));
   vr_status s = check_volume(vol, &a->vol);
@@ -334,75 +334,102 @@ void vr_blocks_free(vr_blocks *b) {
   delete b;
 }
 
-static vr_status render_views(RenderArgs &a, const vr_camera *cams, int32_t n_cams, float *out_rgba, void *stream,
-                              const float4 *preint = nullptr) {
+}  // extern "C"
+
+namespace vr {
+
+vr_status render_views(RenderArgs &a, const vr_camera *cams, int32_t n_cams, float *out_rgba, void *stream,
+                       const float4 *preint, const RenderScratch *scratch) {
   const size_t view_floats = (size_t)a.W * a.H * 4;
+  hipStream_t st = (hipStream_t)stream;
   // the blocks' occupancy under this TF, once for all views (without it the
   // kernels decide from min/max and the TF on every block change)
   uint32_t *bits = nullptr;
-  bool radius = false;
+  bool own_bits = false, radius = false;
   if (a.mc.skip && a.vol.minmax) {
-    const int64_t words = ((int64_t)a.vol.nbx * a.vol.nby * a.vol.nbz + 31) / 32;
-    const int64_t rwords = ((int64_t)a.vol.nbx * a.vol.nby * a.vol.nbz + 15) / 16;
-    if (hipMallocAsync(reinterpret_cast<void **>(&bits), (size_t)(words + rwords) * 4, (hipStream_t)stream) !=
-        hipSuccess) {
+    if (scratch) {
+      bits = scratch->occ;
+    } else if (hipMallocAsync(reinterpret_cast<void **>(&bits), occupancy_bytes(a.vol), st) != hipSuccess) {
       (void)hipGetLastError();
       bits = nullptr;
     } else {
+      own_bits = true;
+    }
+    if (bits) {
       // (pre-integration leaps block by block: its cells span two blocks)
       if (!preint && occupancy_planes_fit(a.vol, a.tf.K)) {
-        radius = launch_occupancy_planes(a.vol, a.tf, bits, (hipStream_t)stream) == hipSuccess;
+        radius = launch_occupancy_planes(a.vol, a.tf, bits, st) == hipSuccess;
         if (!radius) (void)hipGetLastError();
       }
-      if (!radius && launch_occupancy_bits(a.vol, a.tf, bits, (hipStream_t)stream) != hipSuccess) {
+      if (!radius && launch_occupancy_bits(a.vol, a.tf, bits, st) != hipSuccess) {
         (void)hipGetLastError();
-        (void)hipFreeAsync(bits, (hipStream_t)stream);
+        if (own_bits) (void)hipFreeAsync(bits, st);
         bits = nullptr;
+        own_bits = false;
       }
     }
   }
   a.vol.occ = bits;
   a.vol.occ_radius = radius ? kEmptyRadiusMax : 0;
-  for (int32_t v0 = 0; v0 < n_cams; v0 += kMaxCamsPerLaunch) {
-    const int32_t n = std::min(kMaxCamsPerLaunch, n_cams - v0);
+  // views per launch: what the kernel arguments carry and, with scratch,
+  // what its order area holds
+  int32_t per_launch = kMaxCamsPerLaunch;
+  if (scratch) {
+    const int64_t tiles = (int64_t)((a.W + kSuperEdge - 1) / kSuperEdge) * ((a.H + kSuperEdge - 1) / kSuperEdge);
+    per_launch = (int32_t)std::min<int64_t>(kMaxCamsPerLaunch, scratch->order_ints / tiles);
+  }
+  vr_status result = VR_OK;
+  for (int32_t v0 = 0; v0 < n_cams; v0 += per_launch) {
+    const int32_t n = std::min(per_launch, n_cams - v0);
     for (int32_t i = 0; i < n; ++i) check_camera(&cams[v0 + i], &a.cams[i]);
     a.n_views = n;
     a.out = out_rgba + (size_t)v0 * view_floats;
-    a.order = make_tile_order(a, (hipStream_t)stream);
-    hipError_t e = preint ? launch_render_preint(a, preint, (hipStream_t)stream) : launch_render(a, (hipStream_t)stream);
-    if (a.order) (void)hipFreeAsync(const_cast<int32_t *>(a.order), (hipStream_t)stream);
+    bool own_order = false;
+    if (scratch) {
+      a.order = launch_tile_order(a, scratch->order, st) == hipSuccess ? scratch->order : nullptr;
+      if (!a.order) (void)hipGetLastError();
+    } else {
+      a.order = make_tile_order(a, st);
+      own_order = a.order != nullptr;
+    }
+    hipError_t e = preint ? launch_render_preint(a, preint, st) : launch_render(a, st);
+    if (own_order) (void)hipFreeAsync(const_cast<int32_t *>(a.order), st);
     a.order = nullptr;
     if (e != hipSuccess) {
-      if (bits) (void)hipFreeAsync(bits, (hipStream_t)stream);
-      return hip_fail(e, "render launch");
+      result = hip_fail(e, "render launch");
+      break;
     }
   }
-  if (bits) (void)hipFreeAsync(bits, (hipStream_t)stream);
+  if (own_bits) (void)hipFreeAsync(bits, st);
   a.vol.occ = nullptr;
   a.vol.occ_radius = 0;
-  return VR_OK;
+  return result;
 }
+
+}  // namespace vr
+
+extern "C" {
 
 vr_status vr_render(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,
                     const vr_tf *tf, const vr_params *p, float *out_rgba, void *stream) {
   RenderArgs a;
-  vr_status s = prepare(vol, blocks, cams, n_cams, tf, p, &a);
+  vr_status s = prepare_render(vol, blocks, cams, n_cams, tf, p, &a);
   if (s) return s;
   if (!out_rgba) return fail(VR_E_INVALID_ARG, "out_rgba is NULL");
-  return render_views(a, cams, n_cams, out_rgba, stream);
+  return render_views(a, cams, n_cams, out_rgba, stream, nullptr, nullptr);
 }
 
 vr_status vr_render_shaded(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,
                            const vr_tf *tf, const vr_params *p, const vr_shading *shading, float *out_rgba,
                            void *stream) {
   RenderArgs a;
-  vr_status s = prepare(vol, blocks, cams, n_cams, tf, p, &a);
+  vr_status s = prepare_render(vol, blocks, cams, n_cams, tf, p, &a);
   if (s) return s;
   if (p->filter != VR_FILTER_BSPLINE) return fail(VR_E_UNSUPPORTED, "local lighting uses the cubic B-spline only");
   if ((s = check_shading(shading, &a.shade))) return s;
   if (!out_rgba) return fail(VR_E_INVALID_ARG, "out_rgba is NULL");
   a.shaded = 1;
-  return render_views(a, cams, n_cams, out_rgba, stream);
+  return render_views(a, cams, n_cams, out_rgba, stream, nullptr, nullptr);
 }
 
 vr_status vr_preint_build(const vr_tf *tf, float step, void *stream, vr_preint **out) {
@@ -456,7 +483,7 @@ vr_status vr_render_preint(const vr_volume *vol, const vr_blocks *blocks, const 
                            const vr_tf *tf, const vr_params *p, const vr_preint *table, float *out_rgba,
                            void *stream) {
   RenderArgs a;
-  vr_status s = prepare(vol, blocks, cams, n_cams, tf, p, &a);
+  vr_status s = prepare_render(vol, blocks, cams, n_cams, tf, p, &a);
   if (s) return s;
   if (p->filter != VR_FILTER_BSPLINE) return fail(VR_E_UNSUPPORTED, "pre-integration uses the cubic B-spline only");
   if (!table) return fail(VR_E_INVALID_ARG, "pre-integration table is NULL");
@@ -464,7 +491,7 @@ vr_status vr_render_preint(const vr_volume *vol, const vr_blocks *blocks, const 
       table->step != p->step)
     return fail(VR_E_INVALID_ARG, "the pre-integration table was built for another TF or step");
   if (!out_rgba) return fail(VR_E_INVALID_ARG, "out_rgba is NULL");
-  return render_views(a, cams, n_cams, out_rgba, stream, table->table);
+  return render_views(a, cams, n_cams, out_rgba, stream, table->table, nullptr);
 }
 
 vr_status vr_prefilter_bspline(const vr_volume *vol, float *coeff_out, void *stream) {
@@ -506,7 +533,7 @@ vr_status vr_render_backward(const vr_volume *vol, const vr_blocks *blocks, cons
                              const vr_tf *tf, const vr_params *p, const float *out_rgba, const float *grad_rgba,
                              float *grad_volume, float *grad_tf, void *stream) {
   BackwardArgs b;
-  vr_status s = prepare(vol, blocks, cams, n_cams, tf, p, &b.r);
+  vr_status s = prepare_render(vol, blocks, cams, n_cams, tf, p, &b.r);
   if (s) return s;
   if (p->filter != VR_FILTER_BSPLINE) return fail(VR_E_UNSUPPORTED, "the adjoint is of the cubic B-spline render");
   if (!out_rgba || !grad_rgba) return fail(VR_E_INVALID_ARG, "out_rgba and grad_rgba are required");

@@ -213,7 +213,7 @@ int64_t render_grid(const RenderArgs &a) {
   return grid_size_for(a.W, a.H, a.n_views, a.chunk_edge);
 }
 
-int32_t *make_tile_order(const RenderArgs &a, hipStream_t s) {
+hipError_t launch_tile_order(const RenderArgs &a, int32_t *order, hipStream_t s) {
   OrderArgs o;
   o.tx = (a.W + kSuperEdge - 1) / kSuperEdge;
   o.ty = (a.H + kSuperEdge - 1) / kSuperEdge;
@@ -242,11 +242,18 @@ int32_t *make_tile_order(const RenderArgs &a, hipStream_t s) {
     o.cx[v] = (float)fmin(fmax((col + 0.5) / kSuperEdge - 0.5, -1e6), 1e6);
     o.cy[v] = (float)fmin(fmax((row + 0.5) / kSuperEdge - 0.5, -1e6), 1e6);
   }
-  const int64_t n = (int64_t)a.n_views * o.tx * o.ty;
-  int32_t *order = nullptr;
-  if (hipMallocAsync((void **)&order, (size_t)n * sizeof(int32_t), s) != hipSuccess) return nullptr;
   hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(kOrderThreads), 0, s, o, order);
-  if (hipGetLastError() != hipSuccess) {
+  return hipGetLastError();
+}
+
+int64_t tile_order_count(const RenderArgs &a) {
+  return (int64_t)a.n_views * ((a.W + kSuperEdge - 1) / kSuperEdge) * ((a.H + kSuperEdge - 1) / kSuperEdge);
+}
+
+int32_t *make_tile_order(const RenderArgs &a, hipStream_t s) {
+  int32_t *order = nullptr;
+  if (hipMallocAsync((void **)&order, (size_t)tile_order_count(a) * sizeof(int32_t), s) != hipSuccess) return nullptr;
+  if (launch_tile_order(a, order, s) != hipSuccess) {
     (void)hipFreeAsync(order, s);
     return nullptr;
   }

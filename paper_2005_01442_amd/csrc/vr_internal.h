@@ -83,6 +83,10 @@ int64_t render_grid(const RenderArgs &a);
 // hipFreeAsync after its launches.  nullptr when it cannot be allocated (the
 // Morton mapping is used then).
 int32_t *make_tile_order(const RenderArgs &a, hipStream_t s);
+// The same order written into `order` (tile_order_count(a) entries, every one
+// written), allocating nothing.
+hipError_t launch_tile_order(const RenderArgs &a, int32_t *order, hipStream_t s);
+int64_t tile_order_count(const RenderArgs &a);
 hipError_t launch_render_backward(const BackwardArgs &a, hipStream_t s);
 hipError_t launch_block_minmax(const VolConst &v, float2 *out, hipStream_t s);
 hipError_t launch_block_occupancy(const VolConst &v, const TfConst &tf, uint8_t *occ, hipStream_t s);
@@ -123,6 +127,25 @@ struct ServeItem {
   int32_t slot;
   int16_t sx, sy;
 };
+
+// Device memory a render may use instead of allocating: room for the
+// workgroup order of one launch and for the occupancy planes of the volume's
+// block grid.  Every entry a launch reads is written by that launch first.
+struct RenderScratch {
+  int32_t *order;
+  int64_t order_ints;
+  uint32_t *occ;
+  size_t occ_bytes;
+};
+
+// Validate the arguments of vr_render-like calls and fill the launch
+// arguments (cameras excluded); api.cpp.
+vr_status prepare_render(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,
+                         const vr_tf *tf, const vr_params *p, RenderArgs *a);
+// Render the views of `a` (all launches); with `scratch` nothing is
+// allocated (the caller has checked that its sizes suffice).
+vr_status render_views(RenderArgs &a, const vr_camera *cams, int32_t n_cams, float *out_rgba, void *stream,
+                       const float4 *preint, const RenderScratch *scratch);
 
 // Device address of the current device's TF status word (device_state.hip),
 // nullptr when it cannot be obtained.
