@@ -11,56 +11,165 @@
 
 namespace vr {
 
+// One workgroup per row of blocks (by, bz): the x-rows of its footprint,
+// [16 by - 1, 16 by + 17] x [16 bz - 1, 16 bz + 17] (clamped), are streamed
+// once; the eight wavefronts take every eighth row, four rows per trip (their
+// loads in flight together).  In a pass over 32 blocks of x, a lane holds the
+// E/2 voxels of half a block: even lane 2i the low half of block i of the
+// pass plus the voxel before it, odd lane 2i + 1 the high half plus the two
+// after it (x clamped to the row, which duplicates edge voxels and leaves
+// min and max unchanged), so the block's footprint along x is the pair's
+// union, combined with one lane swap.  The even lane keeps the running (min,
+// max) over the rows; the wavefronts are combined in LDS at the end of the
+// pass.  WIDE (E = 16, rows of a multiple of 8 voxels, 16-byte aligned data):
+// a lane's half block is one or two 16-byte loads.
+constexpr int kMinmaxHalf = 8;   // voxels per lane per row in one trip: half of a 16-voxel block
+constexpr int kMinmaxRows = 4;   // rows per wavefront trip
+constexpr int kMinmaxThreads = 512;  // eight wavefronts: more rows in flight per row of blocks
+
 template <typename T>
-__device__ inline float load_voxel(const void *p, uint32_t i) {
-  return (float)reinterpret_cast<const T *>(p)[i];
+__device__ inline void half_block_range(const T *row, int xa, int half, int nx, bool hi, float &mn, float &mx) {
+  // the footprint's apron: one voxel before the block, two after it
+  const float a0 = (float)row[hi ? min(xa + half, nx - 1) : max(xa - 1, 0)];
+  const float a1 = (float)row[hi ? min(xa + half + 1, nx - 1) : min(xa, nx - 1)];
+  mn = fminf(mn, fminf(a0, a1));
+  mx = fmaxf(mx, fmaxf(a0, a1));
+  for (int i0 = 0; i0 < half; i0 += kMinmaxHalf) {  // one trip for E <= 16
+    float a[kMinmaxHalf];
+#pragma unroll
+    for (int i = 0; i < kMinmaxHalf; ++i) a[i] = (float)row[min(xa + min(i0 + i, half - 1), nx - 1)];
+#pragma unroll
+    for (int i = 0; i < kMinmaxHalf; ++i) {
+      mn = fminf(mn, a[i]);
+      mx = fmaxf(mx, a[i]);
+    }
+  }
 }
 
-// One workgroup per block streams its footprint and reduces it.
+// WIDE: E = 16, rows of a multiple of 8 voxels, 16-byte aligned.  A lane's
+// half block (xa a multiple of 8) is one 16-byte load (two for fp32); past
+// the row's end the row's last 8 voxels stand in (they lie in the last
+// block's footprint).  The apron comes from the neighbouring lanes' loads
+// (the last voxel of lane - 1, the first two of lane + 1); only the lanes at
+// the ends of a pass load theirs (lane 0 the voxel before the pass, lane 63
+// the two after it, clamped to the row).
 template <typename T>
-__global__ __launch_bounds__(kWgSize) void k_block_minmax(const VolConst v, float2 *out) {
-  __shared__ float smin[kWgSize / kWaveSize], smax[kWgSize / kWaveSize];
-  const int64_t b = blockIdx.x;
-  const int bx = (int)(b % v.nbx), by = (int)((b / v.nbx) % v.nby), bz = (int)(b / ((int64_t)v.nbx * v.nby));
-  const int E = v.edge;
-  const int x0 = max(bx * E - 1, 0), x1 = min(bx * E + E + 1, v.nx - 1);
+__device__ inline void half_block_range_wide(const T *row, int xa, int nx, int lane, bool first_pass, float &mn,
+                                             float &mx) {
+  const T *p = row + min(xa, nx - kMinmaxHalf);
+  float a[kMinmaxHalf];
+  if constexpr (sizeof(T) == 2) {
+    const uint4 q = *reinterpret_cast<const uint4 *>(p);
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint16_t lo = (uint16_t)(w[i] & 0xffffu), h = (uint16_t)(w[i] >> 16);
+      a[2 * i] = (float)*reinterpret_cast<const T *>(&lo);
+      a[2 * i + 1] = (float)*reinterpret_cast<const T *>(&h);
+    }
+  } else {
+    const float4 q0 = reinterpret_cast<const float4 *>(p)[0], q1 = reinterpret_cast<const float4 *>(p)[1];
+    a[0] = q0.x; a[1] = q0.y; a[2] = q0.z; a[3] = q0.w;
+    a[4] = q1.x; a[5] = q1.y; a[6] = q1.z; a[7] = q1.w;
+  }
+  const float left = __shfl_up(a[kMinmaxHalf - 1], 1, kWaveSize);
+  const float right0 = __shfl_down(a[0], 1, kWaveSize), right1 = __shfl_down(a[1], 1, kWaveSize);
+  float ap0, ap1;
+  if (lane & 1) {
+    if (lane == kWaveSize - 1) {
+      ap0 = (float)row[min(xa + kMinmaxHalf, nx - 1)];
+      ap1 = (float)row[min(xa + kMinmaxHalf + 1, nx - 1)];
+    } else {
+      ap0 = right0;
+      ap1 = right1;
+    }
+  } else {
+    ap0 = lane == 0 ? (first_pass ? a[0] : (float)row[max(xa - 1, 0)]) : left;
+    ap1 = ap0;
+  }
+  mn = fminf(mn, fminf(ap0, ap1));
+  mx = fmaxf(mx, fmaxf(ap0, ap1));
+#pragma unroll
+  for (int i = 0; i < kMinmaxHalf; ++i) {
+    mn = fminf(mn, a[i]);
+    mx = fmaxf(mx, a[i]);
+  }
+}
+
+template <typename T, bool WIDE>
+__global__ __launch_bounds__(kMinmaxThreads) void k_block_minmax(const VolConst v, float2 *out) {
+  constexpr int kWaves = kMinmaxThreads / kWaveSize;
+  __shared__ float smin[kWaves][kWaveSize / 2], smax[kWaves][kWaveSize / 2];
+  // XCD-aware: the hardware hands workgroup i to XCD i mod 8; each XCD takes
+  // a contiguous run of rows of blocks, so the footprint rows neighbouring
+  // rows of blocks share are read through the same L2
+  const int nrows = v.nby * v.nbz, per_xcd = (nrows + kXcds - 1) / kXcds;
+  const int q = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+  if (q >= nrows) return;  // uniform: padding of the last XCD's run
+  const int by = q % v.nby, bz = q / v.nby;
+  const int E = v.edge, half = E / 2;
   const int y0 = max(by * E - 1, 0), y1 = min(by * E + E + 1, v.ny - 1);
   const int z0 = max(bz * E - 1, 0), z1 = min(bz * E + E + 1, v.nz - 1);
-  const int ex = x1 - x0 + 1, ey = y1 - y0 + 1, ez = z1 - z0 + 1;
-  const int count = ex * ey * ez;
-  float mn = INFINITY, mx = -INFINITY;
-  for (int i = threadIdx.x; i < count; i += kWgSize) {
-    int x = x0 + i % ex, y = y0 + (i / ex) % ey, z = z0 + i / (ex * ey);
-    uint32_t idx = ((uint32_t)z * (uint32_t)v.ny + (uint32_t)y) * (uint32_t)v.nx + (uint32_t)x;
-    float a = load_voxel<T>(v.data, idx);
-    mn = fminf(mn, a);
-    mx = fmaxf(mx, a);
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    mn = fminf(mn, __shfl_xor(mn, off, kWaveSize));
-    mx = fmaxf(mx, __shfl_xor(mx, off, kWaveSize));
-  }
+  const int ny = y1 - y0 + 1, rows = ny * (z1 - z0 + 1);
   const int wave = threadIdx.x / kWaveSize, lane = threadIdx.x % kWaveSize;
-  if (lane == 0) {
-    smin[wave] = mn;
-    smax[wave] = mx;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < kWgSize / kWaveSize; ++w) {
-      mn = fminf(mn, smin[w]);
-      mx = fmaxf(mx, smax[w]);
+  const T *base = reinterpret_cast<const T *>(v.data);
+  const int per_pass = kWaveSize / 2;  // blocks per pass
+  for (int bx0 = 0; bx0 < v.nbx; bx0 += per_pass) {
+    const int bx = bx0 + lane / 2;          // this lane's block
+    const bool hi = lane & 1;
+    const int xa = bx * E + (hi ? half : 0);  // first voxel of its half
+    float mn = INFINITY, mx = -INFINITY;
+    for (int r0 = wave; r0 < rows; r0 += kWaves * kMinmaxRows) {
+#pragma unroll
+      for (int u = 0; u < kMinmaxRows; ++u) {
+        const int r = min(r0 + u * kWaves, rows - 1);  // a repeated last row changes nothing
+        const int y = y0 + r % ny, z = z0 + r / ny;
+        const T *row = base + ((size_t)z * (size_t)v.ny + (size_t)y) * (size_t)v.nx;
+        if constexpr (WIDE)
+          half_block_range_wide<T>(row, xa, v.nx, lane, bx0 == 0, mn, mx);
+        else
+          half_block_range<T>(row, xa, half, v.nx, hi, mn, mx);
+      }
     }
-    out[b] = make_float2(mn, mx);
+    // the pair's union: the even lane takes its odd neighbour's range
+    mn = fminf(mn, __shfl_xor(mn, 1, kWaveSize));
+    mx = fmaxf(mx, __shfl_xor(mx, 1, kWaveSize));
+    if (!hi) {
+      smin[wave][lane / 2] = mn;
+      smax[wave][lane / 2] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x < per_pass) {
+      const int b = bx0 + threadIdx.x;
+      float m0 = smin[0][threadIdx.x], m1 = smax[0][threadIdx.x];
+#pragma unroll
+      for (int w = 1; w < kWaves; ++w) {
+        m0 = fminf(m0, smin[w][threadIdx.x]);
+        m1 = fmaxf(m1, smax[w][threadIdx.x]);
+      }
+      if (b < v.nbx) out[((int64_t)bz * v.nby + by) * v.nbx + b] = make_float2(m0, m1);
+    }
+    __syncthreads();
   }
 }
 
 hipError_t launch_block_minmax(const VolConst &v, float2 *out, hipStream_t s) {
-  int64_t nb = (int64_t)v.nbx * v.nby * v.nbz;
+  const unsigned grid = (unsigned)(((int64_t)v.nby * v.nbz + kXcds - 1) / kXcds * kXcds);
+  const bool wide = v.edge == 2 * kMinmaxHalf && v.nx % kMinmaxHalf == 0 &&
+                    (reinterpret_cast<uintptr_t>(v.data) & 15u) == 0;
   switch (v.dtype) {
-  case kU16: hipLaunchKernelGGL(k_block_minmax<uint16_t>, dim3((unsigned)nb), dim3(kWgSize), 0, s, v, out); break;
-  case kI16: hipLaunchKernelGGL(k_block_minmax<int16_t>, dim3((unsigned)nb), dim3(kWgSize), 0, s, v, out); break;
-  case kF32: hipLaunchKernelGGL(k_block_minmax<float>, dim3((unsigned)nb), dim3(kWgSize), 0, s, v, out); break;
+  case kU16:
+    if (wide) hipLaunchKernelGGL((k_block_minmax<uint16_t, true>), dim3(grid), dim3(kMinmaxThreads), 0, s, v, out);
+    else hipLaunchKernelGGL((k_block_minmax<uint16_t, false>), dim3(grid), dim3(kMinmaxThreads), 0, s, v, out);
+    break;
+  case kI16:
+    if (wide) hipLaunchKernelGGL((k_block_minmax<int16_t, true>), dim3(grid), dim3(kMinmaxThreads), 0, s, v, out);
+    else hipLaunchKernelGGL((k_block_minmax<int16_t, false>), dim3(grid), dim3(kMinmaxThreads), 0, s, v, out);
+    break;
+  case kF32:
+    if (wide) hipLaunchKernelGGL((k_block_minmax<float, true>), dim3(grid), dim3(kMinmaxThreads), 0, s, v, out);
+    else hipLaunchKernelGGL((k_block_minmax<float, false>), dim3(grid), dim3(kMinmaxThreads), 0, s, v, out);
+    break;
   default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -106,6 +106,18 @@ def test_dtypes_and_odd_row_lengths(dtype):
 
 
 def test_blocks_and_occupancy_exact():
+    """Block min/max of every dtype, edges 4..64, rows of any length: the
+    16-byte-load path (edge 16, x a multiple of 8: 96, 24 whose last block is
+    half, 64) and the general one, integer-exact against the oracle."""
+    rng = np.random.default_rng(37)
+    for dims in ((24, 33, 17), (64, 40, 24), (37, 29, 23), (136, 20, 18)):
+        base = synth.ct_phantom_i16(*dims, seed=39, n_soft=3, n_bone=2)
+        for vol in (base, (base.astype(np.int32) + 1024).clip(0, 4095).astype(np.uint16),
+                    base.astype(np.float32) + rng.standard_normal(base.shape).astype(np.float32)):
+            v = upload_volume(vol)
+            for edge in (4, 8, 16, 32, 64):
+                mm = vr.vr_blocks_minmax(vr.vr_build_blocks(v, edge)).cpu().numpy().astype(np.float64)
+                assert np.array_equal(mm, oracle.blocks(vol, edge)), (dims, vol.dtype, edge)
     for dims, edge in (((96, 80, 72), 16), ((37, 29, 23), 8), ((50, 17, 33), 16)):
         vol = synth.ct_phantom_i16(*dims, seed=38, n_soft=4, n_bone=3)
         v = upload_volume(vol)
