@@ -405,6 +405,8 @@ typedef struct {
     int32_t max_batch_tiles;   /* 16x16-pixel work items per launch (0 = 2048)        */
     int32_t device;            /* HIP device ordinal                                  */
     int32_t reserved;
+    uint64_t brick_pool_bytes; /* device pool shared by out-of-core volumes, taken
+                                  from the budget at the first such volume (0: none) */
 } vr_serve_config;
 
 /* One request.  tf_table_host: HOST K*4 floats, copied at submit. */
@@ -441,6 +443,21 @@ vr_status vr_serve_create(const vr_serve_config *cfg, vr_server **out);
  * blocks count against the budget (pooled result images are freed to make
  * room); VR_E_BUDGET when they do not fit.  *volume_id receives the id. */
 vr_status vr_serve_add_volume(vr_server *s, const vr_volume *vol, int32_t block_edge, int32_t *volume_id);
+
+/* Register an out-of-core volume: `host_vol` is a HOST volume (read during
+ * the call only; no 4 GiB limit), kept as pinned host bricks of edge
+ * `brick_edge` (a power of two in [8, 128]) as vr_bricked_create does, for
+ * volumes larger than the HBM budget (the paper's block decomposition of
+ * data beyond GPU memory, Section 2).  Its bricks take turns in the server's
+ * brick pool (vr_serve_config.brick_pool_bytes, allocated at the first such
+ * volume and charged to the budget); its block structures are charged too.
+ * Requests on it are submitted like any other; they are admitted in the
+ * same FIFO order, and a worker thread renders them one at a time, pass by
+ * pass through the pool, while in-core requests keep batching.  The image is
+ * bit-identical to vr_render of the volume with 16^3 skip blocks.
+ * Errors: VR_E_INVALID_ARG (no brick pool configured, invalid volume or
+ * edge), VR_E_BUDGET, VR_E_OOM, VR_E_DEVICE. */
+vr_status vr_serve_add_host_volume(vr_server *s, const vr_volume *host_vol, int32_t brick_edge, int32_t *volume_id);
 
 /* Unregister; VR_E_BUSY while requests on it are queued or in flight. */
 vr_status vr_serve_remove_volume(vr_server *s, int32_t volume_id);

@@ -46,6 +46,7 @@ __all__ = [
     "Server",
     "vr_serve_create",
     "vr_serve_add_volume",
+    "vr_serve_add_host_volume",
     "vr_serve_remove_volume",
     "vr_serve_submit",
     "vr_serve_wait",
@@ -472,8 +473,9 @@ def _request_struct(volume_id, cam, tf_table_np, v0, v1, step, ert, use_skip):
     return r
 
 
-def vr_serve_create(hbm_budget_bytes=4 << 30, max_inflight=32, max_batch_tiles=0, device=0):
-    cfg = _abi.vr_serve_config(int(hbm_budget_bytes), int(max_inflight), int(max_batch_tiles), int(device), 0)
+def vr_serve_create(hbm_budget_bytes=4 << 30, max_inflight=32, max_batch_tiles=0, device=0, brick_pool_bytes=0):
+    cfg = _abi.vr_serve_config(int(hbm_budget_bytes), int(max_inflight), int(max_batch_tiles), int(device), 0,
+                               int(brick_pool_bytes))
     out = ctypes.c_void_p()
     check(lib().vr_serve_create(ctypes.byref(cfg), ctypes.byref(out)))
     return out
@@ -482,6 +484,21 @@ def vr_serve_create(hbm_budget_bytes=4 << 30, max_inflight=32, max_batch_tiles=0
 def vr_serve_add_volume(server, volume: Volume, block_edge=16):
     vid = ctypes.c_int32(-1)
     check(lib().vr_serve_add_volume(server, ctypes.byref(volume.c), int(block_edge), ctypes.byref(vid)))
+    return int(vid.value)
+
+
+def vr_serve_add_host_volume(server, host_array, brick_edge=64):
+    """Register a host (NumPy, (nz, ny, nx) uint16/int16/float32) volume as
+    out-of-core bricks that take turns in the server's brick pool."""
+    import numpy as np
+
+    arr = np.ascontiguousarray(host_array)
+    if str(arr.dtype) not in _NP_DTYPES or arr.ndim != 3:
+        raise ValueError("host_array must be a 3-D uint16, int16 or float32 array")
+    nz, ny, nx = arr.shape
+    hv = _abi.vr_volume(arr.ctypes.data, _NP_DTYPES[str(arr.dtype)], 0, nx, ny, nz)
+    vid = ctypes.c_int32(-1)
+    check(lib().vr_serve_add_host_volume(server, ctypes.byref(hv), int(brick_edge), ctypes.byref(vid)))
     return int(vid.value)
 
 
@@ -527,9 +544,13 @@ def vr_serve_destroy(server):
 class Server:
     """Object wrapper of the vr_serve_* calls."""
 
-    def __init__(self, hbm_budget_bytes=4 << 30, max_inflight=32, max_batch_tiles=0, device=0):
-        self.handle = vr_serve_create(hbm_budget_bytes, max_inflight, max_batch_tiles, device)
+    def __init__(self, hbm_budget_bytes=4 << 30, max_inflight=32, max_batch_tiles=0, device=0, brick_pool_bytes=0):
+        self.handle = vr_serve_create(hbm_budget_bytes, max_inflight, max_batch_tiles, device, brick_pool_bytes)
         self._volumes = {}
+
+    def add_host_volume(self, host_array, brick_edge=64):
+        """Out-of-core volume (host bricks through the shared brick pool)."""
+        return vr_serve_add_host_volume(self.handle, host_array, brick_edge)
 
     def add_volume(self, volume: Volume, block_edge=16):
         vid = vr_serve_add_volume(self.handle, volume, block_edge)

@@ -72,7 +72,7 @@ class vr_bricked_stats(ctypes.Structure):
 
 class vr_serve_config(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", c_uint64), ("max_inflight", c_int32), ("max_batch_tiles", c_int32),
-                ("device", c_int32), ("reserved", c_int32)]
+                ("device", c_int32), ("reserved", c_int32), ("brick_pool_bytes", c_uint64)]
 
 
 class vr_request(ctypes.Structure):
@@ -122,6 +122,7 @@ PROTOTYPES = {
     "vr_serve_create": ([POINTER(vr_serve_config), POINTER(c_void_p)], c_int32),
     "vr_serve_add_volume": ([c_void_p, POINTER(vr_volume), c_int32, POINTER(c_int32)], c_int32),
     "vr_serve_remove_volume": ([c_void_p, c_int32], c_int32),
+    "vr_serve_add_host_volume": ([c_void_p, POINTER(vr_volume), c_int32, POINTER(c_int32)], c_int32),
     "vr_serve_submit": ([c_void_p, POINTER(vr_request), POINTER(c_uint64)], c_int32),
     "vr_serve_wait": ([c_void_p, c_uint64, c_int64, POINTER(c_void_p)], c_int32),
     "vr_serve_release": ([c_void_p, c_uint64], c_int32),

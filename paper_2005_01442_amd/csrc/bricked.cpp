@@ -27,7 +27,19 @@
 
 #include "vr_internal.h"
 
+namespace vr {
+// Device memory bricks of several volumes take turns in (a server's shared
+// pool): the volume that renders owns all of it; a volume that renders after
+// another finds none of its bricks resident.
+struct BrickArena {
+  char *mem = nullptr;
+  uint64_t bytes = 0;
+  const vr_bricked *owner = nullptr;
+};
+}  // namespace vr
+
 struct vr_bricked {
+  vr::BrickArena *arena;   // shared pool (nullptr: the pool below is this volume's own)
   int32_t dtype;
   int64_t nx, ny, nz;
   int32_t E, S;
@@ -195,7 +207,11 @@ static void destroy(vr_bricked *v) {
   (void)hipFree(v->fine_minmax_dev);
   (void)hipFree(v->fine_bits_dev);
   (void)hipFree(v->occ_dev);
-  (void)hipFree(v->pool);
+  if (v->arena) {
+    if (v->arena->owner == v) v->arena->owner = nullptr;
+  } else {
+    (void)hipFree(v->pool);
+  }
   (void)hipFree(v->state);
   (void)hipFree(v->next);
   delete v;
@@ -205,9 +221,29 @@ static void destroy(vr_bricked *v) {
 
 using namespace vr;
 
-extern "C" {
+namespace vr {
 
-vr_status vr_bricked_create(const vr_volume *host_vol, int32_t brick_edge, uint64_t pool_bytes, vr_bricked **out) {
+// Device bytes a bricked volume holds besides its pool: block and skip-block
+// ranges, occupancy, page tables, occupancy bits.
+BrickArena *brick_arena_new(char *mem, uint64_t bytes) {
+  BrickArena *a = new (std::nothrow) BrickArena();
+  if (a) {
+    a->mem = mem;
+    a->bytes = bytes;
+  }
+  return a;
+}
+
+void brick_arena_delete(BrickArena *a) { delete a; }
+
+uint64_t bricked_device_bytes(const vr_bricked *v) {
+  const VolConst f = fine_grid(v);
+  return (uint64_t)v->nbricks * (sizeof(float2) + 1 + 2 * sizeof(int32_t)) + (uint64_t)v->nfine * sizeof(float2) +
+         occupancy_bytes(f);
+}
+
+vr_status bricked_create(const vr_volume *host_vol, int32_t brick_edge, uint64_t pool_bytes, BrickArena *arena,
+                         vr_bricked **out) {
   if (!out) return fail(VR_E_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (!host_vol || !host_vol->data) return fail(VR_E_INVALID_ARG, "host volume or its data is NULL");
@@ -220,6 +256,8 @@ vr_status vr_bricked_create(const vr_volume *host_vol, int32_t brick_edge, uint6
     return fail(VR_E_INVALID_ARG, "brick edge %d is not a power of two in [8, 128]", brick_edge);
   vr_bricked *v = new (std::nothrow) vr_bricked();
   if (!v) return fail(VR_E_OOM, "host allocation failed");
+  v->arena = arena;
+  if (arena) pool_bytes = arena->bytes;
   v->dtype = host_vol->dtype;
   v->nx = host_vol->nx;
   v->ny = host_vol->ny;
@@ -287,7 +325,7 @@ vr_status vr_bricked_create(const vr_volume *host_vol, int32_t brick_edge, uint6
       (e = hipMalloc(&v->occ_dev, nb)) != hipSuccess ||
       (e = hipMalloc(&v->page_dev[0], nb * sizeof(int32_t))) != hipSuccess ||
       (e = hipMalloc(&v->page_dev[1], nb * sizeof(int32_t))) != hipSuccess ||
-      (e = hipMalloc(&v->pool, (size_t)(v->nslots * v->slot_bytes))) != hipSuccess) {
+      (!arena && (e = hipMalloc(&v->pool, (size_t)(v->nslots * v->slot_bytes))) != hipSuccess)) {
     destroy(v);
     return fail(VR_E_OOM, "device allocation for the brick pool: %s", hipGetErrorString(e));
   }
@@ -311,6 +349,7 @@ vr_status vr_bricked_create(const vr_volume *host_vol, int32_t brick_edge, uint6
     destroy(v);
     return hip_fail(e, "copy brick min/max");
   }
+  if (arena) v->pool = arena->mem;
   v->slot_brick.assign((size_t)v->nslots, -1);
   v->brick_slot.assign(nb, -1);
   memset(&v->stats, 0, sizeof(v->stats));
@@ -319,6 +358,14 @@ vr_status vr_bricked_create(const vr_volume *host_vol, int32_t brick_edge, uint6
   v->stats.brick_bytes = (uint64_t)v->slot_bytes;
   *out = v;
   return VR_OK;
+}
+
+}  // namespace vr
+
+extern "C" {
+
+vr_status vr_bricked_create(const vr_volume *host_vol, int32_t brick_edge, uint64_t pool_bytes, vr_bricked **out) {
+  return bricked_create(host_vol, brick_edge, pool_bytes, nullptr, out);
 }
 
 vr_status vr_brick_order(const int64_t dims[3], int32_t brick_edge, const vr_camera *cam, int64_t *order_out,
@@ -359,6 +406,20 @@ vr_status vr_bricked_render(vr_bricked *v, const vr_camera *cams, int32_t n_cams
   hipStream_t st = (hipStream_t)stream;
   const int64_t npix = (int64_t)cams[0].width * cams[0].height;
   hipError_t e;
+  if (v->arena && v->arena->owner != v) {
+    // another volume's bricks fill the shared pool: its copies and passes
+    // must be over before ours overwrite the slots (its passes ran on this
+    // stream: the server renders one out-of-core request at a time on one
+    // stream), and none of our bricks are resident
+    const vr_bricked *prev = v->arena->owner;
+    if (prev && ((e = hipStreamSynchronize(prev->copy_stream)) != hipSuccess ||
+                 (e = hipStreamSynchronize(st)) != hipSuccess))
+      return hip_fail(e, "brick pool hand-over");
+    std::fill(v->slot_brick.begin(), v->slot_brick.end(), -1);
+    std::fill(v->brick_slot.begin(), v->brick_slot.end(), -1);
+    v->copied_rec[0] = v->copied_rec[1] = v->rendered_rec[0] = v->rendered_rec[1] = false;
+    v->arena->owner = v;
+  }
   if (npix > v->state_cap) {
     (void)hipFree(v->state);
     (void)hipFree(v->next);

@@ -14,7 +14,11 @@
 //      that arrives while others are on the GPU joins the next launch),
 //   3. keeps two launches in flight on two streams, each launch carrying its
 //      own copy of the request descriptors and TF tables (no cross-stream
-//      dependencies), and retires requests when their last item completes.
+//      dependencies), and retires requests when their last item completes;
+//   4. hands admitted requests on out-of-core volumes (host bricks, the
+//      paper's block decomposition of data beyond GPU memory) to a worker
+//      thread that renders them one at a time through the shared brick pool,
+//      pass by pass on a third stream, while in-core requests keep batching.
 // The per-pixel arithmetic is the whole-image kernel's, so a request's image
 // is the same alone and in any mix.
 #include <algorithm>
@@ -47,6 +51,8 @@ struct Request {
   uint64_t ticket = 0;
   int32_t volume_id = 0;
   CamConst cam{};
+  vr_camera cam_desc{};     // as submitted (the out-of-core path takes it)
+  bool out_of_core = false;
   std::vector<float> tf;  // K*4, host copy
   int32_t K = 0;
   float v0 = 0, v1 = 1;
@@ -74,7 +80,8 @@ struct Volume {
   VolConst vc{};
   bool radius_fits = false;  // the radius plane can be built for its block grid
   vr_blocks *blocks = nullptr;
-  size_t resident_bytes = 0;  // the volume's memory + its blocks (charged)
+  vr_bricked *bricked = nullptr;  // out of core: host bricks (no device volume, no blocks)
+  size_t resident_bytes = 0;  // the volume's memory + its blocks, or its bricked structures (charged)
   int64_t users = 0;  // queued + admitted requests
 };
 
@@ -128,6 +135,17 @@ struct vr_server {
   Batch batches[2];
   int next_batch = 0;
 
+  // out of core: the shared brick pool and the worker that renders requests
+  // on host-brick volumes
+  char *brick_pool = nullptr;
+  BrickArena *arena = nullptr;
+  std::thread ooc_thread;
+  std::condition_variable cv_ooc;
+  std::deque<uint64_t> ooc_queue;    // admitted out-of-core tickets
+  hipStream_t ooc_stream = nullptr;
+  float *ooc_tf = nullptr;           // device TF staging of the worker
+  float *ooc_tf_host = nullptr;      // pinned
+
   // stats
   uint64_t n_submitted = 0, n_admitted = 0, n_completed = 0, n_rejected = 0, n_launches = 0, n_items = 0;
   std::vector<double> latencies_ms;
@@ -180,7 +198,8 @@ bool make_room(vr_server *s, size_t bytes) {
 size_t request_bytes(const vr_server *s, int32_t volume_id, size_t image_bytes, bool skip) {
   auto it = s->volumes.find(volume_id);
   size_t b = image_bytes;
-  if (skip && it != s->volumes.end() && it->second.vc.minmax) b += occupancy_bytes(it->second.vc);
+  if (skip && it != s->volumes.end() && !it->second.bricked && it->second.vc.minmax)
+    b += occupancy_bytes(it->second.vc);
   return b;
 }
 
@@ -238,7 +257,7 @@ void fail_all(vr_server *s, vr_status st) {
 void admit(vr_server *s) {
   while (!s->queue.empty() && (int32_t)s->admitted.size() < s->cfg.max_inflight) {
     Request &r = *s->requests[s->queue.front()];
-    const bool skip = r.mc.skip && s->volumes[r.volume_id].vc.minmax;
+    const bool skip = !r.out_of_core && r.mc.skip && s->volumes[r.volume_id].vc.minmax;
     const size_t need = request_bytes(s, r.volume_id, r.image_bytes, r.mc.skip != 0);
     if (s->resident_bytes + need > s->cfg.hbm_budget_bytes) {
       note_queue(s);
@@ -273,6 +292,80 @@ void admit(vr_server *s) {
     note_queue(s);
     s->admitted.push_back(r.ticket);
     s->n_admitted++;
+    if (r.out_of_core) {
+      s->ooc_queue.push_back(r.ticket);
+      s->cv_ooc.notify_one();
+    }
+  }
+}
+
+// Finish a request the worker rendered; lock held.
+void complete(vr_server *s, Request &r, vr_status st) {
+  const double t = now_s();
+  if (r.state != RState::Admitted) {  // failed or cancelled meanwhile (its slot is already freed)
+    s->cv_done.notify_all();
+    return;
+  }
+  auto at = std::find(s->admitted.begin(), s->admitted.end(), r.ticket);
+  if (at != s->admitted.end()) s->admitted.erase(at);
+  s->volumes[r.volume_id].users--;
+  if (st == VR_OK) {
+    r.state = RState::Done;
+    r.t_done = t;
+    s->latencies_ms.push_back((r.t_done - r.t_submit) * 1e3);
+    s->n_completed++;
+    s->pixels_done += (uint64_t)r.cam.W * r.cam.H;
+  } else {
+    r.state = RState::Failed;
+    r.error = st;
+  }
+  s->cv_done.notify_all();
+  s->cv_work.notify_one();  // a slot is free
+}
+
+// The out-of-core worker: renders admitted requests on host-brick volumes
+// one at a time (they share the brick pool), through vr_bricked_render on
+// its own stream.
+void ooc_worker(vr_server *s) {
+  (void)hipSetDevice(s->cfg.device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    s->cv_ooc.wait(lk, [&] { return s->stop || !s->ooc_queue.empty(); });
+    if (s->ooc_queue.empty()) break;  // stop requested and nothing left
+    const uint64_t t = s->ooc_queue.front();
+    s->ooc_queue.pop_front();
+    auto it = s->requests.find(t);
+    if (it == s->requests.end()) continue;
+    Request &r = *it->second;
+    if (r.state != RState::Admitted) continue;  // cancelled meanwhile
+    if (s->stop) {
+      r.state = RState::Cancelled;
+      s->admitted.erase(std::find(s->admitted.begin(), s->admitted.end(), r.ticket));
+      s->volumes[r.volume_id].users--;
+      s->cv_done.notify_all();
+      continue;
+    }
+    vr_bricked *bv = s->volumes[r.volume_id].bricked;
+    const size_t tf_bytes = (size_t)r.K * 16;
+    memcpy(s->ooc_tf_host, r.tf.data(), tf_bytes);
+    const vr_camera cam = r.cam_desc;
+    vr_params p{};
+    p.step = r.mc.step;
+    p.ert_threshold = r.mc.ert;
+    p.use_skip = 1;
+    p.filter = VR_FILTER_BSPLINE;
+    p.counters = nullptr;
+    vr_tf tf{s->ooc_tf, r.K, r.v0, r.v1};
+    float *image = r.image;
+    lk.unlock();  // the volume stays registered: this request counts as its user
+    vr_status st = VR_OK;
+    hipError_t e = hipMemcpyAsync(s->ooc_tf, s->ooc_tf_host, tf_bytes, hipMemcpyHostToDevice, s->ooc_stream);
+    if (e != hipSuccess) st = hip_fail(e, "out-of-core TF upload");
+    if (st == VR_OK) st = vr_bricked_render(bv, &cam, 1, &tf, &p, image, s->ooc_stream);
+    if (st == VR_OK && (e = hipStreamSynchronize(s->ooc_stream)) != hipSuccess)
+      st = hip_fail(e, "out-of-core render");
+    lk.lock();
+    complete(s, r, st);
   }
 }
 
@@ -310,7 +403,7 @@ bool issue(vr_server *s, Batch &b) {
   std::vector<uint64_t> live;
   for (uint64_t t : s->admitted) {
     Request &r = *s->requests[t];
-    if (r.items_issued < r.items_total) live.push_back(t);
+    if (!r.out_of_core && r.items_issued < r.items_total) live.push_back(t);
   }
   if (live.empty()) return false;
   const int32_t cap_items = s->cfg.max_batch_tiles;
@@ -514,9 +607,15 @@ vr_status vr_serve_create(const vr_serve_config *cfg, vr_server **out) {
     *b.samples_host = 0;
     if ((e = hipMalloc((void **)&b.dev, cap)) != hipSuccess) return fail(VR_E_OOM, "device staging: %s", hipGetErrorString(e));
   }
+  if ((e = hipStreamCreateWithFlags(&s->ooc_stream, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+  if ((e = hipMalloc((void **)&s->ooc_tf, (size_t)VR_MAX_TF_NODES * 16)) != hipSuccess)
+    return fail(VR_E_OOM, "TF staging: %s", hipGetErrorString(e));
+  if ((e = hipHostMalloc((void **)&s->ooc_tf_host, (size_t)VR_MAX_TF_NODES * 16, hipHostMallocDefault)) != hipSuccess)
+    return hip_fail(e, "pinned TF staging");
   s->q_since = s->q_last = now_s();
   vr_server *raw = s.release();
   raw->thread = std::thread(scheduler, raw);
+  raw->ooc_thread = std::thread(ooc_worker, raw);
   *out = raw;
   return VR_OK;
 }
@@ -564,12 +663,65 @@ vr_status vr_serve_add_volume(vr_server *s, const vr_volume *vol, int32_t block_
   return VR_OK;
 }
 
+vr_status vr_serve_add_host_volume(vr_server *s, const vr_volume *host_vol, int32_t brick_edge, int32_t *volume_id) {
+  if (!s || !volume_id) return fail(VR_E_INVALID_ARG, "server or volume_id is NULL");
+  if (s->cfg.brick_pool_bytes == 0) return fail(VR_E_INVALID_ARG, "the server was created without a brick pool");
+  (void)hipSetDevice(s->cfg.device);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return fail(VR_E_SHUTDOWN, "server is shutting down");
+    if (!s->arena) {
+      if (!make_room(s, s->cfg.brick_pool_bytes))
+        return fail(VR_E_BUDGET, "the brick pool (%llu bytes) does not fit the HBM budget",
+                    (unsigned long long)s->cfg.brick_pool_bytes);
+      char *mem = nullptr;
+      hipError_t e = hipMalloc((void **)&mem, (size_t)s->cfg.brick_pool_bytes);
+      if (e != hipSuccess) return fail(VR_E_OOM, "brick pool: %s", hipGetErrorString(e));
+      BrickArena *a = brick_arena_new(mem, s->cfg.brick_pool_bytes);
+      if (!a) {
+        (void)hipFree(mem);
+        return fail(VR_E_OOM, "host allocation failed");
+      }
+      s->brick_pool = mem;
+      s->arena = a;
+      charge(s, s->cfg.brick_pool_bytes);
+      s->resident_bytes += s->cfg.brick_pool_bytes;
+    }
+  }
+  // pinned host bricks and their device structures (the pool is the arena's;
+  // the worker's renders take turns in it)
+  vr_bricked *bv = nullptr;
+  vr_status st = bricked_create(host_vol, brick_edge, 0, s->arena, &bv);
+  if (st) return st;
+  std::lock_guard<std::mutex> lk(s->mu);
+  const size_t db = (size_t)bricked_device_bytes(bv);
+  if (!make_room(s, db)) {
+    vr_bricked_free(bv);
+    return fail(VR_E_BUDGET, "the out-of-core volume's block structures (%zu bytes) do not fit the HBM budget", db);
+  }
+  charge(s, db);
+  s->resident_bytes += db;
+  int32_t id = s->next_volume++;
+  Volume &v = s->volumes[id];
+  v.desc = *host_vol;
+  v.desc.data = nullptr;  // host memory, read at registration only
+  memset(&v.vc, 0, sizeof(v.vc));
+  v.vc.nx = (int32_t)host_vol->nx;
+  v.vc.ny = (int32_t)host_vol->ny;
+  v.vc.nz = (int32_t)host_vol->nz;
+  v.bricked = bv;
+  v.resident_bytes = db;
+  *volume_id = id;
+  return VR_OK;
+}
+
 vr_status vr_serve_remove_volume(vr_server *s, int32_t volume_id) {
   if (!s) return fail(VR_E_INVALID_ARG, "server is NULL");
   std::lock_guard<std::mutex> lk(s->mu);
   auto it = s->volumes.find(volume_id);
   if (it == s->volumes.end()) return fail(VR_E_NOT_FOUND, "unknown volume %d", volume_id);
   if (it->second.users > 0) return fail(VR_E_BUSY, "volume %d has %lld requests queued or in flight", volume_id, (long long)it->second.users);
+  if (it->second.bricked) vr_bricked_free(it->second.bricked);
   vr_blocks_free(it->second.blocks);
   s->hbm_used -= it->second.resident_bytes;
   s->resident_bytes -= it->second.resident_bytes;
@@ -582,6 +734,7 @@ vr_status vr_serve_submit(vr_server *s, const vr_request *req, uint64_t *ticket)
   std::unique_ptr<Request> r(new Request());
   vr_status st = check_camera(&req->cam, &r->cam);
   if (st) return st;
+  r->cam_desc = req->cam;
   if (!req->tf_table_host) return fail(VR_E_INVALID_ARG, "tf_table_host is NULL");
   if (req->K < 2 || req->K > VR_MAX_TF_NODES) return fail(VR_E_INVALID_ARG, "TF node count K=%d outside [2, %d]", req->K, VR_MAX_TF_NODES);
   if (!std::isfinite(req->tf_v0) || !std::isfinite(req->tf_v1) || !(req->tf_v1 > req->tf_v0))
@@ -658,6 +811,8 @@ vr_status vr_serve_submit(vr_server *s, const vr_request *req, uint64_t *ticket)
                 need, (unsigned long long)s->resident_bytes, (unsigned long long)s->cfg.hbm_budget_bytes);
   }
   Volume &v = vit->second;
+  r->out_of_core = v.bricked != nullptr;
+  if (r->out_of_core) r->items_total = 0;  // rendered by the out-of-core worker
   r->ticket = s->next_ticket++;
   r->t_submit = now_s();
   v.users++;
@@ -781,6 +936,11 @@ vr_status vr_serve_destroy(vr_server *s) {
     s->cv_work.notify_all();
   }
   if (s->thread.joinable()) s->thread.join();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->cv_ooc.notify_all();
+  }
+  if (s->ooc_thread.joinable()) s->ooc_thread.join();
   (void)hipSetDevice(s->cfg.device);
   for (Batch &b : s->batches) {
     if (b.stream) (void)hipStreamSynchronize(b.stream);
@@ -816,7 +976,15 @@ vr_status vr_serve_destroy(vr_server *s) {
   for (auto &kv : s->image_pool) (void)hipFree(kv.second);
   for (auto &kv : s->occ_pool) (void)hipFree(kv.second);
   for (uint32_t *p : s->occ_retired) (void)hipFree(p);
-  for (auto &kv : s->volumes) vr_blocks_free(kv.second.blocks);
+  for (auto &kv : s->volumes) {
+    vr_blocks_free(kv.second.blocks);
+    if (kv.second.bricked) vr_bricked_free(kv.second.bricked);
+  }
+  if (s->ooc_stream) (void)hipStreamDestroy(s->ooc_stream);
+  if (s->ooc_tf) (void)hipFree(s->ooc_tf);
+  if (s->ooc_tf_host) (void)hipHostFree(s->ooc_tf_host);
+  if (s->brick_pool) (void)hipFree(s->brick_pool);
+  brick_arena_delete(s->arena);
   delete s;
   return VR_OK;
 }

@@ -147,6 +147,16 @@ vr_status prepare_render(const vr_volume *vol, const vr_blocks *blocks, const vr
 vr_status render_views(RenderArgs &a, const vr_camera *cams, int32_t n_cams, float *out_rgba, void *stream,
                        const float4 *preint, const RenderScratch *scratch);
 
+// Out-of-core volumes whose bricks share one device pool (bricked.cpp): the
+// pool is the arena's; a volume that renders after another finds none of its
+// bricks resident.  Renders of volumes sharing an arena must not overlap.
+struct BrickArena;
+vr_status bricked_create(const vr_volume *host_vol, int32_t brick_edge, uint64_t pool_bytes, BrickArena *arena,
+                         vr_bricked **out);
+uint64_t bricked_device_bytes(const vr_bricked *v);
+BrickArena *brick_arena_new(char *mem, uint64_t bytes);
+void brick_arena_delete(BrickArena *a);
+
 // Device address of the current device's TF status word (device_state.hip),
 // nullptr when it cannot be obtained.
 uint32_t *tf_status_word();

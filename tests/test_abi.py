@@ -55,7 +55,7 @@ def test_struct_layout_matches_the_header(abi, tmp_path):
         "vr_tf": ["table", "K", "v0", "v1"],
         "vr_params": ["step", "ert_threshold", "use_skip", "counters"],
         "vr_shading": ["ambient", "shininess", "light", "headlight", "grad_min"],
-        "vr_serve_config": ["hbm_budget_bytes", "max_inflight", "max_batch_tiles", "device"],
+        "vr_serve_config": ["hbm_budget_bytes", "max_inflight", "max_batch_tiles", "device", "brick_pool_bytes"],
         "vr_request": ["volume_id", "K", "tf_table_host", "tf_v1", "cam", "step", "use_skip"],
         "vr_serve_stats": ["submitted", "tiles", "p50_ms", "p99_ms", "busy_s", "samples", "samples_per_s",
                            "queued_max", "queued_mean", "resident_bytes"],

@@ -235,3 +235,53 @@ def test_c4_mix_matches_alone_renders_and_the_oracle():
         f"samples {st['samples']}")
     assert st["completed"] == len(reqs) and st["launches"] >= 2 and st["samples"] > 0
     srv.close()
+
+
+def test_out_of_core_volumes_served_in_the_mix():
+    """Volumes larger than the HBM budget served through the shared brick
+    pool: a 256x256x512 int16 host volume (64 MiB) and a 200x180x300 one
+    (21 MiB) with a 96 MiB budget and a 24 MiB brick pool (64^3 bricks), next
+    to a resident in-core volume; requests on all three submitted at once.
+    Every out-of-core image equals vr_render of the same volume in core with
+    16^3 skip blocks (bit-identical) and the FP64 oracle on sampled pixels;
+    the in-core ones equal their alone renders; the pool is charged once."""
+    big = synth.ct_phantom_i16(256, 256, 512, seed=66, n_soft=8, n_bone=5)
+    mid = synth.ct_phantom_i16(200, 180, 300, seed=67, n_soft=6, n_bone=4)
+    inc = synth.ct_phantom_i16(96, 96, 80, seed=68, n_soft=5, n_bone=4)
+    tf = synth.tf1()
+    srv = vr.Server(hbm_budget_bytes=96 << 20, max_inflight=8, brick_pool_bytes=24 << 20)
+    dinc = upload_volume(inc)
+    vid_inc = srv.add_volume(dinc)
+    vid_big = srv.add_host_volume(big, 64)
+    vid_mid = srv.add_host_volume(mid, 64)
+    st = srv.stats()
+    assert st["hbm_used"] <= 96 << 20 and st["resident_bytes"] >= 24 << 20
+    rng = np.random.default_rng(69)
+    reqs = []
+    for i in range(12):
+        vid, host = [(vid_big, big), (vid_mid, mid), (vid_inc, inc)][i % 3]
+        dims = host.shape[::-1]
+        W = [48, 96, 130][i % 3]
+        cam = synth.orbit_camera(dims, rng.standard_normal(3), 60.0, W, W - 8)
+        t = srv.submit(vid, cam, tf.table, tf.v0, tf.v1, 0.5, 0.99 if i % 2 else 0.0, True)
+        reqs.append((t, host, cam, 0.99 if i % 2 else 0.0))
+    t_dev = upload_tf(tf)
+    for q, (t, host, cam, ert) in enumerate(reqs):
+        got = srv.result(t, cam.height, cam.width).cpu().numpy()
+        dv = upload_volume(host)
+        alone = vr.vr_render(dv, vr.vr_build_blocks(dv, 16), [cam], t_dev, 0.5, ert, True)[0].cpu().numpy()
+        assert np.array_equal(got, alone), (q, host.shape)
+        del dv
+        pix = synth.sample_pixels(1, cam.width, cam.height, 150, seed=300 + q)
+        ref = oracle.render(host, [cam], tf, 0.5, ert=ert, pixels=pix)
+        compare_with_flags(got[pix[:, 1], pix[:, 2]].astype(np.float64), ref["rgba"], ref["flags"],
+                           ert if ert else 1.0)
+    st = srv.stats()
+    log(f"out-of-core serving: {st['completed']} completed, hbm peak {st['hbm_peak'] / 2**20:.1f} MiB")
+    assert st["completed"] == 12 and st["hbm_peak"] <= 96 << 20
+    srv.remove_volume(vid_big)
+    srv.close()
+    plain = vr.Server(hbm_budget_bytes=64 << 20)
+    with pytest.raises(vr.VrError, match="brick pool"):
+        plain.add_host_volume(mid, 64)
+    plain.close()
