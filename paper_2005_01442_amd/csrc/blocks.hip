@@ -30,7 +30,9 @@ constexpr int kMinmaxThreads = 512;  // eight wavefronts: more rows in flight pe
 template <typename T>
 __device__ inline void half_block_range(const T *row, int xa, int half, int nx, bool hi, float &mn, float &mx) {
   // the footprint's apron: one voxel before the block, two after it
-  const float a0 = (float)row[hi ? min(xa + half, nx - 1) : max(xa - 1, 0)];
+  // (lanes whose block lies past the grid in the last pass clamp too: every
+  // index stays inside the row)
+  const float a0 = (float)row[hi ? min(xa + half, nx - 1) : min(max(xa - 1, 0), nx - 1)];
   const float a1 = (float)row[hi ? min(xa + half + 1, nx - 1) : min(xa, nx - 1)];
   mn = fminf(mn, fminf(a0, a1));
   mx = fmaxf(mx, fmaxf(a0, a1));
@@ -84,7 +86,7 @@ __device__ inline void half_block_range_wide(const T *row, int xa, int nx, int l
       ap1 = right1;
     }
   } else {
-    ap0 = lane == 0 ? (first_pass ? a[0] : (float)row[max(xa - 1, 0)]) : left;
+    ap0 = lane == 0 ? (first_pass ? a[0] : (float)row[min(max(xa - 1, 0), nx - 1)]) : left;
     ap1 = ap0;
   }
   mn = fminf(mn, fminf(ap0, ap1));
