@@ -107,6 +107,7 @@ size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
 struct vr_server {
   vr_serve_config cfg{};
+  const ServeOps *ops = nullptr;  // device operations (HIP, or a CPU stand-in)
   std::mutex mu;
   std::condition_variable cv_work;   // scheduler wake-up
   std::condition_variable cv_done;   // waiters
@@ -180,12 +181,12 @@ bool make_room(vr_server *s, size_t bytes) {
                      (s->occ_pool.empty() || std::prev(s->image_pool.end())->first >= std::prev(s->occ_pool.end())->first);
     if (img) {
       auto big = std::prev(s->image_pool.end());
-      (void)hipFree(big->second);
+      (void)s->ops->dev_free(big->second);
       s->hbm_used -= big->first;
       s->image_pool.erase(big);
     } else {
       auto big = std::prev(s->occ_pool.end());
-      (void)hipFree(big->second);
+      (void)s->ops->dev_free(big->second);
       s->hbm_used -= big->first;
       s->occ_pool.erase(big);
     }
@@ -216,10 +217,7 @@ T *acquire(vr_server *s, std::multimap<size_t, T *> &pool, size_t bytes) {
   }
   if (!make_room(s, bytes)) return nullptr;
   T *p = nullptr;
-  if (hipMalloc(reinterpret_cast<void **>(&p), bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    return nullptr;
-  }
+  if (s->ops->dev_alloc(reinterpret_cast<void **>(&p), bytes) != hipSuccess) return nullptr;
   charge(s, bytes);
   return p;
 }
@@ -327,7 +325,7 @@ void complete(vr_server *s, Request &r, vr_status st) {
 // one at a time (they share the brick pool), through vr_bricked_render on
 // its own stream.
 void ooc_worker(vr_server *s) {
-  (void)hipSetDevice(s->cfg.device);
+  (void)s->ops->set_device(s->cfg.device);
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
     s->cv_ooc.wait(lk, [&] { return s->stop || !s->ooc_queue.empty(); });
@@ -359,10 +357,10 @@ void ooc_worker(vr_server *s) {
     float *image = r.image;
     lk.unlock();  // the volume stays registered: this request counts as its user
     vr_status st = VR_OK;
-    hipError_t e = hipMemcpyAsync(s->ooc_tf, s->ooc_tf_host, tf_bytes, hipMemcpyHostToDevice, s->ooc_stream);
+    hipError_t e = s->ops->copy_async(s->ooc_tf, s->ooc_tf_host, tf_bytes, hipMemcpyHostToDevice, s->ooc_stream);
     if (e != hipSuccess) st = hip_fail(e, "out-of-core TF upload");
     if (st == VR_OK) st = vr_bricked_render(bv, &cam, 1, &tf, &p, image, s->ooc_stream);
-    if (st == VR_OK && (e = hipStreamSynchronize(s->ooc_stream)) != hipSuccess)
+    if (st == VR_OK && (e = s->ops->stream_sync(s->ooc_stream)) != hipSuccess)
       st = hip_fail(e, "out-of-core render");
     lk.lock();
     complete(s, r, st);
@@ -504,7 +502,7 @@ bool issue(vr_server *s, Batch &b) {
                    [](const std::pair<float, ServeItem> &a, const std::pair<float, ServeItem> &c) { return a.first < c.first; });
   for (size_t q = 0; q < keyed.size(); ++q) items[q] = keyed[q].second;
   *reinterpret_cast<unsigned long long *>(b.host + off_count) = 0;  // the launch's sample counter
-  hipError_t e = hipMemcpyAsync(b.dev, b.host, total, hipMemcpyHostToDevice, b.stream);
+  hipError_t e = s->ops->copy_async(b.dev, b.host, total, hipMemcpyHostToDevice, b.stream);
   for (auto &rn : occ_new) {  // from the TF tables just copied
     if (e != hipSuccess) break;
     Request &r = *rn.first;
@@ -515,18 +513,18 @@ bool issue(vr_server *s, Batch &b) {
     tc.v0 = r.v0;
     tc.scale = (float)(r.K - 1) / (r.v1 - r.v0);
     tc.status = nullptr;
-    e = r.occ_radius > 0 ? launch_occupancy_planes(v.vc, tc, r.occ, b.stream)
-                         : launch_occupancy_bits(v.vc, tc, r.occ, b.stream);
+    e = s->ops->occupancy(v.vc, tc, r.occ, r.occ_radius > 0, b.stream);
   }
-  if (e == hipSuccess) e = hipEventRecord(b.occ_done, b.stream);
-  if (e == hipSuccess && wait_other) e = hipStreamWaitEvent(b.stream, other.occ_done, 0);
+  if (e == hipSuccess) e = s->ops->event_record(b.occ_done, b.stream);
+  if (e == hipSuccess && wait_other) e = s->ops->stream_wait(b.stream, other.occ_done);
   if (e == hipSuccess)
-    e = launch_serve_batch(reinterpret_cast<const ServeSlot *>(b.dev + off_slots),
+    e = s->ops->launch_batch(reinterpret_cast<const ServeSlot *>(b.dev + off_slots),
                            reinterpret_cast<const ServeItem *>(b.dev + off_items), (int32_t)item, max_k,
                            reinterpret_cast<unsigned long long *>(b.dev + off_count), b.stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(b.samples_host, b.dev + off_count, sizeof(unsigned long long), hipMemcpyDeviceToHost, b.stream);
-  if (e == hipSuccess) e = hipEventRecord(b.done, b.stream);
+    e = s->ops->copy_async(b.samples_host, b.dev + off_count, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           b.stream);
+  if (e == hipSuccess) e = s->ops->event_record(b.done, b.stream);
   if (e != hipSuccess) {
     fail(VR_E_DEVICE, "serve launch: %s", hipGetErrorString(e));
     fail_all(s, VR_E_DEVICE);
@@ -539,7 +537,7 @@ bool issue(vr_server *s, Batch &b) {
 }
 
 void scheduler(vr_server *s) {
-  (void)hipSetDevice(s->cfg.device);
+  (void)s->ops->set_device(s->cfg.device);
   std::unique_lock<std::mutex> lk(s->mu);
   while (!s->stop) {
     admit(s);
@@ -551,7 +549,7 @@ void scheduler(vr_server *s) {
     bool retired = false;
     for (Batch &b : s->batches) {
       if (!b.busy) continue;
-      hipError_t e = hipEventQuery(b.done);
+      hipError_t e = s->ops->event_query(b.done);
       if (e == hipSuccess) {
         retire(s, b);
         retired = true;
@@ -576,48 +574,144 @@ void scheduler(vr_server *s) {
   }
 }
 
+// Device memory, streams, events and pinned buffers the server holds (also
+// after a failed create); lock not needed (no thread runs).
+void free_server_resources(vr_server *s) {
+  const ServeOps *o = s->ops;
+  for (Batch &b : s->batches) {
+    if (b.done) (void)o->event_destroy(b.done);
+    if (b.occ_done) (void)o->event_destroy(b.occ_done);
+    if (b.stream) (void)o->stream_destroy(b.stream);
+    if (b.host) (void)o->host_free(b.host);
+    if (b.samples_host) (void)o->host_free(b.samples_host);
+    if (b.dev) (void)o->dev_free(b.dev);
+  }
+  for (auto &kv : s->requests) {
+    if (kv.second->image) (void)o->dev_free(kv.second->image);
+    if (kv.second->occ) (void)o->dev_free(kv.second->occ);
+  }
+  for (auto &kv : s->image_pool) (void)o->dev_free(kv.second);
+  for (auto &kv : s->occ_pool) (void)o->dev_free(kv.second);
+  for (uint32_t *p : s->occ_retired) (void)o->dev_free(p);
+  for (auto &kv : s->volumes) {
+    if (kv.second.blocks) o->free_blocks(kv.second.blocks);
+    if (kv.second.bricked) vr_bricked_free(kv.second.bricked);
+  }
+  if (s->ooc_stream) (void)o->stream_destroy(s->ooc_stream);
+  if (s->ooc_tf) (void)o->dev_free(s->ooc_tf);
+  if (s->ooc_tf_host) (void)o->host_free(s->ooc_tf_host);
+  if (s->brick_pool) (void)o->dev_free(s->brick_pool);
+  brick_arena_delete(s->arena);
+}
+
+hipError_t hip_device_count(int *n) { return hipGetDeviceCount(n); }
+hipError_t hip_set_device(int d) { return hipSetDevice(d); }
+hipError_t hip_stream_create(hipStream_t *st) { return hipStreamCreateWithFlags(st, hipStreamNonBlocking); }
+hipError_t hip_stream_destroy(hipStream_t st) { return hipStreamDestroy(st); }
+hipError_t hip_stream_sync(hipStream_t st) { return hipStreamSynchronize(st); }
+hipError_t hip_event_create(hipEvent_t *e) { return hipEventCreateWithFlags(e, hipEventDisableTiming); }
+hipError_t hip_event_destroy(hipEvent_t e) { return hipEventDestroy(e); }
+hipError_t hip_event_record(hipEvent_t e, hipStream_t st) { return hipEventRecord(e, st); }
+hipError_t hip_event_query(hipEvent_t e) { return hipEventQuery(e); }
+hipError_t hip_stream_wait(hipStream_t st, hipEvent_t e) { return hipStreamWaitEvent(st, e, 0); }
+hipError_t hip_dev_alloc(void **p, size_t n) {
+  const hipError_t e = hipMalloc(p, n);
+  if (e != hipSuccess) (void)hipGetLastError();
+  return e;
+}
+hipError_t hip_dev_free(void *p) { return hipFree(p); }
+hipError_t hip_host_alloc(void **p, size_t n) { return hipHostMalloc(p, n, hipHostMallocDefault); }
+hipError_t hip_host_free(void *p) { return hipHostFree(p); }
+hipError_t hip_copy_async(void *dst, const void *src, size_t n, hipMemcpyKind k, hipStream_t st) {
+  return hipMemcpyAsync(dst, src, n, k, st);
+}
+hipError_t hip_occupancy(const VolConst &v, const TfConst &tf, uint32_t *bits, bool radius, hipStream_t st) {
+  return radius ? launch_occupancy_planes(v, tf, bits, st) : launch_occupancy_bits(v, tf, bits, st);
+}
+vr_status hip_build_blocks(const vr_volume *vol, int32_t edge, vr_blocks **out, VolConst *vc) {
+  vr_blocks *blocks = nullptr;
+  vr_status st = check_volume(vol, vc);
+  if (st) return st;
+  if ((st = vr_build_blocks(vol, edge, nullptr, &blocks))) return st;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    vr_blocks_free(blocks);
+    return hip_fail(e, "block build");
+  }
+  if ((st = attach_blocks(blocks, vol, vc))) {
+    vr_blocks_free(blocks);
+    return st;
+  }
+  *out = blocks;
+  return VR_OK;
+}
+
+const ServeOps kHipOps = {hip_device_count, hip_set_device,  hip_stream_create, hip_stream_destroy, hip_stream_sync,
+                          hip_event_create, hip_event_destroy, hip_event_record, hip_event_query,    hip_stream_wait,
+                          hip_dev_alloc,    hip_dev_free,    hip_host_alloc,    hip_host_free,      hip_copy_async,
+                          hip_occupancy,    launch_serve_batch, hip_build_blocks, vr_blocks_free};
+
 }  // namespace
 
-extern "C" {
+namespace vr {
 
-vr_status vr_serve_create(const vr_serve_config *cfg, vr_server **out) {
-  if (!cfg || !out) return fail(VR_E_INVALID_ARG, "config or out is NULL");
+const ServeOps *serve_hip_ops() { return &kHipOps; }
+
+vr_status serve_create_with_ops(const vr_serve_config *cfg, const ServeOps *ops, vr_server **out) {
+  if (!cfg || !out || !ops) return fail(VR_E_INVALID_ARG, "config or out is NULL");
   *out = nullptr;
   if (cfg->max_inflight < 1 || cfg->max_inflight > 1024) return fail(VR_E_INVALID_ARG, "max_inflight outside [1, 1024]");
   if (cfg->max_batch_tiles < 0 || cfg->max_batch_tiles > (1 << 20)) return fail(VR_E_INVALID_ARG, "max_batch_tiles outside [0, 2^20]");
   if (cfg->hbm_budget_bytes == 0) return fail(VR_E_INVALID_ARG, "hbm_budget_bytes is zero");
   int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev)
+  if (ops->device_count(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev)
     return fail(VR_E_INVALID_ARG, "device %d not available", cfg->device);
   std::unique_ptr<vr_server> s(new (std::nothrow) vr_server());
   if (!s) return fail(VR_E_OOM, "host allocation failed");
   s->cfg = *cfg;
+  s->ops = ops;
   if (s->cfg.max_batch_tiles == 0) s->cfg.max_batch_tiles = 2048;
-  hipError_t e = hipSetDevice(cfg->device);
-  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipError_t e = ops->set_device(cfg->device);
+  vr_status st = VR_OK;
+  if (e != hipSuccess) st = hip_fail(e, "set device");
   const size_t cap = batch_capacity(s->cfg);
   for (Batch &b : s->batches) {
+    if (st) break;
     b.cap = cap;
-    if ((e = hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
-    if ((e = hipEventCreateWithFlags(&b.done, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
-    if ((e = hipEventCreateWithFlags(&b.occ_done, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "event");
-    if ((e = hipHostMalloc((void **)&b.host, cap, hipHostMallocDefault)) != hipSuccess) return hip_fail(e, "pinned staging");
-    if ((e = hipHostMalloc((void **)&b.samples_host, sizeof(unsigned long long), hipHostMallocDefault)) != hipSuccess)
-      return hip_fail(e, "pinned counter");
-    *b.samples_host = 0;
-    if ((e = hipMalloc((void **)&b.dev, cap)) != hipSuccess) return fail(VR_E_OOM, "device staging: %s", hipGetErrorString(e));
+    if ((e = ops->stream_create(&b.stream)) != hipSuccess || (e = ops->event_create(&b.done)) != hipSuccess ||
+        (e = ops->event_create(&b.occ_done)) != hipSuccess)
+      st = hip_fail(e, "stream or event");
+    else if ((e = ops->host_alloc((void **)&b.host, cap)) != hipSuccess ||
+             (e = ops->host_alloc((void **)&b.samples_host, sizeof(unsigned long long))) != hipSuccess)
+      st = hip_fail(e, "pinned staging");
+    else if ((e = ops->dev_alloc((void **)&b.dev, cap)) != hipSuccess)
+      st = fail(VR_E_OOM, "device staging: %s", hipGetErrorString(e));
+    else
+      *b.samples_host = 0;
   }
-  if ((e = hipStreamCreateWithFlags(&s->ooc_stream, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
-  if ((e = hipMalloc((void **)&s->ooc_tf, (size_t)VR_MAX_TF_NODES * 16)) != hipSuccess)
-    return fail(VR_E_OOM, "TF staging: %s", hipGetErrorString(e));
-  if ((e = hipHostMalloc((void **)&s->ooc_tf_host, (size_t)VR_MAX_TF_NODES * 16, hipHostMallocDefault)) != hipSuccess)
-    return hip_fail(e, "pinned TF staging");
+  if (!st && (e = ops->stream_create(&s->ooc_stream)) != hipSuccess) st = hip_fail(e, "stream");
+  if (!st && (e = ops->dev_alloc((void **)&s->ooc_tf, (size_t)VR_MAX_TF_NODES * 16)) != hipSuccess)
+    st = fail(VR_E_OOM, "TF staging: %s", hipGetErrorString(e));
+  if (!st && (e = ops->host_alloc((void **)&s->ooc_tf_host, (size_t)VR_MAX_TF_NODES * 16)) != hipSuccess)
+    st = hip_fail(e, "pinned TF staging");
+  if (st) {
+    free_server_resources(s.get());
+    return st;
+  }
   s->q_since = s->q_last = now_s();
   vr_server *raw = s.release();
   raw->thread = std::thread(scheduler, raw);
   raw->ooc_thread = std::thread(ooc_worker, raw);
   *out = raw;
   return VR_OK;
+}
+
+}  // namespace vr
+
+extern "C" {
+
+vr_status vr_serve_create(const vr_serve_config *cfg, vr_server **out) {
+  return serve_create_with_ops(cfg, serve_hip_ops(), out);
 }
 
 vr_status vr_serve_add_volume(vr_server *s, const vr_volume *vol, int32_t block_edge, int32_t *volume_id) {
@@ -630,23 +724,14 @@ vr_status vr_serve_add_volume(vr_server *s, const vr_volume *vol, int32_t block_
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return fail(VR_E_SHUTDOWN, "server is shutting down");
   }
-  (void)hipSetDevice(s->cfg.device);
-  if ((st = vr_build_blocks(vol, block_edge, nullptr, &blocks))) return st;
-  hipError_t e = hipDeviceSynchronize();
-  if (e != hipSuccess) {
-    vr_blocks_free(blocks);
-    return hip_fail(e, "block build");
-  }
-  if ((st = attach_blocks(blocks, vol, &vc))) {
-    vr_blocks_free(blocks);
-    return st;
-  }
+  (void)s->ops->set_device(s->cfg.device);
+  if ((st = s->ops->build_blocks(vol, block_edge, &blocks, &vc))) return st;
   std::lock_guard<std::mutex> lk(s->mu);
   // the volume's own memory (caller-owned, resident) and its blocks (plain and widened ranges)
   const size_t vb = (size_t)vc.bytes;
   const size_t bb = 2 * (size_t)vc.nbx * vc.nby * vc.nbz * sizeof(float2);
   if (!make_room(s, vb + bb)) {
-    vr_blocks_free(blocks);
+    s->ops->free_blocks(blocks);
     return fail(VR_E_BUDGET, "volume (%zu bytes) and blocks (%zu bytes) do not fit the HBM budget (%llu of %llu bytes held)",
                 vb, bb, (unsigned long long)s->hbm_used, (unsigned long long)s->cfg.hbm_budget_bytes);
   }
@@ -666,7 +751,7 @@ vr_status vr_serve_add_volume(vr_server *s, const vr_volume *vol, int32_t block_
 vr_status vr_serve_add_host_volume(vr_server *s, const vr_volume *host_vol, int32_t brick_edge, int32_t *volume_id) {
   if (!s || !volume_id) return fail(VR_E_INVALID_ARG, "server or volume_id is NULL");
   if (s->cfg.brick_pool_bytes == 0) return fail(VR_E_INVALID_ARG, "the server was created without a brick pool");
-  (void)hipSetDevice(s->cfg.device);
+  (void)s->ops->set_device(s->cfg.device);
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return fail(VR_E_SHUTDOWN, "server is shutting down");
@@ -675,11 +760,11 @@ vr_status vr_serve_add_host_volume(vr_server *s, const vr_volume *host_vol, int3
         return fail(VR_E_BUDGET, "the brick pool (%llu bytes) does not fit the HBM budget",
                     (unsigned long long)s->cfg.brick_pool_bytes);
       char *mem = nullptr;
-      hipError_t e = hipMalloc((void **)&mem, (size_t)s->cfg.brick_pool_bytes);
+      hipError_t e = s->ops->dev_alloc((void **)&mem, (size_t)s->cfg.brick_pool_bytes);
       if (e != hipSuccess) return fail(VR_E_OOM, "brick pool: %s", hipGetErrorString(e));
       BrickArena *a = brick_arena_new(mem, s->cfg.brick_pool_bytes);
       if (!a) {
-        (void)hipFree(mem);
+        (void)s->ops->dev_free(mem);
         return fail(VR_E_OOM, "host allocation failed");
       }
       s->brick_pool = mem;
@@ -722,7 +807,7 @@ vr_status vr_serve_remove_volume(vr_server *s, int32_t volume_id) {
   if (it == s->volumes.end()) return fail(VR_E_NOT_FOUND, "unknown volume %d", volume_id);
   if (it->second.users > 0) return fail(VR_E_BUSY, "volume %d has %lld requests queued or in flight", volume_id, (long long)it->second.users);
   if (it->second.bricked) vr_bricked_free(it->second.bricked);
-  vr_blocks_free(it->second.blocks);
+  if (it->second.blocks) s->ops->free_blocks(it->second.blocks);
   s->hbm_used -= it->second.resident_bytes;
   s->resident_bytes -= it->second.resident_bytes;
   s->volumes.erase(it);
@@ -941,9 +1026,9 @@ vr_status vr_serve_destroy(vr_server *s) {
     s->cv_ooc.notify_all();
   }
   if (s->ooc_thread.joinable()) s->ooc_thread.join();
-  (void)hipSetDevice(s->cfg.device);
+  (void)s->ops->set_device(s->cfg.device);
   for (Batch &b : s->batches) {
-    if (b.stream) (void)hipStreamSynchronize(b.stream);
+    if (b.stream) (void)s->ops->stream_sync(b.stream);
   }
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -961,30 +1046,7 @@ vr_status vr_serve_destroy(vr_server *s) {
     std::unique_lock<std::mutex> lk(s->mu);
     s->cv_done.wait(lk, [&] { return s->waiters == 0; });
   }
-  for (Batch &b : s->batches) {
-    if (b.done) (void)hipEventDestroy(b.done);
-    if (b.occ_done) (void)hipEventDestroy(b.occ_done);
-    if (b.stream) (void)hipStreamDestroy(b.stream);
-    if (b.host) (void)hipHostFree(b.host);
-    if (b.samples_host) (void)hipHostFree(b.samples_host);
-    if (b.dev) (void)hipFree(b.dev);
-  }
-  for (auto &kv : s->requests) {
-    if (kv.second->image) (void)hipFree(kv.second->image);
-    if (kv.second->occ) (void)hipFree(kv.second->occ);
-  }
-  for (auto &kv : s->image_pool) (void)hipFree(kv.second);
-  for (auto &kv : s->occ_pool) (void)hipFree(kv.second);
-  for (uint32_t *p : s->occ_retired) (void)hipFree(p);
-  for (auto &kv : s->volumes) {
-    vr_blocks_free(kv.second.blocks);
-    if (kv.second.bricked) vr_bricked_free(kv.second.bricked);
-  }
-  if (s->ooc_stream) (void)hipStreamDestroy(s->ooc_stream);
-  if (s->ooc_tf) (void)hipFree(s->ooc_tf);
-  if (s->ooc_tf_host) (void)hipHostFree(s->ooc_tf_host);
-  if (s->brick_pool) (void)hipFree(s->brick_pool);
-  brick_arena_delete(s->arena);
+  free_server_resources(s);
   delete s;
   return VR_OK;
 }

@@ -161,6 +161,38 @@ void brick_arena_delete(BrickArena *a);
 // nullptr when it cannot be obtained.
 uint32_t *tf_status_word();
 
+// Device operations of the serving loop (serve.cpp).  The server makes every
+// device call through one of these tables: serve_hip_ops() is the HIP one;
+// a CPU stand-in lets the scheduler's host threads be checked on their own
+// (ThreadSanitizer, no device).  Each returns hipSuccess or an error;
+// event_query returns hipErrorNotReady while the event's work runs.
+struct ServeOps {
+  hipError_t (*device_count)(int *n);
+  hipError_t (*set_device)(int device);
+  hipError_t (*stream_create)(hipStream_t *s);
+  hipError_t (*stream_destroy)(hipStream_t s);
+  hipError_t (*stream_sync)(hipStream_t s);
+  hipError_t (*event_create)(hipEvent_t *e);
+  hipError_t (*event_destroy)(hipEvent_t e);
+  hipError_t (*event_record)(hipEvent_t e, hipStream_t s);
+  hipError_t (*event_query)(hipEvent_t e);
+  hipError_t (*stream_wait)(hipStream_t s, hipEvent_t e);
+  hipError_t (*dev_alloc)(void **p, size_t bytes);
+  hipError_t (*dev_free)(void *p);
+  hipError_t (*host_alloc)(void **p, size_t bytes);
+  hipError_t (*host_free)(void *p);
+  hipError_t (*copy_async)(void *dst, const void *src, size_t bytes, hipMemcpyKind kind, hipStream_t s);
+  hipError_t (*occupancy)(const VolConst &v, const TfConst &tf, uint32_t *bits, bool radius, hipStream_t s);
+  hipError_t (*launch_batch)(const ServeSlot *slots_dev, const ServeItem *items_dev, int32_t n_items,
+                             int32_t max_tf_k, unsigned long long *samples, hipStream_t s);
+  // build the blocks of a resident volume (complete on return) and fill vc
+  // with the volume and block constants; free_blocks releases them
+  vr_status (*build_blocks)(const vr_volume *vol, int32_t edge, vr_blocks **out, VolConst *vc);
+  void (*free_blocks)(vr_blocks *b);
+};
+const ServeOps *serve_hip_ops();
+vr_status serve_create_with_ops(const vr_serve_config *cfg, const ServeOps *ops, vr_server **out);
+
 // Validation helpers of the ABI layer (api.cpp); each fills the kernel-side
 // constants and records vr_last_error on failure.
 vr_status fail(vr_status s, const char *fmt, ...);
