@@ -8,7 +8,9 @@
 // blocks with nothing visible are skipped (block decomposition, "Pros" (b)).
 //
 // Work layout: a wavefront owns an 8x8 pixel tile (one ray per lane), a
-// workgroup of four wavefronts a 16x16 super-tile.  The transfer function and
+// workgroup of four wavefronts a 16x16 super-tile; the whole-image forward
+// kernel marches each ray with a pair of lanes instead (8x4 rays per
+// wavefront, half a super-tile per workgroup).  The transfer function and
 // its non-zero-extinction bitmask live in LDS.  Volume taps are fetched with
 // raw buffer loads (bounds-checked by the hardware): an x-row of four int16
 // taps is one dwordx3 load plus two v_alignbit, an fp32 row one dwordx4 load.
