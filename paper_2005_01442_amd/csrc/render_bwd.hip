@@ -262,13 +262,21 @@ __device__ inline void box_apply(GradBox &b, unsigned long long staged) {
   __builtin_amdgcn_wave_barrier();
 }
 
-template <int DT>
+// The adjoint marches each ray with a group of kBwdRayGroup lanes (see
+// walk_group): every lane recomputes its own samples, the group's chain gives
+// each lane T_k a_k, T_{k+1} and C_{<=k} of its sample, and the lane applies
+// that sample's adjoint.
+#ifndef VR_BWD_RAY_GROUP
+#define VR_BWD_RAY_GROUP 2
+#endif
+constexpr int kBwdRayGroup = VR_BWD_RAY_GROUP;
+static_assert(kBwdRayGroup == 1 || kBwdRayGroup == 2 || kBwdRayGroup == 4, "ray groups lie within a quad");
+
+template <int G, int DT>
 __device__ inline void march_backward(const VolConst &v, const TfShared &s, float *sgtf, GradBox &box,
                                       const TfConst &tf, const MarchConst &mc, const Ray &r,
                                       __amdgpu_buffer_rsrc_t rs, float4 g, float4 fin, float *grad_vol) {
-  float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, T = 1.0f;
   const float sl2 = mc.step * 1.4426950408889634f;
-  const bool ert_on = mc.ert > 0.0f && mc.ert < 1.0f;
   const float Tend = 1.0f - fin.w;
   // TF-gradient contributions of consecutive samples in one TF segment are
   // summed in registers and written to LDS when the segment changes
@@ -290,40 +298,44 @@ __device__ inline void march_backward(const VolConst &v, const TfShared &s, floa
     if (grad_vol && box.cells) box_apply(box, __ballot(staged));
     staged = false;
   };
-  // the taps of the next lattice point are loaded while this one is
+  // the taps of this lane's next lattice point are loaded while this one is
   // processed (in the adjoint every lattice point of a ray is usually visited)
   TapPrefetch<DT> pf;
   pf.ix = INT_MIN;
-  auto visit = [&](int k, float px, float py, float pz) -> bool {
-    Stencil st = make_stencil(px, py, pz);
-    float val = reconstruct_prefetched<DT>(pf, rs, v, st);
-    if (k + 1 < r.k0 + r.ns) {
+  float sx = 0.0f, sy = 0.0f, sz = 0.0f;  // this lane's sample: its position
+  Classified cq;                          // and classification, kept for its adjoint
+  auto eval = [&](int k, float px, float py, float pz) -> ChainSample {
+    sx = px;
+    sy = py;
+    sz = pz;
+    const Stencil st = make_stencil(px, py, pz);
+    const float val = reconstruct_prefetched<DT>(pf, rs, v, st);
+    if (k + G < r.k0 + r.ns) {
       float qx, qy, qz;
-      lattice_point(r, mc.step, k + 1, qx, qy, qz);
+      lattice_point(r, mc.step, k + G, qx, qy, qz);
       prefetch_taps<DT>(pf, rs, v, (int)floorf(qx), (int)floorf(qy), (int)floorf(qz));
     }
-    Classified q = classify(s, tf.K, tf.v0, tf.scale, val);
-    float e = transmit(q.c.w, sl2);
-    float ta = T * (1.0f - e);  // T_k a_k
-    C0 = fmaf(ta, q.c.x, C0);
-    C1 = fmaf(ta, q.c.y, C1);
-    C2 = fmaf(ta, q.c.z, C2);
-    T = T * e;  // T_{k+1}
-    // adjoint of sample k
+    cq = classify(s, tf.K, tf.v0, tf.scale, val);
+    return ChainSample{cq.c.x, cq.c.y, cq.c.z, transmit(cq.c.w, sl2)};
+  };
+  // adjoint of this lane's sample k, given T_k a_k, T_{k+1} and C_{<=k}
+  auto take = [&](bool mine, const ChainState &o) {
+    if (!mine) return;
+    const float ta = o.ta, T = o.T;
     float dc0 = g.x * ta, dc1 = g.y * ta, dc2 = g.z * ta;
     float acc = g.w * Tend;
-    acc = fmaf(g.x, T * q.c.x - (fin.x - C0), acc);
-    acc = fmaf(g.y, T * q.c.y - (fin.y - C1), acc);
-    acc = fmaf(g.z, T * q.c.z - (fin.z - C2), acc);
+    acc = fmaf(g.x, T * cq.c.x - (fin.x - o.C0), acc);
+    acc = fmaf(g.y, T * cq.c.y - (fin.y - o.C1), acc);
+    acc = fmaf(g.z, T * cq.c.z - (fin.z - o.C2), acc);
     float dsig = mc.step * acc;
     if (sgtf) {
-      if (q.j != cj) {
+      if (cq.j != cj) {
         flush_tf();
-        cj = q.j;
+        cj = cq.j;
 #pragma unroll
         for (int i = 0; i < 8; ++i) ga[i] = 0.0f;
       }
-      float w1 = q.w, w0 = 1.0f - q.w;
+      float w1 = cq.w, w0 = 1.0f - cq.w;
       ga[0] = fmaf(w0, dc0, ga[0]);
       ga[1] = fmaf(w0, dc1, ga[1]);
       ga[2] = fmaf(w0, dc2, ga[2]);
@@ -333,23 +345,24 @@ __device__ inline void march_backward(const VolConst &v, const TfShared &s, floa
       ga[6] = fmaf(w1, dc2, ga[6]);
       ga[7] = fmaf(w1, dsig, ga[7]);
     }
-    if (grad_vol && !q.clamped) {
-      float4 a = s.node[q.j], b = s.node[q.j + 1];
+    if (grad_vol && !cq.clamped) {
+      float4 a = s.node[cq.j], b = s.node[cq.j + 1];
       float dv = dc0 * (b.x - a.x);
       dv = fmaf(dc1, b.y - a.y, dv);
       dv = fmaf(dc2, b.z - a.z, dv);
       dv = fmaf(dsig, b.w - a.w, dv);
       dv *= tf.scale;
       if (dv != 0.0f) {
+        const Stencil st = make_stencil(sx, sy, sz);  // (recomputed: fewer registers across the chain)
         if (box.valid)
           staged = box_stage(box, v, st, dv);
         else
           scatter_taps(grad_vol, v, st, dv);
       }
     }
-    return !(ert_on && (1.0f - T) >= mc.ert);
   };
-  walk(v, s, tf, mc, r, visit, prep, post);
+  float4 acc = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+  walk_group<G>(v, s, tf, mc, r, eval, prep, take, post, acc);
   if (sgtf) flush_tf();
   if (grad_vol) box_flush(box, grad_vol, v);
 }
@@ -361,7 +374,8 @@ __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(2, 2)))
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const BackwardArgs &a = kernarg<BackwardArgs>();
   const RenderArgs &ra = a.r;
-  SuperTile st = tile_of(ra.order, blockIdx.x, ra.W, ra.H, ra.n_views, ra.chunk_edge);
+  int part;
+  SuperTile st = group_tile_of<kBwdRayGroup>(ra.order, blockIdx.x, ra.W, ra.H, ra.n_views, ra.chunk_edge, part);
   const int K = ra.tf.K;
   const uint32_t tf_bytes = tf_lds_bytes(K);
   float *sgtf = a.grad_tf ? reinterpret_cast<float *>(lds + tf_bytes) : nullptr;
@@ -394,7 +408,7 @@ __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(2, 2)))
   }
   if (!st.valid) return;  // uniform over the workgroup
   int col, row;
-  pixel_of(st.sx, st.sy, col, row);
+  group_pixel_of<kBwdRayGroup>(st.sx, st.sy, part, col, row);
   // every lane enters the march (it steps the wavefront in unison); lanes
   // outside the image or without a gradient carry an empty ray
   Ray r;
@@ -411,7 +425,7 @@ __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(2, 2)))
     }
   }
   __amdgpu_buffer_rsrc_t rs = make_rsrc(ra.vol.data, ra.vol.bytes);
-  march_backward<DT>(ra.vol, s, sgtf, box, ra.tf, ra.mc, r, rs, g, fin, a.grad_vol);
+  march_backward<kBwdRayGroup, DT>(ra.vol, s, sgtf, box, ra.tf, ra.mc, r, rs, g, fin, a.grad_vol);
   if (sgtf) {
     __syncthreads();
     for (int j = threadIdx.x; j < 4 * K; j += kWgSize) {
@@ -424,7 +438,7 @@ __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(2, 2)))
 hipError_t launch_render_backward(const BackwardArgs &a0, hipStream_t s) {
   BackwardArgs a = a0;
   const RenderArgs &ra = a.r;
-  int64_t grid = render_grid(ra);
+  const int64_t grid = group_grid(render_grid(ra), kBwdRayGroup);
   uint32_t lds = tf_lds_bytes(ra.tf.K) + (a.grad_tf ? (uint32_t)ra.tf.K * 16u : 0u);
   const uint32_t box_bytes = (uint32_t)(kWgSize / kWaveSize) * (kBoxCells + kWaveSize * kRec) * 4u;
   const uint32_t with_box = box_lds_offset(ra.tf.K, a.grad_tf != nullptr) + box_bytes;

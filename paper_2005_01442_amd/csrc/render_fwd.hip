@@ -5,8 +5,6 @@
 // the scalar with the tricubic B-spline, classify through the TF
 // (post-classification), composite front to back, stop once the opacity
 // reaches the threshold, and leap over blocks that cannot be visible.
-#include <type_traits>
-
 #include "vr_internal.h"
 
 namespace vr {
@@ -96,155 +94,36 @@ __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfCon
   return make_float4(C0, C1, C2, 1.0f - T);
 }
 
-// ---------------------------------------------------------------------------
-// Ray groups.  G consecutive lanes (within a quad) march one ray: at each step
-// of the wavefront, lane j of a group takes lattice index k + j and the
-// wavefront advances G indices.  A wavefront then holds 64 / G rays and
-// finishes them in about 1 / G of the steps, so the longest tiles of an image
-// -- the rays through the whole volume, which set the kernel's length -- are
-// split into G times as many, G times shorter pieces of work.
-//
-// Each lane evaluates its own sample (skipping, leaps, box staging as in the
-// one-lane walk); the group's G samples are then composited front to back in
-// index order by every lane of the group, with the one-lane march's
-// operations in its order, so the result is bit-identical to it.  A sample
-// the ray does not take (outside its extent, in an empty block, or after the
-// step's sample that ended it) enters the chain as the identity (c = 0,
-// transmittance 1), which leaves colour and transmittance unchanged exactly.
-// ---------------------------------------------------------------------------
+// The whole-image kernel marches each ray with a group of kRayGroup lanes
+// (see walk_group): pairs, measured against one and four lanes per ray.
 #ifndef VR_RAY_GROUP
 #define VR_RAY_GROUP 2
 #endif
 constexpr int kRayGroup = VR_RAY_GROUP;
 static_assert(kRayGroup == 1 || kRayGroup == 2 || kRayGroup == 4, "ray groups lie within a quad");
 
-// Lane I of each ray group, to every lane of the group (a DPP quad
-// permutation: [I, I, 2 + I, 2 + I] for pairs, [I, I, I, I] for quads).
-template <int G, int I>
-__device__ inline float from_group_lane(float x) {
-  if constexpr (G == 1) {
-    return x;
-  } else {
-    constexpr int hi = G == 2 ? 2 + I : I;
-    constexpr int ctrl = I | (I << 2) | (hi << 4) | (hi << 6);
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), ctrl, 0xF, 0xF, false));
-  }
-}
-
 template <int G, int DT, bool SHADE, int F>
 __device__ inline float4 march_group(const VolConst &v, const TfShared &s, const TfConst &tf, const MarchConst &mc,
                                      const ShadeConst &sc, const Ray &r, __amdgpu_buffer_rsrc_t rs, ValBox &box,
                                      uint32_t &evaluated, uint32_t &unstaged) {
-  const int j = (int)(threadIdx.x % kWaveSize) % G;  // this lane's place in its group
-  float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, T = 1.0f;
   const float sl2 = mc.step * 1.4426950408889634f;
   float tf_v0 = tf.v0, tf_scale = tf.scale;
   asm volatile("" : "+v"(tf_v0), "+v"(tf_scale));
-  const bool ert_on = mc.ert > 0.0f && mc.ert < 1.0f;
   RayLight rl;
   if constexpr (SHADE) rl = ray_light(sc, r.d);
   constexpr int kFillBatch = SHADE || F == 2 ? 2 : 4;
-
-  // the one-lane walk (see walk) with the lattice index of lane j at k + j
-  const int kb = r.hit ? r.k0 : 0x7fffffff;
-  const int ke = r.hit ? r.k0 + r.ns : 0;
-  bool alive = r.hit;
-  int k = wave_min_i32(kb);
-  const int kend = wave_max_i32(ke);
-  int kfree = kb;  // indices below kfree: before the ray, or left in an empty block
-  VolConst vg = v;
-  asm volatile("" : "+v"(vg.nx), "+v"(vg.ny), "+v"(vg.nz), "+v"(vg.edge_shift), "+v"(vg.nbx), "+v"(vg.nby));
-  int cur_block = -1;
-  bool cur_occ = false;
-  int bc[3] = {0, 0, 0};
-  while (k < kend) {
-    const int kk = k + j;
-    const bool in = alive && kk >= kfree && kk < ke;
-    bool want = in;
-    float px, py, pz;
-    lattice_point(r, mc.step, kk, px, py, pz);
-    const int ix = (int)floorf(px), iy = (int)floorf(py), iz = (int)floorf(pz);
-    if (in && mc.skip) {
-      const int b = block_of_cell(vg, ix, iy, iz, bc);
-      if (b != cur_block) {
-        cur_block = b;
-        cur_occ = block_occupied(v, s, tf, b);
-      }
-      want = cur_occ;
-    }
-    if (__ballot(want) == 0ull) {
-      // no lane takes a sample at k .. k + G - 1: leap to the smallest index
-      // any lane may need (every index below it is known to be unneeded)
-      if (in) kfree = leap_target(vg, r, bc, mc.step, kk, empty_radius(v, cur_block));
-      const int prop = alive && kk < ke ? kfree : 0x7fffffff;
-      const int m = wave_min_i32(prop);
-      k = m > k + G ? m : k + G;
-      continue;
-    }
+  auto prep = [&](bool want, float px, float py, float pz) {
     if (box.cells) vbox_prepare<DT, kFillBatch>(box, rs, v, r, want, px, py, pz);
-    float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, e = 1.0f;  // the identity unless taken
-    if (want) {
-      const Classified q = eval_sample<DT, SHADE, F>(v, s, tf, tf_v0, tf_scale, sc, rl, rs, box, px, py, pz, unstaged);
-      c0 = q.c.x;
-      c1 = q.c.y;
-      c2 = q.c.z;
-      e = transmit(q.c.w, sl2);
-    }
-    bool live = alive, mine = false;
-    auto take = [&](auto I_) {
-      constexpr int I = decltype(I_)::value;
-      const float ei = from_group_lane<G, I>(e), xi = from_group_lane<G, I>(c0);
-      const float yi = from_group_lane<G, I>(c1), zi = from_group_lane<G, I>(c2);
-      if (j == I) mine = want && live;
-      const float ee = live ? ei : 1.0f;
-      const float ta = T * (1.0f - ee);
-      C0 = fmaf(ta, xi, C0);
-      C1 = fmaf(ta, yi, C1);
-      C2 = fmaf(ta, zi, C2);
-      T = T * ee;
-      if (ert_on && (1.0f - T) >= mc.ert) live = false;
-    };
-    take(std::integral_constant<int, 0>{});
-    if constexpr (G > 1) take(std::integral_constant<int, 1>{});
-    if constexpr (G > 2) {
-      take(std::integral_constant<int, 2>{});
-      take(std::integral_constant<int, 3>{});
-    }
-    alive = live;
-    evaluated += mine ? 1u : 0u;
-    k += G;
-  }
-  return make_float4(C0, C1, C2, 1.0f - T);
-}
-
-// Workgroup -> (super-tile, part): with ray groups of G lanes a workgroup
-// covers 16 / G rows of a 16x16 super-tile.  The G parts of super-tile item q
-// are workgroups 8 G (q / 8) + 8 p + q % 8 (p < G), all on the XCD of q.
-template <int G>
-__device__ inline SuperTile group_tile_of(const RenderArgs &a, int64_t wg, int &part) {
-  const int64_t q = (wg / (kXcds * G)) * kXcds + wg % kXcds;
-  part = (int)((wg / kXcds) % G);
-  if (a.order) {
-    const int64_t n = (int64_t)a.n_views * ((a.W + kSuperEdge - 1) / kSuperEdge) * ((a.H + kSuperEdge - 1) / kSuperEdge);
-    if (q >= n) {
-      SuperTile st;
-      st.view = st.sx = st.sy = 0;
-      st.valid = false;
-      return st;
-    }
-  }
-  return tile_of(a.order, q, a.W, a.H, a.n_views, a.chunk_edge);
-}
-
-// Pixel of this lane's ray: wavefront w of part p covers a TW x TH block
-// (8x8, 8x4, 4x4 for G = 1, 2, 4), ray r = lane / G the pixel
-// (r mod TW, r / TW) of it.
-template <int G>
-__device__ inline void group_pixel_of(int sx, int sy, int part, int &col, int &row) {
-  constexpr int TW = G <= 2 ? 8 : 4, TH = kWaveSize / G / TW, WX = kSuperEdge / TW;
-  const int wave = threadIdx.x / kWaveSize, ray = (threadIdx.x % kWaveSize) / G;
-  col = sx * kSuperEdge + (wave % WX) * TW + ray % TW;
-  row = sy * kSuperEdge + part * (kSuperEdge / G) + (wave / WX) * TH + ray / TW;
+  };
+  auto eval = [&](int, float px, float py, float pz) -> ChainSample {
+    const Classified q = eval_sample<DT, SHADE, F>(v, s, tf, tf_v0, tf_scale, sc, rl, rs, box, px, py, pz, unstaged);
+    return ChainSample{q.c.x, q.c.y, q.c.z, transmit(q.c.w, sl2)};
+  };
+  auto take = [&](bool mine, const ChainState &) { evaluated += mine ? 1u : 0u; };
+  NoPost post;
+  float4 acc = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
+  walk_group<G>(v, s, tf, mc, r, eval, prep, take, post, acc);
+  return make_float4(acc.x, acc.y, acc.z, 1.0f - acc.w);
 }
 
 // The LDS value boxes bound the workgroups per CU (14^3 boxes: three, i.e.
@@ -272,7 +151,7 @@ void k_render(const RenderArgs args) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const RenderArgs &a = kernarg<RenderArgs>();
   int part;
-  SuperTile st = group_tile_of<kRayGroup>(a, blockIdx.x, part);
+  SuperTile st = group_tile_of<kRayGroup>(a.order, blockIdx.x, a.W, a.H, a.n_views, a.chunk_edge, part);
   if (!st.valid) return;  // uniform over the workgroup
   TfShared s = carve_tf(lds, a.tf.K);
   if (a.occ_lds_words > 0)
@@ -457,8 +336,7 @@ int32_t *make_tile_order(const RenderArgs &a, hipStream_t s) {
 
 hipError_t launch_render(const RenderArgs &a0, hipStream_t s) {
   RenderArgs a = a0;
-  // (the grid of render_grid rounded up to a multiple of 8, times the parts)
-  const int64_t grid = (render_grid(a) + kXcds - 1) / kXcds * kXcds * kRayGroup;
+  const int64_t grid = group_grid(render_grid(a), kRayGroup);
   uint32_t lds = tf_lds_bytes(a.tf.K);
   const uint32_t with_box = vbox_lds_offset(a.tf.K) + vbox_lds_bytes();
   a.use_box = with_box <= max_lds_per_workgroup() ? 1 : 0;

@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace vr {
 
 constexpr int kTileEdge = 8;          // pixels per wavefront tile edge
@@ -1182,6 +1184,128 @@ __device__ inline void walk(const VolConst &v, const TfShared &s, const TfConst 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Ray groups.  G consecutive lanes (within a quad) march one ray: at each step
+// of the wavefront, lane j of a group takes lattice index k + j and the
+// wavefront advances G indices.  A wavefront then holds 64 / G rays and
+// finishes them in about 1 / G of the steps, so the longest tiles of an image
+// -- the rays through the whole volume, which set a kernel's length -- are
+// split into G times as many, G times shorter pieces of work.
+//
+// Each lane evaluates its own sample (skipping, leaps and staging as in walk);
+// the group's G samples are then composited front to back in index order by
+// every lane of the group, with the one-lane march's operations in its order,
+// so colour, transmittance and the termination sample are bit-identical to
+// it.  A sample the ray does not take (outside its extent, in an empty block,
+// or after the step's sample that ended it) enters the chain as the identity
+// (c = 0, transmittance 1), which changes nothing exactly.
+// ---------------------------------------------------------------------------
+
+// Lane I of each ray group, to every lane of the group (a DPP quad
+// permutation: [I, I, 2 + I, 2 + I] for pairs, [I, I, I, I] for quads).
+template <int G, int I>
+__device__ inline float from_group_lane(float x) {
+  if constexpr (G == 1) {
+    return x;
+  } else {
+    constexpr int hi = G == 2 ? 2 + I : I;
+    constexpr int ctrl = I | (I << 2) | (hi << 4) | (hi << 6);
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), ctrl, 0xF, 0xF, false));
+  }
+}
+
+// A classified sample as it enters the compositing chain: colour and
+// transmittance exp(-sigma step).
+struct ChainSample {
+  float c0, c1, c2, e;
+};
+
+// The state of a ray after one of its samples: T_k a_k of that sample, and
+// colour and transmittance after it.
+struct ChainState {
+  float ta, C0, C1, C2, T;
+};
+
+// walk for ray groups.  eval(k, px, py, pz) -> ChainSample evaluates this
+// lane's sample (called only where the ray takes it); take(mine, own) runs on
+// every lane after the chain, `mine` telling whether this lane's sample was
+// composited and `own` the ray's state right after it; prep and post as in
+// walk.  acc carries the ray's (C0, C1, C2, T) in and out.
+template <int G, class Eval, class Prep, class Take, class Post>
+__device__ inline void walk_group(const VolConst &v, const TfShared &s, const TfConst &tf, const MarchConst &mc,
+                                  const Ray &r, Eval &eval, Prep &prep, Take &take, Post &post, float4 &acc) {
+  const int j = (int)(threadIdx.x % kWaveSize) % G;  // this lane's place in its group
+  const bool ert_on = mc.ert > 0.0f && mc.ert < 1.0f;
+  float C0 = acc.x, C1 = acc.y, C2 = acc.z, T = acc.w;
+  const int kb = r.hit ? r.k0 : 0x7fffffff;
+  const int ke = r.hit ? r.k0 + r.ns : 0;
+  bool alive = r.hit;
+  int k = wave_min_i32(kb);
+  const int kend = wave_max_i32(ke);
+  int kfree = kb;  // indices below kfree: before the ray, or left in an empty block
+  VolConst vg = v;
+  asm volatile("" : "+v"(vg.nx), "+v"(vg.ny), "+v"(vg.nz), "+v"(vg.edge_shift), "+v"(vg.nbx), "+v"(vg.nby));
+  int cur_block = -1;
+  bool cur_occ = false;
+  int bc[3] = {0, 0, 0};
+  while (k < kend) {
+    const int kk = k + j;
+    const bool in = alive && kk >= kfree && kk < ke;
+    bool want = in;
+    float px, py, pz;
+    lattice_point(r, mc.step, kk, px, py, pz);
+    const int ix = (int)floorf(px), iy = (int)floorf(py), iz = (int)floorf(pz);
+    if (in && mc.skip) {
+      const int b = block_of_cell(vg, ix, iy, iz, bc);
+      if (b != cur_block) {
+        cur_block = b;
+        cur_occ = block_occupied(v, s, tf, b);
+      }
+      want = cur_occ;
+    }
+    if (__ballot(want) == 0ull) {
+      // no lane takes a sample at k .. k + G - 1: leap to the smallest index
+      // any lane may need (every index below it is known to be unneeded)
+      if (in) kfree = leap_target(vg, r, bc, mc.step, kk, empty_radius(v, cur_block));
+      const int prop = alive && kk < ke ? kfree : 0x7fffffff;
+      const int m = wave_min_i32(prop);
+      k = m > k + G ? m : k + G;
+      continue;
+    }
+    prep(want, px, py, pz);
+    ChainSample q = {0.0f, 0.0f, 0.0f, 1.0f};  // the identity unless taken
+    if (want) q = eval(kk, px, py, pz);
+    bool live = alive, mine = false;
+    ChainState own = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    auto link = [&](auto I_) {
+      constexpr int I = decltype(I_)::value;
+      const float ei = from_group_lane<G, I>(q.e), xi = from_group_lane<G, I>(q.c0);
+      const float yi = from_group_lane<G, I>(q.c1), zi = from_group_lane<G, I>(q.c2);
+      const bool at = j == I;
+      if (at) mine = want && live;
+      const float ee = live ? ei : 1.0f;
+      const float ta = T * (1.0f - ee);
+      C0 = fmaf(ta, xi, C0);
+      C1 = fmaf(ta, yi, C1);
+      C2 = fmaf(ta, zi, C2);
+      T = T * ee;
+      if (at) own = ChainState{ta, C0, C1, C2, T};
+      if (ert_on && (1.0f - T) >= mc.ert) live = false;
+    };
+    link(std::integral_constant<int, 0>{});
+    if constexpr (G > 1) link(std::integral_constant<int, 1>{});
+    if constexpr (G > 2) {
+      link(std::integral_constant<int, 2>{});
+      link(std::integral_constant<int, 3>{});
+    }
+    alive = live;
+    take(mine, own);
+    post();
+    k += G;
+  }
+  acc = make_float4(C0, C1, C2, T);
+}
+
 __device__ inline bool block_occupied(const VolConst &v, const TfShared &s, const TfConst &tf, int b) {
   if (s.occ_lds) return (s.occ[b >> 5] >> (b & 31)) & 1u;
   if (v.occ) return (v.occ[b >> 5] >> (b & 31)) & 1u;
@@ -1283,6 +1407,40 @@ __device__ inline void pixel_of(int sx, int sy, int &col, int &row) {
   int wave = threadIdx.x / kWaveSize, lane = threadIdx.x % kWaveSize;
   col = sx * kSuperEdge + (wave & 1) * kTileEdge + (lane & 7);
   row = sy * kSuperEdge + (wave >> 1) * kTileEdge + (lane >> 3);
+}
+
+// Workgroup -> (super-tile, part): with ray groups of G lanes a workgroup
+// covers 16 / G rows of a 16x16 super-tile.  The G parts of super-tile item q
+// are workgroups 8 G (q / 8) + 8 p + q % 8 (p < G), all on the XCD of q.
+template <int G>
+__device__ inline SuperTile group_tile_of(const int32_t *order, int64_t wg, int W, int H, int views, int ce,
+                                          int &part) {
+  const int64_t q = (wg / (kXcds * G)) * kXcds + wg % kXcds;
+  part = (int)((wg / kXcds) % G);
+  if (order && q >= (int64_t)views * ((W + kSuperEdge - 1) / kSuperEdge) * ((H + kSuperEdge - 1) / kSuperEdge)) {
+    SuperTile st;
+    st.view = st.sx = st.sy = 0;
+    st.valid = false;
+    return st;
+  }
+  return tile_of(order, q, W, H, views, ce);
+}
+
+// Pixel of this lane's ray: wavefront w of part p covers a TW x TH block
+// (8x8, 8x4, 4x4 for G = 1, 2, 4), ray r = lane / G the pixel
+// (r mod TW, r / TW) of it.
+template <int G>
+__device__ inline void group_pixel_of(int sx, int sy, int part, int &col, int &row) {
+  constexpr int TW = G <= 2 ? 8 : 4, TH = kWaveSize / G / TW, WX = kSuperEdge / TW;
+  const int wave = threadIdx.x / kWaveSize, ray = (threadIdx.x % kWaveSize) / G;
+  col = sx * kSuperEdge + (wave % WX) * TW + ray % TW;
+  row = sy * kSuperEdge + part * (kSuperEdge / G) + (wave / WX) * TH + ray / TW;
+}
+
+// Workgroups of a launch over `items` super-tile items (or the padded Morton
+// grid) with ray groups of G lanes.
+__host__ __device__ inline int64_t group_grid(int64_t items, int G) {
+  return (items + kXcds - 1) / kXcds * kXcds * G;
 }
 
 // The kernel's by-value argument struct, read in place from the kernarg
