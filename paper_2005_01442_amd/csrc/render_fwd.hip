@@ -351,22 +351,25 @@ hipError_t launch_render(const RenderArgs &a0, hipStream_t s) {
   return launch_render_as<false, 0>(a, grid, lds, s);
 }
 
-// Serving: one workgroup per work item, a 16x16 super-tile of one admitted
-// request; the items of a launch may come from many requests of different
+// Serving: kRayGroup workgroups per work item, a 16x16 super-tile of one
+// admitted request, its rays marched by lane groups as in the whole-image
+// kernel; the items of a launch may come from many requests of different
 // volumes, sizes and TFs.  The per-ray arithmetic is the whole-image
 // kernel's, so a request's pixels do not depend on what it is batched with.
 __global__ __launch_bounds__(kWgSize) void k_serve(const ServeSlot *slots, const ServeItem *items, int lds_k,
                                                    int use_box, unsigned long long *samples) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
-  const ServeItem it = items[blockIdx.x];
+  const ServeItem it = items[blockIdx.x / kRayGroup];  // (the item's parts are consecutive workgroups)
+  const int part = (int)(blockIdx.x % kRayGroup);
   const ServeSlot &sl = slots[it.slot];
   TfShared s = carve_tf(lds, sl.tf.K);
   const bool tf_ok = load_tf(s, sl.tf);
   int col, row;
-  pixel_of(it.sx, it.sy, col, row);
+  group_pixel_of<kRayGroup>(it.sx, it.sy, part, col, row);
   const bool inside = col < sl.cam.W && row < sl.cam.H;
+  const bool lead = (threadIdx.x % kRayGroup) == 0;
   if (!tf_ok) {  // (the server validates every table at submit)
-    if (inside) reinterpret_cast<float4 *>(sl.out)[(size_t)row * sl.cam.W + col] = nan_rgba();
+    if (inside && lead) reinterpret_cast<float4 *>(sl.out)[(size_t)row * sl.cam.W + col] = nan_rgba();
     return;
   }
   Ray r;
@@ -382,12 +385,13 @@ __global__ __launch_bounds__(kWgSize) void k_serve(const ServeSlot *slots, const
   box.cells = use_box ? reinterpret_cast<float *>(lds + vbox_lds_offset(lds_k)) + (threadIdx.x / kWaveSize) * kVBoxCells
                       : nullptr;
   float4 rgba;
+  const ShadeConst sc{};
   switch (sl.vol.dtype) {  // uniform over the workgroup
-  case kU16: rgba = march<kU16, false>(sl.vol, s, sl.tf, sl.mc, ShadeConst{}, r, rs, box, evaluated, unstaged); break;
-  case kI16: rgba = march<kI16, false>(sl.vol, s, sl.tf, sl.mc, ShadeConst{}, r, rs, box, evaluated, unstaged); break;
-  default: rgba = march<kF32, false>(sl.vol, s, sl.tf, sl.mc, ShadeConst{}, r, rs, box, evaluated, unstaged); break;
+  case kU16: rgba = march_group<kRayGroup, kU16, false, 0>(sl.vol, s, sl.tf, sl.mc, sc, r, rs, box, evaluated, unstaged); break;
+  case kI16: rgba = march_group<kRayGroup, kI16, false, 0>(sl.vol, s, sl.tf, sl.mc, sc, r, rs, box, evaluated, unstaged); break;
+  default: rgba = march_group<kRayGroup, kF32, false, 0>(sl.vol, s, sl.tf, sl.mc, sc, r, rs, box, evaluated, unstaged); break;
   }
-  if (inside) reinterpret_cast<float4 *>(sl.out)[(size_t)row * sl.cam.W + col] = rgba;
+  if (inside && lead) reinterpret_cast<float4 *>(sl.out)[(size_t)row * sl.cam.W + col] = rgba;
   wave_count(samples, evaluated);
 }
 
@@ -401,8 +405,8 @@ hipError_t launch_serve_batch(const ServeSlot *slots_dev, const ServeItem *items
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_serve),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_serve, dim3((unsigned)n_items), dim3(kWgSize), lds, s, slots_dev, items_dev, max_tf_k,
-                     use_box, samples);
+  hipLaunchKernelGGL(k_serve, dim3((unsigned)(n_items * kRayGroup)), dim3(kWgSize), lds, s, slots_dev, items_dev,
+                     max_tf_k, use_box, samples);
   return hipGetLastError();
 }
 
