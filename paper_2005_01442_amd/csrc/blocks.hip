@@ -22,9 +22,10 @@ namespace vr {
 // union, combined with one lane swap.  The even lane keeps the running (min,
 // max) over the rows; the wavefronts are combined in LDS at the end of the
 // pass.  WIDE (E = 16, rows of a multiple of 8 voxels, 16-byte aligned data):
-// a lane's half block is one or two 16-byte loads.
+// a lane's half block is one or two 16-byte loads; 16-bit voxels take
+// k_block_minmax_pk16 (packed integer min/max, z streaming) below.
 constexpr int kMinmaxHalf = 8;   // voxels per lane per row in one trip: half of a 16-voxel block
-constexpr int kMinmaxRows = 4;   // rows per wavefront trip
+constexpr int kMinmaxRows = 4;   // rows per wavefront trip (2 to 8 measured; 8 slower)
 constexpr int kMinmaxThreads = 512;  // eight wavefronts: more rows in flight per row of blocks
 
 template <typename T>
@@ -98,6 +99,157 @@ __device__ inline void half_block_range_wide(const T *row, int xa, int nx, int l
   }
 }
 
+// WIDE for 16-bit voxels: the running (min, max) of a lane stay packed 16-bit
+// integers (two per register, v_pk_min / v_pk_max over the four dwords of a
+// load), exact, and become floats once per pass; the apron dwords come from
+// the neighbouring lanes (the last dword of lane - 1, of which the high half
+// is the voxel before the block; the first dword of lane + 1, both halves
+// after it).
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct Packed16;
+template <>
+struct Packed16<int16_t> {
+  typedef s16x2 V;
+  static constexpr short kLo = -32768, kHi = 32767;
+};
+template <>
+struct Packed16<uint16_t> {
+  typedef u16x2 V;
+  static constexpr unsigned short kLo = 0, kHi = 65535;
+};
+
+template <typename T>
+__device__ inline void half_block_range_pk16(const T *row, int xa, int nx, int lane, bool first_pass,
+                                             typename Packed16<T>::V &mn, typename Packed16<T>::V &mx) {
+  typedef typename Packed16<T>::V V;
+  const uint4 q = *reinterpret_cast<const uint4 *>(row + min(xa, nx - kMinmaxHalf));
+  const V w0 = __builtin_bit_cast(V, q.x), w1 = __builtin_bit_cast(V, q.y);
+  const V w2 = __builtin_bit_cast(V, q.z), w3 = __builtin_bit_cast(V, q.w);
+  mn = __builtin_elementwise_min(mn, __builtin_elementwise_min(__builtin_elementwise_min(w0, w1),
+                                                               __builtin_elementwise_min(w2, w3)));
+  mx = __builtin_elementwise_max(mx, __builtin_elementwise_max(__builtin_elementwise_max(w0, w1),
+                                                               __builtin_elementwise_max(w2, w3)));
+  const uint32_t left = (uint32_t)__shfl_up((int)q.w, 1, kWaveSize);
+  const uint32_t right = (uint32_t)__shfl_down((int)q.x, 1, kWaveSize);
+  uint32_t ap;
+  if (lane & 1) {
+    if (lane == kWaveSize - 1) {
+      const uint32_t a0 = (uint16_t)row[min(xa + kMinmaxHalf, nx - 1)], a1 = (uint16_t)row[min(xa + kMinmaxHalf + 1, nx - 1)];
+      ap = a0 | (a1 << 16);
+    } else {
+      ap = right;
+    }
+  } else {
+    uint32_t v;  // the voxel before the block, in the low half
+    if (lane == 0)
+      v = first_pass ? (q.x & 0xffffu) : (uint16_t)row[min(max(xa - 1, 0), nx - 1)];
+    else
+      v = left >> 16;
+    ap = v | (v << 16);
+  }
+  mn = __builtin_elementwise_min(mn, __builtin_bit_cast(V, ap));
+  mx = __builtin_elementwise_max(mx, __builtin_bit_cast(V, ap));
+}
+
+// One workgroup per row of blocks in x and BZ consecutive blocks in z: the
+// x-rows of the footprint are streamed in z order, each read once, and a row
+// adds to the one or two blocks in z whose footprint holds it (z in
+// [16 b - 1, 16 b + 17]): rows shared by vertically neighbouring blocks are
+// not read again.  (With BZ = 1 every block row reads its own footprint, as
+// k_block_minmax does; the launch takes BZ = 4 when that still leaves about
+// four workgroups per CU.)
+template <typename T, int BZ>
+__global__ __launch_bounds__(kMinmaxThreads) void k_block_minmax_pk16(const VolConst v, float2 *out) {
+  typedef typename Packed16<T>::V V;
+  constexpr int kWaves = kMinmaxThreads / kWaveSize;
+  constexpr int E = 2 * kMinmaxHalf;
+  __shared__ float smin[BZ][kWaves][kWaveSize / 2], smax[BZ][kWaves][kWaveSize / 2];
+  // XCD-aware: workgroup i runs on XCD i mod 8; each XCD takes a contiguous
+  // run of items, neighbouring rows of blocks in y side by side
+  const int nchunks = (v.nbz + BZ - 1) / BZ;
+  const int nitems = v.nby * nchunks, per_xcd = (nitems + kXcds - 1) / kXcds;
+  const int q = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+  if (q >= nitems) return;
+  const int by = q % v.nby, bz0 = (q / v.nby) * BZ, nbz = min(BZ, v.nbz - bz0);
+  const int y0 = max(by * E - 1, 0), y1 = min(by * E + E + 1, v.ny - 1);
+  const int z0 = max(bz0 * E - 1, 0), z1 = min((bz0 + nbz) * E + 1, v.nz - 1);
+  const int ny = y1 - y0 + 1, rows = ny * (z1 - z0 + 1);
+  // the wavefront index, as a uniform value: the row walk below stays scalar
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWaveSize));
+  const int lane = threadIdx.x % kWaveSize;
+  const T *base = reinterpret_cast<const T *>(v.data);
+  constexpr int per_pass = kWaveSize / 2;  // blocks per pass
+  for (int bx0 = 0; bx0 < v.nbx; bx0 += per_pass) {
+    const int bx = bx0 + lane / 2;
+    const bool hi = lane & 1;
+    const int xa = bx * E + (hi ? kMinmaxHalf : 0);
+    V mn[BZ], mx[BZ];
+#pragma unroll
+    for (int j = 0; j < BZ; ++j) {
+      mn[j] = V{Packed16<T>::kHi, Packed16<T>::kHi};
+      mx[j] = V{Packed16<T>::kLo, Packed16<T>::kLo};
+    }
+    // footprint row r = (y - y0) + ny (z - z0), walked by increments (no
+    // division per row); rows past the last repeat it, which changes nothing
+    int r = wave, y = y0 + wave % ny, z = z0 + wave / ny;
+    while (r < rows) {
+#pragma unroll
+      for (int u = 0; u < kMinmaxRows; ++u) {
+        const bool in = r < rows;
+        const int yy = in ? y : y1, zz = in ? z : z1;
+        const T *row = base + ((size_t)zz * (size_t)v.ny + (size_t)yy) * (size_t)v.nx;
+        V rmn = V{Packed16<T>::kHi, Packed16<T>::kHi}, rmx = V{Packed16<T>::kLo, Packed16<T>::kLo};
+        half_block_range_pk16<T>(row, xa, v.nx, lane, bx0 == 0, rmn, rmx);
+        if constexpr (BZ == 1) {
+          mn[0] = __builtin_elementwise_min(mn[0], rmn);
+          mx[0] = __builtin_elementwise_max(mx[0], rmx);
+        } else {
+          // the blocks in z whose footprint holds row zz (one, or two at a
+          // boundary), relative to this item's first
+          const int jhi = (zz + 1) / E - bz0, jlo = (zz + E - 2) / E - 1 - bz0;
+#pragma unroll
+          for (int j = 0; j < BZ; ++j)
+            if ((j == jhi || j == jlo) && j < nbz) {  // uniform
+              mn[j] = __builtin_elementwise_min(mn[j], rmn);
+              mx[j] = __builtin_elementwise_max(mx[j], rmx);
+            }
+        }
+        r += kWaves;
+        y += kWaves;
+        while (y > y1) {
+          y -= ny;
+          ++z;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < BZ; ++j) {
+      float fmn = (float)min(mn[j].x, mn[j].y), fmx = (float)max(mx[j].x, mx[j].y);
+      fmn = fminf(fmn, __shfl_xor(fmn, 1, kWaveSize));
+      fmx = fmaxf(fmx, __shfl_xor(fmx, 1, kWaveSize));
+      if (!hi) {
+        smin[j][wave][lane / 2] = fmn;
+        smax[j][wave][lane / 2] = fmx;
+      }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < per_pass * nbz; t += kMinmaxThreads) {
+      const int j = t / per_pass, i = t % per_pass, b = bx0 + i;
+      float m0 = smin[j][0][i], m1 = smax[j][0][i];
+#pragma unroll
+      for (int w = 1; w < kWaves; ++w) {
+        m0 = fminf(m0, smin[j][w][i]);
+        m1 = fmaxf(m1, smax[j][w][i]);
+      }
+      if (b < v.nbx) out[((int64_t)(bz0 + j) * v.nby + by) * v.nbx + b] = make_float2(m0, m1);
+    }
+    __syncthreads();
+  }
+}
+
 template <typename T, bool WIDE>
 __global__ __launch_bounds__(kMinmaxThreads) void k_block_minmax(const VolConst v, float2 *out) {
   constexpr int kWaves = kMinmaxThreads / kWaveSize;
@@ -155,17 +307,33 @@ __global__ __launch_bounds__(kMinmaxThreads) void k_block_minmax(const VolConst 
   }
 }
 
+// Blocks in z per workgroup of the 16-bit kernel: four when that leaves at
+// least kMinmaxStreamItems workgroups (four per CU), else one.
+constexpr int kMinmaxStreamItems = 1024;
+
+template <typename T>
+static void launch_minmax_pk16(const VolConst &v, float2 *out, hipStream_t s) {
+  const int64_t items4 = (int64_t)v.nby * ((v.nbz + 3) / 4);
+  if (items4 >= kMinmaxStreamItems) {
+    const unsigned grid = (unsigned)((items4 + kXcds - 1) / kXcds * kXcds);
+    hipLaunchKernelGGL((k_block_minmax_pk16<T, 4>), dim3(grid), dim3(kMinmaxThreads), 0, s, v, out);
+  } else {
+    const unsigned grid = (unsigned)(((int64_t)v.nby * v.nbz + kXcds - 1) / kXcds * kXcds);
+    hipLaunchKernelGGL((k_block_minmax_pk16<T, 1>), dim3(grid), dim3(kMinmaxThreads), 0, s, v, out);
+  }
+}
+
 hipError_t launch_block_minmax(const VolConst &v, float2 *out, hipStream_t s) {
   const unsigned grid = (unsigned)(((int64_t)v.nby * v.nbz + kXcds - 1) / kXcds * kXcds);
   const bool wide = v.edge == 2 * kMinmaxHalf && v.nx % kMinmaxHalf == 0 &&
                     (reinterpret_cast<uintptr_t>(v.data) & 15u) == 0;
   switch (v.dtype) {
   case kU16:
-    if (wide) hipLaunchKernelGGL((k_block_minmax<uint16_t, true>), dim3(grid), dim3(kMinmaxThreads), 0, s, v, out);
+    if (wide) launch_minmax_pk16<uint16_t>(v, out, s);
     else hipLaunchKernelGGL((k_block_minmax<uint16_t, false>), dim3(grid), dim3(kMinmaxThreads), 0, s, v, out);
     break;
   case kI16:
-    if (wide) hipLaunchKernelGGL((k_block_minmax<int16_t, true>), dim3(grid), dim3(kMinmaxThreads), 0, s, v, out);
+    if (wide) launch_minmax_pk16<int16_t>(v, out, s);
     else hipLaunchKernelGGL((k_block_minmax<int16_t, false>), dim3(grid), dim3(kMinmaxThreads), 0, s, v, out);
     break;
   case kF32:

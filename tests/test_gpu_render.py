@@ -132,6 +132,27 @@ def test_blocks_and_occupancy_exact():
             assert np.array_equal(occ, oracle.occupancy(want, tf))
 
 
+def test_blocks_streamed_in_z_exact():
+    """Grids with at least 1024 (row of blocks, four blocks in z) items take the
+    16-bit kernel that streams four blocks in z per workgroup, each footprint
+    row read once and added to the one or two blocks holding it: integer-exact
+    against the oracle, with a last chunk of three blocks and a last block of
+    half height (nz = 1000) and a partial last block in x (nx = 24)."""
+    rng = np.random.default_rng(41)
+    for dims in ((24, 1040, 1000), (32, 1024, 1024)):
+        nx, ny, nz = dims
+        base = rng.integers(-1024, 3000, size=(nz, ny, nx)).astype(np.int16)
+        # smooth structure plus a few extreme voxels on block boundaries in z
+        for z in (15, 16, 17, 31, 32, 33, 991, 999):
+            if z < nz:
+                base[z, rng.integers(0, ny, 8), rng.integers(0, nx, 8)] = (-32768 if z % 2 else 32767)
+        for vol in (base, (base.astype(np.int32) + 32768).astype(np.uint16)):
+            log(f"streamed block min/max {dims} {vol.dtype}")
+            v = upload_volume(vol)
+            mm = vr.vr_blocks_minmax(vr.vr_build_blocks(v, 16)).cpu().numpy().astype(np.float64)
+            assert np.array_equal(mm, oracle.blocks(vol, 16)), (dims, vol.dtype)
+
+
 def test_camera_inside_volume_and_misses():
     vol = _small_ct()
     dims = (96, 80, 72)
