@@ -384,7 +384,13 @@ void vr_bricked_free(vr_bricked *bricked);
  *   Both are OVERWRITTEN (zeroed, then accumulated with atomics, so the
  *   summation order is not deterministic).
  * Skipping is used only when grad_tf is NULL (zero-extinction nodes still
- * receive TF gradients).  Errors as vr_render. */
+ * receive TF gradients).  When every sample is visited and `blocks` is given
+ * (also with p->use_skip = 0; it must then have been built for `vol`), a
+ * sample in a block that is empty under the TF and constant over its
+ * footprint takes that constant as its value, without reconstruction, and
+ * runs of such samples (which change neither colour nor transmittance) are
+ * accounted for at once; the gradients equal those without `blocks` up to
+ * summation order.  Errors as vr_render. */
 vr_status vr_render_backward(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,
                              const vr_tf *tf, const vr_params *p, const float *out_rgba, const float *grad_rgba,
                              float *grad_volume, float *grad_tf, void *stream);

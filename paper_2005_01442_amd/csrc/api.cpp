@@ -137,7 +137,7 @@ vr_status check_march(float step, float ert, int32_t use_skip, MarchConst *out) 
     out->step = step;
     out->ert = (ert > 0.0f && ert < 1.0f) ? ert : 0.0f;
     out->skip = use_skip ? 1 : 0;
-    out->pad = 0;
+    out->flat = 0;
   }
   return VR_OK;
 }
@@ -537,7 +537,11 @@ vr_status vr_render_backward(const vr_volume *vol, const vr_blocks *blocks, cons
   if (s) return s;
   if (p->filter != VR_FILTER_BSPLINE) return fail(VR_E_UNSUPPORTED, "the adjoint is of the cubic B-spline render");
   if (!out_rgba || !grad_rgba) return fail(VR_E_INVALID_ARG, "out_rgba and grad_rgba are required");
+  if (!p->use_skip && blocks && (s = attach_blocks(blocks, vol, &b.r.vol))) return s;
   if (grad_tf) b.r.mc.skip = 0;  // zero-extinction nodes still receive TF gradients
+  // every sample is visited: with the blocks' min/max, samples in constant
+  // empty blocks take the constant without reconstruction
+  b.r.mc.flat = !b.r.mc.skip && b.r.vol.minmax ? 1 : 0;
   b.r.counters = nullptr;
   hipStream_t st = (hipStream_t)stream;
   const int64_t nvox = (int64_t)vol->nx * vol->ny * vol->nz;

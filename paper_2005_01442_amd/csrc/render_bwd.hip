@@ -318,6 +318,30 @@ __device__ inline void march_backward(const VolConst &v, const TfShared &s, floa
     cq = classify(s, tf.K, tf.v0, tf.scale, val);
     return ChainSample{cq.c.x, cq.c.y, cq.c.z, transmit(cq.c.w, sl2)};
   };
+  // TF gradient of the dsig-only adjoint of one sample with classification q
+  // (its colour gradient is zero: T_k a_k = 0), n identical samples at once
+  auto tf_sigma = [&](const Classified &q, float dsig, float n) {
+    if (q.j != cj) {
+      flush_tf();
+      cj = q.j;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) ga[i] = 0.0f;
+    }
+    const float d = n * dsig;
+    ga[3] = fmaf(1.0f - q.w, d, ga[3]);
+    ga[7] = fmaf(q.w, d, ga[7]);
+  };
+  // n samples of a constant empty block (extinction 0, so a = 0 and the ray's
+  // state is unchanged): only dsig is non-zero, the same for all of them
+  auto flat = [&](int n, const ChainState &o, float value) {
+    if (!sgtf) return;
+    const Classified fq = classify(s, tf.K, tf.v0, tf.scale, value);
+    float acc = g.w * Tend;
+    acc = fmaf(g.x, o.T * fq.c.x - (fin.x - o.C0), acc);
+    acc = fmaf(g.y, o.T * fq.c.y - (fin.y - o.C1), acc);
+    acc = fmaf(g.z, o.T * fq.c.z - (fin.z - o.C2), acc);
+    tf_sigma(fq, mc.step * acc, (float)n);
+  };
   // adjoint of this lane's sample k, given T_k a_k, T_{k+1} and C_{<=k}
   auto take = [&](bool mine, const ChainState &o) {
     if (!mine) return;
@@ -362,7 +386,7 @@ __device__ inline void march_backward(const VolConst &v, const TfShared &s, floa
     }
   };
   float4 acc = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
-  walk_group<G>(v, s, tf, mc, r, eval, prep, take, post, acc);
+  walk_group<G, true>(v, s, tf, mc, r, eval, prep, take, flat, post, acc);
   if (sgtf) flush_tf();
   if (grad_vol) box_flush(box, grad_vol, v);
 }

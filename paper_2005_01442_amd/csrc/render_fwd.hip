@@ -120,9 +120,10 @@ __device__ inline float4 march_group(const VolConst &v, const TfShared &s, const
     return ChainSample{q.c.x, q.c.y, q.c.z, transmit(q.c.w, sl2)};
   };
   auto take = [&](bool mine, const ChainState &) { evaluated += mine ? 1u : 0u; };
+  NoFlat flat;
   NoPost post;
   float4 acc = make_float4(0.0f, 0.0f, 0.0f, 1.0f);
-  walk_group<G>(v, s, tf, mc, r, eval, prep, take, post, acc);
+  walk_group<G>(v, s, tf, mc, r, eval, prep, take, flat, post, acc);
   return make_float4(acc.x, acc.y, acc.z, 1.0f - acc.w);
 }
 

@@ -98,7 +98,11 @@ struct MarchConst {
   float step;
   float ert;        // in (0,1) enables early termination
   int32_t skip;     // nonzero: skip samples in empty blocks
-  int32_t pad;
+  // nonzero (kernels that visit every sample, with the blocks' min/max): a
+  // sample in a block that is empty under the TF and constant over its
+  // footprint takes that constant as its value, without reconstructing it
+  // (every tap of its stencil holds it)
+  int32_t flat;
 };
 
 // ---------------------------------------------------------------------------
@@ -1231,10 +1235,28 @@ struct ChainState {
 // every lane after the chain, `mine` telling whether this lane's sample was
 // composited and `own` the ray's state right after it; prep and post as in
 // walk.  acc carries the ray's (C0, C1, C2, T) in and out.
-template <int G, class Eval, class Prep, class Take, class Post>
+//
+// FLAT (kernels that visit every sample, mc.flat set): a sample in a block
+// that is empty under the TF and constant over its footprint is not
+// evaluated; its value is that constant and it changes neither colour nor
+// transmittance, so the ray's samples in such a block form a run of identical
+// samples in an unchanging state.  flat(n, own, value) accounts for n of them
+// at once: each lane for its own sample of a step, and when no lane of the
+// wavefront has a sample to evaluate the wavefront leaps (as over empty
+// blocks) and the first lane of each group with a flat sample also accounts
+// for the indices the leap passes over -- every one inside that lane's block
+// (the leap ends at or before its block's exit) and not past the ray's end.
+// Every lattice index is accounted exactly once.
+struct NoFlat {
+  __device__ inline void operator()(int, const ChainState &, float) const {}
+};
+
+template <int G, bool FLAT = false, class Eval, class Prep, class Take, class Flat, class Post>
 __device__ inline void walk_group(const VolConst &v, const TfShared &s, const TfConst &tf, const MarchConst &mc,
-                                  const Ray &r, Eval &eval, Prep &prep, Take &take, Post &post, float4 &acc) {
-  const int j = (int)(threadIdx.x % kWaveSize) % G;  // this lane's place in its group
+                                  const Ray &r, Eval &eval, Prep &prep, Take &take, Flat &flat, Post &post,
+                                  float4 &acc) {
+  const int lane = (int)(threadIdx.x % kWaveSize);
+  const int j = lane % G;  // this lane's place in its group
   const bool ert_on = mc.ert > 0.0f && mc.ert < 1.0f;
   float C0 = acc.x, C1 = acc.y, C2 = acc.z, T = acc.w;
   const int kb = r.hit ? r.k0 : 0x7fffffff;
@@ -1246,43 +1268,75 @@ __device__ inline void walk_group(const VolConst &v, const TfShared &s, const Tf
   VolConst vg = v;
   asm volatile("" : "+v"(vg.nx), "+v"(vg.ny), "+v"(vg.nz), "+v"(vg.edge_shift), "+v"(vg.nbx), "+v"(vg.nby));
   int cur_block = -1;
-  bool cur_occ = false;
+  bool cur_occ = false, cur_flat = false;
+  float cur_value = 0.0f;
   int bc[3] = {0, 0, 0};
+  const bool flat_on = FLAT && mc.flat && !mc.skip;
+  const bool by_block = mc.skip || flat_on;
   while (k < kend) {
     const int kk = k + j;
     const bool in = alive && kk >= kfree && kk < ke;
-    bool want = in;
+    bool want = in, is_flat = false;
     float px, py, pz;
     lattice_point(r, mc.step, kk, px, py, pz);
     const int ix = (int)floorf(px), iy = (int)floorf(py), iz = (int)floorf(pz);
-    if (in && mc.skip) {
+    if (in && by_block) {
       const int b = block_of_cell(vg, ix, iy, iz, bc);
       if (b != cur_block) {
         cur_block = b;
         cur_occ = block_occupied(v, s, tf, b);
+        if constexpr (FLAT) {
+          const float2 mm = v.minmax[b];
+          cur_flat = flat_on && !cur_occ && mm.x == mm.y;
+          cur_value = mm.x;
+        }
       }
-      want = cur_occ;
+      if (mc.skip) want = cur_occ;
+      if constexpr (FLAT) {
+        is_flat = cur_flat;
+        want = want && !is_flat;
+      }
     }
     if (__ballot(want) == 0ull) {
       // no lane takes a sample at k .. k + G - 1: leap to the smallest index
-      // any lane may need (every index below it is known to be unneeded)
-      if (in) kfree = leap_target(vg, r, bc, mc.step, kk, empty_radius(v, cur_block));
-      const int prop = alive && kk < ke ? kfree : 0x7fffffff;
+      // any lane may need (every index below it is known to be unneeded or,
+      // flat, accounted below)
+      int prop = alive && kk < ke ? kfree : 0x7fffffff;
+      if (in) {
+        const int t = leap_target(vg, r, bc, mc.step, kk, empty_radius(v, cur_block));
+        if (is_flat)
+          prop = t;  // (a flat run is accounted, never skipped: kfree stays)
+        else
+          prop = kfree = t;
+      }
       const int m = wave_min_i32(prop);
-      k = m > k + G ? m : k + G;
+      const int knext = m > k + G ? m : k + G;
+      if constexpr (FLAT) {
+        const unsigned long long fm = __ballot(is_flat);
+        if (is_flat) {
+          const unsigned gb = (unsigned)(fm >> (lane - j)) & ((1u << G) - 1u);
+          const bool first = (gb & ((1u << j) - 1u)) == 0u;
+          const int n = 1 + (first ? max(min(knext, ke) - (k + G), 0) : 0);
+          flat(n, ChainState{0.0f, C0, C1, C2, T}, cur_value);
+        }
+      }
+      k = knext;
       continue;
     }
     prep(want, px, py, pz);
     ChainSample q = {0.0f, 0.0f, 0.0f, 1.0f};  // the identity unless taken
     if (want) q = eval(kk, px, py, pz);
-    bool live = alive, mine = false;
+    bool live = alive, mine = false, mine_flat = false;
     ChainState own = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     auto link = [&](auto I_) {
       constexpr int I = decltype(I_)::value;
       const float ei = from_group_lane<G, I>(q.e), xi = from_group_lane<G, I>(q.c0);
       const float yi = from_group_lane<G, I>(q.c1), zi = from_group_lane<G, I>(q.c2);
       const bool at = j == I;
-      if (at) mine = want && live;
+      if (at) {
+        mine = want && live;
+        mine_flat = is_flat && live;
+      }
       const float ee = live ? ei : 1.0f;
       const float ta = T * (1.0f - ee);
       C0 = fmaf(ta, xi, C0);
@@ -1300,6 +1354,8 @@ __device__ inline void walk_group(const VolConst &v, const TfShared &s, const Tf
     }
     alive = live;
     take(mine, own);
+    if constexpr (FLAT)
+      if (mine_flat) flat(1, own, cur_value);
     post();
     k += G;
   }
