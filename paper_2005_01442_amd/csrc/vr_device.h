@@ -1054,11 +1054,19 @@ __device__ inline float transmit(float sigma, float step_log2e) {
 // Empty-space leaping.  Block of the (clamped) cell of p, and the first
 // lattice index that may leave it.
 // ---------------------------------------------------------------------------
-__device__ inline int block_of_cell(const VolConst &v, int ix, int iy, int iz, int bc[3]) {
+__device__ inline void block_coords(const VolConst &v, int ix, int iy, int iz, int bc[3]) {
   bc[0] = min(max(ix, 0), v.nx - 1) >> v.edge_shift;
   bc[1] = min(max(iy, 0), v.ny - 1) >> v.edge_shift;
   bc[2] = min(max(iz, 0), v.nz - 1) >> v.edge_shift;
+}
+
+__device__ inline int block_index(const VolConst &v, const int bc[3]) {
   return bc[0] + v.nbx * (bc[1] + v.nby * bc[2]);
+}
+
+__device__ inline int block_of_cell(const VolConst &v, int ix, int iy, int iz, int bc[3]) {
+  block_coords(v, ix, iy, iz, bc);
+  return block_index(v, bc);
 }
 
 __device__ inline int block_of(const VolConst &v, float px, float py, float pz, int bc[3]) {
@@ -1281,8 +1289,21 @@ __device__ inline void walk_group(const VolConst &v, const TfShared &s, const Tf
     lattice_point(r, mc.step, kk, px, py, pz);
     const int ix = (int)floorf(px), iy = (int)floorf(py), iz = (int)floorf(pz);
     if (in && by_block) {
-      const int b = block_of_cell(vg, ix, iy, iz, bc);
-      if (b != cur_block) {
+      // the adjoint's every-sample walk forms the block's index only when its
+      // coordinates change (measured faster there; the skipping forward
+      // compares indices)
+      int b;
+      bool changed;
+      if constexpr (FLAT) {
+        const int ox = bc[0], oy = bc[1], oz = bc[2];
+        block_coords(vg, ix, iy, iz, bc);
+        changed = cur_block < 0 || bc[0] != ox || bc[1] != oy || bc[2] != oz;
+        b = changed ? block_index(vg, bc) : cur_block;
+      } else {
+        b = block_of_cell(vg, ix, iy, iz, bc);
+        changed = b != cur_block;
+      }
+      if (changed) {
         cur_block = b;
         cur_occ = block_occupied(v, s, tf, b);
         if constexpr (FLAT) {
