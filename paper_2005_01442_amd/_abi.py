@@ -11,7 +11,9 @@ import os
 from ctypes import c_double, c_float, c_int32, c_int64, c_uint64, c_void_p, POINTER
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libvr.so")
+# VR_LIBRARY names another build of the same library (the diagnostics build
+# of paper_2005_01442_amd.timeline); by default the in-tree libvr.so
+LIB_PATH = os.environ.get("VR_LIBRARY") or os.path.join(HERE, "libvr.so")
 
 VR_OK = 0
 STATUS_NAMES = {
@@ -131,6 +133,7 @@ PROTOTYPES = {
     "vr_serve_destroy": ([c_void_p], c_int32),
     "vr_device_status": ([c_void_p], c_int32),
     "vr_probe_stream_read": ([c_void_p, c_uint64, c_void_p, c_void_p], c_int32),
+    "vr_timeline_read": ([c_int32, c_void_p, c_uint64, POINTER(c_uint64)], c_int32),
 }
 
 _lib = None

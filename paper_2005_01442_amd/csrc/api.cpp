@@ -1,6 +1,7 @@
 // api.cpp -- the C ABI of include/vr.h (except serving, in serve.cpp):
 // argument validation, FP64 camera constants, launch configuration and
 // error reporting.  Kernels live in the .hip files.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdlib>
@@ -11,6 +12,7 @@
 
 #include "vr.h"
 #include "vr_internal.h"
+#include "vr_timeline.h"
 
 struct vr_blocks {
   const void *data;
@@ -527,6 +529,26 @@ vr_status vr_prefilter_bspline(const vr_volume *vol, float *coeff_out, void *str
   (void)hipFreeAsync(dcoef, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "prefilter launch");
   return VR_OK;
+}
+
+vr_status vr_timeline_read(int32_t kernel, uint64_t *host_out, uint64_t max_records, uint64_t *n_records) {
+#ifdef VR_TIMELINE
+  if (kernel != VR_TIMELINE_FORWARD && kernel != VR_TIMELINE_ADJOINT)
+    return fail(VR_E_INVALID_ARG, "unknown timeline kernel %d", kernel);
+  if (!host_out || !n_records) return fail(VR_E_INVALID_ARG, "host_out and n_records are required");
+  const int64_t max = (int64_t)std::min<uint64_t>(max_records, (uint64_t)kTimelineWaves);
+  unsigned long long *h = reinterpret_cast<unsigned long long *>(host_out);
+  const int64_t n = kernel == VR_TIMELINE_FORWARD ? timeline_copy_fwd(h, max) : timeline_copy_bwd(h, max);
+  if (n < 0) return fail(VR_E_DEVICE, "timeline copy failed");
+  *n_records = (uint64_t)n;
+  return VR_OK;
+#else
+  (void)kernel;
+  (void)host_out;
+  (void)max_records;
+  (void)n_records;
+  return fail(VR_E_UNSUPPORTED, "this library keeps no timeline (built without VR_TIMELINE)");
+#endif
 }
 
 vr_status vr_render_backward(const vr_volume *vol, const vr_blocks *blocks, const vr_camera *cams, int32_t n_cams,

@@ -11,6 +11,8 @@
 // arithmetic, so C_{<=k}, T_k and the early-termination sample are the
 // forward's; C_end and T_end come from the saved forward image.  Nothing per
 // sample is stored.
+#include <algorithm>
+
 #include "vr_internal.h"
 
 namespace vr {
@@ -391,12 +393,20 @@ __device__ inline void march_backward(const VolConst &v, const TfShared &s, floa
   if (grad_vol) box_flush(box, grad_vol, v);
 }
 
+#ifdef VR_TIMELINE
+__device__ unsigned long long g_timeline_bwd[kTimelineWaves * 4];
+static int64_t g_timeline_bwd_records = 0;
+#endif
+
 // LDS holds two workgroups per CU (two wavefronts per SIMD): 256 registers.
 template <int DT>
 __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_render_bwd(
     const BackwardArgs args) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const BackwardArgs &a = kernarg<BackwardArgs>();
+#ifdef VR_TIMELINE
+  const unsigned long long tl0 = __builtin_amdgcn_s_memrealtime();
+#endif
   const RenderArgs &ra = a.r;
   int part;
   SuperTile st = group_tile_of<kBwdRayGroup>(ra.order, blockIdx.x, ra.W, ra.H, ra.n_views, ra.chunk_edge, part);
@@ -450,6 +460,13 @@ __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(2, 2)))
   }
   __amdgpu_buffer_rsrc_t rs = make_rsrc(ra.vol.data, ra.vol.bytes);
   march_backward<kBwdRayGroup, DT>(ra.vol, s, sgtf, box, ra.tf, ra.mc, r, rs, g, fin, a.grad_vol);
+#ifdef VR_TIMELINE
+  {
+    const int tx = (ra.W + kSuperEdge - 1) / kSuperEdge, ty = (ra.H + kSuperEdge - 1) / kSuperEdge;
+    timeline_record(g_timeline_bwd, tl0, st.view * tx * ty + st.sy * tx + st.sx,
+                    (threadIdx.x % kBwdRayGroup) == 0 ? (uint32_t)r.ns : 0u);
+  }
+#endif
   if (sgtf) {
     __syncthreads();
     for (int j = threadIdx.x; j < 4 * K; j += kWgSize) {
@@ -463,6 +480,9 @@ hipError_t launch_render_backward(const BackwardArgs &a0, hipStream_t s) {
   BackwardArgs a = a0;
   const RenderArgs &ra = a.r;
   const int64_t grid = group_grid(render_grid(ra), kBwdRayGroup);
+#ifdef VR_TIMELINE
+  g_timeline_bwd_records = grid * (kWgSize / kWaveSize);
+#endif
   uint32_t lds = tf_lds_bytes(ra.tf.K) + (a.grad_tf ? (uint32_t)ra.tf.K * 16u : 0u);
   const uint32_t box_bytes = (uint32_t)(kWgSize / kWaveSize) * (kBoxCells + kWaveSize * kRec) * 4u;
   const uint32_t with_box = box_lds_offset(ra.tf.K, a.grad_tf != nullptr) + box_bytes;
@@ -484,5 +504,15 @@ hipError_t launch_render_backward(const BackwardArgs &a0, hipStream_t s) {
   }
   return hipGetLastError();
 }
+
+#ifdef VR_TIMELINE
+int64_t timeline_copy_bwd(unsigned long long *host, int64_t max) {
+  const int64_t n = std::min<int64_t>(std::min<int64_t>(g_timeline_bwd_records, kTimelineWaves), max);
+  if (hipDeviceSynchronize() != hipSuccess) return -1;
+  if (n > 0 && hipMemcpyFromSymbol(host, HIP_SYMBOL(g_timeline_bwd), (size_t)n * 4 * sizeof(unsigned long long)) != hipSuccess)
+    return -1;
+  return g_timeline_bwd_records;
+}
+#endif
 
 }  // namespace vr

@@ -5,6 +5,8 @@
 // the scalar with the tricubic B-spline, classify through the TF
 // (post-classification), composite front to back, stop once the opacity
 // reaches the threshold, and leap over blocks that cannot be visible.
+#include <algorithm>
+
 #include "vr_internal.h"
 
 namespace vr {
@@ -146,11 +148,19 @@ int32_t occupancy_lds_words(const RenderArgs &a, uint32_t lds) {
   const int64_t words = ((int64_t)a.vol.nbx * a.vol.nby * a.vol.nbz + 31) / 32;
   return (int64_t)lds + words * 4 <= (int64_t)(kLdsPerCu / kFwdWgPerCu) ? (int32_t)words : 0;
 }
+#ifdef VR_TIMELINE
+__device__ unsigned long long g_timeline_fwd[kTimelineWaves * 4];
+static int64_t g_timeline_fwd_records = 0;
+#endif
+
 template <int DT, bool SHADE, int F>
 __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(SHADE ? VR_FWD_MAX_WAVES : VR_FWD_MIN_WAVES, VR_FWD_MAX_WAVES)))
 void k_render(const RenderArgs args) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const RenderArgs &a = kernarg<RenderArgs>();
+#ifdef VR_TIMELINE
+  const unsigned long long tl0 = __builtin_amdgcn_s_memrealtime();
+#endif
   int part;
   SuperTile st = group_tile_of<kRayGroup>(a.order, blockIdx.x, a.W, a.H, a.n_views, a.chunk_edge, part);
   if (!st.valid) return;  // uniform over the workgroup
@@ -197,6 +207,11 @@ void k_render(const RenderArgs args) {
     wave_count(a.counters + 2, lead && r.hit ? 1u : 0u);
     wave_count(a.counters + 3, unstaged);
   }
+#ifdef VR_TIMELINE
+  timeline_record(g_timeline_fwd, tl0, st.view * ((a.W + kSuperEdge - 1) / kSuperEdge) * ((a.H + kSuperEdge - 1) / kSuperEdge) +
+                                           st.sy * ((a.W + kSuperEdge - 1) / kSuperEdge) + st.sx,
+                  evaluated);
+#endif
 }
 
 template <bool SHADE, int F>
@@ -345,6 +360,9 @@ hipError_t launch_render(const RenderArgs &a0, hipStream_t s) {
   a.occ_lds_words = occupancy_lds_words(a, lds);
   lds += (uint32_t)a.occ_lds_words * 4u;
   if (a.vol.dtype != kU16 && a.vol.dtype != kI16 && a.vol.dtype != kF32) return hipErrorInvalidValue;
+#ifdef VR_TIMELINE
+  g_timeline_fwd_records = grid * (kWgSize / kWaveSize);
+#endif
   if (a.shaded) return launch_render_as<true, 0>(a, grid, lds, s);
   if (a.filter == 1) return launch_render_as<false, 1>(a, grid, lds, s);
   if (a.filter == 2) return launch_render_as<false, 2>(a, grid, lds, s);
@@ -410,5 +428,15 @@ hipError_t launch_serve_batch(const ServeSlot *slots_dev, const ServeItem *items
                      max_tf_k, use_box, samples);
   return hipGetLastError();
 }
+
+#ifdef VR_TIMELINE
+int64_t timeline_copy_fwd(unsigned long long *host, int64_t max) {
+  const int64_t n = std::min<int64_t>(std::min<int64_t>(g_timeline_fwd_records, kTimelineWaves), max);
+  if (hipDeviceSynchronize() != hipSuccess) return -1;
+  if (n > 0 && hipMemcpyFromSymbol(host, HIP_SYMBOL(g_timeline_fwd), (size_t)n * 4 * sizeof(unsigned long long)) != hipSuccess)
+    return -1;
+  return g_timeline_fwd_records;
+}
+#endif
 
 }  // namespace vr

@@ -1526,6 +1526,25 @@ template <class T> __device__ inline const T &kernarg() {
   return *(const T *)__builtin_amdgcn_kernarg_segment_ptr();
 }
 
+// Diagnostics (a library built with VR_TIMELINE): lane 0 of every wavefront
+// writes its record (start, end, super-tile << 32 | HW_ID, work) into `tl`.
+constexpr int kTimelineWaves = 1 << 17;
+#ifdef VR_TIMELINE
+__device__ inline void timeline_record(unsigned long long *tl, unsigned long long t0, int tile, uint32_t work) {
+  for (int off = 32; off > 0; off >>= 1) work += __shfl_xor(work, off, kWaveSize);
+  const unsigned long long t1 = __builtin_amdgcn_s_memrealtime();
+  const size_t w = (size_t)blockIdx.x * (kWgSize / kWaveSize) + threadIdx.x / kWaveSize;
+  if (threadIdx.x % kWaveSize == 0 && w < (size_t)kTimelineWaves) {
+    unsigned hw;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_HW_ID)" : "=s"(hw));
+    tl[w * 4 + 0] = t0;
+    tl[w * 4 + 1] = t1;
+    tl[w * 4 + 2] = ((unsigned long long)(unsigned)tile << 32) | hw;
+    tl[w * 4 + 3] = work;
+  }
+}
+#endif
+
 // Sum a per-lane count over the wavefront and add it to a 64-bit counter.
 __device__ inline void wave_count(unsigned long long *ctr, uint32_t v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWaveSize);

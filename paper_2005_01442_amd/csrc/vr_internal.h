@@ -157,6 +157,14 @@ uint64_t bricked_device_bytes(const vr_bricked *v);
 BrickArena *brick_arena_new(char *mem, uint64_t bytes);
 void brick_arena_delete(BrickArena *a);
 
+#ifdef VR_TIMELINE
+// Records of the last launch of the forward / the adjoint (render_fwd.hip,
+// render_bwd.hip): copy up to `max` records into host memory after a device
+// synchronisation; return the launch's record count, or -1.
+int64_t timeline_copy_fwd(unsigned long long *host, int64_t max);
+int64_t timeline_copy_bwd(unsigned long long *host, int64_t max);
+#endif
+
 // Device address of the current device's TF status word (device_state.hip),
 // nullptr when it cannot be obtained.
 uint32_t *tf_status_word();

@@ -125,6 +125,16 @@ def test_validation_without_device(abi):
     assert rc == 1 and b"power of two" in L.vr_last_error()
 
 
+def test_timeline_only_in_the_diagnostics_build(abi):
+    """The product library keeps no per-wavefront timeline."""
+    L = abi.lib()
+    n = ctypes.c_uint64(7)
+    buf = (ctypes.c_uint64 * 8)()
+    assert L.vr_timeline_read(0, ctypes.cast(buf, ctypes.c_void_p), 2, ctypes.byref(n)) == 2  # VR_E_UNSUPPORTED
+    assert b"VR_TIMELINE" in L.vr_last_error()
+    assert n.value == 7
+
+
 def test_serve_config_validation_without_device(abi):
     L = abi.lib()
     out = ctypes.c_void_p()
