@@ -504,6 +504,15 @@ vr_status vr_serve_destroy(vr_server *s);
  * Errors: VR_E_DEVICE. */
 vr_status vr_device_status(void *stream);
 
+/* A render allocates per call (stream-ordered) its blocks' occupancy bits
+ * under the TF and its workgroup order; when one of them cannot be allocated
+ * or built, the call still succeeds with the same image on a slower path
+ * (occupancy decided from min/max on every block change; workgroups in
+ * Morton order).  These counters, process-wide since load, say how often
+ * that happened (vr_render_noalloc allocates nothing).  occupancy, order:
+ * HOST, one uint64_t each.  Errors: VR_E_INVALID_ARG (null pointers). */
+vr_status vr_fallback_counts(uint64_t *occupancy, uint64_t *order);
+
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char *vr_last_error(void);
 

@@ -227,6 +227,14 @@ def device_status(stream=None):
     check(lib().vr_device_status(_stream_ptr(stream)))
 
 
+def fallback_counts():
+    """(occupancy, order): renders that ran a slower path because a per-call
+    buffer could not be allocated or built (``vr_fallback_counts``)."""
+    occ, order = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    check(lib().vr_fallback_counts(ctypes.byref(occ), ctypes.byref(order)))
+    return int(occ.value), int(order.value)
+
+
 def vr_probe_stream_read(buf: torch.Tensor, sink: torch.Tensor, stream=None):
     """Stream-read the whole of the contiguous CUDA tensor ``buf`` once with
     16-byte loads, folding it into ``sink`` (an int32 CUDA tensor of one

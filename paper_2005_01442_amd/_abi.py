@@ -134,6 +134,7 @@ PROTOTYPES = {
     "vr_device_status": ([c_void_p], c_int32),
     "vr_probe_stream_read": ([c_void_p, c_uint64, c_void_p, c_void_p], c_int32),
     "vr_timeline_read": ([c_int32, c_void_p, c_uint64, POINTER(c_uint64)], c_int32),
+    "vr_fallback_counts": ([POINTER(c_uint64), POINTER(c_uint64)], c_int32),
 }
 
 _lib = None

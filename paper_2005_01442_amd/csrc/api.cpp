@@ -2,6 +2,7 @@
 // argument validation, FP64 camera constants, launch configuration and
 // error reporting.  Kernels live in the .hip files.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdlib>
@@ -340,6 +341,10 @@ void vr_blocks_free(vr_blocks *b) {
 
 namespace vr {
 
+// Calls that could not allocate or build their per-call occupancy bits or
+// workgroup order and rendered with the slower paths (same result).
+std::atomic<uint64_t> g_fallback_occupancy{0}, g_fallback_order{0};
+
 vr_status render_views(RenderArgs &a, const vr_camera *cams, int32_t n_cams, float *out_rgba, void *stream,
                        const float4 *preint, const RenderScratch *scratch) {
   const size_t view_floats = (size_t)a.W * a.H * 4;
@@ -357,6 +362,7 @@ vr_status render_views(RenderArgs &a, const vr_camera *cams, int32_t n_cams, flo
     } else {
       own_bits = true;
     }
+    if (!bits) g_fallback_occupancy.fetch_add(1, std::memory_order_relaxed);
     if (bits) {
       // (pre-integration leaps block by block: its cells span two blocks)
       if (!preint && occupancy_planes_fit(a.vol, a.tf.K)) {
@@ -368,6 +374,7 @@ vr_status render_views(RenderArgs &a, const vr_camera *cams, int32_t n_cams, flo
         if (own_bits) (void)hipFreeAsync(bits, st);
         bits = nullptr;
         own_bits = false;
+        g_fallback_occupancy.fetch_add(1, std::memory_order_relaxed);
       }
     }
   }
@@ -394,6 +401,7 @@ vr_status render_views(RenderArgs &a, const vr_camera *cams, int32_t n_cams, flo
       a.order = make_tile_order(a, st);
       own_order = a.order != nullptr;
     }
+    if (!a.order) g_fallback_order.fetch_add(1, std::memory_order_relaxed);
     hipError_t e = preint ? launch_render_preint(a, preint, st) : launch_render(a, st);
     if (own_order) (void)hipFreeAsync(const_cast<int32_t *>(a.order), st);
     a.order = nullptr;
@@ -531,6 +539,13 @@ vr_status vr_prefilter_bspline(const vr_volume *vol, float *coeff_out, void *str
   return VR_OK;
 }
 
+vr_status vr_fallback_counts(uint64_t *occupancy, uint64_t *order) {
+  if (!occupancy || !order) return fail(VR_E_INVALID_ARG, "occupancy and order are required");
+  *occupancy = g_fallback_occupancy.load(std::memory_order_relaxed);
+  *order = g_fallback_order.load(std::memory_order_relaxed);
+  return VR_OK;
+}
+
 vr_status vr_timeline_read(int32_t kernel, uint64_t *host_out, uint64_t max_records, uint64_t *n_records) {
 #ifdef VR_TIMELINE
   if (kernel != VR_TIMELINE_FORWARD && kernel != VR_TIMELINE_ADJOINT)
@@ -584,6 +599,7 @@ vr_status vr_render_backward(const vr_volume *vol, const vr_blocks *blocks, cons
     b.use_box = 0;
     b.pad = 0;
     b.r.order = make_tile_order(b.r, st);
+    if (!b.r.order) g_fallback_order.fetch_add(1, std::memory_order_relaxed);
     e = launch_render_backward(b, st);
     if (b.r.order) (void)hipFreeAsync(const_cast<int32_t *>(b.r.order), st);
     b.r.order = nullptr;

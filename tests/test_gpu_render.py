@@ -221,8 +221,11 @@ def test_c1_full_frame_counts_and_invariants():
     log("c1: building full-size inputs")
     v = upload_volume(c["volume"])
     blocks = vr.vr_build_blocks(v, 16)
+    fb0 = vr.fallback_counts()
     img, ctr = gpu_render(None, c["cameras"], c["tf"], c["step"], ert=c["ert"], use_skip=True, counters=True,
                           vol=v, blocks=blocks)
+    # the timed path: occupancy planes and workgroup order were built (no fallback)
+    assert vr.fallback_counts() == fb0
     noskip = gpu_render(None, c["cameras"], c["tf"], c["step"], ert=c["ert"], use_skip=False, vol=v)
     assert np.array_equal(img, noskip)
     noert = gpu_render(None, c["cameras"], c["tf"], c["step"], ert=0.0, use_skip=True, vol=v, blocks=blocks)
