@@ -79,31 +79,36 @@ __device__ inline float reconstruct_slot(const char *slot, int S, int ox, int oy
   return combine(s, t);
 }
 
-// One pass over one view.  Workgroups of 16x16 pixels, taken centre-out when
-// the launch carries the in-core kernel's super-tile order (the tiles whose
-// rays cross the most volume first), else in raster order; wavefronts of 8x8
-// that march their rays in step (the walk of the in-core
-// kernel, started at each ray's saved index): samples in empty bricks are
-// leapt over, samples in resident bricks evaluated from their slot, and a
-// ray parks at its first sample in an occupied brick of a later pass.
+// One pass over one view.  Each ray is marched by a pair of lanes (the group
+// walk of the in-core kernel, resumed at each ray's saved index), a
+// workgroup covers half a 16x16 super-tile, taken centre-out when the launch
+// carries the in-core kernel's super-tile order (the tiles whose rays cross
+// the most volume first), else in Morton-chunk order: samples in empty
+// bricks are leapt over, samples in resident bricks evaluated from their
+// slot, and a ray parks at its first sample in an occupied brick of a later
+// pass (the sample is not composited; the ray resumes there).
 // state: per pixel (C_r, C_g, C_b, T); next: the next lattice index, or -1
 // once the ray is finished.  first: initialise the state instead of reading it.
 // The LDS boxes allow three workgroups per CU; the register budget matches.
+constexpr int kBrickRayGroup = 2;
+
 template <int DT>
 __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_bricked_pass(
     const BrickedArgs args) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
   const BrickedArgs &a = kernarg<BrickedArgs>();
+  int part;
+  const SuperTile tile = group_tile_of<kBrickRayGroup>(a.order, blockIdx.x, a.W, a.H, 1, kDefaultChunkEdge, part);
+  if (!tile.valid) return;  // uniform over the workgroup
   TfShared s = carve_tf(lds, a.tf.K);
   const bool tf_ok = load_tf(s, a.tf);
-  const int tiles_x = (a.W + kSuperEdge - 1) / kSuperEdge;
-  const int q = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
   int col, row;
-  pixel_of(q % tiles_x, q / tiles_x, col, row);
+  group_pixel_of<kBrickRayGroup>(tile.sx, tile.sy, part, col, row);
   const bool inside = col < a.W && row < a.H;
+  const bool lead = (threadIdx.x % kBrickRayGroup) == 0;  // the lane that stores its ray's state
   const size_t pix = inside ? (size_t)row * a.W + col : 0;
   if (!tf_ok) {  // uniform: an invalid TF finishes every ray with NaN
-    if (inside) {
+    if (inside && lead) {
       a.state[pix] = nan_rgba();
       a.next[pix] = -1;
     }
@@ -126,9 +131,7 @@ __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(3, 3)))
   if (active) r = setup_ray(a.cam, col, row, a.vol.nx, a.vol.ny, a.vol.nz, a.mc.step);
   if (a.first) kstart = r.k0;
   const float sl2 = a.mc.step * 1.4426950408889634f;
-  const bool ert_on = a.mc.ert > 0.0f && a.mc.ert < 1.0f;
   const int S = a.slot_edge, E = a.vol.edge;
-  int parked = -1;
   // LDS value box of the wavefront, filled from one slot: the slot holds its
   // footprint edge-clamped, so within the slot's extent no further clamping
   // is needed and the box sees exactly the taps reconstruct_slot reads.
@@ -138,7 +141,7 @@ __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(3, 3)))
   box.cells = a.use_box ? reinterpret_cast<float *>(lds + vbox_lds_offset(a.tf.K)) + (threadIdx.x / kWaveSize) * kVBoxCells
                         : nullptr;
   int box_slot = -1;  // uniform: the slot the box holds
-  int step_brick = -1, step_slot = -1;  // this lane's brick and slot at the current step (prep -> visit)
+  int step_brick = -1, step_slot = -1;  // this lane's brick and slot at the current step (prep -> eval)
   auto prep = [&](bool want, float px, float py, float pz) {
     step_brick = -1;
     step_slot = -1;
@@ -166,14 +169,11 @@ __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(3, 3)))
     vbox_prepare<DT>(box, srs, sv, r, want, px - (float)(bx * E - 1), py - (float)(by * E - 1),
                      pz - (float)(bz * E - 1));
   };
-  auto visit = [&](int k, float px, float py, float pz) -> bool {
-    int bc[3];
-    const int b = block_of(a.vol, px, py, pz, bc);
+  auto eval = [&](int, float px, float py, float pz) -> ChainSample {
     const int slot = step_slot;
-    if (slot < 0) {  // a later pass holds this brick
-      parked = k;
-      return false;
-    }
+    if (slot < 0) return ChainSample{0.0f, 0.0f, 0.0f, kStopSample};  // a later pass holds this brick
+    int bc[3];
+    block_of(a.vol, px, py, pz, bc);
     Stencil sten = make_stencil(px, py, pz);
     const int ox = bc[0] * E - 1, oy = bc[1] * E - 1, oz = bc[2] * E - 1;
     float val;
@@ -186,21 +186,17 @@ __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(3, 3)))
       val = reconstruct_slot<DT>(a.pool + (size_t)slot * a.slot_bytes, S, ox, oy, oz, a.vol.nx, a.vol.ny, a.vol.nz,
                                  sten);
     }
-    (void)b;
     const Classified q = classify(s, a.tf.K, a.tf.v0, a.tf.scale, val);
-    const float e = transmit(q.c.w, sl2);
-    const float ta = st.w * (1.0f - e);
-    st.x = fmaf(ta, q.c.x, st.x);
-    st.y = fmaf(ta, q.c.y, st.y);
-    st.z = fmaf(ta, q.c.z, st.z);
-    st.w = st.w * e;
-    return !(ert_on && (1.0f - st.w) >= a.mc.ert);
+    return ChainSample{q.c.x, q.c.y, q.c.z, transmit(q.c.w, sl2)};
   };
+  auto take = [](bool, const ChainState &) {};
+  NoFlat flat;
   NoPost post;
   // skipping on the fine blocks; the brick of a sample to evaluate decides
   // whether this pass has it
-  walk<decltype(visit), decltype(prep), NoPost, true>(a.fine, s, a.tf, a.mc, r, visit, prep, post, kstart);
-  if (active) {
+  const int parked = walk_group<kBrickRayGroup, false, true>(a.fine, s, a.tf, a.mc, r, eval, prep, take, flat, post,
+                                                              st, kstart);
+  if (active && lead) {
     a.state[pix] = st;
     a.next[pix] = parked;
   }
@@ -227,10 +223,11 @@ hipError_t launch_bricked_pass(const BrickedArgs &a0, hipStream_t s) {
                                          : reinterpret_cast<const void *>(&k_bricked_pass<kF32>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
+  const int64_t grid = group_grid(a.order ? (int64_t)tiles : grid_size_for(a.W, a.H, 1, kDefaultChunkEdge), kBrickRayGroup);
   switch (a.vol.dtype) {
-  case kU16: hipLaunchKernelGGL(k_bricked_pass<kU16>, dim3((unsigned)tiles), dim3(kWgSize), lds, s, a); break;
-  case kI16: hipLaunchKernelGGL(k_bricked_pass<kI16>, dim3((unsigned)tiles), dim3(kWgSize), lds, s, a); break;
-  default: hipLaunchKernelGGL(k_bricked_pass<kF32>, dim3((unsigned)tiles), dim3(kWgSize), lds, s, a); break;
+  case kU16: hipLaunchKernelGGL(k_bricked_pass<kU16>, dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
+  case kI16: hipLaunchKernelGGL(k_bricked_pass<kI16>, dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
+  default: hipLaunchKernelGGL(k_bricked_pass<kF32>, dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
   }
   return hipGetLastError();
 }

@@ -1259,15 +1259,24 @@ struct NoFlat {
   __device__ inline void operator()(int, const ChainState &, float) const {}
 };
 
-template <int G, bool FLAT = false, class Eval, class Prep, class Take, class Flat, class Post>
-__device__ inline void walk_group(const VolConst &v, const TfShared &s, const TfConst &tf, const MarchConst &mc,
-                                  const Ray &r, Eval &eval, Prep &prep, Take &take, Flat &flat, Post &post,
-                                  float4 &acc) {
+//
+// STOP: a sample whose eval returns a negative transmittance (kStopSample)
+// stops its ray before it: it is not composited, nor is any later sample of
+// its step, and walk_group returns its index (else -1) -- a pass that does
+// not hold the sample's data parks the ray there.  kstart >= 0 resumes a ray
+// at lattice index max(k0, kstart).
+constexpr float kStopSample = -1.0f;
+
+template <int G, bool FLAT = false, bool STOP = false, class Eval, class Prep, class Take, class Flat, class Post>
+__device__ inline int walk_group(const VolConst &v, const TfShared &s, const TfConst &tf, const MarchConst &mc,
+                                 const Ray &r, Eval &eval, Prep &prep, Take &take, Flat &flat, Post &post,
+                                 float4 &acc, int kstart = -1) {
   const int lane = (int)(threadIdx.x % kWaveSize);
   const int j = lane % G;  // this lane's place in its group
   const bool ert_on = mc.ert > 0.0f && mc.ert < 1.0f;
   float C0 = acc.x, C1 = acc.y, C2 = acc.z, T = acc.w;
-  const int kb = r.hit ? r.k0 : 0x7fffffff;
+  int stopped = -1;
+  const int kb = r.hit ? (kstart >= 0 ? max(r.k0, kstart) : r.k0) : 0x7fffffff;
   const int ke = r.hit ? r.k0 + r.ns : 0;
   bool alive = r.hit;
   int k = wave_min_i32(kb);
@@ -1354,6 +1363,12 @@ __device__ inline void walk_group(const VolConst &v, const TfShared &s, const Tf
       const float ei = from_group_lane<G, I>(q.e), xi = from_group_lane<G, I>(q.c0);
       const float yi = from_group_lane<G, I>(q.c1), zi = from_group_lane<G, I>(q.c2);
       const bool at = j == I;
+      if constexpr (STOP) {
+        if (ei < 0.0f && live) {  // kStopSample: the ray stops before this sample
+          stopped = k + I;
+          live = false;
+        }
+      }
       if (at) {
         mine = want && live;
         mine_flat = is_flat && live;
@@ -1381,6 +1396,7 @@ __device__ inline void walk_group(const VolConst &v, const TfShared &s, const Tf
     k += G;
   }
   acc = make_float4(C0, C1, C2, T);
+  return stopped;
 }
 
 __device__ inline bool block_occupied(const VolConst &v, const TfShared &s, const TfConst &tf, int b) {
