@@ -785,7 +785,7 @@ __device__ inline float4 combine_grad(const StencilG &g, const float t[4][4][4])
 #define VR_VBOX_EDGE 14
 #endif
 #ifndef VR_VBOX_ZPAD
-#define VR_VBOX_ZPAD 4
+#define VR_VBOX_ZPAD 2  // z stride 198 (C1 with ray pairs: 0 or 2 1.297 ms, 4 1.320, 6 1.61)
 #endif
 constexpr int kVBox = VR_VBOX_EDGE;
 constexpr int kVBoxZ = kVBox * kVBox + VR_VBOX_ZPAD;  // padded z stride (LDS banks)
