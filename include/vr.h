@@ -215,7 +215,7 @@ vr_status vr_render(const vr_volume *vol, const vr_blocks *blocks, const vr_came
  * graph capture, tight serving loops, harnesses that forbid allocation.
  * Arguments, results and errors as vr_render (the image is bit-identical);
  * nothing is allocated: the per-launch workgroup order and the occupancy
- * planes of the block grid live in a 2 MiB scratch array the library keeps
+ * planes of the block grid live in a 2 MiB (+ 1 KiB) scratch array the library keeps
  * in device memory on every GPU it runs on (until the process ends).
  * Limits: a view of at most 262,144 16x16 tiles (8192 x 8192 pixels; views
  * are launched as many at a time as the scratch orders), and with

@@ -385,7 +385,7 @@ vr_status render_views(RenderArgs &a, const vr_camera *cams, int32_t n_cams, flo
   int32_t per_launch = kMaxCamsPerLaunch;
   if (scratch) {
     const int64_t tiles = (int64_t)((a.W + kSuperEdge - 1) / kSuperEdge) * ((a.H + kSuperEdge - 1) / kSuperEdge);
-    per_launch = (int32_t)std::min<int64_t>(kMaxCamsPerLaunch, scratch->order_ints / tiles);
+    per_launch = (int32_t)std::min<int64_t>(kMaxCamsPerLaunch, (scratch->order_ints - kOrderQueueInts) / tiles);
   }
   vr_status result = VR_OK;
   for (int32_t v0 = 0; v0 < n_cams; v0 += per_launch) {

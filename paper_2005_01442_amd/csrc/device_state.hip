@@ -16,13 +16,14 @@ namespace vr {
 
 __device__ uint32_t g_tf_status;
 
-// Scratch of vr_render_noalloc: the workgroup order of one launch (the first
-// kScratchOrderInts words) and the block grid's occupancy planes (the rest).
+// Scratch of vr_render_noalloc: the workgroup order of one launch with its
+// work-queue counters (the first kScratchOrderInts words) and the block grid's
+// occupancy planes (the rest).
 // Each GPU holds its own copy until the process ends.  Host code uses it only
 // through the per-device address hipGetSymbolAddress returns (the array's
 // name on the host is a stand-in, not a device address).
-constexpr size_t kScratchBytes = 2u << 20;
-constexpr int64_t kScratchOrderInts = 1 << 18;  // 1 MiB: 262,144 super-tiles per launch
+constexpr int64_t kScratchOrderInts = (1 << 18) + kOrderQueueInts;  // 262,144 super-tiles per launch
+constexpr size_t kScratchBytes = (1u << 20) + (size_t)kScratchOrderInts * 4;  // 1 MiB of occupancy planes
 constexpr size_t kScratchOccBytes = kScratchBytes - (size_t)kScratchOrderInts * 4;
 static __device__ __align__(256) uint32_t scratch[kScratchBytes / 4];
 
@@ -98,10 +99,10 @@ extern "C" vr_status vr_render_noalloc(const vr_volume *vol, const vr_blocks *bl
   if (s) return s;
   if (!out_rgba) return fail(VR_E_INVALID_ARG, "out_rgba is NULL");
   const int64_t tiles = (int64_t)((a.W + kSuperEdge - 1) / kSuperEdge) * ((a.H + kSuperEdge - 1) / kSuperEdge);
-  if (tiles > kScratchOrderInts)
+  if (tiles > kScratchOrderInts - kOrderQueueInts)
     return fail(VR_E_INVALID_ARG,
                 "vr_render_noalloc: a %dx%d view has %lld 16x16 tiles; its scratch orders at most %lld per launch",
-                a.W, a.H, (long long)tiles, (long long)kScratchOrderInts);
+                a.W, a.H, (long long)tiles, (long long)(kScratchOrderInts - kOrderQueueInts));
   if (a.mc.skip && occupancy_bytes(a.vol) > kScratchOccBytes)
     return fail(VR_E_INVALID_ARG,
                 "vr_render_noalloc: %lld blocks need %zu bytes of occupancy planes; its scratch holds %zu",

@@ -156,23 +156,20 @@ __device__ unsigned long long g_timeline_fwd[kTimelineWaves * 4];
 static int64_t g_timeline_fwd_records = 0;
 #endif
 
+// One wavefront item: wavefront w of workgroup item i (a part of a
+// super-tile); the counts of its samples are added to the caller's.
 template <int DT, bool SHADE, int F>
-__global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(SHADE ? VR_FWD_MAX_WAVES : (DT == kF32 ? 1 : VR_FWD_MIN_WAVES), VR_FWD_MAX_WAVES)))
-void k_render(const RenderArgs args) {
-  extern __shared__ __attribute__((aligned(16))) char lds[];
-  const RenderArgs &a = kernarg<RenderArgs>();
+__device__ inline void render_wave_item(const RenderArgs &a, const TfShared &s, bool tf_ok, ValBox &box,
+                                        __amdgpu_buffer_rsrc_t rs, int64_t i, int w, uint32_t &evaluated,
+                                        uint32_t &unstaged, uint32_t &lattice, uint32_t &hits) {
 #ifdef VR_TIMELINE
   const unsigned long long tl0 = __builtin_amdgcn_s_memrealtime();
 #endif
   int part;
-  SuperTile st = group_tile_of<kRayGroup>(a.order, blockIdx.x, a.W, a.H, a.n_views, a.chunk_edge, part);
-  if (!st.valid) return;  // uniform over the workgroup
-  TfShared s = carve_tf(lds, a.tf.K);
-  if (a.occ_lds_words > 0)
-    stage_occupancy(s, a.vol, lds + vbox_lds_offset(a.tf.K) + vbox_lds_bytes(), a.occ_lds_words);
-  const bool tf_ok = load_tf(s, a.tf);
+  const SuperTile st = group_tile_of<kRayGroup>(a.order, i, a.W, a.H, a.n_views, a.chunk_edge, part);
+  if (!st.valid) return;  // uniform over the wavefront
   int col, row;
-  group_pixel_of<kRayGroup>(st.sx, st.sy, part, col, row);
+  group_pixel_of<kRayGroup>(st.sx, st.sy, part, w * kWaveSize + (int)(threadIdx.x % kWaveSize), col, row);
   const bool inside = col < a.W && row < a.H;
   const bool lead = (threadIdx.x % kRayGroup) == 0;  // the lane that stores its group's pixel
   if (!tf_ok) {  // uniform: an invalid TF gives NaN pixels
@@ -180,7 +177,6 @@ void k_render(const RenderArgs args) {
     return;
   }
   const CamConst &cam = a.cams[st.view];
-  uint32_t evaluated = 0, unstaged = 0;
   // every lane enters the march (it steps the wavefront in unison); pixels
   // outside the image carry an empty ray
   Ray r;
@@ -188,13 +184,9 @@ void k_render(const RenderArgs args) {
   r.ns = 0;
   r.k0 = 0;
   if (inside) r = setup_ray(cam, col, row, a.vol.nx, a.vol.ny, a.vol.nz, a.mc.step);
-  __amdgpu_buffer_rsrc_t rs = make_rsrc(a.vol.data, a.vol.bytes);
-  ValBox box;
-  box.valid = false;
-  box.ox = box.oy = box.oz = 0;
-  box.cells = a.use_box ? reinterpret_cast<float *>(lds + vbox_lds_offset(a.tf.K)) +
-                              (threadIdx.x / kWaveSize) * kVBoxCells
-                        : nullptr;
+#ifdef VR_TIMELINE
+  const uint32_t before = evaluated;
+#endif
   float4 rgba;
   if constexpr (kRayGroup == 1)
     rgba = march<DT, SHADE, F>(a.vol, s, a.tf, a.mc, a.shade, r, rs, box, evaluated, unstaged);
@@ -204,26 +196,88 @@ void k_render(const RenderArgs args) {
     float4 *o = reinterpret_cast<float4 *>(a.out);
     o[((size_t)st.view * a.H + row) * a.W + col] = rgba;
   }
-  if (a.counters) {
-    wave_count(a.counters + 0, evaluated);
-    wave_count(a.counters + 1, lead ? (uint32_t)r.ns : 0u);
-    wave_count(a.counters + 2, lead && r.hit ? 1u : 0u);
-    wave_count(a.counters + 3, unstaged);
-  }
+  lattice += lead ? (uint32_t)r.ns : 0u;
+  hits += lead && r.hit ? 1u : 0u;
 #ifdef VR_TIMELINE
-  timeline_record(g_timeline_fwd, tl0, st.view * ((a.W + kSuperEdge - 1) / kSuperEdge) * ((a.H + kSuperEdge - 1) / kSuperEdge) +
-                                           st.sy * ((a.W + kSuperEdge - 1) / kSuperEdge) + st.sx,
-                  evaluated);
+  const int tx = (a.W + kSuperEdge - 1) / kSuperEdge, ty = (a.H + kSuperEdge - 1) / kSuperEdge;
+  timeline_record(g_timeline_fwd, (size_t)i * kWavesPerWg + w, tl0, st.view * tx * ty + st.sy * tx + st.sx,
+                  evaluated - before);
 #endif
 }
 
+template <int DT, bool SHADE, int F>
+__global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(SHADE ? VR_FWD_MAX_WAVES : (DT == kF32 ? 1 : VR_FWD_MIN_WAVES), VR_FWD_MAX_WAVES)))
+void k_render(const RenderArgs args) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const RenderArgs &a = kernarg<RenderArgs>();
+  if (!a.queue) {  // one workgroup item per workgroup
+    int part;
+    if (!group_tile_of<kRayGroup>(a.order, blockIdx.x, a.W, a.H, a.n_views, a.chunk_edge, part).valid)
+      return;  // uniform over the workgroup
+  }
+  TfShared s = carve_tf(lds, a.tf.K);
+  if (a.occ_lds_words > 0)
+    stage_occupancy(s, a.vol, lds + vbox_lds_offset(a.tf.K) + vbox_lds_bytes(), a.occ_lds_words);
+  const bool tf_ok = load_tf(s, a.tf);
+  __amdgpu_buffer_rsrc_t rs = make_rsrc(a.vol.data, a.vol.bytes);
+  // the wavefront's LDS value box (its contents stay valid from one item to
+  // the next: the volume is the launch's)
+  ValBox box;
+  box.valid = false;
+  box.ox = box.oy = box.oz = 0;
+  box.cells = a.use_box ? reinterpret_cast<float *>(lds + vbox_lds_offset(a.tf.K)) +
+                              (threadIdx.x / kWaveSize) * kVBoxCells
+                        : nullptr;
+  uint32_t evaluated = 0, unstaged = 0, lattice = 0, hits = 0;
+  if (!a.queue) {
+    render_wave_item<DT, SHADE, F>(a, s, tf_ok, box, rs, blockIdx.x, (int)(threadIdx.x / kWaveSize), evaluated,
+                                   unstaged, lattice, hits);
+  } else {
+    int x = (int)(blockIdx.x % kXcds), tried = 0, w = 0;
+    int64_t i = 0;
+    while (next_wave_item(a.queue, (uint32_t)a.queue_items, x, tried, i, w))
+      render_wave_item<DT, SHADE, F>(a, s, tf_ok, box, rs, i, w, evaluated, unstaged, lattice, hits);
+  }
+  if (a.counters) {
+    wave_count(a.counters + 0, evaluated);
+    wave_count(a.counters + 1, lattice);
+    wave_count(a.counters + 2, hits);
+    wave_count(a.counters + 3, unstaged);
+  }
+}
+
+// Workgroups of `fn` the current device holds at once with `lds` bytes of
+// LDS each (0 when it cannot be found out).
+int64_t resident_workgroups(const void *fn, uint32_t lds) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, kWgSize, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return (int64_t)cus * per;
+}
+
 template <bool SHADE, int F>
-static hipError_t launch_render_as(const RenderArgs &a, int64_t grid, uint32_t lds, hipStream_t s) {
+static hipError_t launch_render_as(const RenderArgs &a0, int64_t grid, uint32_t lds, hipStream_t s) {
+  RenderArgs a = a0;
   const void *fn = a.vol.dtype == kU16   ? reinterpret_cast<const void *>(&k_render<kU16, SHADE, F>)
                    : a.vol.dtype == kI16 ? reinterpret_cast<const void *>(&k_render<kI16, SHADE, F>)
                                          : reinterpret_cast<const void *>(&k_render<kF32, SHADE, F>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
+  // with an order (and its queue counters) the launch is queued: as many
+  // workgroups as the device holds, fed wavefront items
+  a.queue = nullptr;
+  a.queue_items = 0;
+  if (a.order) {
+    const int64_t resident = resident_workgroups(fn, lds);
+    if (resident > 0 && resident < grid) {
+      a.queue = reinterpret_cast<uint32_t *>(const_cast<int32_t *>(a.order) + tile_order_count(a));
+      a.queue_items = (int32_t)(grid / kXcds * kWavesPerWg);
+      grid = resident;
+    }
+  }
   switch (a.vol.dtype) {
   case kU16: hipLaunchKernelGGL((k_render<kU16, SHADE, F>), dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
   case kI16: hipLaunchKernelGGL((k_render<kI16, SHADE, F>), dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
@@ -268,6 +322,7 @@ __global__ __launch_bounds__(kOrderThreads) void k_tile_order(const OrderArgs o,
   __shared__ int cnt[kOrderKeys];
   const int n = o.n_views * o.tx * o.ty;
   for (int i = threadIdx.x; i < kOrderKeys; i += kOrderThreads) cnt[i] = 0;
+  for (int i = threadIdx.x; i < (int)kOrderQueueInts; i += kOrderThreads) order[n + i] = 0;  // queue counters
   __syncthreads();
   for (int q = threadIdx.x; q < n; q += kOrderThreads) atomicAdd(&cnt[order_key(o, q)], 1);
   __syncthreads();
@@ -345,7 +400,8 @@ int64_t tile_order_count(const RenderArgs &a) {
 
 int32_t *make_tile_order(const RenderArgs &a, hipStream_t s) {
   int32_t *order = nullptr;
-  if (hipMallocAsync((void **)&order, (size_t)tile_order_count(a) * sizeof(int32_t), s) != hipSuccess) return nullptr;
+  if (hipMallocAsync((void **)&order, (size_t)(tile_order_count(a) + kOrderQueueInts) * sizeof(int32_t), s) != hipSuccess)
+    return nullptr;
   if (launch_tile_order(a, order, s) != hipSuccess) {
     (void)hipFreeAsync(order, s);
     return nullptr;

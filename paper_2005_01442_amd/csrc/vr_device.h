@@ -1519,15 +1519,20 @@ __device__ inline SuperTile group_tile_of(const int32_t *order, int64_t wg, int 
   return tile_of(order, q, W, H, views, ce);
 }
 
-// Pixel of this lane's ray: wavefront w of part p covers a TW x TH block
-// (8x8, 8x4, 4x4 for G = 1, 2, 4), ray r = lane / G the pixel
-// (r mod TW, r / TW) of it.
+// Pixel of the ray of thread t of a workgroup item: wavefront w = t / 64 of
+// part p covers a TW x TH block (8x8, 8x4, 4x4 for G = 1, 2, 4), ray
+// r = (t mod 64) / G the pixel (r mod TW, r / TW) of it.
 template <int G>
-__device__ inline void group_pixel_of(int sx, int sy, int part, int &col, int &row) {
+__device__ inline void group_pixel_of(int sx, int sy, int part, int t, int &col, int &row) {
   constexpr int TW = G <= 2 ? 8 : 4, TH = kWaveSize / G / TW, WX = kSuperEdge / TW;
-  const int wave = threadIdx.x / kWaveSize, ray = (threadIdx.x % kWaveSize) / G;
+  const int wave = t / kWaveSize, ray = (t % kWaveSize) / G;
   col = sx * kSuperEdge + (wave % WX) * TW + ray % TW;
   row = sy * kSuperEdge + part * (kSuperEdge / G) + (wave / WX) * TH + ray / TW;
+}
+
+template <int G>
+__device__ inline void group_pixel_of(int sx, int sy, int part, int &col, int &row) {
+  group_pixel_of<G>(sx, sy, part, (int)threadIdx.x, col, row);
 }
 
 // Workgroups of a launch over `items` super-tile items (or the padded Morton
@@ -1536,20 +1541,57 @@ __host__ __device__ inline int64_t group_grid(int64_t items, int G) {
   return (items + kXcds - 1) / kXcds * kXcds * G;
 }
 
+// ---------------------------------------------------------------------------
+// Wavefront work queues.  Within an XCD the hardware hands workgroups to its
+// shader engines in strict rotation, and waits for the next one in turn to
+// have room: when the long tiles pile up on one shader engine, the others
+// idle although work is left (measured on the C1 frame: 15-40 % of some
+// engines' slots idle in the middle of the launch).  A queued launch instead
+// starts only as many workgroups as the device holds at once; each of their
+// wavefronts takes wavefront items (wavefront w of workgroup item i) from a
+// counter per XCD until all eight are drained.  Workgroup item i belongs to
+// queue i mod 8 (the XCD it would have run on), queue position
+// 4 (i / 8) + w; a wavefront starts at its own XCD's queue and then helps the
+// others.  The counters sit behind the workgroup order, in the same buffer,
+// and are zeroed by the kernel that writes the order.
+// ---------------------------------------------------------------------------
+constexpr int kQueueStride = 32;                         // ints: one 128-byte line per counter
+constexpr int64_t kOrderQueueInts = kXcds * kQueueStride;  // counters behind the order
+constexpr int kWavesPerWg = kWgSize / kWaveSize;
+
+// Take the next wavefront item (workgroup item i, wavefront w) for a
+// wavefront of XCD-queue cursor x; false once every queue is drained.  Called
+// by the whole wavefront.
+__device__ inline bool next_wave_item(uint32_t *queue, uint32_t per_queue, int &x, int &tried, int64_t &i, int &w) {
+  while (tried < kXcds) {
+    uint32_t idx = 0;
+    if (threadIdx.x % kWaveSize == 0) idx = atomicAdd(queue + x * kQueueStride, 1u);
+    idx = __builtin_amdgcn_readfirstlane(idx);
+    if (idx < per_queue) {
+      i = x + (int64_t)kXcds * (idx / kWavesPerWg);
+      w = (int)(idx % kWavesPerWg);
+      return true;
+    }
+    x = (x + 1) % kXcds;
+    ++tried;
+  }
+  return false;
+}
+
 // The kernel's by-value argument struct, read in place from the kernarg
 // segment (scalar loads; dynamic indexing then needs no private copy).
 template <class T> __device__ inline const T &kernarg() {
   return *(const T *)__builtin_amdgcn_kernarg_segment_ptr();
 }
 
-// Diagnostics (a library built with VR_TIMELINE): lane 0 of every wavefront
-// writes its record (start, end, super-tile << 32 | HW_ID, work) into `tl`.
+// Diagnostics (a library built with VR_TIMELINE): lane 0 of a wavefront
+// writes the record of its wavefront item w (start, end, super-tile << 32 |
+// HW_ID, work) into `tl` (item w = 4 x workgroup item + wavefront).
 constexpr int kTimelineWaves = 1 << 17;
 #ifdef VR_TIMELINE
-__device__ inline void timeline_record(unsigned long long *tl, unsigned long long t0, int tile, uint32_t work) {
+__device__ inline void timeline_record(unsigned long long *tl, size_t w, unsigned long long t0, int tile, uint32_t work) {
   for (int off = 32; off > 0; off >>= 1) work += __shfl_xor(work, off, kWaveSize);
   const unsigned long long t1 = __builtin_amdgcn_s_memrealtime();
-  const size_t w = (size_t)blockIdx.x * (kWgSize / kWaveSize) + threadIdx.x / kWaveSize;
   if (threadIdx.x % kWaveSize == 0 && w < (size_t)kTimelineWaves) {
     unsigned hw;
     asm volatile("s_getreg_b32 %0, hwreg(HW_REG_HW_ID)" : "=s"(hw));

@@ -24,6 +24,8 @@ struct RenderArgs {
   int32_t shaded;                  // nonzero: local lighting with `shade`
   int32_t filter;                  // VR_FILTER_*
   int32_t occ_lds_words;           // > 0: stage vol.occ in LDS (set at launch)
+  uint32_t *queue;                 // wavefront work-queue counters, or nullptr (set at launch)
+  int32_t queue_items;             // wavefront items per queue (set at launch)
   ShadeConst shade;
   CamConst cams[kMaxCamsPerLaunch];
 };
@@ -79,14 +81,19 @@ int64_t render_grid(const RenderArgs &a);
 // Centre-out workgroup order for the views of `a`: super-tiles sorted by
 // their distance to the projection of the volume's centre (the tiles whose
 // rays cross the most volume go first, so the longest tiles do not start
-// last).  Allocated on `s` (stream-ordered); the caller frees it with
-// hipFreeAsync after its launches.  nullptr when it cannot be allocated (the
-// Morton mapping is used then).
+// last), followed by the zeroed counters of the wavefront work queues
+// (kOrderQueueInts).  Allocated on `s` (stream-ordered); the caller frees it
+// with hipFreeAsync after its launches.  nullptr when it cannot be allocated
+// (the Morton mapping is used then).  One order serves one launch: the
+// launch consumes its counters.
 int32_t *make_tile_order(const RenderArgs &a, hipStream_t s);
-// The same order written into `order` (tile_order_count(a) entries, every one
-// written), allocating nothing.
+// The same order and counters written into `order` (tile_order_count(a) +
+// kOrderQueueInts entries, every one written), allocating nothing.
 hipError_t launch_tile_order(const RenderArgs &a, int32_t *order, hipStream_t s);
 int64_t tile_order_count(const RenderArgs &a);
+// Workgroups of kernel `fn` the current device holds at once with `lds` bytes
+// of LDS each (0 when it cannot be found out).
+int64_t resident_workgroups(const void *fn, uint32_t lds);
 hipError_t launch_render_backward(const BackwardArgs &a, hipStream_t s);
 hipError_t launch_block_minmax(const VolConst &v, float2 *out, hipStream_t s);
 hipError_t launch_block_occupancy(const VolConst &v, const TfConst &tf, uint8_t *occ, hipStream_t s);
