@@ -455,9 +455,8 @@ __device__ inline void backward_wave_item(const BackwardArgs &a, const TfShared 
 }
 
 // LDS holds two workgroups per CU (two wavefronts per SIMD): 256 registers.
-// One workgroup item per workgroup: fed from the forward's wavefront queues,
-// the adjoint measured 15 % slower (C1: 9.9 -> 11.4 ms), the item loop
-// costing registers it does not have.
+// Queued like the forward (one workgroup item per workgroup without queue
+// counters); a workgroup's TF gradient stays in its LDS over all its items.
 template <int DT>
 __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_render_bwd(
     const BackwardArgs args) {
@@ -494,11 +493,18 @@ __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(2, 2)))
       for (int j = threadIdx.x; j < 4 * K; j += kWgSize) a.grad_tf[j] = q;
     return;
   }
-  int part;
-  if (!group_tile_of<kBwdRayGroup>(ra.order, blockIdx.x, ra.W, ra.H, ra.n_views, ra.chunk_edge, part).valid)
-    return;  // uniform over the workgroup
   __amdgpu_buffer_rsrc_t rs = make_rsrc(ra.vol.data, ra.vol.bytes);
-  backward_wave_item<DT>(a, s, sgtf, box, rs, blockIdx.x, (int)(threadIdx.x / kWaveSize));
+  if (!ra.queue) {
+    int part;
+    if (!group_tile_of<kBwdRayGroup>(ra.order, blockIdx.x, ra.W, ra.H, ra.n_views, ra.chunk_edge, part).valid)
+      return;  // uniform over the workgroup
+    backward_wave_item<DT>(a, s, sgtf, box, rs, blockIdx.x, (int)(threadIdx.x / kWaveSize));
+  } else {
+    int x = (int)(blockIdx.x % kXcds), tried = 0, w = 0;
+    int64_t i = 0;
+    while (next_wave_item(ra.queue, (uint32_t)ra.queue_items, x, tried, i, w))
+      backward_wave_item<DT>(a, s, sgtf, box, rs, i, w);
+  }
   if (sgtf) {
     __syncthreads();
     for (int j = threadIdx.x; j < 4 * K; j += kWgSize) {
@@ -513,7 +519,7 @@ __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(2, 2)))
 hipError_t launch_render_backward(const BackwardArgs &a0, hipStream_t s) {
   BackwardArgs a = a0;
   const RenderArgs &ra = a.r;
-  const int64_t grid = group_grid(render_grid(ra), kBwdRayGroup);
+  int64_t grid = group_grid(render_grid(ra), kBwdRayGroup);
 #ifdef VR_TIMELINE
   g_timeline_bwd_records = grid * (kWgSize / kWaveSize);
 #endif
@@ -531,7 +537,16 @@ hipError_t launch_render_backward(const BackwardArgs &a0, hipStream_t s) {
   }
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-
+  a.r.queue = nullptr;
+  a.r.queue_items = 0;
+  if (ra.order) {
+    const int64_t resident = resident_workgroups(fn, lds);
+    if (resident > 0 && resident < grid) {
+      a.r.queue = reinterpret_cast<uint32_t *>(const_cast<int32_t *>(ra.order) + tile_order_count(ra));
+      a.r.queue_items = (int32_t)(grid / kXcds * kWavesPerWg);
+      grid = resident;
+    }
+  }
   switch (ra.vol.dtype) {
   case kU16: hipLaunchKernelGGL(k_render_bwd<kU16>, dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
   case kI16: hipLaunchKernelGGL(k_render_bwd<kI16>, dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;

@@ -634,12 +634,17 @@ __device__ inline float reconstruct(__amdgpu_buffer_rsrc_t rs, const VolConst &v
   return f.acc;
 }
 
-// The 16 x-rows of the stencil at cell (ix, iy, iz), loaded ahead of the
-// sample that needs them (for_rows' interior fast path only; else empty).
+// The first kRows of the 16 x-rows of the stencil at cell (ix, iy, iz),
+// loaded ahead of the sample that needs them (for_rows' interior fast path
+// only; else empty); the rest are loaded when the sample is taken.  Holding
+// all 16 across the adjoint's step spilled registers; with 8 the queued
+// adjoint fits 256 without spills (C1 fwd + adjoint 10.0 -> 9.0 ms, C3 292
+// -> 252 ms, with the queue).
 template <int DT> struct TapPrefetch {
-  typename Vox<DT>::RawRow raw[16];
+  static constexpr int kRows = 8;
+  typename Vox<DT>::RawRow raw[kRows];
   int ix, iy, iz;  // ix == INT_MIN: empty
-  uint32_t sh;
+  uint32_t sh, voff;
 };
 
 template <int DT>
@@ -656,9 +661,9 @@ __device__ inline void prefetch_taps(TapPrefetch<DT> &p, __amdgpu_buffer_rsrc_t 
   const uint32_t voff = (DT == kF32) ? e0 * 4u : (e0 & ~1u) * 2u;
   const uint32_t rs_x = (uint32_t)nx * kb, rs_xy = nxy * kb;
 #pragma unroll
-  for (int c = 0; c < 4; ++c)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) p.raw[4 * c + b] = Vox<DT>::row_s_load(rs, voff, (uint32_t)c * rs_xy + (uint32_t)b * rs_x);
+  for (int i = 0; i < TapPrefetch<DT>::kRows; ++i)
+    p.raw[i] = Vox<DT>::row_s_load(rs, voff, (uint32_t)(i / 4) * rs_xy + (uint32_t)(i % 4) * rs_x);
+  p.voff = voff;
   p.sh = (e0 & 1u) * 16u;
   p.ix = ix;
   p.iy = iy;
@@ -671,13 +676,22 @@ template <int DT>
 __device__ inline float reconstruct_prefetched(const TapPrefetch<DT> &p, __amdgpu_buffer_rsrc_t rs, const VolConst &v,
                                                const Stencil &s) {
   if (p.ix != s.ix || p.iy != s.iy || p.iz != s.iz) return reconstruct<DT>(rs, v, s);
+  constexpr int NP = TapPrefetch<DT>::kRows;
+  // the rows not loaded ahead, issued before the prefetched ones are used
+  typename Vox<DT>::RawRow late[16 - NP];
+  const uint32_t kb = (uint32_t)Vox<DT>::kBytes;
+  const uint32_t rs_x = (uint32_t)v.nx * kb, rs_xy = (uint32_t)v.nx * (uint32_t)v.ny * kb;
+#pragma unroll
+  for (int i = NP; i < 16; ++i)
+    late[i - NP] = Vox<DT>::row_s_load(rs, p.voff, (uint32_t)(i / 4) * rs_xy + (uint32_t)(i % 4) * rs_x);
   ValueRows f{s, 0.0f, 0.0f};
 #pragma unroll
   for (int c = 0; c < 4; ++c)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
+      const int i = 4 * c + b;
       float t[4];
-      Vox<DT>::row_unpack(p.raw[4 * c + b], p.sh, t);
+      Vox<DT>::row_unpack(i < NP ? p.raw[i < NP ? i : 0] : late[i < NP ? 0 : i - NP], p.sh, t);
       f(c, b, t);
     }
   return f.acc;
