@@ -500,9 +500,10 @@ __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(2, 2)))
       return;  // uniform over the workgroup
     backward_wave_item<DT>(a, s, sgtf, box, rs, blockIdx.x, (int)(threadIdx.x / kWaveSize));
   } else {
-    int x = (int)(blockIdx.x % kXcds), tried = 0, w = 0;
+    const int x = (int)(blockIdx.x % kXcds);
+    int w = 0;
     int64_t i = 0;
-    while (next_wave_item(ra.queue, (uint32_t)ra.queue_items, x, tried, i, w))
+    while (next_wave_item(ra.queue, (uint32_t)ra.queue_items, x, i, w))
       backward_wave_item<DT>(a, s, sgtf, box, rs, i, w);
   }
   if (sgtf) {
@@ -541,7 +542,7 @@ hipError_t launch_render_backward(const BackwardArgs &a0, hipStream_t s) {
   a.r.queue_items = 0;
   if (ra.order) {
     const int64_t resident = resident_workgroups(fn, lds);
-    if (resident > 0 && resident < grid) {
+    if (resident >= kXcds && resident < grid) {
       a.r.queue = reinterpret_cast<uint32_t *>(const_cast<int32_t *>(ra.order) + tile_order_count(ra));
       a.r.queue_items = (int32_t)(grid / kXcds * kWavesPerWg);
       grid = resident;

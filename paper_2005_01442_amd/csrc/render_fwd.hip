@@ -233,9 +233,10 @@ void k_render(const RenderArgs args) {
     render_wave_item<DT, SHADE, F>(a, s, tf_ok, box, rs, blockIdx.x, (int)(threadIdx.x / kWaveSize), evaluated,
                                    unstaged, lattice, hits);
   } else {
-    int x = (int)(blockIdx.x % kXcds), tried = 0, w = 0;
+    const int x = (int)(blockIdx.x % kXcds);
+    int w = 0;
     int64_t i = 0;
-    while (next_wave_item(a.queue, (uint32_t)a.queue_items, x, tried, i, w))
+    while (next_wave_item(a.queue, (uint32_t)a.queue_items, x, i, w))
       render_wave_item<DT, SHADE, F>(a, s, tf_ok, box, rs, i, w, evaluated, unstaged, lattice, hits);
   }
   if (a.counters) {
@@ -272,7 +273,7 @@ static hipError_t launch_render_as(const RenderArgs &a0, int64_t grid, uint32_t 
   a.queue_items = 0;
   if (a.order) {
     const int64_t resident = resident_workgroups(fn, lds);
-    if (resident > 0 && resident < grid) {
+    if (resident >= kXcds && resident < grid) {
       a.queue = reinterpret_cast<uint32_t *>(const_cast<int32_t *>(a.order) + tile_order_count(a));
       a.queue_items = (int32_t)(grid / kXcds * kWavesPerWg);
       grid = resident;

@@ -1,13 +1,14 @@
-"""Per-wavefront timeline of the whole-image kernels on the C1 frame.
+"""Per-wavefront-item timeline of the whole-image kernels on the C1 frame.
 
 A diagnostics build of the library (``libvr_timeline.so``, compiled with
-VR_TIMELINE) records for every wavefront of the last forward (``k_render``)
-or adjoint (``k_render_bwd``) launch its start and end on the 100 MHz constant
-clock, its super-tile and its work (see include/vr_timeline.h).  This script
-renders the C1 frame (512x512x400 int16 CT phantom -> 1024^2, step 0.5, 16^3
-block skipping, early termination at 0.99) with that build and prints a
-summary: makespan, wave-slot efficiency, the per-XCD ends (workgroup i runs on
-XCD i mod 8), the concurrency over time and the last wavefronts to finish.
+VR_TIMELINE) records for every wavefront item (8x4 rays) of the last forward
+(``k_render``) or adjoint (``k_render_bwd``) launch its start and end on the
+100 MHz constant clock, its super-tile and its work (see
+include/vr_timeline.h).  This script renders the C1 frame (512x512x400 int16
+CT phantom -> 1024^2, step 0.5, 16^3 block skipping, early termination at
+0.99) with that build and prints a summary: makespan, wave-slot efficiency,
+the per-XCD ends (workgroup item i belongs to XCD i mod 8's queue), the
+concurrency over time and the last items to finish.
 
 Run it by path (the package must not be imported first, so that it loads the
 diagnostics build):
