@@ -104,7 +104,7 @@ __device__ inline float4 march(const VolConst &v, const TfShared &s, const TfCon
 constexpr int kRayGroup = VR_RAY_GROUP;
 static_assert(kRayGroup == 1 || kRayGroup == 2 || kRayGroup == 4, "ray groups lie within a quad");
 
-template <int G, int DT, bool SHADE, int F>
+template <int G, int DT, bool SHADE, int F, int ZD = VR_VBOX_Z>
 __device__ inline float4 march_group(const VolConst &v, const TfShared &s, const TfConst &tf, const MarchConst &mc,
                                      const ShadeConst &sc, const Ray &r, __amdgpu_buffer_rsrc_t rs, ValBox &box,
                                      uint32_t &evaluated, uint32_t &unstaged) {
@@ -115,7 +115,7 @@ __device__ inline float4 march_group(const VolConst &v, const TfShared &s, const
   if constexpr (SHADE) rl = ray_light(sc, r.d);
   constexpr int kFillBatch = SHADE || F == 2 ? 2 : 4;
   auto prep = [&](bool want, float px, float py, float pz) {
-    if (box.cells) vbox_prepare<DT, kFillBatch>(box, rs, v, r, want, px, py, pz);
+    if (box.cells) vbox_prepare<DT, kFillBatch, ZD>(box, rs, v, r, want, px, py, pz);
   };
   auto eval = [&](int, float px, float py, float pz) -> ChainSample {
     const Classified q = eval_sample<DT, SHADE, F>(v, s, tf, tf_v0, tf_scale, sc, rl, rs, box, px, py, pz, unstaged);
@@ -141,6 +141,7 @@ __device__ inline float4 march_group(const VolConst &v, const TfShared &s, const
 #define VR_FWD_MIN_WAVES 3
 #endif
 constexpr uint32_t kLdsPerCu = 160u * 1024u;  // gfx950
+constexpr uint64_t kMallBytes = 256ull << 20;   // MI355X: 256 MB of Infinity Cache (MALL)
 constexpr uint32_t kFwdWgPerCu = VR_FWD_MAX_WAVES;  // four wavefronts per workgroup, one per SIMD
 
 // The occupancy bits join the LDS state (after the boxes) when three
@@ -158,7 +159,7 @@ static int64_t g_timeline_fwd_records = 0;
 
 // One wavefront item: wavefront w of workgroup item i (a part of a
 // super-tile); the counts of its samples are added to the caller's.
-template <int DT, bool SHADE, int F>
+template <int DT, bool SHADE, int F, int ZD>
 __device__ inline void render_wave_item(const RenderArgs &a, const TfShared &s, bool tf_ok, ValBox &box,
                                         __amdgpu_buffer_rsrc_t rs, int64_t i, int w, uint32_t &evaluated,
                                         uint32_t &unstaged, uint32_t &lattice, uint32_t &hits) {
@@ -191,7 +192,7 @@ __device__ inline void render_wave_item(const RenderArgs &a, const TfShared &s, 
   if constexpr (kRayGroup == 1)
     rgba = march<DT, SHADE, F>(a.vol, s, a.tf, a.mc, a.shade, r, rs, box, evaluated, unstaged);
   else
-    rgba = march_group<kRayGroup, DT, SHADE, F>(a.vol, s, a.tf, a.mc, a.shade, r, rs, box, evaluated, unstaged);
+    rgba = march_group<kRayGroup, DT, SHADE, F, ZD>(a.vol, s, a.tf, a.mc, a.shade, r, rs, box, evaluated, unstaged);
   if (inside && lead) {
     float4 *o = reinterpret_cast<float4 *>(a.out);
     o[((size_t)st.view * a.H + row) * a.W + col] = rgba;
@@ -205,7 +206,8 @@ __device__ inline void render_wave_item(const RenderArgs &a, const TfShared &s, 
 #endif
 }
 
-template <int DT, bool SHADE, int F>
+// ZD: depth of the LDS value boxes (see ValBox).
+template <int DT, bool SHADE, int F, int ZD = VR_VBOX_Z>
 __global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(SHADE ? VR_FWD_MAX_WAVES : (DT == kF32 ? 1 : VR_FWD_MIN_WAVES), VR_FWD_MAX_WAVES)))
 void k_render(const RenderArgs args) {
   extern __shared__ __attribute__((aligned(16))) char lds[];
@@ -230,14 +232,14 @@ void k_render(const RenderArgs args) {
                         : nullptr;
   uint32_t evaluated = 0, unstaged = 0, lattice = 0, hits = 0;
   if (!a.queue) {
-    render_wave_item<DT, SHADE, F>(a, s, tf_ok, box, rs, blockIdx.x, (int)(threadIdx.x / kWaveSize), evaluated,
+    render_wave_item<DT, SHADE, F, ZD>(a, s, tf_ok, box, rs, blockIdx.x, (int)(threadIdx.x / kWaveSize), evaluated,
                                    unstaged, lattice, hits);
   } else {
     const int x = (int)(blockIdx.x % kXcds);
     int w = 0;
     int64_t i = 0;
     while (next_wave_item(a.queue, (uint32_t)a.queue_items, x, i, w))
-      render_wave_item<DT, SHADE, F>(a, s, tf_ok, box, rs, i, w, evaluated, unstaged, lattice, hits);
+      render_wave_item<DT, SHADE, F, ZD>(a, s, tf_ok, box, rs, i, w, evaluated, unstaged, lattice, hits);
   }
   if (a.counters) {
     wave_count(a.counters + 0, evaluated);
@@ -259,12 +261,12 @@ int64_t resident_workgroups(const void *fn, uint32_t lds) {
   return (int64_t)cus * per;
 }
 
-template <bool SHADE, int F>
+template <bool SHADE, int F, int ZD = VR_VBOX_Z>
 static hipError_t launch_render_as(const RenderArgs &a0, int64_t grid, uint32_t lds, hipStream_t s) {
   RenderArgs a = a0;
-  const void *fn = a.vol.dtype == kU16   ? reinterpret_cast<const void *>(&k_render<kU16, SHADE, F>)
-                   : a.vol.dtype == kI16 ? reinterpret_cast<const void *>(&k_render<kI16, SHADE, F>)
-                                         : reinterpret_cast<const void *>(&k_render<kF32, SHADE, F>);
+  const void *fn = a.vol.dtype == kU16   ? reinterpret_cast<const void *>(&k_render<kU16, SHADE, F, ZD>)
+                   : a.vol.dtype == kI16 ? reinterpret_cast<const void *>(&k_render<kI16, SHADE, F, ZD>)
+                                         : reinterpret_cast<const void *>(&k_render<kF32, SHADE, F, ZD>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   // with an order (and its queue counters) the launch is queued: as many
@@ -280,9 +282,9 @@ static hipError_t launch_render_as(const RenderArgs &a0, int64_t grid, uint32_t 
     }
   }
   switch (a.vol.dtype) {
-  case kU16: hipLaunchKernelGGL((k_render<kU16, SHADE, F>), dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
-  case kI16: hipLaunchKernelGGL((k_render<kI16, SHADE, F>), dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
-  default: hipLaunchKernelGGL((k_render<kF32, SHADE, F>), dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
+  case kU16: hipLaunchKernelGGL((k_render<kU16, SHADE, F, ZD>), dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
+  case kI16: hipLaunchKernelGGL((k_render<kI16, SHADE, F, ZD>), dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
+  default: hipLaunchKernelGGL((k_render<kF32, SHADE, F, ZD>), dim3((unsigned)grid), dim3(kWgSize), lds, s, a); break;
   }
   return hipGetLastError();
 }
@@ -427,6 +429,9 @@ hipError_t launch_render(const RenderArgs &a0, hipStream_t s) {
   if (a.filter == 1) return launch_render_as<false, 1>(a, grid, lds, s);
   if (a.filter == 2) return launch_render_as<false, 2>(a, grid, lds, s);
   if (a.filter == 3) return launch_render_as<false, 3>(a, grid, lds, s);
+  // the shallow value box for volumes the MALL holds (their refills are
+  // cheap, its fill passes fewer), the deep one above
+  if (a.use_box && a.vol.bytes <= kMallBytes) return launch_render_as<false, 0, kVBoxShallow>(a, grid, lds, s);
   return launch_render_as<false, 0>(a, grid, lds, s);
 }
 

@@ -787,25 +787,41 @@ __device__ inline float4 combine_grad(const StencilG &g, const float t[4][4][4])
 }
 
 // ---------------------------------------------------------------------------
-// Value box: each wavefront stages in LDS a kVBox^3 box of the volume over the
-// slab its lanes are sampling, converted to fp32 with clamp-to-edge applied
-// while filling.  A step whose stencils all lie in the box reads its 64 taps
+// Value box: each wavefront stages in LDS a 14 x 14 x ZD (x, y, z) box of the
+// volume over the slab its lanes are sampling, converted to fp32 with
+// clamp-to-edge applied while filling.  ZD = 14, or 13 (kVBoxShallow): its
+// 182 rows of 14 voxels fill in three passes of the wavefront's lanes where
+// 196 need a fourth for 4 rows, while a deeper box is re-placed less often.
+// The whole-image forward takes the shallow box for volumes the 256 MB MALL
+// holds (C1 frame 1.233 -> 1.217 ms, C0 0.133 -> 0.122 ms) and the deep one
+// for larger volumes, whose refills come from HBM (C2 frame 13.0 ms deep,
+// 14.0 ms shallow).  Rows of 16 voxels or 12 rows per slice measured slower.  A step whose stencils all lie in the box reads its 64 taps
 // per sample from LDS, with the same FMA order as the global path (the value
 // is bit-identical).  When a step's stencils leave the box, the box is
 // refilled around them, extended along the marching direction; a step whose
 // stencils spread wider than the box reads from global memory.
 // ---------------------------------------------------------------------------
-#ifndef VR_VBOX_EDGE
-#define VR_VBOX_EDGE 14
+#ifndef VR_VBOX_X
+#define VR_VBOX_X 14
+#endif
+#ifndef VR_VBOX_Y
+#define VR_VBOX_Y 14
+#endif
+#ifndef VR_VBOX_Z
+#define VR_VBOX_Z 14
 #endif
 #ifndef VR_VBOX_ZPAD
 #define VR_VBOX_ZPAD 2  // z stride 198 (C1 with ray pairs: 0 or 2 1.297 ms, 4 1.320, 6 1.61)
 #endif
-constexpr int kVBox = VR_VBOX_EDGE;
-constexpr int kVBoxZ = kVBox * kVBox + VR_VBOX_ZPAD;  // padded z stride (LDS banks)
+constexpr int kVBoxExt[3] = {VR_VBOX_X, VR_VBOX_Y, VR_VBOX_Z};  // extent per axis
+constexpr int kVBox = VR_VBOX_X;                               // row stride (x)
+constexpr int kVBoxRows = VR_VBOX_Y;                           // rows per slice (y)
+constexpr int kVBoxZ = kVBox * kVBoxRows + VR_VBOX_ZPAD;       // padded z stride (LDS banks)
 static_assert(VR_VBOX_ZPAD % 2 == 0, "slices hold float2 pairs");
 static_assert(kVBox % 2 == 0 && kVBox >= 4 && kVBox <= 16, "box rows are filled in pairs from a 16-voxel window");
-constexpr int kVBoxCells = kVBox * kVBoxZ;
+static_assert(VR_VBOX_Y >= 4 && VR_VBOX_Z >= 4, "a stencil fits the box");
+constexpr int kVBoxCells = VR_VBOX_Z * kVBoxZ;
+constexpr int kVBoxShallow = VR_VBOX_Z - 1;  // the shallow box's depth
 
 struct ValBox {
   float *cells;  // this wavefront's LDS cells or nullptr (no staging)
@@ -815,9 +831,10 @@ struct ValBox {
 
 // kBatch rows per lane are loaded before any is stored (all of them by
 // default; kernels short of registers take fewer).
-template <int DT, int kBatch = (kVBox * kVBox + kWaveSize - 1) / kWaveSize>
+template <int DT, int kBatch = (kVBoxRows * VR_VBOX_Z + kWaveSize - 1) / kWaveSize, int ZD = VR_VBOX_Z>
 __device__ inline void vbox_fill(ValBox &b, __amdgpu_buffer_rsrc_t rs, const VolConst &v) {
-  constexpr int kRows = kVBox * kVBox;
+  static_assert(ZD >= 4 && ZD <= VR_VBOX_Z, "the box's depth fits its cells");
+  constexpr int kRows = kVBoxRows * ZD;
   constexpr int kPer = (kRows + kWaveSize - 1) / kWaveSize;  // rows per lane
   const int lane = threadIdx.x % kWaveSize;
   const uint32_t nvox = (uint32_t)v.nx * (uint32_t)v.ny * (uint32_t)v.nz;
@@ -831,8 +848,8 @@ __device__ inline void vbox_fill(ValBox &b, __amdgpu_buffer_rsrc_t rs, const Vol
 #pragma unroll
     for (int j = 0; j < kBatch; ++j) {
       const int row = min(lane + (j0 + j) * kWaveSize, kRows - 1);
-      const uint32_t y = (uint32_t)min(max(b.oy + row % kVBox, 0), v.ny - 1);
-      const uint32_t z = (uint32_t)min(max(b.oz + row / kVBox, 0), v.nz - 1);
+      const uint32_t y = (uint32_t)min(max(b.oy + row % kVBoxRows, 0), v.ny - 1);
+      const uint32_t z = (uint32_t)min(max(b.oz + row / kVBoxRows, 0), v.nz - 1);
       base[j] = (z * (uint32_t)v.ny + y) * (uint32_t)v.nx;
       raw[j] = Vox<DT>::row16_load(rs, base[j] + (uint32_t)max(b.ox, 0));
     }
@@ -849,7 +866,7 @@ __device__ inline void vbox_fill(ValBox &b, __amdgpu_buffer_rsrc_t rs, const Vol
           for (int i = 0; i < kVBox; ++i)
             t[i] = Vox<DT>::one(rs, rowbase + (uint32_t)min(max(b.ox + i, 0), v.nx - 1));
         }
-        float2 *dst = reinterpret_cast<float2 *>(b.cells + (row / kVBox) * kVBoxZ + (row % kVBox) * kVBox);
+        float2 *dst = reinterpret_cast<float2 *>(b.cells + (row / kVBoxRows) * kVBoxZ + (row % kVBoxRows) * kVBox);
 #pragma unroll
         for (int i = 0; i < kVBox / 2; ++i) dst[i] = make_float2(t[2 * i], t[2 * i + 1]);
       }
@@ -866,7 +883,7 @@ __device__ inline void vbox_fill(ValBox &b, __amdgpu_buffer_rsrc_t rs, const Vol
 }
 
 // Wavefront-wide, before the samples of a step.
-template <int DT, int kBatch = (kVBox * kVBox + kWaveSize - 1) / kWaveSize>
+template <int DT, int kBatch = (kVBoxRows * VR_VBOX_Z + kWaveSize - 1) / kWaveSize, int ZD = VR_VBOX_Z>
 __device__ inline void vbox_prepare(ValBox &b, __amdgpu_buffer_rsrc_t rs, const VolConst &v, const Ray &r,
                                     bool want, float px, float py, float pz) {
   int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
@@ -881,7 +898,7 @@ __device__ inline void vbox_prepare(ValBox &b, __amdgpu_buffer_rsrc_t rs, const 
   bool inside = true;
   if (want)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) inside = inside && lo[a] >= o[a] && hi[a] < o[a] + kVBox;
+    for (int a = 0; a < 3; ++a) inside = inside && lo[a] >= o[a] && hi[a] < o[a] + (a == 2 ? ZD : kVBoxExt[a]);
   if (b.valid && __ballot(!inside) == 0ull) return;
   int mn[3], mx[3];
   bool fits = true;
@@ -889,7 +906,7 @@ __device__ inline void vbox_prepare(ValBox &b, __amdgpu_buffer_rsrc_t rs, const 
   for (int a = 0; a < 3; ++a) {
     mn[a] = wave_min_i32(lo[a]);
     mx[a] = wave_max_i32(hi[a]);
-    fits = fits && (mx[a] - mn[a] < kVBox);
+    fits = fits && (mx[a] - mn[a] < (a == 2 ? ZD : kVBoxExt[a]));
   }
   if (!fits) {
     b.valid = false;  // this step reads from global memory
@@ -901,7 +918,7 @@ __device__ inline void vbox_prepare(ValBox &b, __amdgpu_buffer_rsrc_t rs, const 
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const float da = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, r.d[a]), first));
-    org[a] = da >= 0.0f ? mn[a] : mx[a] - kVBox + 1;
+    org[a] = da >= 0.0f ? mn[a] : mx[a] - (a == 2 ? ZD : kVBoxExt[a]) + 1;
   }
   // the lanes may still read the previous contents: order the refill after them
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -909,7 +926,7 @@ __device__ inline void vbox_prepare(ValBox &b, __amdgpu_buffer_rsrc_t rs, const 
   b.ox = __builtin_amdgcn_readfirstlane(org[0]);
   b.oy = __builtin_amdgcn_readfirstlane(org[1]);
   b.oz = __builtin_amdgcn_readfirstlane(org[2]);
-  vbox_fill<DT, kBatch>(b, rs, v);
+  vbox_fill<DT, kBatch, ZD>(b, rs, v);
   b.valid = true;
 }
 
