@@ -155,11 +155,12 @@ __device__ inline float4 nan_rgba() {
 // NaN results instead of rendering, the status word records it, and every
 // block counts as occupied (negative or NaN extinction is read as zero in the
 // LDS copy, so nothing downstream sees it).
+template <int NT = kWgSize>  // threads of the workgroup
 __device__ inline bool load_tf(TfShared &s, const TfConst &tf) {
   const int t = threadIdx.x;
   const float4 *src = reinterpret_cast<const float4 *>(tf.table);
   int bad = 0;
-  for (int j = t; j < tf.K; j += kWgSize) {
+  for (int j = t; j < tf.K; j += NT) {
     float4 n = src[j];
     bad |= tf_node_valid(n) ? 0 : 1;
     n.w = fmaxf(n.w, 0.0f);
@@ -168,14 +169,14 @@ __device__ inline bool load_tf(TfShared &s, const TfConst &tf) {
   bad = __syncthreads_or(bad);
   const int words = (tf.K + 63) / 64;
   const int wave = t / kWaveSize, lane = t % kWaveSize;
-  for (int w = wave; w < words; w += kWgSize / kWaveSize) {
+  for (int w = wave; w < words; w += NT / kWaveSize) {
     int j = w * 64 + lane;
     bool nz = (j < tf.K) && (bad || s.node[j].w != 0.0f);
     unsigned long long m = __ballot(nz);
     if (lane == 0) s.mask[w] = m;
   }
   __syncthreads();
-  for (int j = t; j <= tf.K; j += kWgSize) {
+  for (int j = t; j <= tf.K; j += NT) {
     int w = j / 64, b = j % 64;
     int c = 0;
     for (int q = 0; q < w; ++q) c += __popcll(s.mask[q]);
