@@ -53,6 +53,14 @@ def test_noalloc_matches_render_on_two_calls_second_smaller():
     cams = synth.orbit_cameras((96, 80, 72), 19, 133, 60.0, 24, 20)
     got, ref = _both(v2, None, cams, synth.tf1(), 0.5, 0.0, False)
     assert np.array_equal(got, ref)
+    # two large views in a row: queued launches whose work-queue counters live
+    # in the scratch too (each launch's order kernel zeroes them again)
+    for seed in (137, 138):
+        log(f"no-alloc: queued launch, 1024x768 view (seed {seed})")
+        cams = synth.orbit_cameras((96, 80, 72), 1, seed, 60.0, 1024, 768)
+        got, ref = _both(v2, b2, cams, synth.tf1(), 0.5, 0.99, True)
+        assert np.array_equal(got, ref)
+        assert np.all(got[..., 3] >= 0.0)  # every pixel written (the output starts at -7)
 
 
 def test_noalloc_refuses_sizes_beyond_its_scratch():
