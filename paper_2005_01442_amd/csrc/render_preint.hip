@@ -228,50 +228,79 @@ __device__ inline float4 march_preint(const VolConst &v, const TfShared &s, cons
   return make_float4(C0, C1, C2, 1.0f - T);
 }
 
+// One wavefront item of the pre-integrated render: wavefront w (an 8x8
+// sub-tile) of super-tile item i; n_items bounds the order.
 template <int DT>
-__global__ __launch_bounds__(kWgSize) void k_render_preint(const RenderArgs args, const float4 *tab) {
-  extern __shared__ __attribute__((aligned(16))) char lds[];
-  const RenderArgs &a = kernarg<RenderArgs>();
-  SuperTile st = tile_of(a.order, blockIdx.x, a.W, a.H, a.n_views, a.chunk_edge);
-  if (!st.valid) return;  // uniform over the workgroup
-  TfShared s = carve_tf(lds, a.tf.K);
-  if (a.occ_lds_words > 0)
-    stage_occupancy(s, a.vol, lds + vbox_lds_offset(a.tf.K) + vbox_lds_bytes(), a.occ_lds_words);
-  const bool tf_ok = load_tf(s, a.tf);
-  int col, row;
-  pixel_of(st.sx, st.sy, col, row);
+__device__ inline void preint_wave_item(const RenderArgs &a, const TfShared &s, bool tf_ok, const float4 *tab,
+                                        ValBox &box, __amdgpu_buffer_rsrc_t rs, int64_t i, int w, int64_t n_items,
+                                        uint32_t &evaluated, uint32_t &unstaged, uint32_t &lattice, uint32_t &hits) {
+  if (a.order && i >= n_items) return;  // padding of the last queue
+  const SuperTile st = tile_of(a.order, i, a.W, a.H, a.n_views, a.chunk_edge);
+  if (!st.valid) return;  // uniform over the wavefront
+  const int lane = (int)(threadIdx.x % kWaveSize);
+  const int col = st.sx * kSuperEdge + (w & 1) * kTileEdge + (lane & 7);
+  const int row = st.sy * kSuperEdge + (w >> 1) * kTileEdge + (lane >> 3);
   const bool inside = col < a.W && row < a.H;
   if (!tf_ok) {
     if (inside) reinterpret_cast<float4 *>(a.out)[((size_t)st.view * a.H + row) * a.W + col] = nan_rgba();
     return;
   }
   const CamConst &cam = a.cams[st.view];
-  uint32_t evaluated = 0, unstaged = 0;
   Ray r;
   r.hit = false;
   r.ns = 0;
   r.k0 = 0;
   r.s0 = 0.0f;
   if (inside) r = setup_ray(cam, col, row, a.vol.nx, a.vol.ny, a.vol.nz, a.mc.step);
+  const float4 rgba = march_preint<DT>(a.vol, s, a.tf, a.mc, tab, r, rs, box, evaluated, unstaged);
+  if (inside) reinterpret_cast<float4 *>(a.out)[((size_t)st.view * a.H + row) * a.W + col] = rgba;
+  lattice += (uint32_t)r.ns;
+  hits += r.hit ? 1u : 0u;
+}
+
+// Queued like the whole-image forward (one super-tile per workgroup without
+// queue counters); registers budgeted for three wavefronts per SIMD, which
+// the LDS value boxes allow.
+template <int DT>
+__global__ __launch_bounds__(kWgSize) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_render_preint(
+    const RenderArgs args, const float4 *tab) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const RenderArgs &a = kernarg<RenderArgs>();
+  const int64_t n_items = (int64_t)a.n_views * ((a.W + kSuperEdge - 1) / kSuperEdge) * ((a.H + kSuperEdge - 1) / kSuperEdge);
+  if (!a.queue && !tile_of(a.order, blockIdx.x, a.W, a.H, a.n_views, a.chunk_edge).valid)
+    return;  // uniform over the workgroup
+  TfShared s = carve_tf(lds, a.tf.K);
+  if (a.occ_lds_words > 0)
+    stage_occupancy(s, a.vol, lds + vbox_lds_offset(a.tf.K) + vbox_lds_bytes(), a.occ_lds_words);
+  const bool tf_ok = load_tf(s, a.tf);
   __amdgpu_buffer_rsrc_t rs = make_rsrc(a.vol.data, a.vol.bytes);
   ValBox box;
   box.valid = false;
   box.ox = box.oy = box.oz = 0;
   box.cells = a.use_box ? reinterpret_cast<float *>(lds + vbox_lds_offset(a.tf.K)) + (threadIdx.x / kWaveSize) * kVBoxCells
                         : nullptr;
-  float4 rgba = march_preint<DT>(a.vol, s, a.tf, a.mc, tab, r, rs, box, evaluated, unstaged);
-  if (inside) reinterpret_cast<float4 *>(a.out)[((size_t)st.view * a.H + row) * a.W + col] = rgba;
+  uint32_t evaluated = 0, unstaged = 0, lattice = 0, hits = 0;
+  if (!a.queue) {
+    preint_wave_item<DT>(a, s, tf_ok, tab, box, rs, blockIdx.x, (int)(threadIdx.x / kWaveSize), n_items, evaluated,
+                         unstaged, lattice, hits);
+  } else {
+    const int x = (int)(blockIdx.x % kXcds);
+    int w = 0;
+    int64_t i = 0;
+    while (next_wave_item(a.queue, (uint32_t)a.queue_items, x, i, w))
+      preint_wave_item<DT>(a, s, tf_ok, tab, box, rs, i, w, n_items, evaluated, unstaged, lattice, hits);
+  }
   if (a.counters) {
     wave_count(a.counters + 0, evaluated);
-    wave_count(a.counters + 1, (uint32_t)r.ns);
-    wave_count(a.counters + 2, r.hit ? 1u : 0u);
+    wave_count(a.counters + 1, lattice);
+    wave_count(a.counters + 2, hits);
     wave_count(a.counters + 3, unstaged);
   }
 }
 
 hipError_t launch_render_preint(const RenderArgs &a0, const float4 *tab, hipStream_t s) {
   RenderArgs a = a0;
-  const int64_t grid = render_grid(a);
+  int64_t grid = render_grid(a);
   uint32_t lds = tf_lds_bytes(a.tf.K);
   const uint32_t with_box = vbox_lds_offset(a.tf.K) + vbox_lds_bytes();
   a.use_box = with_box <= max_lds_per_workgroup() ? 1 : 0;
@@ -283,6 +312,17 @@ hipError_t launch_render_preint(const RenderArgs &a0, const float4 *tab, hipStre
                                          : reinterpret_cast<const void *>(&k_render_preint<kF32>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
+  a.queue = nullptr;
+  a.queue_items = 0;
+  if (a.order) {
+    const int64_t resident = resident_workgroups(fn, lds);
+    const int64_t padded = (grid + kXcds - 1) / kXcds * kXcds;  // queue i mod 8 holds items i
+    if (resident >= kXcds && resident < grid) {
+      a.queue = reinterpret_cast<uint32_t *>(const_cast<int32_t *>(a.order) + tile_order_count(a));
+      a.queue_items = (int32_t)(padded / kXcds * kWavesPerWg);
+      grid = resident;
+    }
+  }
   switch (a.vol.dtype) {
   case kU16: hipLaunchKernelGGL(k_render_preint<kU16>, dim3((unsigned)grid), dim3(kWgSize), lds, s, a, tab); break;
   case kI16: hipLaunchKernelGGL(k_render_preint<kI16>, dim3((unsigned)grid), dim3(kWgSize), lds, s, a, tab); break;
